@@ -1,0 +1,252 @@
+"""ctypes wrapper of the FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  The C sources
+cite the paper section each function follows.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    lib.o_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+    lib.o_gauss4.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _u64p, _dp]
+    lib.o_omega.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                            ctypes.c_int, ctypes.c_int, _dp]
+    lib.o_jacobi_rows.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp]
+    lib.o_sym_eig.argtypes = [_dp, ctypes.c_int, _dp, _dp]
+    lib.o_qr_householder.argtypes = [_dp, ctypes.c_int, ctypes.c_int, _dp]
+    lib.o_fd_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.o_fd_create.restype = ctypes.c_void_p
+    lib.o_fd_destroy.argtypes = [ctypes.c_void_p]
+    lib.o_fd_update.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, ctypes.c_int64]
+    lib.o_fd_query.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_fd_buffer.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_fd_buffer.restype = ctypes.c_int64
+    lib.o_fd_fill.argtypes = [ctypes.c_void_p]
+    lib.o_fd_fill.restype = ctypes.c_int64
+    lib.o_fd_shrinks.argtypes = [ctypes.c_void_p]
+    lib.o_fd_shrinks.restype = ctypes.c_int64
+    lib.o_fd_merge.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.o_shrink_exact.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.o_shrink_rand.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_uint64]
+    lib.o_power_iteration.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                      ctypes.c_int, _dp]
+    lib.o_power_iteration.restype = ctypes.c_double
+    lib.o_win_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.o_win_create.restype = ctypes.c_void_p
+    lib.o_win_destroy.argtypes = [ctypes.c_void_p]
+    lib.o_win_update.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, ctypes.c_int64]
+    lib.o_win_advance.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.o_win_query.argtypes = [ctypes.c_void_p, _dp, ctypes.POINTER(ctypes.c_int)]
+    lib.o_win_levels.argtypes = [ctypes.c_void_p]
+    lib.o_win_stats.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p]
+    lib.o_win_level_gram.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def philox4x64_10(ctr, key):
+    """Philox4x64-10 block for a 4-word counter and a 2-word key."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib.o_philox4x64_10(c.ctypes.data_as(_u64p), k.ctypes.data_as(_u64p), out.ctypes.data_as(_u64p))
+    return out
+
+
+def gauss4(seed, stream, ctr):
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    out = np.zeros(4)
+    lib.o_gauss4(seed, stream, c.ctypes.data_as(_u64p), _p(out))
+    return out
+
+
+def omega(seed, stream, b, d, k, tag=0):
+    """Gaussian test matrix (d x k) of shrink ``b``."""
+    lib = _load()
+    out = np.zeros((d, k))
+    lib.o_omega(seed, stream, b, tag, d, k, _p(out))
+    return out
+
+
+def jacobi_rows(X):
+    """One-sided Jacobi on the rows of X: returns (rotated rows sorted, sigma)."""
+    lib = _load()
+    X = _f64(X).copy()
+    m, d = X.shape
+    sig = np.zeros(m)
+    _check(lib.o_jacobi_rows(_p(X), m, d, d, _p(sig)), "jacobi_rows")
+    return X, sig
+
+
+def sym_eig(A):
+    lib = _load()
+    A = _f64(A).copy()
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    _check(lib.o_sym_eig(_p(A), n, _p(w), _p(V)), "sym_eig")
+    return w, V
+
+
+def qr(K):
+    lib = _load()
+    K = _f64(K)
+    m, k = K.shape
+    Q = np.zeros((m, k))
+    _check(lib.o_qr_householder(_p(K), m, k, _p(Q)), "qr")
+    return Q
+
+
+def shrink_exact(X, ell):
+    lib = _load()
+    X = _f64(X).copy()
+    m, d = X.shape
+    _check(lib.o_shrink_exact(_p(X), m, d, d, ell), "shrink_exact")
+    return X
+
+
+def shrink_rand(X, ell, k, q, seed, stream, b):
+    lib = _load()
+    X = _f64(X).copy()
+    m, d = X.shape
+    _check(lib.o_shrink_rand(_p(X), m, d, d, ell, k, q, seed, stream, b), "shrink_rand")
+    return X
+
+
+def power_iteration(C, x0, steps):
+    lib = _load()
+    C = _f64(C)
+    m, d = C.shape
+    x0 = _f64(x0)
+    v = np.zeros(d)
+    s = lib.o_power_iteration(_p(C), m, d, d, _p(x0), steps, _p(v))
+    return s, v
+
+
+class FD:
+    """Frequent Directions, exact (mode 'exact') or randomized (mode 'rand')."""
+
+    def __init__(self, d, ell, mode="exact", k=0, q=1, seed=0, stream=0):
+        lib = _load()
+        m = {"exact": 0, "rand": 1}[mode]
+        self._h = lib.o_fd_create(d, ell, m, k, q, seed, stream)
+        if not self._h:
+            raise ValueError("bad FD parameters")
+        self.d, self.ell = d, ell
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o_fd_destroy(self._h)
+            self._h = None
+
+    def update(self, rows):
+        rows = _f64(np.atleast_2d(rows))
+        if rows.shape[0] == 0:
+            return
+        _check(_lib.o_fd_update(self._h, _p(rows), rows.shape[0], rows.shape[1]), "fd_update")
+
+    def query(self):
+        out = np.zeros((self.ell, self.d))
+        _check(_lib.o_fd_query(self._h, _p(out)), "fd_query")
+        return out
+
+    def buffer(self):
+        r = _lib.o_fd_fill(self._h)
+        out = np.zeros((max(r, 1), self.d))
+        _lib.o_fd_buffer(self._h, _p(out))
+        return out[:r]
+
+    @property
+    def fill(self):
+        return _lib.o_fd_fill(self._h)
+
+    @property
+    def shrinks(self):
+        return _lib.o_fd_shrinks(self._h)
+
+    def merge(self, other):
+        _check(_lib.o_fd_merge(self._h, other._h), "fd_merge")
+
+
+class Window:
+    """ML-AeroSketch over a sliding window of N rows."""
+
+    def __init__(self, d, ell, N, R, q=1, seed=0, stream=0):
+        lib = _load()
+        self._h = lib.o_win_create(d, ell, N, float(R), q, seed, stream)
+        if not self._h:
+            raise ValueError("bad window parameters")
+        self.d, self.ell, self.N = d, ell, N
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o_win_destroy(self._h)
+            self._h = None
+
+    @property
+    def levels(self):
+        return _lib.o_win_levels(self._h)
+
+    def update(self, rows):
+        rows = _f64(np.atleast_2d(rows))
+        if rows.shape[0] == 0:
+            return
+        _check(_lib.o_win_update(self._h, _p(rows), rows.shape[0], rows.shape[1]), "win_update")
+
+    def advance(self, t_now):
+        _check(_lib.o_win_advance(self._h, t_now), "win_advance")
+
+    def query(self):
+        out = np.zeros((self.ell, self.d))
+        lvl = ctypes.c_int(0)
+        _check(_lib.o_win_query(self._h, _p(out), ctypes.byref(lvl)), "win_query")
+        return out, lvl.value
+
+    def stats(self, level):
+        st = np.zeros(6, dtype=np.int64)
+        _check(_lib.o_win_stats(self._h, level, st.ctypes.data_as(_i64p)), "win_stats")
+        keys = ["dumps", "raw", "dirs", "fill", "queue", "shrinks"]
+        return dict(zip(keys, st.tolist()))
+
+    def level_gram(self, level):
+        G = np.zeros((self.d, self.d))
+        _check(_lib.o_win_level_gram(self._h, level, _p(G)), "win_level_gram")
+        return G

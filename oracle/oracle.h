@@ -1,0 +1,105 @@
+/*
+ * oracle.h -- plain, slow, FP64 CPU reference for the Frequent-Directions
+ * (FD) shrink and its randomized variant.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this code; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no source with the GPU path.
+ *
+ * Paper: "Near-Optimal Time Matrix Sketch Framework for Persistent, Sliding
+ * Window, and Distributed Streams" (arXiv 2601.02019).
+ *   - FD buffer and shrink: Sec. 2.3 "Frequent Directions".
+ *   - Randomized factorisation: Sec. 2.2, Algorithm "Simultaneous Iteration"
+ *     (simul_iter).
+ *   - Power iteration: Sec. 2.2, Algorithm "Power Iteration".
+ *   - Update loop with the FD reduce: Algorithm "AeroSketch: Update".
+ *   - Query with the final shrink: Algorithm "AeroSketch: Query".
+ *   - Sliding window: Algorithm "ML-AeroSketch".
+ *   - Merge: Lemma "Decomposability" (appendix, proof of the P5 theorem).
+ *
+ * Conventions: every matrix is row-major FP64 with an explicit leading
+ * dimension; every function returns 0 on success and a negative code on a
+ * bad argument or non-convergence.
+ */
+#ifndef SKETCH_ORACLE_H
+#define SKETCH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- counter-based random numbers (Philox4x64-10, Salmon et al. SC'11) -- */
+void o_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+/* Four standard normals from one Philox block by the Box-Muller transform. */
+void o_gauss4(uint64_t seed, uint64_t stream, const uint64_t ctr[4], double out[4]);
+/* Omega[i][j] (d x k, row-major) for shrink number b: counter (i, j/4, b, tag). */
+void o_omega(uint64_t seed, uint64_t stream, uint64_t b, uint64_t tag,
+             int d, int k, double* omega);
+
+/* ---- dense linear algebra --------------------------------------------- */
+/* One-sided (Hestenes) Jacobi on the m rows of X (m x d, ld): rows are
+ * rotated until mutually orthogonal, then sorted by norm (descending);
+ * sigma[i] = norm of row i. */
+int o_jacobi_rows(double* X, int m, int d, int ld, double* sigma);
+/* Cyclic two-sided Jacobi eigen-decomposition of symmetric A (n x n).
+ * w: eigenvalues descending; V (n x n): eigenvectors in columns. A is
+ * destroyed. */
+int o_sym_eig(double* A, int n, double* w, double* V);
+/* Householder QR of K (m x k, m >= k): Q (m x k) with orthonormal columns
+ * spanning range(K) (completed arbitrarily if K is rank deficient). */
+int o_qr_householder(const double* K, int m, int k, double* Q);
+
+/* ---- Frequent Directions state machine --------------------------------- */
+typedef struct o_fd o_fd;
+enum { O_EXACT = 0, O_RAND = 1 };
+/* mode O_EXACT: FD with an exact SVD in every shrink.
+ * mode O_RAND : the SVD replaced by simul_iter on the buffer with target rank
+ *               k and q power steps, Omega drawn from Philox(seed, stream). */
+o_fd* o_fd_create(int d, int ell, int mode, int k, int q,
+                  uint64_t seed, uint64_t stream);
+void o_fd_destroy(o_fd* s);
+int o_fd_update(o_fd* s, const double* rows, int64_t n, int64_t ld);
+/* ell x d sketch: f_ell of the buffer rows (non-destructive). */
+int o_fd_query(const o_fd* s, double* out);
+/* Raw buffer rows [0, r) into out (r x d); returns r. */
+int64_t o_fd_buffer(const o_fd* s, double* out);
+int64_t o_fd_fill(const o_fd* s);
+int64_t o_fd_shrinks(const o_fd* s);
+/* dst absorbs the non-zero rows of src's queried sketch as ordinary rows. */
+int o_fd_merge(o_fd* dst, const o_fd* src);
+/* One shrink of an m-row buffer X in place, exposed for tests. */
+int o_shrink_exact(double* X, int m, int d, int ld, int ell);
+int o_shrink_rand(double* X, int m, int d, int ld, int ell, int k, int q,
+                  uint64_t seed, uint64_t stream, uint64_t b);
+
+/* ---- power iteration (Algorithm "Power Iteration") on C^T C ------------ */
+/* C is m x d. x0 is the start vector (length d, need not be normalised).
+ * Returns the Rayleigh quotient after `steps` steps; v receives the vector. */
+double o_power_iteration(const double* C, int m, int d, int ld,
+                         const double* x0, int steps, double* v);
+
+/* ---- sliding window: ML-AeroSketch ------------------------------------- */
+typedef struct o_win o_win;
+/* d, ell (eps = 2/ell), window N, R (bound on squared row norms; L =
+ * max(1, ceil(log2 R)) levels), q power steps of simul_iter. */
+o_win* o_win_create(int d, int ell, int64_t N, double R, int q,
+                    uint64_t seed, uint64_t stream);
+void o_win_destroy(o_win* w);
+int o_win_update(o_win* w, const double* rows, int64_t n, int64_t ld);
+/* Move time forward to t_now without rows (expires old entries). */
+int o_win_advance(o_win* w, int64_t t_now);
+/* ell x d sketch of the window (T-N, T]. level_out: the level used. */
+int o_win_query(const o_win* w, double* out, int* level_out);
+int o_win_levels(const o_win* w);
+/* Diagnostics of one level: counts of dumps, raw rows, dumped directions,
+ * residual rows and queue length. */
+int o_win_stats(const o_win* w, int level, int64_t* stats /* [6] */);
+/* Gram of the level's restored matrix B_T (d x d), Algorithm "Query" lines
+ * 1-4, with the in-window raw rows added. */
+int o_win_level_gram(const o_win* w, int level, double* G);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
