@@ -1,0 +1,171 @@
+/*
+ * sketch.h -- C ABI of the MI355X (gfx950) matrix-sketch library.
+ *
+ * The library maintains Frequent-Directions (FD) sketches of row streams on
+ * one GPU.  Each time a sketch's 2*ell-row buffer fills, it is shrunk: the
+ * buffer is factorised, the ell-th largest squared singular value is
+ * subtracted from every squared singular value (clamped at zero) and an
+ * (ell-1)-row sketch is rebuilt (paper Sec. 2.3 "Frequent Directions";
+ * Algorithm "AeroSketch: Update" lines 1-6).  With SK_SHRINK_RAND the exact
+ * SVD is replaced by the randomized factorisation of Algorithm "Simultaneous
+ * Iteration" (Sec. 2.2) applied to the buffer, with the Gaussian test matrix
+ * on the d side (Omega, d x k) drawn from Philox4x64-10.
+ *
+ * Problem statements served (paper Sec. 2.1):
+ *   - persistent stream sketch (SK_PERSISTENT): cov-error of the whole stream;
+ *   - sliding window (SK_WINDOW): Algorithm "ML-AeroSketch", window of the
+ *     last window_N rows;
+ *   - distributed streams: per-site sketches combined by sketch_merge
+ *     (Lemma "Decomposability").
+ *
+ * Conventions (all entry points):
+ *   - Matrices are row-major.  A row block is n_rows x d with leading
+ *     dimension ld >= d (elements).
+ *   - on_device != 0: the pointer is device memory of the sketch's GPU;
+ *     otherwise host memory.  The caller owns every input and output buffer;
+ *     the library owns all sketch state and scratch (allocated at create).
+ *   - Work is ordered on the sketch's HIP stream.  sketch_update returns once
+ *     the work is enqueued; device inputs must stay valid until sketch_sync,
+ *     a query, or a later call on the same handle has returned.  Host inputs
+ *     are copied before sketch_update returns.
+ *   - sketch_query blocks until B_out holds the result.
+ *   - Errors: no exception crosses the ABI.  On SK_EINVAL / SK_ESHAPE /
+ *     SK_EUNSUPPORTED the sketch state is unchanged.  A failed HIP call or a
+ *     non-converged eigen-solve makes the handle sticky-SK_EDEVICE.
+ *     sketch_last_error() returns a thread-local message for the last
+ *     failing call on the calling thread.
+ *   - Threading: one handle must not be used by two threads at once;
+ *     distinct handles are independent.
+ *   - Query output: ell rows; B_out^T B_out is the sketch (rows in descending
+ *     norm, signs arbitrary).  Compare B^T B, never B.
+ */
+#ifndef SKETCH_H
+#define SKETCH_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sketch_s* sketch_t; /* opaque, library-owned */
+
+typedef enum {
+    SK_OK = 0,
+    SK_EINVAL = -1,       /* bad argument (NULL, negative size, ld < d, ...)   */
+    SK_ENOMEM = -2,       /* device or host allocation failed / over budget     */
+    SK_EDEVICE = -3,      /* HIP error or eigen-solver failure (sticky)         */
+    SK_ESHAPE = -4,       /* shapes of two sketches do not match                */
+    SK_EUNSUPPORTED = -5, /* operation not defined for this kind of sketch      */
+    SK_ESTATE = -6        /* call out of order (e.g. time moving backwards)     */
+} sk_status;
+
+typedef enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 } sk_dtype;
+typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1 } sk_kind;
+typedef enum { SK_SHRINK_EXACT = 0, SK_SHRINK_RAND = 1 } sk_shrink;
+
+typedef struct {
+    int32_t d;            /* row dimension, >= 1                                  */
+    int32_t ell;          /* sketch rows (buffer holds 2*ell), >= 2              */
+    int32_t kind;         /* sk_kind                                             */
+    int32_t shrink;       /* sk_shrink (persistent sketches)                     */
+    int32_t state_dtype;  /* SK_F64 or SK_F32: dtype of the resident buffer      */
+    int32_t proj_dtype;   /* SK_F64, SK_F32 or SK_BF16: dtype of C*Omega inputs  */
+    int32_t q;            /* power steps of simul_iter (>= 0)                    */
+    int32_t oversample;   /* k = min(ell + oversample, 2*ell, d)                 */
+    int64_t window_N;     /* SK_WINDOW: window length in rows                    */
+    double R;             /* SK_WINDOW: bound on squared row norms (>= 1)        */
+    uint64_t seed;        /* Philox key word 0                                   */
+    uint64_t stream_id;   /* Philox key word 1                                   */
+    int32_t device;       /* HIP device ordinal                                  */
+    int32_t use_given_stream; /* 1: order work on hip_stream even when it is NULL
+                                 (the default stream); 0: NULL means a stream
+                                 owned by the library                           */
+    void* hip_stream;     /* hipStream_t to order work on                        */
+} sketch_config;
+
+/* Fills *cfg with defaults: exact FP64 persistent sketch, q = 1, no
+ * oversampling, seed 0, device 0, library-owned stream.  d and ell are 0 and
+ * must be set by the caller. */
+sk_status sketch_config_init(sketch_config* cfg);
+
+/* Creates a sketch; allocates all device state up front.
+ * SK_EINVAL for bad fields; SK_ENOMEM if allocation fails or the
+ * library-wide memory budget (sketch_set_memory_budget) would be exceeded. */
+sk_status sketch_create(const sketch_config* cfg, sketch_t* out);
+
+/* Appends n_rows rows (n_rows x d, leading dimension ld, element type dtype)
+ * to the stream.  Rows are copied into the buffer (converted to the state
+ * dtype, round-to-nearest-even); every time the buffer reaches 2*ell rows a
+ * shrink runs (Algorithm "AeroSketch: Update" lines 1-6).  n_rows == 0 is a
+ * no-op.  For SK_WINDOW sketches each row advances time by one. */
+sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld,
+                        int32_t dtype, int32_t on_device);
+
+/* Same for sparse rows in CSR form: indptr (n_rows + 1, int64, indptr[0] may
+ * be non-zero), column indices (int32, in [0, d)), values (float32).
+ * Duplicate indices within a row are summed.  Persistent sketches only. */
+sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* indices,
+                            const float* values, int64_t n_rows, int32_t on_device);
+
+/* Writes the ell x d sketch (row-major, dtype SK_F64 or SK_F32) to B_out.
+ * Persistent: f_ell of the buffer rows, i.e. one exact shrink of the current
+ * buffer when it holds >= ell rows (Algorithm "AeroSketch: Query" lines 5-7).
+ * Window: the query of Algorithm "ML-AeroSketch" for the window (T-N, T].
+ * Non-destructive. */
+sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device);
+
+/* SK_WINDOW only: moves time to t_now >= current time without rows and
+ * expires what left the window.  SK_EUNSUPPORTED on persistent sketches,
+ * SK_ESTATE if t_now is in the past. */
+sk_status window_advance(sketch_t h, int64_t t_now);
+
+/* dst absorbs each source sketch in order: the non-zero rows of the source's
+ * query are appended to dst as ordinary rows (stack and re-shrink, Lemma
+ * "Decomposability").  Sources are unchanged.  SK_ESHAPE if d differs;
+ * persistent sketches only. */
+sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src);
+
+/* Binary-tree merge of n_src sketches (same d and ell) into dst, which must be
+ * empty: level by level, pairs (2i, 2i+1) in index order are stacked and
+ * shrunk; the shrinks of one level run as one batched launch. */
+sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32_t n_src);
+
+/* Blocks until all work enqueued on h has finished; reports deferred device
+ * errors (e.g. a non-converged eigen-solve). */
+sk_status sketch_sync(sketch_t h);
+
+/* Waits for outstanding work and frees the sketch.  NULL is a no-op. */
+sk_status sketch_destroy(sketch_t h);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* sketch_last_error(void);
+
+typedef struct {
+    int64_t rows_seen;    /* rows appended so far (time for windows)              */
+    int64_t fill;         /* rows in the buffer now                                */
+    int64_t shrinks;      /* shrinks run so far                                    */
+    int64_t device_bytes; /* device memory owned by the sketch                     */
+    int32_t k;            /* target rank of the randomized shrink (0 if exact)     */
+    int32_t levels;       /* window levels (1 for persistent sketches)             */
+} sketch_info_t;
+
+sk_status sketch_info(sketch_t h, sketch_info_t* info);
+
+/* Library-wide cap (bytes) on device memory held by live sketches; 0 = no
+ * cap.  sketch_create returns SK_ENOMEM instead of exceeding it.  Used for
+ * admission control by a serving loop. */
+sk_status sketch_set_memory_budget(int64_t bytes);
+int64_t sketch_memory_in_use(void);
+
+/* Batched update: count sketches, each with its own device row block
+ * (rows[i], n[i] rows, ld[i] = its d).  All sketches must share one HIP
+ * stream and device.  Ingest and the shrinks that fall due are grouped
+ * across sketches: one launch per pipeline stage serves every sketch whose
+ * buffer filled at that point, whatever its d and ell. */
+sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
+                              int32_t count, int32_t dtype);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

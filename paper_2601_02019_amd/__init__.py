@@ -1,0 +1,238 @@
+"""MI355X (gfx950) Frequent-Directions sketches with a randomized shrink.
+
+Python front end over the C ABI in include/sketch.h.  The functions below
+have the C names and only marshal arguments; the ``Sketch`` class wraps a
+handle for convenience.  Device rows are torch tensors on the sketch's GPU;
+host rows may be numpy arrays or CPU tensors.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    SK_BF16, SK_EDEVICE, SK_EINVAL, SK_ENOMEM, SK_ESHAPE, SK_ESTATE, SK_EUNSUPPORTED, SK_F32,
+    SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
+    sketch_config, sketch_info_t,
+)
+
+_TORCH_DT = {torch.float64: SK_F64, torch.float32: SK_F32, torch.bfloat16: SK_BF16}
+_NP_DT = {np.dtype(np.float64): SK_F64, np.dtype(np.float32): SK_F32}
+_NAME_DT = {"f64": SK_F64, "f32": SK_F32, "bf16": SK_BF16}
+
+
+def _dt(x):
+    if isinstance(x, int):
+        return x
+    return _NAME_DT[x]
+
+
+def sketch_config_init():
+    cfg = sketch_config()
+    _lib.check(_lib.load().sketch_config_init(ctypes.byref(cfg)), "sketch_config_init")
+    return cfg
+
+
+def sketch_create(cfg):
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().sketch_create(ctypes.byref(cfg), ctypes.byref(h)), "sketch_create")
+    return h
+
+
+def _rows_arg(rows):
+    """(pointer, n, ld, dtype, on_device, keepalive) for a 2-D row block."""
+    if isinstance(rows, torch.Tensor):
+        if rows.dim() != 2:
+            raise ValueError("rows must be 2-D")
+        if rows.stride(1) != 1:
+            rows = rows.contiguous()
+        dt = _TORCH_DT[rows.dtype]
+        return rows.data_ptr(), rows.shape[0], rows.stride(0), dt, int(rows.is_cuda), rows
+    a = np.asarray(rows)
+    if a.ndim != 2:
+        raise ValueError("rows must be 2-D")
+    if a.dtype not in _NP_DT:
+        a = a.astype(np.float64)
+    a = np.ascontiguousarray(a)
+    return a.ctypes.data, a.shape[0], a.shape[1], _NP_DT[a.dtype], 0, a
+
+
+def sketch_update(h, rows):
+    ptr, n, ld, dt, dev, keep = _rows_arg(rows)
+    _lib.check(_lib.load().sketch_update(h, ctypes.c_void_p(ptr), n, ld, dt, dev), "sketch_update")
+    return keep
+
+
+def sketch_update_csr(h, indptr, indices, values):
+    on_dev = isinstance(indptr, torch.Tensor) and indptr.is_cuda
+    if on_dev:
+        ip, ix, vv = indptr.contiguous(), indices.contiguous(), values.contiguous()
+        assert ip.dtype == torch.int64 and ix.dtype == torch.int32 and vv.dtype == torch.float32
+        ptrs = (ip.data_ptr(), ix.data_ptr(), vv.data_ptr())
+        keep = (ip, ix, vv)
+    else:
+        ip = np.ascontiguousarray(indptr, dtype=np.int64)
+        ix = np.ascontiguousarray(indices, dtype=np.int32)
+        vv = np.ascontiguousarray(values, dtype=np.float32)
+        ptrs = (ip.ctypes.data, ix.ctypes.data, vv.ctypes.data)
+        keep = (ip, ix, vv)
+    n = (ip.shape[0] - 1)
+    _lib.check(_lib.load().sketch_update_csr(h, *(ctypes.c_void_p(p) for p in ptrs), n, int(on_dev)),
+               "sketch_update_csr")
+    return keep
+
+
+def sketch_query(h, out):
+    """Writes the ell x d sketch into ``out`` (torch tensor, CUDA or CPU, or
+    a numpy array), float64 or float32, contiguous."""
+    if isinstance(out, torch.Tensor):
+        assert out.is_contiguous()
+        dt = _TORCH_DT[out.dtype]
+        _lib.check(_lib.load().sketch_query(h, ctypes.c_void_p(out.data_ptr()), dt, int(out.is_cuda)),
+                   "sketch_query")
+    else:
+        assert out.flags["C_CONTIGUOUS"]
+        _lib.check(_lib.load().sketch_query(h, ctypes.c_void_p(out.ctypes.data), _NP_DT[out.dtype], 0),
+                   "sketch_query")
+    return out
+
+
+def window_advance(h, t_now):
+    _lib.check(_lib.load().window_advance(h, int(t_now)), "window_advance")
+
+
+def _handles(srcs):
+    arr = (ctypes.c_void_p * len(srcs))()
+    for i, s in enumerate(srcs):
+        arr[i] = s.value if isinstance(s, ctypes.c_void_p) else s.handle.value
+    return arr
+
+
+def sketch_merge(dst, srcs):
+    _lib.check(_lib.load().sketch_merge(dst, _handles(srcs), len(srcs)), "sketch_merge")
+
+
+def sketch_merge_tree(dst, srcs):
+    _lib.check(_lib.load().sketch_merge_tree(dst, _handles(srcs), len(srcs)), "sketch_merge_tree")
+
+
+def sketch_sync(h):
+    _lib.check(_lib.load().sketch_sync(h), "sketch_sync")
+
+
+def sketch_destroy(h):
+    _lib.check(_lib.load().sketch_destroy(h), "sketch_destroy")
+
+
+def sketch_last_error():
+    return _lib.load().sketch_last_error().decode(errors="replace")
+
+
+def sketch_info(h):
+    info = sketch_info_t()
+    _lib.check(_lib.load().sketch_info(h, ctypes.byref(info)), "sketch_info")
+    return {f: getattr(info, f) for f, _ in sketch_info_t._fields_}
+
+
+def sketch_set_memory_budget(nbytes):
+    _lib.check(_lib.load().sketch_set_memory_budget(int(nbytes)), "sketch_set_memory_budget")
+
+
+def sketch_memory_in_use():
+    return _lib.load().sketch_memory_in_use()
+
+
+def sketch_update_batch(sketches, rows_list, dtype=None):
+    """Batched update: rows_list[i] is a contiguous CUDA tensor (n_i x d_i)."""
+    n = len(sketches)
+    hs = _handles(sketches)
+    ptrs = (ctypes.c_void_p * n)()
+    ns = (ctypes.c_int64 * n)()
+    dt = None
+    for i, r in enumerate(rows_list):
+        assert isinstance(r, torch.Tensor) and r.is_cuda and r.is_contiguous()
+        ptrs[i] = r.data_ptr()
+        ns[i] = r.shape[0]
+        dt = _TORCH_DT[r.dtype] if dt is None else dt
+    if dtype is not None:
+        dt = _dt(dtype)
+    _lib.check(_lib.load().sketch_update_batch(hs, ptrs, ns, n, SK_F32 if dt is None else dt),
+               "sketch_update_batch")
+
+
+class Sketch:
+    """Owning wrapper of one sketch handle."""
+
+    def __init__(self, d, ell, kind="persistent", shrink="exact", state_dtype="f64",
+                 proj_dtype="f64", q=1, oversample=0, window_N=0, R=1.0, seed=0, stream_id=0,
+                 device=0, stream=None):
+        cfg = sketch_config_init()
+        cfg.d, cfg.ell = d, ell
+        cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW}[kind]
+        cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
+        cfg.state_dtype = _dt(state_dtype)
+        cfg.proj_dtype = _dt(proj_dtype)
+        cfg.q, cfg.oversample = q, oversample
+        cfg.window_N, cfg.R = int(window_N), float(R)
+        cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        if stream is not False:
+            # order the sketch's work on the torch stream (handle 0 is the
+            # default stream, which the C ABI takes only with this flag)
+            cfg.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+            cfg.use_given_stream = 1
+        self.d, self.ell = d, ell
+        self.device = device
+        self.handle = sketch_create(cfg)
+        self._keep = []
+
+    def update(self, rows):
+        keep = sketch_update(self.handle, rows)
+        if isinstance(rows, torch.Tensor) and rows.is_cuda:
+            self._keep.append(keep)
+            if len(self._keep) > 64:
+                self.sync()
+        return self
+
+    def update_csr(self, indptr, indices, values):
+        keep = sketch_update_csr(self.handle, indptr, indices, values)
+        if isinstance(indptr, torch.Tensor) and indptr.is_cuda:
+            self._keep.append(keep)
+        return self
+
+    def query(self, dtype=torch.float64, out=None):
+        if out is None:
+            out = torch.empty((self.ell, self.d), dtype=dtype, device=f"cuda:{self.device}")
+        sketch_query(self.handle, out)
+        self._keep.clear()
+        return out
+
+    def advance(self, t_now):
+        window_advance(self.handle, t_now)
+
+    def merge(self, srcs):
+        sketch_merge(self.handle, srcs)
+
+    def merge_tree(self, srcs):
+        sketch_merge_tree(self.handle, srcs)
+
+    def sync(self):
+        sketch_sync(self.handle)
+        self._keep.clear()
+
+    def info(self):
+        return sketch_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            sketch_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,97 @@
+"""ctypes binding of libsketch.so (include/sketch.h).
+
+Argument marshalling only: every step of the sketch runs in the library's HIP
+kernels.  torch is imported first so that the library binds to the same HIP
+runtime as torch (both use the soname libamdhip64.so.7); torch provides device
+memory and streams.  If the library is missing the import fails loudly --
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading libsketch.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsketch.so")
+
+SK_OK, SK_EINVAL, SK_ENOMEM, SK_EDEVICE, SK_ESHAPE, SK_EUNSUPPORTED, SK_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SK_F64, SK_F32, SK_BF16 = 0, 1, 2
+SK_PERSISTENT, SK_WINDOW = 0, 1
+SK_SHRINK_EXACT, SK_SHRINK_RAND = 0, 1
+
+STATUS_NAMES = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_ENOMEM", -3: "SK_EDEVICE", -4: "SK_ESHAPE",
+                -5: "SK_EUNSUPPORTED", -6: "SK_ESTATE"}
+
+
+class sketch_config(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32), ("ell", ctypes.c_int32), ("kind", ctypes.c_int32),
+        ("shrink", ctypes.c_int32), ("state_dtype", ctypes.c_int32), ("proj_dtype", ctypes.c_int32),
+        ("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("window_N", ctypes.c_int64),
+        ("R", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64),
+        ("device", ctypes.c_int32), ("use_given_stream", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class sketch_info_t(ctypes.Structure):
+    _fields_ = [
+        ("rows_seen", ctypes.c_int64), ("fill", ctypes.c_int64), ("shrinks", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("k", ctypes.c_int32), ("levels", ctypes.c_int32),
+    ]
+
+
+EXPORTS = [
+    "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query",
+    "window_advance", "sketch_merge", "sketch_merge_tree", "sketch_sync", "sketch_destroy",
+    "sketch_last_error", "sketch_info", "sketch_set_memory_budget", "sketch_memory_in_use",
+    "sketch_update_batch",
+]
+
+_lib = None
+
+
+def load():
+    """Loads libsketch.so (built by paper_2601_02019_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_02019_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.sketch_config_init.argtypes = [ctypes.POINTER(sketch_config)]
+    lib.sketch_create.argtypes = [ctypes.POINTER(sketch_config), ctypes.POINTER(vp)]
+    lib.sketch_update.argtypes = [vp, vp, i64, i64, i32, i32]
+    lib.sketch_update_csr.argtypes = [vp, vp, vp, vp, i64, i32]
+    lib.sketch_query.argtypes = [vp, vp, i32, i32]
+    lib.window_advance.argtypes = [vp, i64]
+    lib.sketch_merge.argtypes = [vp, ctypes.POINTER(vp), i32]
+    lib.sketch_merge_tree.argtypes = [vp, ctypes.POINTER(vp), i32]
+    lib.sketch_sync.argtypes = [vp]
+    lib.sketch_destroy.argtypes = [vp]
+    lib.sketch_last_error.argtypes = []
+    lib.sketch_last_error.restype = ctypes.c_char_p
+    lib.sketch_info.argtypes = [vp, ctypes.POINTER(sketch_info_t)]
+    lib.sketch_set_memory_budget.argtypes = [i64]
+    lib.sketch_memory_in_use.argtypes = []
+    lib.sketch_memory_in_use.restype = i64
+    lib.sketch_update_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                        i32, i32]
+    for name in EXPORTS:
+        if name not in ("sketch_last_error", "sketch_memory_in_use"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class SketchError(RuntimeError):
+    def __init__(self, code, where):
+        msg = load().sketch_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code != SK_OK:
+        raise SketchError(code, where)
+    return code

@@ -1,0 +1,457 @@
+// k_core.hip -- the FP64 core of the shrink (gfx950).
+//
+//   k_core_gemm   small FP64 products between scratch slots (power steps
+//                 G Q, Rayleigh-Ritz Q^T G Q, CholeskyQR products, Z = Q U)
+//   k_cholinv     Cholesky of the basis Gram W = Y^T Y with rank dropping,
+//                 then L^{-1} (CholeskyQR: Q = Y L^{-T})
+//   k_jacobi      symmetric eigen-decomposition by parallel-ordered cyclic
+//                 Jacobi: G = C C^T (exact shrink, size m) or the k x k
+//                 Rayleigh-Ritz matrix (Algorithm "Simultaneous Iteration"
+//                 line 5); eigenvalues sorted descending with vectors
+//   k_threshold   delta = ell-th eigenvalue; T = diag(f) Z^T with
+//                 f_i = sqrt(max(lambda_i - delta, 0) / lambda_i)
+//                 (Sec. 2.3 FD shrink; Algorithm "AeroSketch: Update" line 4)
+//
+// All arithmetic is FP64; reductions are in a fixed order, so results do not
+// depend on how many tasks share a launch.
+#include "sk_device.h"
+#include "sk_kernels.h"
+
+namespace sk {
+
+// ------------------------------------------------------------ small GEMM
+// C[M x N] = op(A) op(B), op(A) = A or A^T (TA), op(B) = B or B^T (TB).
+// dims: bits [1:0] M, [3:2] N, [5:4] K select 0 -> task m, 1 -> k,
+// 2 -> the eigen-problem size.
+__device__ __forceinline__ int dim_sel(const Task& t, int code) {
+    return code == 0 ? t.m : (code == 1 ? t.s->k : eig_n(t));
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_core_gemm(const Task* tasks, int sa, int sb, int sc,
+                                                   int dims) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    const SkDev* s = t.s;
+    const int M = dim_sel(t, dims & 3), N = dim_sel(t, (dims >> 2) & 3), K = dim_sel(t, (dims >> 4) & 3);
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    if (r0 >= M || c0 >= N) return;
+    const double* A = s->slot[sa];
+    const double* B = s->slot[sb];
+    double* C = s->slot[sc];
+    const int lda = s->sld[sa], ldb = s->sld[sb], ldc = s->sld[sc];
+    __shared__ double As[16][64 + 2];
+    __shared__ double Bs[16][64 + 2];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int kk = 0; kk < K; kk += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;  // 1024 elements of a 64 x 16 slice
+            if (!TA) {  // A row-major: consecutive threads walk k
+                const int r = e >> 4, k = e & 15;
+                As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(r0 + r) * lda + kk + k] : 0.0;
+            } else {    // A^T: consecutive threads walk the row index of op(A)
+                const int r = e & 63, k = e >> 6;
+                As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(kk + k) * lda + r0 + r] : 0.0;
+            }
+            if (!TB) {
+                const int c = e & 63, k = e >> 6;
+                Bs[k][c] = (c0 + c < N && kk + k < K) ? B[(int64_t)(kk + k) * ldb + c0 + c] : 0.0;
+            } else {
+                const int c = e >> 4, k = e & 15;
+                Bs[k][c] = (c0 + c < N && kk + k < K) ? B[(int64_t)(c0 + c) * ldb + kk + k] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = As[k][ty * 4 + i];
+                b[i] = Bs[k][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + ty * 4 + i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tx * 4 + j;
+            if (c < N) C[(int64_t)r * ldc + c] = acc[i][j];
+        }
+    }
+}
+
+// Index pair (a <= b) of the e-th entry of an upper triangle of order n,
+// counted row by row over (b, a) with a <= b: e = b (b + 1) / 2 + a.
+__device__ __forceinline__ void tri_index(int e, int& a, int& b) {
+    int bb = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while ((bb + 1) * (bb + 2) / 2 <= e) ++bb;
+    while (bb * (bb + 1) / 2 > e) --bb;
+    b = bb;
+    a = e - bb * (bb + 1) / 2;
+}
+
+// ------------------------------------------------------------ Cholesky
+// W (k x k, slot sw) -> X = L^{-1} (slot sx, lower), L L^T = W.  A pivot at
+// or below 1e-14 of its original diagonal marks the column as numerically
+// dependent: its row and column of X are zero, so the basis Q = Y X^T gets a
+// zero column there and the spanned subspace keeps only the independent part.
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int sx, int lds_max) {
+    extern __shared__ double lds[];
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind != T_SHRINK_RAND) return;
+    const SkDev* s = t.s;
+    const int n = s->k;
+    if (LDS != (n <= lds_max)) return;
+    const double* W = s->slot[sw];
+    const int ldw = s->sld[sw];
+    double* X = s->slot[sx];
+    const int ldx = s->sld[sx];
+    double* L = LDS ? lds : s->slot[S_EA];
+    const int ldl = n;
+    __shared__ double diag0[512];
+    __shared__ int drop[512];
+    __shared__ double dj_sh;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int e = tid; e < n * n; e += nth) {
+        const int i = e / n, j = e % n;
+        L[(int64_t)i * ldl + j] = (j <= i) ? 0.5 * (W[(int64_t)i * ldw + j] + W[(int64_t)j * ldw + i]) : 0.0;
+        if (i == j) diag0[i] = W[(int64_t)i * ldw + i];
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double piv = L[(int64_t)j * ldl + j];
+            const bool ok = piv > 1e-14 * diag0[j] && piv > 1e-300;
+            drop[j] = ok ? 0 : 1;
+            dj_sh = ok ? sqrt(piv) : 0.0;
+            L[(int64_t)j * ldl + j] = dj_sh;
+        }
+        __syncthreads();
+        const double dj = dj_sh;
+        const bool dr = drop[j] != 0;
+        for (int i = j + 1 + tid; i < n; i += nth) {
+            double* p = &L[(int64_t)i * ldl + j];
+            *p = dr ? 0.0 : *p / dj;
+        }
+        __syncthreads();
+        const int rem = n - j - 1;
+        if (!dr && rem > 0) {
+            const int cnt = rem * (rem + 1) / 2;
+            for (int e = tid; e < cnt; e += nth) {
+                int a, b;
+                tri_index(e, a, b);          // a <= b
+                const int l = j + 1 + a, i = j + 1 + b;  // l <= i
+                L[(int64_t)i * ldl + l] -= L[(int64_t)i * ldl + j] * L[(int64_t)l * ldl + j];
+            }
+        }
+        __syncthreads();
+    }
+    // X = L^{-1}: row i from rows < i (forward substitution, columns in parallel)
+    for (int i = 0; i < n; ++i) {
+        const double lii = L[(int64_t)i * ldl + i];
+        for (int c = tid; c < n; c += nth) {
+            double v = 0.0;
+            if (c <= i && !drop[i]) {
+                double acc = (c == i) ? 1.0 : 0.0;
+                for (int l = c; l < i; ++l) acc -= L[(int64_t)i * ldl + l] * X[(int64_t)l * ldx + c];
+                v = acc / lii;
+            }
+            X[(int64_t)i * ldx + c] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ Jacobi
+// Parallel cyclic Jacobi, round-robin ("chess tournament") ordering: in each
+// of the ne-1 steps of a sweep the ne/2 index pairs are disjoint, so all
+// rotations of a step commute and are applied together as A <- J^T A J on
+// 2 x 2 blocks, V <- V J.  Rotation of pair (p, q): Golub & Van Loan's
+// symmetric Schur step (tau = (a_qq - a_pp) / (2 a_pq)).  A pair is skipped
+// when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) or below 1e-17 ||A||_F; the solve
+// ends after a sweep without rotations.
+constexpr int JAC_MAX_SWEEPS = 40;
+
+__device__ __forceinline__ int rr_player(int slot, int step, int ne) {
+    return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ne - 1);
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max) {
+    extern __shared__ double lds[];
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    const SkDev* s = t.s;
+    const int n = eig_n(t);
+    if (LDS != (n <= lds_max)) return;
+    const bool rnd = t.kind == T_SHRINK_RAND;
+    const double* Ain = s->slot[rnd ? S_M : S_G];
+    const int ldin = s->sld[rnd ? S_M : S_G];
+    double* A = LDS ? lds : s->slot[S_EA];
+    const int la = n;
+    double* V = s->slot[S_EV];
+    const int lv = n;
+    double* U = s->slot[S_U];
+    const int lu = s->sld[S_U];
+    double* lam = s->slot[S_LAM];
+
+    __shared__ double cs_c[2][256], cs_s[2][256];
+    __shared__ int pp[2][256], qq[2][256];
+    __shared__ int rot_count[2];
+    __shared__ double red[32];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int ne = (n + 1) & ~1;
+    const int np = ne / 2;
+
+    double loc = 0.0;
+    for (int e = tid; e < n * n; e += nth) {
+        const int i = e / n, j = e % n;
+        const double v = 0.5 * (Ain[(int64_t)i * ldin + j] + Ain[(int64_t)j * ldin + i]);
+        A[(int64_t)i * la + j] = v;
+        V[(int64_t)i * lv + j] = (i == j) ? 1.0 : 0.0;
+        loc += v * v;
+    }
+    // block reduction of ||A||_F^2 in a fixed order
+    for (int off = 32; off > 0; off >>= 1) loc += __shfl_down(loc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = loc;
+    if (tid < 2) rot_count[tid] = 0;
+    __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < (nth + 63) / 64; ++w) fro2 += red[w];
+    const double floor_abs = 1e-300 + 1e-17 * sqrt(fro2);
+
+    int sweep = 0;
+    bool done = (n <= 1);
+    while (!done && sweep < JAC_MAX_SWEEPS) {
+        const int sb = sweep & 1;
+        if (tid == 0) rot_count[sb] = 0;
+        __syncthreads();
+        for (int step = 0; step < ne - 1; ++step) {
+            const int b = step & 1;
+            for (int m = tid; m < np; m += nth) {
+                int p = rr_player(m, step, ne), q = rr_player(ne - 1 - m, step, ne);
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                double c = 1.0, sn = 0.0;
+                if (q < n) {
+                    const double apq = A[(int64_t)p * la + q];
+                    const double app = A[(int64_t)p * la + p];
+                    const double aqq = A[(int64_t)q * la + q];
+                    if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        sn = tt * c;
+                        atomicAdd(&rot_count[sb], 1);
+                    }
+                }
+                cs_c[b][m] = c;
+                cs_s[b][m] = sn;
+                pp[b][m] = p;
+                qq[b][m] = q;
+            }
+            __syncthreads();
+            // A <- J^T A J on the 2 x 2 blocks (m1, m2), m1 <= m2; mirrors written
+            const int nblk = np * (np + 1) / 2;
+            for (int e = tid; e < nblk; e += nth) {
+                int m1, m2;
+                tri_index(e, m1, m2);
+                const int p1 = pp[b][m1], q1 = qq[b][m1], p2 = pp[b][m2], q2 = qq[b][m2];
+                const double c1 = cs_c[b][m1], s1 = cs_s[b][m1], c2 = cs_c[b][m2], s2 = cs_s[b][m2];
+                const bool hq1 = q1 < n, hq2 = q2 < n;
+                const double a00 = A[(int64_t)p1 * la + p2];
+                const double a01 = hq2 ? A[(int64_t)p1 * la + q2] : 0.0;
+                const double a10 = hq1 ? A[(int64_t)q1 * la + p2] : 0.0;
+                const double a11 = (hq1 && hq2) ? A[(int64_t)q1 * la + q2] : 0.0;
+                // rows: [p1; q1] <- [c1 -s1; s1 c1] [p1; q1]
+                const double r00 = c1 * a00 - s1 * a10, r01 = c1 * a01 - s1 * a11;
+                const double r10 = s1 * a00 + c1 * a10, r11 = s1 * a01 + c1 * a11;
+                // columns: [p2 q2] <- [p2 q2] [c2 s2; -s2 c2]
+                double n00 = r00 * c2 - r01 * s2, n01 = r00 * s2 + r01 * c2;
+                double n10 = r10 * c2 - r11 * s2, n11 = r10 * s2 + r11 * c2;
+                if (m1 == m2) {
+                    n01 = 0.0;
+                    n10 = 0.0;
+                }
+                A[(int64_t)p1 * la + p2] = n00;
+                if (hq2) A[(int64_t)p1 * la + q2] = n01;
+                if (hq1) A[(int64_t)q1 * la + p2] = n10;
+                if (hq1 && hq2) A[(int64_t)q1 * la + q2] = n11;
+                if (m1 != m2) {
+                    A[(int64_t)p2 * la + p1] = n00;
+                    if (hq2) A[(int64_t)q2 * la + p1] = n01;
+                    if (hq1) A[(int64_t)p2 * la + q1] = n10;
+                    if (hq1 && hq2) A[(int64_t)q2 * la + q1] = n11;
+                }
+            }
+            // V <- V J
+            for (int e = tid; e < n * np; e += nth) {
+                const int i = e / np, mm = e % np;
+                const int p = pp[b][mm], q = qq[b][mm];
+                if (q >= n) continue;
+                const double c = cs_c[b][mm], sn = cs_s[b][mm];
+                const double vp = V[(int64_t)i * lv + p], vq = V[(int64_t)i * lv + q];
+                V[(int64_t)i * lv + p] = c * vp - sn * vq;
+                V[(int64_t)i * lv + q] = sn * vp + c * vq;
+            }
+            __syncthreads();
+        }
+        done = rot_count[sb] == 0;
+        ++sweep;
+    }
+    // eigenvalues sorted descending (ties by index), vectors permuted along
+    for (int i = tid; i < n; i += nth) {
+        const double li = A[(int64_t)i * la + i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[(int64_t)j * la + j];
+            rank += (lj > li) || (lj == li && j < i);
+        }
+        lam[rank] = li;
+        for (int r = 0; r < n; ++r) U[(int64_t)r * lu + rank] = V[(int64_t)r * lv + i];
+    }
+    if (tid == 0) {
+        if (!done) atomicAdd(&s->info[0], 1);
+        atomicMax(&s->info[1], sweep);
+    }
+}
+
+// ------------------------------------------------------------ threshold
+// T (ell x m) = diag(f) Z^T with Z = U (exact) or Q U (randomized);
+// delta = lambda_ell (0 when fewer than ell eigenvalues); rows i >= min(n, ell)
+// and rows with f = 0 are zero.
+__global__ __launch_bounds__(256) void k_threshold(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    const SkDev* s = t.s;
+    const int n = eig_n(t), m = t.m, ell = s->ell;
+    const double* lam = s->slot[S_LAM];
+    const bool rnd = t.kind == T_SHRINK_RAND;
+    const double* Z = s->slot[rnd ? S_Z : S_U];
+    const int ldz = s->sld[rnd ? S_Z : S_U];
+    double* T = s->slot[S_T];
+    const int ldt = s->sld[S_T];
+    const double delta = (n >= ell) ? fmax(lam[ell - 1], 0.0) : 0.0;
+    const int keep = n < ell ? n : ell;
+    const double lmax = fmax(lam[0], 0.0);
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < ell * m; e += gridDim.x * 256) {
+        const int i = e / m, j = e % m;
+        double f = 0.0;
+        if (i < keep) {
+            const double li = lam[i];
+            if (li > 1e-300 && li > 1e-30 * lmax && li - delta > 0.0) f = sqrt((li - delta) / li);
+        }
+        T[(int64_t)i * ldt + j] = (i < keep) ? f * Z[(int64_t)j * ldz + i] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+// Largest n whose n x n FP64 matrix fits the dynamic LDS a kernel may take
+// (device limit minus the kernel's static LDS), capped at 128.
+static int g_jac_lds = -1, g_chol_lds = -1;
+
+static int lds_cap(const void* f) {
+    int dev = 0, maxsh = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int avail = maxsh - (int)fa.sharedSizeBytes;
+    int n = 0;
+    while ((n + 2) <= 128 && 8 * (n + 2) * (n + 2) <= avail) n += 2;
+    if (n > 0 && 8 * n * n > 65536) {
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 8 * n * n) != hipSuccess) {
+            (void)hipGetLastError();
+            while (n > 0 && 8 * n * n > 65536) n -= 2;
+        }
+    }
+    return n;
+}
+
+static void init_lds_caps() {
+    if (g_jac_lds < 0) g_jac_lds = lds_cap((const void*)k_jacobi<true>);
+    if (g_chol_lds < 0) g_chol_lds = lds_cap((const void*)k_cholinv<true>);
+}
+
+int jacobi_lds_max() {
+    init_lds_caps();
+    return g_jac_lds;
+}
+int chol_lds_max() {
+    init_lds_caps();
+    return g_chol_lds;
+}
+
+hipError_t launch_core_gemm(const Task* tasks, int count, int max_M, int max_N, bool ta, bool tb,
+                            int sa, int sb, int sc, int dims, hipStream_t st) {
+    const dim3 grid((unsigned)((max_N + 63) / 64), (unsigned)((max_M + 63) / 64), (unsigned)count);
+    if (!ta && !tb) hipLaunchKernelGGL((k_core_gemm<false, false>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else if (ta && !tb) hipLaunchKernelGGL((k_core_gemm<true, false>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else if (!ta && tb) hipLaunchKernelGGL((k_core_gemm<false, true>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else hipLaunchKernelGGL((k_core_gemm<true, true>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholinv(const Task* tasks, int count, int max_k, bool any_small, bool any_large,
+                          int sw, int sx, hipStream_t st) {
+    const int cap = chol_lds_max();
+    const dim3 grid(1, 1, (unsigned)count);
+    if (any_small && cap > 0) {
+        const int kk = max_k < cap ? max_k : cap;
+        hipLaunchKernelGGL((k_cholinv<true>), grid, dim3(1024), sizeof(double) * (size_t)kk * kk, st,
+                           tasks, sw, sx, cap);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (any_large || cap == 0) hipLaunchKernelGGL((k_cholinv<false>), grid, dim3(1024), 0, st, tasks, sw, sx, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small, bool any_large,
+                         hipStream_t st) {
+    const int cap = jacobi_lds_max();
+    const dim3 grid(1, 1, (unsigned)count);
+    if (any_small && cap > 0) {
+        const int nn = max_n < cap ? max_n : cap;
+        hipLaunchKernelGGL((k_jacobi<true>), grid, dim3(1024), sizeof(double) * (size_t)nn * nn, st, tasks, cap);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (any_large || cap == 0) hipLaunchKernelGGL((k_jacobi<false>), grid, dim3(1024), 0, st, tasks, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold(const Task* tasks, int count, int max_ell, int max_m, hipStream_t st) {
+    int blocks = (max_ell * max_m + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(k_threshold, dim3((unsigned)blocks, 1, (unsigned)count), dim3(256), 0, st, tasks);
+    return hipGetLastError();
+}
+
+}  // namespace sk

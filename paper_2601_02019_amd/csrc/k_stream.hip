@@ -1,0 +1,452 @@
+// k_stream.hip -- the d-sized kernels of the shrink and the row ingest
+// (gfx950).  Everything here reads task lists (sk_device.h); one launch per
+// stage serves every task of a batch.
+//
+//   k_ingest       rows -> buffer rows [row0, row0 + n) with dtype conversion
+//                  (Algorithm "AeroSketch: Update" line 1)
+//   k_ingest_csr   the same for CSR rows
+//   k_omega        Omega^T (k x d) from Philox4x64-10 + Box-Muller
+//                  (Algorithm "Simultaneous Iteration" line 1)
+//   k_nt_partial   split-K partial products C C^T (Gram of the buffer) and
+//                  C Omega (line 2's first product), FP64 accumulation
+//   k_reduce       fixed-order sum of the split-K partials (deterministic)
+//   k_rebuild      B' = T C: the FD rebuild diag(f) Z^T C (Sec. 2.3)
+//   k_convert_rows FP64 staging -> caller dtype
+#include "sk_device.h"
+#include "sk_kernels.h"
+
+namespace sk {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ double to_f64(float v) { return (double)v; }
+__device__ __forceinline__ double to_f64(uint16_t b) {
+    return (double)__uint_as_float(((uint32_t)b) << 16);
+}
+template <typename T> __device__ __forceinline__ T from_f64(double v);
+template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
+template <> __device__ __forceinline__ float from_f64<float>(double v) { return (float)v; }
+// bfloat16 with round-to-nearest-even from float (the float itself RNE from double)
+template <> __device__ __forceinline__ uint16_t from_f64<uint16_t>(double v) {
+    float f = (float)v;
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------- Philox
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t y0 = hi1 ^ c[1] ^ k0;
+        const uint64_t y2 = hi0 ^ c[3] ^ k1;
+        c[0] = y0;
+        c[1] = lo1;
+        c[2] = y2;
+        c[3] = lo0;
+    }
+}
+
+// Four N(0,1) draws for counter (c0, c1, c2, c3) and key (seed, stream):
+// Box-Muller on (w0, w1) and (w2, w3); u1 in (0, 1], u2 in [0, 1) from the
+// top 53 bits of each word.
+__device__ __forceinline__ void gauss4(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1,
+                                       uint64_t c2, uint64_t c3, double out[4]) {
+    uint64_t c[4] = {c0, c1, c2, c3};
+    philox4x64_10(c, seed, stream);
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double u1 = (double)((c[2 * h] >> 11) + 1) * 0x1p-53;
+        const double u2 = (double)(c[2 * h + 1] >> 11) * 0x1p-53;
+        const double rad = sqrt(-2.0 * log(u1));
+        double sn, cs;
+        sincos(two_pi * u2, &sn, &cs);
+        out[2 * h] = rad * cs;
+        out[2 * h + 1] = rad * sn;
+    }
+}
+
+// ---------------------------------------------------------------- ingest
+template <typename Tin, typename Tst>
+__global__ __launch_bounds__(256) void k_ingest(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    const int row = blockIdx.y;
+    if (t.kind != T_INGEST || row >= t.nrows) return;
+    const SkDev* s = t.s;
+    Tst* dst = (Tst*)s->buf[t.par] + (int64_t)(t.row0 + row) * s->ld;
+    const Tin* src = (const Tin*)t.src + (int64_t)row * t.src_ld;
+    const int d = s->d;
+    for (int c = (blockIdx.x * 256 + threadIdx.x) * 4; c < d; c += gridDim.x * 1024) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (c + u < d) dst[c + u] = from_f64<Tst>(to_f64(src[c + u]));
+    }
+}
+
+// One workgroup per sparse row: the row is assembled in LDS (duplicates
+// summed) and written out densely.
+template <typename Tst>
+__global__ __launch_bounds__(256) void k_ingest_csr(const Task* tasks) {
+    extern __shared__ double rowbuf[];
+    const Task& t = tasks[blockIdx.z];
+    const int row = blockIdx.y;
+    if (t.kind != T_INGEST || row >= t.nrows) return;
+    const SkDev* s = t.s;
+    const int d = s->d;
+    for (int c = threadIdx.x; c < d; c += 256) rowbuf[c] = 0.0;
+    __syncthreads();
+    const int64_t b = t.indptr[row], e = t.indptr[row + 1];
+    for (int64_t p = b + threadIdx.x; p < e; p += 256) {
+        const int j = t.indices[p];
+        if (j >= 0 && j < d) atomicAdd(&rowbuf[j], (double)t.values[p]);
+    }
+    __syncthreads();
+    Tst* dst = (Tst*)s->buf[t.par] + (int64_t)(t.row0 + row) * s->ld;
+    for (int c = threadIdx.x; c < d; c += 256) dst[c] = from_f64<Tst>(rowbuf[c]);
+}
+
+// ---------------------------------------------------------------- Omega^T
+template <typename Tp>
+__global__ __launch_bounds__(256) void k_omega(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind != T_SHRINK_RAND) return;
+    const SkDev* s = t.s;
+    const int i = blockIdx.x * 256 + threadIdx.x;  // coordinate in R^d
+    const int jg = blockIdx.y;                       // column group of 4
+    if (i >= s->d || 4 * jg >= s->k) return;
+    double g[4];
+    gauss4(s->seed, s->stream, (uint64_t)i, (uint64_t)jg, (uint64_t)t.shrink_idx, 0ull, g);
+    Tp* om = (Tp*)s->omegaT;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * jg + u < s->k) om[(int64_t)(4 * jg + u) * s->ld + i] = from_f64<Tp>(g[u]);
+}
+
+// ---------------------------------------------------------------- A B^T
+// MODE 0: Gram C C^T over the m buffer rows (upper tiles only);
+// MODE 1: C Omega with Omega^T stored k x ld.
+// 64 x 64 output tile, 16-deep k slices through LDS, 4 x 4 per thread.
+template <typename TA, typename TB, int MODE>
+__global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    if (MODE == 1 && t.kind != T_SHRINK_RAND) return;
+    const SkDev* s = t.s;
+    const int M = t.m;
+    const int N = MODE == 0 ? t.m : s->k;
+    const int splits = MODE == 0 ? s->sg : s->sp;
+    const int kc = MODE == 0 ? s->kcg : s->kcp;
+    if ((int)blockIdx.y >= splits) return;
+    const int ntm = (M + 63) >> 6, ntn = (N + 63) >> 6;
+    int ti, tj;
+    if (MODE == 0) {
+        int idx = blockIdx.x;
+        if (idx >= ntm * (ntm + 1) / 2) return;
+        ti = 0;
+        while (idx >= ntm - ti) {
+            idx -= ntm - ti;
+            ++ti;
+        }
+        tj = ti + idx;
+    } else {
+        if ((int)blockIdx.x >= ntm * ntn) return;
+        ti = blockIdx.x / ntn;
+        tj = blockIdx.x % ntn;
+    }
+    const TA* A = (const TA*)s->buf[t.par];
+    const TB* B = MODE == 0 ? (const TB*)s->buf[t.par] : (const TB*)s->omegaT;
+    const int64_t ld = s->ld;
+    const int kend = (s->d + 15) & ~15;
+    const int k0 = blockIdx.y * kc;
+    const int k1 = min(k0 + kc, kend);
+
+    __shared__ double As[16][64 + 2];
+    __shared__ double Bs[16][64 + 2];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int lr = tid >> 2, lk = (tid & 3) * 4;
+    const int ga = ti * 64 + lr, gb = tj * 64 + lr;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    for (int kk = k0; kk < k1; kk += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            As[lk + u][lr] = (ga < M) ? to_f64(A[(int64_t)ga * ld + kk + lk + u]) : 0.0;
+            Bs[lk + u][lr] = (gb < N) ? to_f64(B[(int64_t)gb * ld + kk + lk + u]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = As[k][ty * 4 + i];
+                b[i] = Bs[k][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    const int ldp = s->sld[MODE == 0 ? S_GPART : S_PPART];
+    const int64_t pstride = (int64_t)s->n2 * ldp;
+    double* part = s->slot[MODE == 0 ? S_GPART : S_PPART] + (int64_t)blockIdx.y * pstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = ti * 64 + ty * 4 + i;
+        if (r >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = tj * 64 + tx * 4 + j;
+            if (c < N) part[(int64_t)r * ldp + c] = acc[i][j];
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    if (MODE == 1 && t.kind != T_SHRINK_RAND) return;
+    const SkDev* s = t.s;
+    const int M = t.m;
+    const int N = MODE == 0 ? t.m : s->k;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    int i = idx / N, j = idx % N;
+    if (MODE == 0 && (i >> 6) > (j >> 6)) {  // lower tiles read the transposed partials
+        const int tmp = i;
+        i = j;
+        j = tmp;
+    }
+    const int splits = MODE == 0 ? s->sg : s->sp;
+    const int ldp = s->sld[MODE == 0 ? S_GPART : S_PPART];
+    const int64_t pstride = (int64_t)s->n2 * ldp;
+    const double* part = s->slot[MODE == 0 ? S_GPART : S_PPART];
+    double acc = 0.0;
+    for (int q = 0; q < splits; ++q) acc += part[q * pstride + (int64_t)i * ldp + j];
+    const int so = MODE == 0 ? S_G : S_P;
+    s->slot[so][(int64_t)(idx / N) * s->sld[so] + (idx % N)] = acc;
+}
+
+// ---------------------------------------------------------------- rebuild
+// rows_out x d = T (rows_out x m, FP64) . C (m x d).  QUERY writes ell rows
+// to the FP64 query staging; otherwise ell-1 rows to the other buffer.
+template <typename Tst, bool QUERY>
+__global__ __launch_bounds__(256) void k_rebuild(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    if (QUERY != (t.kind == T_QUERY)) return;
+    const SkDev* s = t.s;
+    const int rows_out = QUERY ? s->ell : s->ell - 1;
+    const int K = t.m;
+    const int N = s->d;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    if (r0 >= rows_out || c0 >= N) return;
+    const double* T = s->slot[S_T];
+    const int ldt = s->sld[S_T];
+    const Tst* X = (const Tst*)s->buf[t.par];
+    const int64_t ld = s->ld;
+
+    __shared__ double As[16][64 + 2];
+    __shared__ double Bs[16][64 + 2];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int kk = 0; kk < K; kk += 16) {
+        {   // T tile: 64 rows x 16 k
+            const int lr = tid >> 2, lk = (tid & 3) * 4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = r0 + lr, k = kk + lk + u;
+                As[lk + u][lr] = (r < rows_out && k < K) ? T[(int64_t)r * ldt + k] : 0.0;
+            }
+        }
+        {   // C tile: 16 k rows x 64 columns (columns < ld are always allocated)
+            const int kr = tid >> 4, lc = (tid & 15) * 4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kk + kr;
+                Bs[kr][lc + u] = (k < K) ? to_f64(X[(int64_t)k * ld + c0 + lc + u]) : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = As[k][ty * 4 + i];
+                b[i] = Bs[k][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + ty * 4 + i;
+        if (r >= rows_out) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tx * 4 + j;
+            if (c >= N) continue;
+            if (QUERY)
+                s->slot[S_QOUT][(int64_t)r * ld + c] = acc[i][j];
+            else
+                ((Tst*)s->buf[1 - t.par])[(int64_t)r * ld + c] = from_f64<Tst>(acc[i][j]);
+        }
+    }
+}
+
+template <typename To>
+__global__ __launch_bounds__(256) void k_convert_rows(const double* src, int64_t lds, To* dst,
+                                                      int64_t ldd, int rows, int cols) {
+    const int r = blockIdx.y;
+    if (r >= rows) return;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < cols; c += gridDim.x * 256)
+        dst[(int64_t)r * ldd + c] = from_f64<To>(src[(int64_t)r * lds + c]);
+}
+
+template <typename Tst>
+__global__ __launch_bounds__(256) void k_rows_to_f64(const Tst* src, int64_t lds, double* dst,
+                                                     int64_t ldd, int rows, int cols) {
+    const int r = blockIdx.y;
+    if (r >= rows) return;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < cols; c += gridDim.x * 256)
+        dst[(int64_t)r * ldd + c] = to_f64(src[(int64_t)r * lds + c]);
+}
+
+// ---------------------------------------------------------------- launchers
+static inline dim3 g3(int x, int y, int z) { return dim3((unsigned)x, (unsigned)y, (unsigned)z); }
+
+hipError_t launch_ingest(const Task* tasks, int count, int max_rows, int max_d, int in_dtype,
+                         int st_dtype, hipStream_t st) {
+    const dim3 grid = g3((max_d + 1023) / 1024, max_rows, count);
+    if (st_dtype == DT_F64) {
+        if (in_dtype == DT_F64) hipLaunchKernelGGL((k_ingest<double, double>), grid, dim3(256), 0, st, tasks);
+        else if (in_dtype == DT_F32) hipLaunchKernelGGL((k_ingest<float, double>), grid, dim3(256), 0, st, tasks);
+        else hipLaunchKernelGGL((k_ingest<uint16_t, double>), grid, dim3(256), 0, st, tasks);
+    } else {
+        if (in_dtype == DT_F64) hipLaunchKernelGGL((k_ingest<double, float>), grid, dim3(256), 0, st, tasks);
+        else if (in_dtype == DT_F32) hipLaunchKernelGGL((k_ingest<float, float>), grid, dim3(256), 0, st, tasks);
+        else hipLaunchKernelGGL((k_ingest<uint16_t, float>), grid, dim3(256), 0, st, tasks);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ingest_csr(const Task* tasks, int count, int max_rows, int max_d, int st_dtype,
+                             hipStream_t st) {
+    const dim3 grid = g3(1, max_rows, count);
+    const size_t lds = sizeof(double) * (size_t)max_d;
+    if (st_dtype == DT_F64) hipLaunchKernelGGL((k_ingest_csr<double>), grid, dim3(256), lds, st, tasks);
+    else hipLaunchKernelGGL((k_ingest_csr<float>), grid, dim3(256), lds, st, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega(const Task* tasks, int count, int max_d, int max_k, int pj_dtype,
+                        hipStream_t st) {
+    const dim3 grid = g3((max_d + 255) / 256, (max_k + 3) / 4, count);
+    if (pj_dtype == DT_F64) hipLaunchKernelGGL((k_omega<double>), grid, dim3(256), 0, st, tasks);
+    else if (pj_dtype == DT_F32) hipLaunchKernelGGL((k_omega<float>), grid, dim3(256), 0, st, tasks);
+    else hipLaunchKernelGGL((k_omega<uint16_t>), grid, dim3(256), 0, st, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(const Task* tasks, int count, int max_m, int max_splits, int st_dtype,
+                       hipStream_t st) {
+    const int nt = (max_m + 63) / 64;
+    const dim3 grid = g3(nt * (nt + 1) / 2, max_splits, count);
+    if (st_dtype == DT_F64) hipLaunchKernelGGL((k_nt_partial<double, double, 0>), grid, dim3(256), 0, st, tasks);
+    else hipLaunchKernelGGL((k_nt_partial<float, float, 0>), grid, dim3(256), 0, st, tasks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2 = g3((max_m * max_m + 255) / 256, 1, count);
+    hipLaunchKernelGGL((k_reduce<0>), g2, dim3(256), 0, st, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const Task* tasks, int count, int max_m, int max_k, int max_splits,
+                          int st_dtype, int pj_dtype, hipStream_t st) {
+    const int ntm = (max_m + 63) / 64, ntn = (max_k + 63) / 64;
+    const dim3 grid = g3(ntm * ntn, max_splits, count);
+    if (st_dtype == DT_F64) {
+        if (pj_dtype == DT_F64) hipLaunchKernelGGL((k_nt_partial<double, double, 1>), grid, dim3(256), 0, st, tasks);
+        else if (pj_dtype == DT_F32) hipLaunchKernelGGL((k_nt_partial<double, float, 1>), grid, dim3(256), 0, st, tasks);
+        else hipLaunchKernelGGL((k_nt_partial<double, uint16_t, 1>), grid, dim3(256), 0, st, tasks);
+    } else {
+        if (pj_dtype == DT_F64) hipLaunchKernelGGL((k_nt_partial<float, double, 1>), grid, dim3(256), 0, st, tasks);
+        else if (pj_dtype == DT_F32) hipLaunchKernelGGL((k_nt_partial<float, float, 1>), grid, dim3(256), 0, st, tasks);
+        else return launch_project_bf16(tasks, count, max_m, max_k, max_splits, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2 = g3((max_m * max_k + 255) / 256, 1, count);
+    hipLaunchKernelGGL((k_reduce<1>), g2, dim3(256), 0, st, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_proj(const Task* tasks, int count, int max_m, int max_k, hipStream_t st) {
+    const dim3 g2 = g3((max_m * max_k + 255) / 256, 1, count);
+    hipLaunchKernelGGL((k_reduce<1>), g2, dim3(256), 0, st, tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild(const Task* tasks, int count, int max_ell, int max_d, int st_dtype,
+                          bool query, hipStream_t st) {
+    const dim3 grid = g3((max_d + 63) / 64, (max_ell + 63) / 64, count);
+    if (st_dtype == DT_F64) {
+        if (query) hipLaunchKernelGGL((k_rebuild<double, true>), grid, dim3(256), 0, st, tasks);
+        else hipLaunchKernelGGL((k_rebuild<double, false>), grid, dim3(256), 0, st, tasks);
+    } else {
+        if (query) hipLaunchKernelGGL((k_rebuild<float, true>), grid, dim3(256), 0, st, tasks);
+        else hipLaunchKernelGGL((k_rebuild<float, false>), grid, dim3(256), 0, st, tasks);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_rows(const double* src, int64_t lds, void* dst, int64_t ldd, int rows,
+                               int cols, int out_dtype, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid = g3((cols + 255) / 256 < 64 ? (cols + 255) / 256 : 64, rows, 1);
+    if (out_dtype == DT_F64)
+        hipLaunchKernelGGL((k_convert_rows<double>), grid, dim3(256), 0, st, src, lds, (double*)dst, ldd, rows, cols);
+    else
+        hipLaunchKernelGGL((k_convert_rows<float>), grid, dim3(256), 0, st, src, lds, (float*)dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_to_f64(const void* src, int64_t lds, int st_dtype, double* dst, int64_t ldd,
+                              int rows, int cols, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid = g3((cols + 255) / 256 < 64 ? (cols + 255) / 256 : 64, rows, 1);
+    if (st_dtype == DT_F64)
+        hipLaunchKernelGGL((k_rows_to_f64<double>), grid, dim3(256), 0, st, (const double*)src, lds, dst, ldd, rows, cols);
+    else
+        hipLaunchKernelGGL((k_rows_to_f64<float>), grid, dim3(256), 0, st, (const float*)src, lds, dst, ldd, rows, cols);
+    return hipGetLastError();
+}
+
+}  // namespace sk

@@ -1,0 +1,928 @@
+// sk_api.cpp -- host engine and C ABI (include/sketch.h).
+//
+// The host owns each sketch's state machine: it knows from row counts alone
+// when the buffer fills (Algorithm "AeroSketch: Update" line 2), so a whole
+// update call is planned on the host as a list of Task records (ingest
+// segments and shrinks), uploaded once, and executed as a stream-ordered
+// sequence of task-list launches without any device-to-host round trip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sketch.h"
+#include "sk_device.h"
+#include "sk_kernels.h"
+#include "sk_window.h"
+
+using namespace sk;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+static thread_local const char* g_stage = "";  // last pipeline stage launched
+static std::atomic<int64_t> g_in_use{0};
+static std::atomic<int64_t> g_budget{0};
+
+static sk_status fail(sk_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(h, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) return (h)->device_fail(std::string(#expr) + " [" + g_stage + \
+                                                      "]: " + hipGetErrorString(_e));       \
+    } while (0)
+
+static int dtype_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// --------------------------------------------------------------- task arena
+// Pinned host mirror + device array of Task records, used as two halves in
+// alternation; a half is rewritten only after the event recorded behind the
+// last launch that read it has completed.
+struct TaskArena {
+    Task* host = nullptr;
+    Task* dev = nullptr;
+    int cap = 0;  // per half
+    int half = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+
+    hipError_t reserve(int n, hipStream_t st) {
+        if (n <= cap) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        release();
+        int c = std::max(n, 256);
+        e = hipHostMalloc((void**)&host, sizeof(Task) * 2 * (size_t)c, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = hipMalloc((void**)&dev, sizeof(Task) * 2 * (size_t)c);
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < 2; ++i) {
+            e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+            used[i] = false;
+        }
+        cap = c;
+        return hipSuccess;
+    }
+    // Copies tasks to the next half; returns its device pointer.
+    hipError_t upload(const std::vector<Task>& tasks, hipStream_t st, Task** out) {
+        hipError_t e = reserve((int)tasks.size(), st);
+        if (e != hipSuccess) return e;
+        half ^= 1;
+        if (used[half]) {
+            e = hipEventSynchronize(ev[half]);
+            if (e != hipSuccess) return e;
+        }
+        Task* h = host + (size_t)half * cap;
+        Task* d = dev + (size_t)half * cap;
+        std::memcpy(h, tasks.data(), sizeof(Task) * tasks.size());
+        e = hipMemcpyAsync(d, h, sizeof(Task) * tasks.size(), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        *out = d;
+        return hipSuccess;
+    }
+    hipError_t done(hipStream_t st) {
+        used[half] = true;
+        return hipEventRecord(ev[half], st);
+    }
+    void release() {
+        if (host) (void)hipHostFree(host);
+        if (dev) (void)hipFree(dev);
+        for (int i = 0; i < 2; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        host = nullptr;
+        dev = nullptr;
+        ev[0] = ev[1] = nullptr;
+        cap = 0;
+    }
+};
+
+// ------------------------------------------------------------------ sketch
+struct sketch_s {
+    sketch_config cfg{};
+    int d = 0, ell = 0, n2 = 0, k = 0, q = 0;
+    bool rnd = false;
+    int st = DT_F64, pj = DT_F64;
+    int64_t ld = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    SkDev host{};
+    SkDev* dev = nullptr;
+    std::vector<void*> allocs;
+    int64_t bytes = 0;
+    int par = 0;
+    int64_t fill = 0, shrinks = 0, rows_seen = 0;
+    bool sticky = false;
+    std::string sticky_msg;
+    void* stage = nullptr;  // device staging of host inputs / outputs
+    size_t stage_bytes = 0;
+    int64_t* csr_stage_ptr = nullptr;
+    TaskArena arena;
+    WindowState* win = nullptr;
+    bool counted = false;
+
+    sk_status device_fail(const std::string& msg) {
+        sticky = true;
+        sticky_msg = msg;
+        return fail(SK_EDEVICE, msg);
+    }
+    hipError_t dalloc(void** p, size_t n) {
+        if (n == 0) n = 8;
+        hipError_t e = hipMalloc(p, n);
+        if (e == hipSuccess) {
+            allocs.push_back(*p);
+            bytes += (int64_t)n;
+        }
+        return e;
+    }
+    hipError_t ensure_stage(size_t n) {
+        if (n <= stage_bytes) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        if (stage) (void)hipFree(stage);
+        stage = nullptr;
+        stage_bytes = 0;
+        e = hipMalloc(&stage, n);
+        if (e == hipSuccess) stage_bytes = n;
+        return e;
+    }
+};
+
+// Split-K plan: about 512 workgroups in total for a launch.
+static void splitk_plan(int tiles, int d, int* splits, int* chunk) {
+    int s = std::max(1, (512 + tiles - 1) / tiles);
+    s = std::min(s, std::max(1, (d + 127) / 128));
+    int kc = (int)round_up((d + s - 1) / s, 16);
+    s = (d + kc - 1) / kc;
+    *splits = std::max(1, s);
+    *chunk = kc;
+}
+
+static sk_status build_device_state(sketch_t h) {
+    const int d = h->d, ell = h->ell, n2 = h->n2, k = h->k;
+    const int neig = std::max(n2, k);
+    const int kk = std::max(k, 1);
+    SkDev& s = h->host;
+    std::memset(&s, 0, sizeof(s));
+    s.d = d;
+    s.ell = ell;
+    s.n2 = n2;
+    s.k = k;
+    s.st = h->st;
+    s.pj = h->pj;
+    s.ld = h->ld;
+    s.seed = h->cfg.seed;
+    s.stream = h->cfg.stream_id;
+    const int ntg = (n2 + 63) / 64;
+    splitk_plan(ntg * (ntg + 1) / 2, d, &s.sg, &s.kcg);
+    splitk_plan(ntg * ((kk + 63) / 64), d, &s.sp, &s.kcp);
+    const size_t es = (size_t)dtype_size(h->st);
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(h, h->dalloc(&s.buf[b], es * (size_t)n2 * (size_t)h->ld));
+        HIP_TRY(h, hipMemset(s.buf[b], 0, es * (size_t)n2 * (size_t)h->ld));
+    }
+    if (h->rnd) {
+        const size_t ps = (size_t)dtype_size(h->pj);
+        HIP_TRY(h, h->dalloc(&s.omegaT, ps * (size_t)k * (size_t)h->ld));
+        HIP_TRY(h, hipMemset(s.omegaT, 0, ps * (size_t)k * (size_t)h->ld));
+    }
+    struct Sz { int slot; int64_t rows, cols; };
+    const int64_t mk = h->rnd ? kk : 1;
+    const Sz sizes[] = {
+        {S_G, n2, n2},       {S_P, n2, mk},        {S_Y, n2, mk},      {S_Q, n2, mk},
+        {S_Q1, n2, mk},      {S_W, mk, mk},        {S_X, mk, mk},      {S_T1, n2, mk},
+        {S_M, mk, mk},       {S_U, neig, neig},    {S_Z, n2, mk},      {S_T, ell, n2},
+        {S_LAM, 1, neig},    {S_EA, neig, neig},   {S_EV, neig, neig},
+        {S_GPART, (int64_t)s.sg * n2, n2},
+        {S_PPART, (int64_t)(h->rnd ? s.sp : 1) * n2, mk},
+        {S_QOUT, ell, h->ld},
+    };
+    for (const Sz& z : sizes) {
+        void* p = nullptr;
+        HIP_TRY(h, h->dalloc(&p, sizeof(double) * (size_t)z.rows * (size_t)z.cols));
+        s.slot[z.slot] = (double*)p;
+        s.sld[z.slot] = (int32_t)z.cols;
+    }
+    s.sld[S_LAM] = 1;
+    void* info = nullptr;
+    HIP_TRY(h, h->dalloc(&info, 64));
+    HIP_TRY(h, hipMemset(info, 0, 64));
+    s.info = (int32_t*)info;
+    HIP_TRY(h, h->dalloc((void**)&h->dev, sizeof(SkDev)));
+    HIP_TRY(h, hipMemcpy(h->dev, &s, sizeof(SkDev), hipMemcpyHostToDevice));
+    return SK_OK;
+}
+
+// ---------------------------------------------------------- stage sequences
+namespace {
+
+struct Group {
+    int count = 0;
+    int max_m = 0, max_k = 0, max_d = 0, max_ell = 0, max_sg = 1, max_sp = 1, max_n = 0;
+    bool small = false, large = false, small_k = false, large_k = false;
+    int q = 0, st = DT_F64, pj = DT_F64;
+};
+
+Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tasks, size_t first,
+               size_t count) {
+    Group g;
+    g.count = (int)count;
+    for (size_t i = first; i < first + count; ++i) {
+        const sketch_t h = owners[i];
+        const Task& t = tasks[i];
+        g.max_m = std::max(g.max_m, t.m);
+        g.max_k = std::max(g.max_k, h->k);
+        g.max_d = std::max(g.max_d, h->d);
+        g.max_ell = std::max(g.max_ell, h->ell);
+        g.max_sg = std::max(g.max_sg, h->host.sg);
+        g.max_sp = std::max(g.max_sp, h->host.sp);
+        const int n = (t.kind == T_SHRINK_RAND) ? h->k : t.m;
+        g.max_n = std::max(g.max_n, n);
+        if (n <= jacobi_lds_max()) g.small = true;
+        else g.large = true;
+        if (h->k <= chol_lds_max()) g.small_k = true;
+        else g.large_k = true;
+        g.q = h->q;
+        g.st = h->st;
+        g.pj = h->pj;
+    }
+    return g;
+}
+
+inline int dims(int M, int N, int K) { return M | (N << 2) | (K << 4); }  // 0 m, 1 k, 2 n
+
+hipError_t cholqr2(const Task* t, const Group& g, int sy, int sq, hipStream_t st) {
+    hipError_t e;
+    // pass 1: W = Y^T Y, X = chol(W)^{-1}, Q1 = Y X^T
+    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, sy, sy, S_W, dims(1, 1, 0), st))) return e;
+    if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
+    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, sy, S_X, S_Q1, dims(0, 1, 1), st))) return e;
+    // pass 2 on Q1
+    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q1, S_Q1, S_W, dims(1, 1, 0), st))) return e;
+    if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
+    g_stage = "core_gemm";
+    return launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, S_Q1, S_X, sq, dims(0, 1, 1), st);
+}
+
+// Runs the shrink stages for `count` tasks of one kind starting at t.
+hipError_t run_shrinks(const Task* t, const Group& g, int kind, hipStream_t st) {
+    hipError_t e;
+    if (kind == T_SHRINK_RAND) {
+        if ((g_stage = "omega", e = launch_omega(t, g.count, g.max_d, g.max_k, g.pj, st))) return e;
+        if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e;
+        if ((g_stage = "project", e = launch_project(t, g.count, g.max_m, g.max_k, g.max_sp, g.st, g.pj, st))) return e;
+        int cur = S_P;
+        for (int it = 0; it < g.q; ++it) {
+            if ((e = cholqr2(t, g, cur, S_Q, st))) return e;
+            if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_Y, dims(0, 1, 0), st))) return e;
+            cur = S_Y;
+        }
+        if ((e = cholqr2(t, g, cur, S_Q, st))) return e;
+        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_T1, dims(0, 1, 0), st))) return e;
+        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q, S_T1, S_M, dims(1, 1, 0), st))) return e;
+        if ((g_stage = "jacobi", e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st))) return e;
+        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_Q, S_U, S_Z, dims(0, 1, 1), st))) return e;
+    } else {
+        if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e;
+        if ((g_stage = "jacobi", e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st))) return e;
+    }
+    if ((g_stage = "threshold", e = launch_threshold(t, g.count, g.max_ell, g.max_m, st))) return e;
+    return launch_rebuild(t, g.count, g.max_ell, g.max_d, g.st, kind == T_QUERY, st);
+}
+
+}  // namespace
+
+// Executes a planned list: consecutive tasks of one kind form a launch group.
+static sk_status execute(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
+                         int in_dtype, bool csr) {
+    if (tasks.empty()) return SK_OK;
+    Task* dt = nullptr;
+    HIP_TRY(h, h->arena.upload(tasks, h->stream, &dt));
+    size_t i = 0;
+    while (i < tasks.size()) {
+        size_t j = i + 1;
+        while (j < tasks.size() && tasks[j].kind == tasks[i].kind && tasks[j].kind != T_QUERY) {
+            // a sketch may appear once per group only (its stages are not reentrant)
+            bool dup = false;
+            for (size_t u = i; u < j; ++u)
+                if (owners[u] == owners[j]) dup = true;
+            if (dup) break;
+            ++j;
+        }
+        const Group g = describe(owners, tasks, i, j - i);
+        if (tasks[i].kind == T_INGEST) {
+            int max_rows = 0;
+            for (size_t u = i; u < j; ++u) max_rows = std::max(max_rows, tasks[u].nrows);
+            if (csr) HIP_TRY(h, launch_ingest_csr(dt + i, g.count, max_rows, g.max_d, g.st, h->stream));
+            else HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
+        } else {
+            HIP_TRY(h, run_shrinks(dt + i, g, tasks[i].kind, h->stream));
+        }
+        i = j;
+    }
+    HIP_TRY(h, h->arena.done(h->stream));
+    return SK_OK;
+}
+
+// Plans ingest segments and shrinks for n rows appended to h.
+static void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dtype,
+                      const int64_t* indptr, const int32_t* idx, const float* val,
+                      std::vector<sketch_t>& owners, std::vector<Task>& tasks) {
+    const int64_t esz = src ? dtype_size(in_dtype) : 0;
+    int64_t pos = 0;
+    while (pos < n) {
+        const int64_t take = std::min<int64_t>(n - pos, h->n2 - h->fill);
+        Task t{};
+        t.s = h->dev;
+        t.kind = T_INGEST;
+        t.par = h->par;
+        t.row0 = (int32_t)h->fill;
+        t.nrows = (int32_t)take;
+        t.src_dtype = in_dtype;
+        t.src_ld = src_ld;
+        t.src = src ? src + pos * src_ld * esz : nullptr;
+        t.indptr = indptr ? indptr + pos : nullptr;
+        t.indices = idx;
+        t.values = val;
+        owners.push_back(h);
+        tasks.push_back(t);
+        h->fill += take;
+        h->rows_seen += take;
+        pos += take;
+        if (h->fill == h->n2) {
+            Task s{};
+            s.s = h->dev;
+            s.kind = h->rnd ? T_SHRINK_RAND : T_SHRINK_EXACT;
+            s.par = h->par;
+            s.m = h->n2;
+            s.shrink_idx = h->shrinks;
+            owners.push_back(h);
+            tasks.push_back(s);
+            h->par ^= 1;
+            h->fill = h->ell - 1;
+            h->shrinks += 1;
+        }
+    }
+}
+
+sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
+                          int in_dtype);
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+sk_status sketch_config_init(sketch_config* cfg) {
+    if (!cfg) return fail(SK_EINVAL, "sketch_config_init: cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->kind = SK_PERSISTENT;
+    cfg->shrink = SK_SHRINK_EXACT;
+    cfg->state_dtype = SK_F64;
+    cfg->proj_dtype = SK_F64;
+    cfg->q = 1;
+    cfg->R = 1.0;
+    return SK_OK;
+}
+
+sk_status sketch_create(const sketch_config* cfg, sketch_t* out) {
+    if (!cfg || !out) return fail(SK_EINVAL, "sketch_create: NULL argument");
+    *out = nullptr;
+    if (cfg->d < 1 || cfg->ell < 2) return fail(SK_EINVAL, "sketch_create: need d >= 1 and ell >= 2");
+    if (cfg->ell > 256) return fail(SK_EINVAL, "sketch_create: ell > 256 is not supported");
+    if (cfg->state_dtype != SK_F64 && cfg->state_dtype != SK_F32)
+        return fail(SK_EINVAL, "sketch_create: state_dtype must be SK_F64 or SK_F32");
+    if (cfg->proj_dtype < SK_F64 || cfg->proj_dtype > SK_BF16)
+        return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
+    if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
+        return fail(SK_EINVAL, "sketch_create: bad shrink");
+    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW)
+        return fail(SK_EINVAL, "sketch_create: bad kind");
+    if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
+        return fail(SK_EINVAL, "sketch_create: bad q or oversample");
+    if (cfg->kind == SK_WINDOW && (cfg->window_N < 1 || !(cfg->R >= 1.0)))
+        return fail(SK_EINVAL, "sketch_create: window needs window_N >= 1 and R >= 1");
+    if (cfg->d > (1 << 20)) return fail(SK_EINVAL, "sketch_create: d too large");
+    sketch_t h = new sketch_s();
+    h->cfg = *cfg;
+    h->d = cfg->d;
+    h->ell = cfg->ell;
+    h->n2 = 2 * cfg->ell;
+    h->rnd = cfg->kind == SK_PERSISTENT && cfg->shrink == SK_SHRINK_RAND;
+    h->k = h->rnd ? std::min(std::min(cfg->ell + cfg->oversample, 2 * cfg->ell), cfg->d) : 0;
+    h->q = cfg->q;
+    h->st = cfg->state_dtype;
+    h->pj = cfg->proj_dtype;
+    h->ld = round_up(cfg->d, 64);
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(SK_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    if (cfg->hip_stream || cfg->use_given_stream) {
+        h->stream = (hipStream_t)cfg->hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(SK_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    sk_status rc;
+    if (cfg->kind == SK_WINDOW) rc = window_create(h);
+    else rc = build_device_state(h);
+    const int64_t budget = g_budget.load();
+    if (rc == SK_OK && budget > 0 && g_in_use.load() + h->bytes > budget) {
+        rc = fail(SK_ENOMEM, "sketch_create: memory budget exceeded");
+    }
+    if (rc != SK_OK) {
+        std::string msg = g_err;
+        sketch_destroy(h);
+        g_err = msg;
+        return rc == SK_EDEVICE ? SK_ENOMEM : rc;
+    }
+    g_in_use += h->bytes;
+    h->counted = true;
+    *out = h;
+    return SK_OK;
+}
+
+static sk_status check_handle(sketch_t h, const char* what) {
+    if (!h) return fail(SK_EINVAL, std::string(what) + ": NULL handle");
+    if (h->sticky) return fail(SK_EDEVICE, std::string(what) + ": sketch is in a failed state: " + h->sticky_msg);
+    return SK_OK;
+}
+
+sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld, int32_t dtype,
+                        int32_t on_device) {
+    sk_status rc = check_handle(h, "sketch_update");
+    if (rc) return rc;
+    if (n_rows < 0) return fail(SK_EINVAL, "sketch_update: n_rows < 0");
+    if (n_rows == 0) return SK_OK;
+    if (!rows) return fail(SK_EINVAL, "sketch_update: rows is NULL");
+    if (ld < h->d) return fail(SK_EINVAL, "sketch_update: ld < d");
+    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, "sketch_update: bad dtype");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const char* src = (const char*)rows;
+    const size_t es = (size_t)dtype_size(dtype);
+    if (!on_device) {
+        const size_t nb = es * (size_t)((n_rows - 1) * ld + h->d);
+        HIP_TRY(h, h->ensure_stage(nb));
+        HIP_TRY(h, hipMemcpyAsync(h->stage, rows, nb, hipMemcpyHostToDevice, h->stream));
+        src = (const char*)h->stage;
+    }
+    if (h->win) {
+        rc = window_update(h, src, n_rows, ld, dtype);
+    } else {
+        std::vector<sketch_t> owners;
+        std::vector<Task> tasks;
+        plan_rows(h, n_rows, src, ld, dtype, nullptr, nullptr, nullptr, owners, tasks);
+        rc = execute(h, owners, tasks, dtype, false);
+    }
+    if (rc) return rc;
+    if (!on_device) HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return SK_OK;
+}
+
+sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* indices,
+                            const float* values, int64_t n_rows, int32_t on_device) {
+    sk_status rc = check_handle(h, "sketch_update_csr");
+    if (rc) return rc;
+    if (n_rows < 0) return fail(SK_EINVAL, "sketch_update_csr: n_rows < 0");
+    if (n_rows == 0) return SK_OK;
+    if (!indptr || !indices || !values) return fail(SK_EINVAL, "sketch_update_csr: NULL array");
+    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_update_csr: window sketches take dense rows");
+    if (h->d > 16384) return fail(SK_EUNSUPPORTED, "sketch_update_csr: d > 16384");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const int64_t* ip = indptr;
+    const int32_t* ix = indices;
+    const float* vv = values;
+    if (!on_device) {
+        const int64_t nnz0 = indptr[0], nnz = indptr[n_rows] - indptr[0];
+        if (nnz < 0) return fail(SK_EINVAL, "sketch_update_csr: indptr not non-decreasing");
+        const size_t b1 = sizeof(int64_t) * (size_t)(n_rows + 1);
+        const size_t b2 = sizeof(int32_t) * (size_t)nnz, b3 = sizeof(float) * (size_t)nnz;
+        HIP_TRY(h, h->ensure_stage(b1 + round_up((int64_t)b2, 256) + b3 + 512));
+        char* base = (char*)h->stage;
+        std::vector<int64_t> shifted(indptr, indptr + n_rows + 1);
+        for (auto& v : shifted) v -= nnz0;
+        HIP_TRY(h, hipMemcpyAsync(base, shifted.data(), b1, hipMemcpyHostToDevice, h->stream));
+        char* pix = base + round_up((int64_t)b1, 256);
+        char* pv = pix + round_up((int64_t)b2, 256);
+        HIP_TRY(h, hipMemcpyAsync(pix, indices + nnz0, b2, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(pv, values + nnz0, b3, hipMemcpyHostToDevice, h->stream));
+        ip = (const int64_t*)base;
+        ix = (const int32_t*)pix;
+        vv = (const float*)pv;
+    }
+    std::vector<sketch_t> owners;
+    std::vector<Task> tasks;
+    plan_rows(h, n_rows, nullptr, 0, DT_F32, ip, ix, vv, owners, tasks);
+    rc = execute(h, owners, tasks, DT_F32, true);
+    if (rc) return rc;
+    if (!on_device) HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return SK_OK;
+}
+
+// Query into the sketch's FP64 staging (QOUT, ell x ld), on its stream.
+static sk_status query_to_qout(sketch_t h) {
+    const int64_t r = h->fill;
+    double* qout = h->host.slot[S_QOUT];
+    if (r >= h->ell) {
+        std::vector<sketch_t> owners{h};
+        Task t{};
+        t.s = h->dev;
+        t.kind = T_QUERY;
+        t.par = h->par;
+        t.m = (int32_t)r;
+        std::vector<Task> tasks{t};
+        return execute(h, owners, tasks, DT_F64, false);
+    }
+    HIP_TRY(h, hipMemsetAsync(qout, 0, sizeof(double) * (size_t)h->ell * (size_t)h->ld, h->stream));
+    HIP_TRY(h, launch_rows_to_f64(h->host.buf[h->par], h->ld, h->st, qout, h->ld, (int)r, h->d, h->stream));
+    return SK_OK;
+}
+
+static sk_status check_info(sketch_t h) {
+    int32_t info[2] = {0, 0};
+    const int32_t* dinfo = h->win ? window_info_ptr(h) : h->host.info;
+    HIP_TRY(h, hipMemcpy(info, dinfo, sizeof(info), hipMemcpyDeviceToHost));
+    if (info[0] != 0) return h->device_fail("eigen-solver did not converge");
+    return SK_OK;
+}
+
+sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device) {
+    sk_status rc = check_handle(h, "sketch_query");
+    if (rc) return rc;
+    if (!B_out) return fail(SK_EINVAL, "sketch_query: B_out is NULL");
+    if (dtype != SK_F64 && dtype != SK_F32) return fail(SK_EINVAL, "sketch_query: dtype must be F64 or F32");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const double* src = nullptr;
+    if (h->win) {
+        rc = window_query(h, &src);
+    } else {
+        rc = query_to_qout(h);
+        src = h->host.slot[S_QOUT];
+    }
+    if (rc) return rc;
+    const size_t es = (size_t)dtype_size(dtype);
+    const size_t nb = es * (size_t)h->ell * (size_t)h->d;
+    if (on_device) {
+        HIP_TRY(h, launch_convert_rows(src, h->ld, B_out, h->d, h->ell, h->d, dtype, h->stream));
+    } else {
+        HIP_TRY(h, h->ensure_stage(nb));
+        HIP_TRY(h, launch_convert_rows(src, h->ld, h->stage, h->d, h->ell, h->d, dtype, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(B_out, h->stage, nb, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_info(h);
+}
+
+sk_status window_advance(sketch_t h, int64_t t_now) {
+    sk_status rc = check_handle(h, "window_advance");
+    if (rc) return rc;
+    if (!h->win) return fail(SK_EUNSUPPORTED, "window_advance: not a window sketch");
+    return window_advance_impl(h, t_now);
+}
+
+sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src) {
+    sk_status rc = check_handle(dst, "sketch_merge");
+    if (rc) return rc;
+    if (n_src < 0 || (n_src > 0 && !srcs)) return fail(SK_EINVAL, "sketch_merge: bad source list");
+    if (dst->win) return fail(SK_EUNSUPPORTED, "sketch_merge: window sketches cannot be merged");
+    for (int i = 0; i < n_src; ++i) {
+        if ((rc = check_handle(srcs[i], "sketch_merge"))) return rc;
+        if (srcs[i]->d != dst->d) return fail(SK_ESHAPE, "sketch_merge: d differs");
+        if (srcs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_merge: window source");
+        if (srcs[i] == dst) return fail(SK_EINVAL, "sketch_merge: dst listed as a source");
+    }
+    HIP_TRY(dst, hipSetDevice(dst->cfg.device));
+    for (int i = 0; i < n_src; ++i) {
+        sketch_t s = srcs[i];
+        if (s->fill == 0) continue;
+        if ((rc = query_to_qout(s))) return rc;
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        if ((rc = check_info(s))) return rc;
+        const int64_t nz = s->fill >= s->ell ? s->ell - 1 : s->fill;
+        // the rows are read on dst's stream: copy them to dst's staging first
+        const size_t nb = sizeof(double) * (size_t)nz * (size_t)s->ld;
+        HIP_TRY(dst, dst->ensure_stage(nb));
+        HIP_TRY(dst, hipMemcpyAsync(dst->stage, s->host.slot[S_QOUT], nb, hipMemcpyDeviceToDevice, dst->stream));
+        std::vector<sketch_t> owners;
+        std::vector<Task> tasks;
+        plan_rows(dst, nz, (const char*)dst->stage, s->ld, DT_F64, nullptr, nullptr, nullptr, owners, tasks);
+        if ((rc = execute(dst, owners, tasks, DT_F64, false))) return rc;
+        HIP_TRY(dst, hipStreamSynchronize(dst->stream));
+    }
+    return SK_OK;
+}
+
+sk_status sketch_sync(sketch_t h) {
+    sk_status rc = check_handle(h, "sketch_sync");
+    if (rc) return rc;
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_info(h);
+}
+
+sk_status sketch_destroy(sketch_t h) {
+    if (!h) return SK_OK;
+    (void)hipSetDevice(h->cfg.device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->win) window_destroy(h);
+    for (void* p : h->allocs) (void)hipFree(p);
+    if (h->stage) (void)hipFree(h->stage);
+    h->arena.release();
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    if (h->counted) g_in_use -= h->bytes;
+    delete h;
+    return SK_OK;
+}
+
+const char* sketch_last_error(void) { return g_err.c_str(); }
+
+sk_status sketch_info(sketch_t h, sketch_info_t* info) {
+    if (!h || !info) return fail(SK_EINVAL, "sketch_info: NULL argument");
+    info->rows_seen = h->win ? window_time(h) : h->rows_seen;
+    info->fill = h->fill;
+    info->shrinks = h->shrinks;
+    info->device_bytes = h->bytes;
+    info->k = h->k;
+    info->levels = h->win ? window_levels(h) : 1;
+    return SK_OK;
+}
+
+sk_status sketch_set_memory_budget(int64_t bytes) {
+    if (bytes < 0) return fail(SK_EINVAL, "sketch_set_memory_budget: negative");
+    g_budget = bytes;
+    return SK_OK;
+}
+
+int64_t sketch_memory_in_use(void) { return g_in_use.load(); }
+
+sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n, int32_t count,
+                              int32_t dtype) {
+    if (count < 0 || (count > 0 && (!hs || !rows || !n))) return fail(SK_EINVAL, "sketch_update_batch: bad arguments");
+    if (count == 0) return SK_OK;
+    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, "sketch_update_batch: bad dtype");
+    sk_status rc;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = check_handle(hs[i], "sketch_update_batch"))) return rc;
+        if (hs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_update_batch: window sketch");
+        if (hs[i]->stream != hs[0]->stream || hs[i]->cfg.device != hs[0]->cfg.device)
+            return fail(SK_EINVAL, "sketch_update_batch: sketches must share stream and device");
+        if (n[i] < 0) return fail(SK_EINVAL, "sketch_update_batch: negative row count");
+        if (n[i] > 0 && !rows[i]) return fail(SK_EINVAL, "sketch_update_batch: NULL rows");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return fail(SK_EINVAL, "sketch_update_batch: a sketch is listed twice");
+    }
+    sketch_t h0 = hs[0];
+    HIP_TRY(h0, hipSetDevice(h0->cfg.device));
+    // Lock-step rounds: round r holds every sketch's r-th ingest segment, then
+    // the shrinks those segments triggered, grouped by shrink flavour.
+    struct Cursor { int64_t pos = 0; };
+    std::vector<Cursor> cur((size_t)count);
+    std::vector<sketch_t> owners;
+    std::vector<Task> tasks;
+    const int64_t es = dtype_size(dtype);
+    bool more = true;
+    while (more) {
+        more = false;
+        std::vector<std::pair<sketch_t, Task>> ing, shr;
+        for (int i = 0; i < count; ++i) {
+            sketch_t h = hs[i];
+            if (cur[i].pos >= n[i]) continue;
+            const int64_t take = std::min<int64_t>(n[i] - cur[i].pos, h->n2 - h->fill);
+            Task t{};
+            t.s = h->dev;
+            t.kind = T_INGEST;
+            t.par = h->par;
+            t.row0 = (int32_t)h->fill;
+            t.nrows = (int32_t)take;
+            t.src_dtype = dtype;
+            t.src_ld = h->d;
+            t.src = (const char*)rows[i] + cur[i].pos * h->d * es;
+            ing.push_back({h, t});
+            h->fill += take;
+            h->rows_seen += take;
+            cur[i].pos += take;
+            if (h->fill == h->n2) {
+                Task s{};
+                s.s = h->dev;
+                s.kind = h->rnd ? T_SHRINK_RAND : T_SHRINK_EXACT;
+                s.par = h->par;
+                s.m = h->n2;
+                s.shrink_idx = h->shrinks;
+                shr.push_back({h, s});
+                h->par ^= 1;
+                h->fill = h->ell - 1;
+                h->shrinks += 1;
+            }
+            if (cur[i].pos < n[i]) more = true;
+        }
+        for (auto& p : ing) {
+            owners.push_back(p.first);
+            tasks.push_back(p.second);
+        }
+        // group shrinks so that one launch sequence serves one flavour
+        std::stable_sort(shr.begin(), shr.end(), [](const std::pair<sketch_t, Task>& a,
+                                                     const std::pair<sketch_t, Task>& b) {
+            auto key = [](const std::pair<sketch_t, Task>& p) {
+                return ((int64_t)p.second.kind << 32) | ((int64_t)p.first->q << 16) |
+                       ((int64_t)p.first->st << 8) | (int64_t)p.first->pj;
+            };
+            return key(a) < key(b);
+        });
+        for (auto& p : shr) {
+            owners.push_back(p.first);
+            tasks.push_back(p.second);
+        }
+    }
+    return execute_batched(h0, owners, tasks, dtype);
+}
+
+}  // extern "C"
+
+// Batched execution: like execute(), but a group also breaks where the shrink
+// flavour (q, dtypes) changes.
+sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
+                          int in_dtype) {
+    if (tasks.empty()) return SK_OK;
+    Task* dt = nullptr;
+    HIP_TRY(h, h->arena.upload(tasks, h->stream, &dt));
+    size_t i = 0;
+    while (i < tasks.size()) {
+        size_t j = i + 1;
+        while (j < tasks.size() && tasks[j].kind == tasks[i].kind && owners[j]->q == owners[i]->q &&
+               owners[j]->st == owners[i]->st && owners[j]->pj == owners[i]->pj &&
+               tasks[j].kind != T_QUERY)
+            ++j;
+        const Group g = describe(owners, tasks, i, j - i);
+        if (tasks[i].kind == T_INGEST) {
+            int max_rows = 0;
+            for (size_t u = i; u < j; ++u) max_rows = std::max(max_rows, tasks[u].nrows);
+            HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
+        } else {
+            HIP_TRY(h, run_shrinks(dt + i, g, tasks[i].kind, h->stream));
+        }
+        i = j;
+    }
+    HIP_TRY(h, h->arena.done(h->stream));
+    return SK_OK;
+}
+
+// ------------------------------------------------------------ merge tree
+// Level by level, children (2i, 2i+1) are stacked into a node buffer and
+// shrunk; all node shrinks of one level are one task group.
+extern "C" sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32_t n_src) {
+    sk_status rc = check_handle(dst, "sketch_merge_tree");
+    if (rc) return rc;
+    if (n_src < 1 || !srcs) return fail(SK_EINVAL, "sketch_merge_tree: need at least one source");
+    if (dst->win) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window sketch");
+    if (dst->fill != 0 || dst->rows_seen != 0) return fail(SK_ESTATE, "sketch_merge_tree: dst must be empty");
+    for (int i = 0; i < n_src; ++i) {
+        if ((rc = check_handle(srcs[i], "sketch_merge_tree"))) return rc;
+        if (srcs[i]->d != dst->d || srcs[i]->ell != dst->ell)
+            return fail(SK_ESHAPE, "sketch_merge_tree: d and ell must match");
+        if (srcs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window source");
+    }
+    HIP_TRY(dst, hipSetDevice(dst->cfg.device));
+    // leaves: each source's queried sketch
+    std::vector<sketch_t> level;
+    std::vector<int64_t> rows_of;
+    for (int i = 0; i < n_src; ++i) {
+        if ((rc = query_to_qout(srcs[i]))) return rc;
+        HIP_TRY(srcs[i], hipStreamSynchronize(srcs[i]->stream));
+        if ((rc = check_info(srcs[i]))) return rc;
+    }
+    // node sketches: same configuration as dst on dst's stream
+    sketch_config ncfg = dst->cfg;
+    ncfg.hip_stream = dst->stream;
+    std::vector<sketch_t> temps;
+    auto cleanup = [&]() {
+        for (sketch_t t : temps) sketch_destroy(t);
+    };
+    // current level: pointers to FP64 row blocks (ld = dst->ld) and counts
+    std::vector<const double*> cur_rows;
+    std::vector<int64_t> cur_n;
+    for (int i = 0; i < n_src; ++i) {
+        cur_rows.push_back(srcs[i]->host.slot[S_QOUT]);
+        cur_n.push_back(srcs[i]->fill >= srcs[i]->ell ? srcs[i]->ell - 1 : srcs[i]->fill);
+    }
+    int depth = 0;
+    while (cur_rows.size() > 1) {
+        std::vector<sketch_t> owners;
+        std::vector<Task> tasks;
+        std::vector<const double*> nxt_rows;
+        std::vector<int64_t> nxt_n;
+        std::vector<sketch_t> nodes;
+        for (size_t i = 0; i + 1 < cur_rows.size(); i += 2) {
+            sketch_t node = nullptr;
+            ncfg.stream_id = dst->cfg.stream_id * 1315423911ull + (uint64_t)(depth * 65536 + (int)i / 2 + 1);
+            if ((rc = sketch_create(&ncfg, &node))) {
+                cleanup();
+                return rc;
+            }
+            temps.push_back(node);
+            nodes.push_back(node);
+            // stack both children into the node buffer, then shrink the stack
+            for (int c = 0; c < 2; ++c) {
+                const int64_t nr = cur_n[i + c];
+                if (nr == 0) continue;
+                Task t{};
+                t.s = node->dev;
+                t.kind = T_INGEST;
+                t.par = node->par;
+                t.row0 = (int32_t)node->fill;
+                t.nrows = (int32_t)nr;
+                t.src_dtype = DT_F64;
+                t.src_ld = dst->ld;
+                t.src = cur_rows[i + c];
+                owners.push_back(node);
+                tasks.push_back(t);
+                node->fill += nr;
+                node->rows_seen += nr;
+            }
+        }
+        // ingest tasks first (one group), then one shrink group for all nodes
+        std::vector<sketch_t> o2;
+        std::vector<Task> t2;
+        for (size_t u = 0; u < tasks.size(); ++u) {
+            o2.push_back(owners[u]);
+            t2.push_back(tasks[u]);
+        }
+        // split the ingest list so that a node appears once per group
+        std::vector<sketch_t> oi;
+        std::vector<Task> ti;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<sketch_t> seen;
+            for (size_t u = 0; u < t2.size(); ++u) {
+                bool first = std::find(seen.begin(), seen.end(), o2[u]) == seen.end();
+                if ((pass == 0) == first) {
+                    oi.push_back(o2[u]);
+                    ti.push_back(t2[u]);
+                }
+                seen.push_back(o2[u]);
+            }
+        }
+        for (sketch_t node : nodes) {
+            if (node->fill >= node->ell) {
+                Task s{};
+                s.s = node->dev;
+                s.kind = node->rnd ? T_SHRINK_RAND : T_SHRINK_EXACT;
+                s.par = node->par;
+                s.m = (int32_t)node->fill;
+                s.shrink_idx = 0;
+                oi.push_back(node);
+                ti.push_back(s);
+                node->par ^= 1;
+                node->fill = node->ell - 1;
+                node->shrinks += 1;
+            }
+        }
+        if ((rc = execute_batched(dst, oi, ti, DT_F64))) {
+            cleanup();
+            return rc;
+        }
+        // children of the next level: the nodes' buffers (converted to FP64)
+        for (sketch_t node : nodes) {
+            double* q = node->host.slot[S_QOUT];
+            HIP_TRY(dst, launch_rows_to_f64(node->host.buf[node->par], node->ld, node->st, q, node->ld,
+                                            (int)node->fill, node->d, dst->stream));
+            nxt_rows.push_back(q);
+            nxt_n.push_back(node->fill);
+        }
+        if (cur_rows.size() % 2 == 1) {
+            nxt_rows.push_back(cur_rows.back());
+            nxt_n.push_back(cur_n.back());
+        }
+        cur_rows.swap(nxt_rows);
+        cur_n.swap(nxt_n);
+        ++depth;
+    }
+    // dst takes the root's rows
+    std::vector<sketch_t> owners;
+    std::vector<Task> tasks;
+    plan_rows(dst, cur_n[0], (const char*)cur_rows[0], dst->ld, DT_F64, nullptr, nullptr, nullptr,
+              owners, tasks);
+    rc = execute(dst, owners, tasks, DT_F64, false);
+    if (rc == SK_OK) {
+        hipError_t e = hipStreamSynchronize(dst->stream);
+        if (e != hipSuccess) rc = dst->device_fail(std::string("merge_tree sync: ") + hipGetErrorString(e));
+    }
+    if (rc == SK_OK) {
+        for (sketch_t t : temps)
+            if ((rc = check_info(t))) break;
+    }
+    cleanup();
+    return rc;
+}

@@ -1,0 +1,40 @@
+// sk_kernels.h -- host-side launchers of the gfx950 kernels.  Every launcher
+// takes a device array of `count` Task records; the max_* arguments size the
+// grid to the largest task, smaller tasks exit their surplus workgroups.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sk_device.h"
+
+namespace sk {
+
+hipError_t launch_ingest(const Task* tasks, int count, int max_rows, int max_d, int in_dtype,
+                         int st_dtype, hipStream_t st);
+hipError_t launch_ingest_csr(const Task* tasks, int count, int max_rows, int max_d, int st_dtype,
+                             hipStream_t st);
+hipError_t launch_omega(const Task* tasks, int count, int max_d, int max_k, int pj_dtype,
+                        hipStream_t st);
+hipError_t launch_gram(const Task* tasks, int count, int max_m, int max_splits, int st_dtype,
+                       hipStream_t st);
+hipError_t launch_project(const Task* tasks, int count, int max_m, int max_k, int max_splits,
+                          int st_dtype, int pj_dtype, hipStream_t st);
+hipError_t launch_project_bf16(const Task* tasks, int count, int max_m, int max_k, int max_splits,
+                               hipStream_t st);
+hipError_t launch_reduce_proj(const Task* tasks, int count, int max_m, int max_k, hipStream_t st);
+hipError_t launch_rebuild(const Task* tasks, int count, int max_ell, int max_d, int st_dtype,
+                          bool query, hipStream_t st);
+hipError_t launch_convert_rows(const double* src, int64_t lds, void* dst, int64_t ldd, int rows,
+                               int cols, int out_dtype, hipStream_t st);
+hipError_t launch_rows_to_f64(const void* src, int64_t lds, int st_dtype, double* dst, int64_t ldd,
+                              int rows, int cols, hipStream_t st);
+
+hipError_t launch_core_gemm(const Task* tasks, int count, int max_M, int max_N, bool ta, bool tb,
+                            int sa, int sb, int sc, int dims, hipStream_t st);
+hipError_t launch_cholinv(const Task* tasks, int count, int max_k, bool any_small, bool any_large,
+                          int sw, int sx, hipStream_t st);
+hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small, bool any_large,
+                         hipStream_t st);
+hipError_t launch_threshold(const Task* tasks, int count, int max_ell, int max_m, hipStream_t st);
+int jacobi_lds_max();
+int chol_lds_max();
+
+}  // namespace sk

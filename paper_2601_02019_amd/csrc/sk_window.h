@@ -1,0 +1,17 @@
+// sk_window.h -- sliding-window sketches (Algorithm "ML-AeroSketch") behind
+// the same C ABI.  Implemented in sk_window.cpp.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/sketch.h"
+
+struct WindowState;
+
+sk_status window_create(sketch_t h);
+sk_status window_update(sketch_t h, const char* rows_dev, int64_t n, int64_t ld, int dtype);
+sk_status window_query(sketch_t h, const double** out_f64);
+sk_status window_advance_impl(sketch_t h, int64_t t_now);
+void window_destroy(sketch_t h);
+const int32_t* window_info_ptr(sketch_t h);
+int64_t window_time(sketch_t h);
+int32_t window_levels(sketch_t h);

@@ -1,0 +1,51 @@
+"""CPU checks of the C-ABI library: it loads without a GPU and exports every
+entry point that include/sketch.h declares (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sketch.h")
+LIB = os.path.join(ROOT, "paper_2601_02019_amd", "libsketch.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:sk_status|const char\*|int64_t)\s+(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["sketch_create", "sketch_update", "sketch_query", "window_advance", "sketch_merge",
+              "sketch_destroy", "sketch_sync", "sketch_last_error", "sketch_update_csr",
+              "sketch_update_batch", "sketch_merge_tree"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsketch.so not built")
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsketch.so not built")
+def test_library_loads_and_rejects_bad_config_without_gpu():
+    from paper_2601_02019_amd import _lib
+    lib = _lib.load()
+    cfg = _lib.sketch_config()
+    assert lib.sketch_config_init(ctypes.byref(cfg)) == 0
+    assert cfg.q == 1 and cfg.state_dtype == _lib.SK_F64
+    h = ctypes.c_void_p()
+    # d = 0 is rejected before any device call
+    assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+    assert b"d >= 1" in lib.sketch_last_error()
+    assert lib.sketch_update(None, None, 1, 1, 0, 1) == _lib.SK_EINVAL
+    assert lib.sketch_destroy(None) == _lib.SK_OK

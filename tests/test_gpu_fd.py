@@ -1,0 +1,281 @@
+"""GPU parity of the persistent FD sketch (exact and randomized shrink)
+against the FP64 oracle, through the C ABI.
+
+Tolerances:
+  - FP64 state and FP64 projection: relative Frobenius difference of B^T B
+    at most 1e-9.
+  - FP32 state or bf16 projection: covariance error at most 1.05x the
+    oracle's (same algorithm, q, k and Philox stream) and within the FD
+    bound ||A||_F^2 / ell.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import cov_err_gram, gram, note, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2601_02019_amd  # noqa: F401  (fails loudly if the library is missing)
+    yield
+    torch.cuda.synchronize()
+
+
+def make(d, ell, **kw):
+    from paper_2601_02019_amd import Sketch
+    return Sketch(d, ell, **kw)
+
+
+def run_oracle(A, d, ell, mode="exact", k=0, q=1, seed=0, stream=0, chunks=None):
+    o = oracle.FD(d, ell, mode, k=k, q=q, seed=seed, stream=stream)
+    o.update(A)
+    return o
+
+
+# ------------------------------------------------------------------ exact
+def test_exact_fp64_persistent_small_workload_full_size():
+    # n = 10,000, d = 256, ell = 32, FP64, rank-20 signal 10 * 0.8^i + N(0, 0.1^2)
+    note("exact fp64 d=256 ell=32 n=10000")
+    A = synth.persistent_small()
+    o = run_oracle(A, 256, 32)
+    s = make(256, 32, shrink="exact", state_dtype="f64")
+    s.update(torch.from_numpy(A).cuda())
+    B = s.query()
+    assert s.info()["shrinks"] == o.shrinks == 302
+    assert s.info()["fill"] == o.fill
+    assert rel_fro(gram(B), gram(o.query())) <= 1e-9
+
+
+@pytest.mark.parametrize("d,ell,n", [(40, 6, 100), (64, 16, 300), (100, 8, 17), (130, 20, 333),
+                                     (33, 24, 200), (16, 9, 77)])
+def test_exact_fp64_shapes(d, ell, n):
+    note(f"exact fp64 d={d} ell={ell} n={n}")
+    A = synth.lowrank_rows(n, d, 4 * 0.8 ** np.arange(min(d, 15)), 0.05, seed=d * 7 + ell)
+    o = run_oracle(A, d, ell)
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+def test_ragged_update_calls_equal_one_call():
+    d, ell = 96, 12
+    A = synth.lowrank_rows(500, d, np.linspace(3, 0.5, 30), 0.05, seed=3)
+    s1, s2 = make(d, ell), make(d, ell)
+    s1.update(torch.from_numpy(A).cuda())
+    cuts = [0, 1, 2, 25, 26, 100, 101, 333, 500]
+    At = torch.from_numpy(A).cuda()
+    for a, b in zip(cuts, cuts[1:]):
+        s2.update(At[a:b])
+    B1, B2 = s1.query(), s2.query()
+    assert torch.equal(B1, B2)
+
+
+def test_host_input_and_strided_rows():
+    d, ell = 50, 5
+    A = synth.lowrank_rows(120, d, np.linspace(3, 0.5, 10), 0.05, seed=4)
+    wide = np.zeros((120, 64))
+    wide[:, :d] = A
+    s1, s2 = make(d, ell), make(d, ell)
+    s1.update(A)                                        # host numpy
+    s2.update(torch.from_numpy(wide).cuda()[:, :d])     # device, ld = 64
+    B1, B2 = s1.query(), s2.query()
+    assert torch.equal(B1, B2)
+    Bh = np.zeros((ell, d))
+    from paper_2601_02019_amd import sketch_query
+    sketch_query(s1.handle, Bh)                          # host output
+    assert np.array_equal(Bh, B1.cpu().numpy())
+
+
+def test_query_before_any_shrink_and_empty():
+    d, ell = 30, 8
+    s = make(d, ell)
+    B = s.query()
+    assert torch.count_nonzero(B) == 0
+    A = synth.lowrank_rows(5, d, np.linspace(3, 1, 10), 0.1, seed=1)
+    s.update(torch.from_numpy(A).cuda())               # 5 < ell rows: returned as is
+    B = s.query()
+    assert rel_fro(gram(B), A.T @ A) < 1e-14
+    A2 = synth.lowrank_rows(7, d, np.linspace(3, 1, 10), 0.1, seed=2)
+    s.update(torch.from_numpy(A2).cuda())              # 12 rows: f_ell of them
+    o = run_oracle(np.vstack([A, A2]), d, ell)
+    assert rel_fro(gram(s.query()), gram(o.query())) < 1e-12
+
+
+def test_query_is_non_destructive():
+    d, ell = 64, 8
+    A = synth.lowrank_rows(300, d, np.linspace(3, 1, 20), 0.1, seed=5)
+    s = make(d, ell)
+    s.update(torch.from_numpy(A[:150]).cuda())
+    s.query()
+    s.update(torch.from_numpy(A[150:]).cuda())
+    o = run_oracle(A, d, ell)
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+# ------------------------------------------------------------- randomized
+@pytest.mark.parametrize("d,ell,q,p", [(256, 32, 1, 0), (128, 16, 0, 0), (96, 12, 2, 4),
+                                       (200, 40, 1, 8), (64, 24, 1, 0)])
+def test_rand_fp64_matches_oracle(d, ell, q, p):
+    note(f"rand fp64 d={d} ell={ell} q={q} p={p}")
+    n = 1500
+    A = synth.lowrank_rows(n, d, 10 * 0.8 ** np.arange(20), 0.1, seed=d + ell)
+    k = min(ell + p, 2 * ell, d)
+    o = run_oracle(A, d, ell, "rand", k=k, q=q, seed=11, stream=5)
+    s = make(d, ell, shrink="rand", q=q, oversample=p, seed=11, stream_id=5)
+    s.update(torch.from_numpy(A).cuda())
+    assert s.info()["k"] == k
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+def test_rand_fp64_rank_deficient_buffer():
+    # rank-6 stream with k = ell = 16: the projected basis is rank deficient
+    d, ell = 80, 16
+    A = synth.lowrank_rows(400, d, np.linspace(3, 1, 6), 0.0, seed=8)
+    o = run_oracle(A, d, ell, "rand", k=ell, q=1, seed=1, stream=2)
+    s = make(d, ell, shrink="rand", q=1, seed=1, stream_id=2)
+    s.update(torch.from_numpy(A).cuda())
+    Bg, Bo = gram(s.query()), gram(o.query())
+    assert rel_fro(Bg, Bo) <= 1e-9
+    assert rel_fro(Bg, A.T @ A) <= 1e-9          # rank < ell: no error at all
+
+
+@pytest.mark.parametrize("pj", ["f32", "bf16"])
+def test_rand_fp32_state_reduced_precision_projection(pj):
+    note(f"rand fp32 state proj={pj}")
+    d, ell, q = 512, 32, 1
+    A = synth.lowrank_rows(4000, d, np.arange(1, 129) ** -0.8, 0.03, seed=21)
+    o = run_oracle(A, d, ell, "rand", k=ell, q=q, seed=3, stream=9)
+    s = make(d, ell, shrink="rand", q=q, state_dtype="f32", proj_dtype=pj, seed=3, stream_id=9)
+    s.update(torch.from_numpy(A.astype(np.float32)).cuda())
+    AtA = A.T @ A
+    eg = cov_err_gram(AtA, gram(s.query()))
+    eo = cov_err_gram(AtA, gram(o.query()))
+    note(f"  cov-err gpu {eg:.4e} oracle {eo:.4e} bound {np.trace(AtA) / ell:.4e}")
+    assert eg <= 1.05 * eo
+    assert eg <= np.trace(AtA) / ell
+
+
+def test_exact_fp32_state():
+    d, ell = 300, 20
+    A = synth.lowrank_rows(2000, d, np.arange(1, 81) ** -0.7, 0.05, seed=22)
+    o = run_oracle(A, d, ell)
+    s = make(d, ell, state_dtype="f32")
+    s.update(torch.from_numpy(A.astype(np.float32)).cuda())
+    AtA = A.T @ A
+    eg = cov_err_gram(AtA, gram(s.query()))
+    eo = cov_err_gram(AtA, gram(o.query()))
+    assert eg <= 1.05 * eo and eg <= np.trace(AtA) / ell
+
+
+# ------------------------------------------------------------------ merge
+def test_merge_matches_oracle():
+    d, ell = 64, 8
+    parts = [synth.lowrank_rows(150 + 37 * i, d, np.linspace(3, 0.5, 20), 0.1, seed=30 + i)
+             for i in range(3)]
+    os_, gs = [], []
+    for p in parts:
+        o = oracle.FD(d, ell)
+        o.update(p)
+        os_.append(o)
+        g = make(d, ell)
+        g.update(torch.from_numpy(p).cuda())
+        gs.append(g)
+    od = oracle.FD(d, ell)
+    for o in os_:
+        od.merge(o)
+    gd = make(d, ell)
+    gd.merge(gs)
+    assert rel_fro(gram(gd.query()), gram(od.query())) <= 1e-9
+
+
+def test_merge_tree_matches_pairwise_oracle():
+    d, ell, m = 48, 6, 5
+    parts = [synth.lowrank_rows(90 + 13 * i, d, np.linspace(3, 0.5, 20), 0.1, seed=40 + i)
+             for i in range(m)]
+    gs = []
+    leaves = []
+    for p in parts:
+        o = oracle.FD(d, ell)
+        o.update(p)
+        Bq = o.query()
+        leaves.append(Bq[: (ell - 1 if o.fill >= ell else o.fill)])
+        g = make(d, ell)
+        g.update(torch.from_numpy(p).cuda())
+        gs.append(g)
+    # oracle tree: stack pairs (2i, 2i+1), shrink when the stack has >= ell rows
+    level = leaves
+    while len(level) > 1:
+        nxt = []
+        for i in range(0, len(level) - 1, 2):
+            X = np.vstack([level[i], level[i + 1]])
+            if X.shape[0] >= ell:
+                X = oracle.shrink_exact(X, ell)[: ell - 1]
+            nxt.append(X)
+        if len(level) % 2:
+            nxt.append(level[-1])
+        level = nxt
+    gd = make(d, ell)
+    gd.merge_tree(gs)
+    ref = oracle.FD(d, ell)
+    ref.update(level[0])
+    assert rel_fro(gram(gd.query()), gram(ref.query())) <= 1e-9
+
+
+# ------------------------------------------------------------ batched / CSR
+def test_batched_update_equals_individual_updates_bitwise():
+    from paper_2601_02019_amd import sketch_update_batch
+    shapes = [(64, 8, "exact"), (128, 16, "rand"), (96, 12, "rand"), (64, 8, "rand"), (200, 20, "exact")]
+    rows = [torch.from_numpy(synth.lowrank_rows(70 + 40 * i, d, np.linspace(3, 0.5, 12), 0.1,
+                                                 seed=50 + i).astype(np.float32)).cuda()
+            for i, (d, ell, _) in enumerate(shapes)]
+    alone, mixed = [], []
+    for i, (d, ell, mode) in enumerate(shapes):
+        a = make(d, ell, shrink=mode, state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=i)
+        a.update(rows[i])
+        alone.append(a.query())
+        mixed.append(make(d, ell, shrink=mode, state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=i))
+    sketch_update_batch(mixed, rows)
+    for i in range(len(shapes)):
+        assert torch.equal(mixed[i].query(), alone[i]), i
+
+
+def test_csr_ingest_equals_dense():
+    d, ell = 256, 16
+    ip, ix, vv = synth.streams.sparse_sites(600, d=d, density=0.02, seed=4, site=1)
+    dense = synth.streams.csr_to_dense(ip, ix, vv, d).astype(np.float32)
+    s1 = make(d, ell, state_dtype="f32")
+    s1.update(torch.from_numpy(dense).cuda())
+    s2 = make(d, ell, state_dtype="f32")
+    s2.update_csr(ip, ix, vv)
+    s3 = make(d, ell, state_dtype="f32")
+    s3.update_csr(torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(), torch.from_numpy(vv).cuda())
+    B1 = s1.query()
+    assert torch.equal(s2.query(), B1)
+    assert torch.equal(s3.query(), B1)
+
+
+# ------------------------------------------------------------------ errors
+def test_error_paths_leave_state_unchanged():
+    from paper_2601_02019_amd import SketchError, sketch_update
+    import ctypes
+    from paper_2601_02019_amd import _lib
+    s = make(32, 4)
+    A = torch.randn(10, 32, dtype=torch.float64, device="cuda")
+    s.update(A)
+    before = s.query().clone()
+    lib = _lib.load()
+    assert lib.sketch_update(s.handle, ctypes.c_void_p(A.data_ptr()), 5, 16, 0, 1) == _lib.SK_EINVAL
+    assert lib.sketch_update(s.handle, ctypes.c_void_p(A.data_ptr()), -1, 32, 0, 1) == _lib.SK_EINVAL
+    assert lib.window_advance(s.handle, 5) == _lib.SK_EUNSUPPORTED
+    other = make(33, 4)
+    arr = (ctypes.c_void_p * 1)(other.handle.value)
+    assert lib.sketch_merge(s.handle, arr, 1) == _lib.SK_ESHAPE
+    assert torch.equal(s.query(), before)
+    with pytest.raises(SketchError):
+        sketch_update(s.handle, np.zeros((3, 31)))
