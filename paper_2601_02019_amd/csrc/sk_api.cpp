@@ -11,6 +11,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -130,6 +131,8 @@ struct sketch_s {
     TaskArena arena;
     WindowState* win = nullptr;
     bool counted = false;
+    double* coop = nullptr;   // cooperative-kernel scratch (see coop_* offsets)
+    int* coop_ctrl = nullptr;
 
     sk_status device_fail(const std::string& msg) {
         sticky = true;
@@ -158,6 +161,21 @@ struct sketch_s {
     }
 };
 
+// Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
+// 256 workgroup partials, 16 inverse diagonal blocks of 32 x 32, 512 pivots.
+static const int64_t COOP_UBUF = 0, COOP_PART = 16 * 1024, COOP_LINV = COOP_PART + 256,
+                     COOP_D0 = COOP_LINV + 16 * 1024, COOP_DOUBLES = COOP_D0 + 512;
+
+// Problem sizes from which one task alone runs the cooperative solvers.
+static int coop_min_n() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_COOP_MIN_N");
+        v = e ? atoi(e) : 96;
+    }
+    return v;
+}
+
 // Split-K plan: about 512 workgroups in total for a launch.
 static void splitk_plan(int tiles, int d, int* splits, int* chunk) {
     int s = std::max(1, (512 + tiles - 1) / tiles);
@@ -171,6 +189,7 @@ static void splitk_plan(int tiles, int d, int* splits, int* chunk) {
 static sk_status build_device_state(sketch_t h) {
     const int d = h->d, ell = h->ell, n2 = h->n2, k = h->k;
     const int neig = std::max(n2, k);
+    const int neig32 = (int)round_up(neig, 32);  // cooperative solvers pad to 32
     const int kk = std::max(k, 1);
     SkDev& s = h->host;
     std::memset(&s, 0, sizeof(s));
@@ -202,7 +221,7 @@ static sk_status build_device_state(sketch_t h) {
         {S_G, n2, n2},       {S_P, n2, mk},        {S_Y, n2, mk},      {S_Q, n2, mk},
         {S_Q1, n2, mk},      {S_W, mk, mk},        {S_X, mk, mk},      {S_T1, n2, mk},
         {S_M, mk, mk},       {S_U, neig, neig},    {S_Z, n2, mk},      {S_T, ell, n2},
-        {S_LAM, 1, neig},    {S_EA, neig, neig},   {S_EV, neig, neig},
+        {S_LAM, 1, neig},    {S_EA, neig32, neig32}, {S_EV, neig32, neig32},
         {S_GPART, (int64_t)s.sg * n2, n2},
         {S_PPART, (int64_t)(h->rnd ? s.sp : 1) * n2, mk},
         {S_QOUT, ell, h->ld},
@@ -214,6 +233,14 @@ static sk_status build_device_state(sketch_t h) {
         s.sld[z.slot] = (int32_t)z.cols;
     }
     s.sld[S_LAM] = 1;
+    {
+        void* p = nullptr;
+        HIP_TRY(h, h->dalloc(&p, sizeof(double) * COOP_DOUBLES));
+        h->coop = (double*)p;
+        HIP_TRY(h, h->dalloc(&p, 64 * sizeof(int)));
+        HIP_TRY(h, hipMemset(p, 0, 64 * sizeof(int)));
+        h->coop_ctrl = (int*)p;
+    }
     void* info = nullptr;
     HIP_TRY(h, h->dalloc(&info, 64));
     HIP_TRY(h, hipMemset(info, 0, 64));
@@ -231,6 +258,8 @@ struct Group {
     int max_m = 0, max_k = 0, max_d = 0, max_ell = 0, max_sg = 1, max_sp = 1, max_n = 0;
     bool small = false, large = false, small_k = false, large_k = false;
     int q = 0, st = DT_F64, pj = DT_F64;
+    double* coop = nullptr;
+    int* coop_ctrl = nullptr;
 };
 
 Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tasks, size_t first,
@@ -255,23 +284,41 @@ Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tas
         g.q = h->q;
         g.st = h->st;
         g.pj = h->pj;
+        g.coop = h->coop;
+        g.coop_ctrl = h->coop_ctrl;
     }
     return g;
 }
 
 inline int dims(int M, int N, int K) { return M | (N << 2) | (K << 4); }  // 0 m, 1 k, 2 n
 
-hipError_t cholqr2(const Task* t, const Group& g, int sy, int sq, hipStream_t st) {
+hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hipStream_t st) {
     hipError_t e;
-    // pass 1: W = Y^T Y, X = chol(W)^{-1}, Q1 = Y X^T
-    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, sy, sy, S_W, dims(1, 1, 0), st))) return e;
-    if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
-    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, sy, S_X, S_Q1, dims(0, 1, 1), st))) return e;
-    // pass 2 on Q1
-    if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q1, S_Q1, S_W, dims(1, 1, 0), st))) return e;
-    if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
-    g_stage = "core_gemm";
-    return launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, S_Q1, S_X, sq, dims(0, 1, 1), st);
+    if (g.count == 1 && g.max_k >= coop_min_n()) {
+        g_stage = "cholqr_coop";
+        return launch_cholqr_coop(t, g.max_m, g.max_k, sy, sq, passes, g.coop + COOP_LINV,
+                                  g.coop + COOP_D0, st);
+    }
+    int src = sy;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int dst = (pass == passes - 1) ? sq : S_Q1;
+        if (dst == src) return hipErrorInvalidValue;
+        // W = Y^T Y, X = chol(W)^{-1}, dst = Y X^T
+        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, src, src, S_W, dims(1, 1, 0), st))) return e;
+        if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
+        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
+        src = dst;
+    }
+    return hipSuccess;
+}
+
+hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
+    if (g.count == 1 && g.max_n >= coop_min_n()) {
+        g_stage = "jacobi_coop";
+        return launch_jacobi_coop(t, g.max_n, g.coop + COOP_UBUF, g.coop + COOP_PART, g.coop_ctrl, st);
+    }
+    g_stage = "jacobi";
+    return launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
 }
 
 // Runs the shrink stages for `count` tasks of one kind starting at t.
@@ -283,20 +330,22 @@ hipError_t run_shrinks(const Task* t, const Group& g, int kind, hipStream_t st) 
         if ((g_stage = "project", e = launch_project(t, g.count, g.max_m, g.max_k, g.max_sp, g.st, g.pj, st))) return e;
         int cur = S_P;
         for (int it = 0; it < g.q; ++it) {
-            if ((e = cholqr2(t, g, cur, S_Q, st))) return e;
+            // a well-conditioned basis of the iterate's span is enough between steps
+            if ((e = cholqr(t, g, cur, S_Q, 1, st))) return e;
             if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_Y, dims(0, 1, 0), st))) return e;
             cur = S_Y;
         }
-        if ((e = cholqr2(t, g, cur, S_Q, st))) return e;
+        if ((e = cholqr(t, g, cur, S_Q, 2, st))) return e;
         if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_T1, dims(0, 1, 0), st))) return e;
         if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q, S_T1, S_M, dims(1, 1, 0), st))) return e;
-        if ((g_stage = "jacobi", e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st))) return e;
+        if ((e = eig(t, g, st))) return e;
         if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_Q, S_U, S_Z, dims(0, 1, 1), st))) return e;
     } else {
         if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e;
-        if ((g_stage = "jacobi", e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st))) return e;
+        if ((e = eig(t, g, st))) return e;
     }
     if ((g_stage = "threshold", e = launch_threshold(t, g.count, g.max_ell, g.max_m, st))) return e;
+    g_stage = "rebuild";
     return launch_rebuild(t, g.count, g.max_ell, g.max_d, g.st, kind == T_QUERY, st);
 }
 

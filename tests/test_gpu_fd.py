@@ -279,3 +279,40 @@ def test_error_paths_leave_state_unchanged():
     assert torch.equal(s.query(), before)
     with pytest.raises(SketchError):
         sketch_update(s.handle, np.zeros((3, 31)))
+
+
+# ----------------------------------------------- large single problems
+# eigen-problems of order >= 96 run on the cooperative multi-workgroup solvers
+@pytest.mark.parametrize("d,ell,n", [(300, 64, 1500), (160, 100, 900)])
+def test_exact_fp64_large_eigenproblem(d, ell, n):
+    note(f"exact fp64 coop d={d} ell={ell} n={n}")
+    A = synth.lowrank_rows(n, d, 5 * np.arange(1, 151) ** -0.7, 0.05, seed=d + ell)
+    o = run_oracle(A, d, ell)
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+@pytest.mark.parametrize("d,ell,q,p", [(512, 100, 1, 0), (400, 128, 2, 0), (256, 64, 1, 40)])
+def test_rand_fp64_large_core(d, ell, q, p):
+    note(f"rand fp64 coop d={d} ell={ell} q={q} p={p}")
+    A = synth.lowrank_rows(4 * ell + 300, d, 5 * np.arange(1, 201) ** -0.7, 0.05, seed=d * ell)
+    k = min(ell + p, 2 * ell, d)
+    o = run_oracle(A, d, ell, "rand", k=k, q=q, seed=2, stream=3)
+    s = make(d, ell, shrink="rand", q=q, oversample=p, seed=2, stream_id=3)
+    s.update(torch.from_numpy(A).cuda())
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+def test_bf16_projection_tracks_fp32_projection():
+    # the bf16 MFMA projection computes the same product as the FP32 path up
+    # to bf16 rounding of the inputs: the sketches agree closely
+    d, ell = 512, 64
+    A = torch.from_numpy(synth.lowrank_rows(1000, d, np.arange(1, 129) ** -0.8, 0.03,
+                                            seed=77).astype(np.float32)).cuda()
+    sa = make(d, ell, shrink="rand", state_dtype="f32", proj_dtype="f32", seed=5, stream_id=1)
+    sb = make(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", seed=5, stream_id=1)
+    sa.update(A)
+    sb.update(A)
+    ga, gb = gram(sa.query()), gram(sb.query())
+    assert rel_fro(gb, ga) < 2e-2
