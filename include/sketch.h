@@ -165,6 +165,40 @@ int64_t sketch_memory_in_use(void);
 sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
                               int32_t count, int32_t dtype);
 
+/* ---- profiling -------------------------------------------------------------
+ * Per-stage GPU time of the pipeline, measured with HIP events recorded on
+ * the sketch's stream around every launch of the enabled stages.  Disabled by
+ * default.  Stage bits: */
+enum {
+    SK_STAGE_INGEST = 1u << 0,    /* row copy into the buffer                    */
+    SK_STAGE_OMEGA = 1u << 1,     /* Philox test matrix                          */
+    SK_STAGE_GRAM = 1u << 2,      /* buffer Gram C C^T (split-K + reduce)         */
+    SK_STAGE_PROJECT = 1u << 3,   /* C Omega (split-K + reduce)                   */
+    SK_STAGE_CHOLQR = 1u << 4,    /* CholeskyQR of the iterate                    */
+    SK_STAGE_CORE_GEMM = 1u << 5, /* power steps, Rayleigh-Ritz and Z = Q U       */
+    SK_STAGE_EIG = 1u << 6,       /* symmetric eigen-solve                        */
+    SK_STAGE_THRESHOLD = 1u << 7, /* delta and the rebuild matrix                 */
+    SK_STAGE_REBUILD = 1u << 8,   /* B' = T C                                     */
+    SK_STAGE_ALL = 0x1ffu
+};
+
+typedef struct {
+    char name[24];
+    int64_t calls;        /* launches timed                                  */
+    double total_ms;      /* summed event-to-event time                      */
+} sketch_stage_time;
+
+/* Enables (mask != 0) or disables event timing of the given stages for h and
+ * clears the accumulated times. */
+sk_status sketch_profile_enable(sketch_t h, uint32_t stage_mask);
+
+/* Waits for h's stream and returns up to max_entries accumulated stage times
+ * (only stages with at least one timed launch).  *n_out receives the count.
+ * Entries after the stages report solver counters of the last cooperative
+ * eigen-solve ("eig_sweeps" etc.) in total_ms with calls = 0. */
+sk_status sketch_profile_read(sketch_t h, sketch_stage_time* out, int32_t max_entries,
+                              int32_t* n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -161,6 +161,27 @@ def sketch_update_batch(sketches, rows_list, dtype=None):
                "sketch_update_batch")
 
 
+def sketch_profile_enable(h, stages="all"):
+    """Event-times the given stages (names of _lib.SK_STAGE, or "all")."""
+    if stages == "all":
+        mask = _lib.SK_STAGE_ALL
+    elif isinstance(stages, int):
+        mask = stages
+    else:
+        mask = 0
+        for st in stages:
+            mask |= _lib.SK_STAGE[st]
+    _lib.check(_lib.load().sketch_profile_enable(h, mask), "sketch_profile_enable")
+
+
+def sketch_profile_read(h):
+    """{stage: (calls, total_ms)} plus solver counters (calls = 0)."""
+    buf = (_lib.sketch_stage_time * 64)()
+    n = ctypes.c_int32(0)
+    _lib.check(_lib.load().sketch_profile_read(h, buf, 64, ctypes.byref(n)), "sketch_profile_read")
+    return {buf[i].name.decode(): (buf[i].calls, buf[i].total_ms) for i in range(min(n.value, 64))}
+
+
 class Sketch:
     """Owning wrapper of one sketch handle."""
 
@@ -224,6 +245,12 @@ class Sketch:
 
     def info(self):
         return sketch_info(self.handle)
+
+    def profile(self, stages="all"):
+        sketch_profile_enable(self.handle, stages)
+
+    def profile_read(self):
+        return sketch_profile_read(self.handle)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

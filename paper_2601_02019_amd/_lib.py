@@ -40,11 +40,19 @@ class sketch_info_t(ctypes.Structure):
     ]
 
 
+class sketch_stage_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("calls", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+SK_STAGE = {"ingest": 1 << 0, "omega": 1 << 1, "gram": 1 << 2, "project": 1 << 3, "cholqr": 1 << 4,
+            "core_gemm": 1 << 5, "eig": 1 << 6, "threshold": 1 << 7, "rebuild": 1 << 8}
+SK_STAGE_ALL = 0x1FF
+
 EXPORTS = [
     "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query",
     "window_advance", "sketch_merge", "sketch_merge_tree", "sketch_sync", "sketch_destroy",
     "sketch_last_error", "sketch_info", "sketch_set_memory_budget", "sketch_memory_in_use",
-    "sketch_update_batch",
+    "sketch_update_batch", "sketch_profile_enable", "sketch_profile_read",
 ]
 
 _lib = None
@@ -77,6 +85,8 @@ def load():
     lib.sketch_memory_in_use.restype = i64
     lib.sketch_update_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64),
                                         i32, i32]
+    lib.sketch_profile_enable.argtypes = [vp, ctypes.c_uint32]
+    lib.sketch_profile_read.argtypes = [vp, ctypes.POINTER(sketch_stage_time), i32, ctypes.POINTER(i32)]
     for name in EXPORTS:
         if name not in ("sketch_last_error", "sketch_memory_in_use"):
             getattr(lib, name).restype = ctypes.c_int

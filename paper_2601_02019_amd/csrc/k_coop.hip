@@ -14,14 +14,11 @@
 //                  Q = Y L^{-T} by row blocks; optionally a second pass.
 //
 // Launched with hipLaunchCooperativeKernel so that every workgroup is
-// resident; the grid barriers are cooperative_groups grid syncs.  Every
-// reduction runs in a fixed order, so results repeat bit for bit.
-#include <hip/hip_cooperative_groups.h>
-
+// resident; the grid barriers are agent-scope arrival counters (GridBar).
+// Every floating-point reduction runs in a fixed order, so results repeat
+// bit for bit.
 #include "sk_device.h"
 #include "sk_kernels.h"
-
-namespace cg = cooperative_groups;
 
 namespace sk {
 
@@ -29,6 +26,34 @@ constexpr int BW = 16;    // block width
 constexpr int PB = 32;    // pair-block size (two blocks)
 constexpr int PBL = 33;   // padded LDS leading dimension
 constexpr int COOP_MAX_SWEEPS = 40;
+
+// Grid barrier for a cooperative launch: an arrival counter (zeroed by the
+// host before the launch) with agent-scope release on arrival and acquire
+// while waiting.  Every workgroup is resident (cooperative launch), so every
+// wait ends; the spin is bounded all the same and records a timeout in
+// bar[1] instead of hanging.
+struct GridBar {
+    unsigned* bar;
+    unsigned nblk;
+    unsigned epoch;
+    __device__ void sync() {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ++epoch;
+            const unsigned target = epoch * nblk;
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1u << 26)) {
+                    __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+};
 
 __device__ __forceinline__ int rrp(int slot, int step, int ne) {
     return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ne - 1);
@@ -40,14 +65,15 @@ __device__ __forceinline__ int pb_index(int P, int e, int step, int nb) {
     return blk * BW + (e & (BW - 1));
 }
 
-// Parallel cyclic Jacobi of a 32 x 32 symmetric matrix in LDS (ld PBL) with
-// eigenvectors accumulated in V (LDS).  Returns the rotations performed.
+// Parallel cyclic Jacobi sweeps (at most max_sweeps) of a 32 x 32 symmetric
+// matrix in LDS (ld PBL) with the rotations accumulated in V (LDS).  Returns
+// the rotations performed.
 __device__ int lds_jacobi32(double* A, double* V, double floor_abs, int* sh_rot, double* cs,
-                            int* pq) {
+                            int* pq, int max_sweeps) {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int n = PB, np = PB / 2;
     int total = 0;
-    for (int sweep = 0; sweep < COOP_MAX_SWEEPS; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) *sh_rot = 0;
         __syncthreads();
         for (int step = 0; step < n - 1; ++step) {
@@ -126,8 +152,8 @@ __device__ __forceinline__ void lds_mm32(const double* X, const double* Y, doubl
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* ubuf, double* part,
-                                                     int* ctrl) {
-    cg::grid_group grid = cg::this_grid();
+                                                     int* ctrl, double* stats, unsigned* bar) {
+    GridBar grid{bar, gridDim.x, 0u};
     const Task& t = tasks[0];
     const SkDev* s = t.s;
     const int n = eig_n(t);
@@ -167,12 +193,18 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
     grid.sync();
     double fro2 = 0.0;
     for (int w = 0; w < G; ++w) fro2 += part[w];
-    const double floor_abs = 1e-300 + 1e-17 * sqrt(fro2);
+    // off-diagonal entries below eps ||A||_F are rounding noise: not rotated
+    const double floor_abs = 1e-300 + 1.1e-16 * sqrt(fro2);
 
+    // workgroup 0 keeps a wall-clock account of its phases (diagnostics)
+    const bool timer = (wg == 0 && tid == 0);
+    uint64_t tA = 0, tSA = 0, tB = 0, tSB = 0, t0 = timer ? wall_clock64() : 0, t1;
+    int steps_done = 0;
     int sweep = 0;
     for (; sweep < COOP_MAX_SWEEPS; ++sweep) {
         const int par = sweep & 1;
         for (int step = 0; step < nb - 1; ++step) {
+            ++steps_done;
             // ---- phase A: diagonalise each pair's 32 x 32 sub-problem
             for (int P = wg; P < np; P += G) {
                 for (int e = tid; e < PB * PB; e += 256) {
@@ -181,13 +213,16 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
                     sV[i * PBL + j] = (i == j) ? 1.0 : 0.0;
                 }
                 __syncthreads();
-                const int rot = lds_jacobi32(sA, sV, floor_abs, &sh_rot, cs, pq);
+                // one sweep per block step: the outer cycle revisits every pair
+                const int rot = lds_jacobi32(sA, sV, floor_abs, &sh_rot, cs, pq, 1);
                 if (tid == 0 && rot > 0) atomicAdd(&ctrl[par], rot);
                 double* U = ubuf + (int64_t)P * PB * PB;
                 for (int e = tid; e < PB * PB; e += 256) U[e] = sV[(e / PB) * PBL + (e % PB)];
                 __syncthreads();
             }
+            if (timer) { t1 = wall_clock64(); tA += t1 - t0; t0 = t1; }
             grid.sync();
+            if (timer) { t1 = wall_clock64(); tSA += t1 - t0; t0 = t1; }
             // ---- phase B: block rotations, sandwich tiles then V tiles
             const int nsand = np * (np + 1) / 2;
             const int nvt = (N / PB) * np;
@@ -215,8 +250,7 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
                     __syncthreads();
                     for (int e = tid; e < PB * PB; e += 256) {
                         const int i = e / PB, j = e % PB;
-                        double v = sA[i * PBL + j];
-                        if (P == Q && i != j) v = 0.0;
+                        const double v = sA[i * PBL + j];
                         const int gi = pb_index(P, i, step, nb), gj = pb_index(Q, j, step, nb);
                         A[(int64_t)gi * N + gj] = v;
                         if (P != Q) A[(int64_t)gj * N + gi] = v;
@@ -241,7 +275,9 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
                     __syncthreads();
                 }
             }
+            if (timer) { t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
             grid.sync();
+            if (timer) { t1 = wall_clock64(); tSB += t1 - t0; t0 = t1; }
         }
         const bool done = ctrl[par] == 0;
         grid.sync();  // everyone has read ctrl[par] before it is reset
@@ -266,6 +302,14 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
     if (wg == 0 && tid == 0) {
         if (sweep >= COOP_MAX_SWEEPS) atomicAdd(&s->info[0], 1);
         atomicMax(&s->info[1], sweep + 1);
+        stats[0] += (double)(sweep + 1);
+        stats[1] += (double)steps_done;
+        stats[2] += (double)tA;
+        stats[3] += (double)tSA;
+        stats[4] += (double)tB;
+        stats[5] += (double)tSB;
+        stats[6] += 1.0;
+        stats[7] = (double)G;
     }
 }
 
@@ -317,8 +361,8 @@ __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, d
 }
 
 __global__ __launch_bounds__(256) void k_cholqr_coop(const Task* tasks, int sy, int sq, int passes,
-                                                     double* linv, double* d0g) {
-    cg::grid_group grid = cg::this_grid();
+                                                     double* linv, double* d0g, unsigned* bar) {
+    GridBar grid{bar, gridDim.x, 0u};
     const Task& t = tasks[0];
     const SkDev* s = t.s;
     const int m = t.m, k = s->k;
@@ -505,25 +549,29 @@ static int coop_grid(const void* f, int want) {
 }
 
 hipError_t launch_jacobi_coop(const Task* task, int n, double* ubuf, double* part, int* ctrl,
-                              hipStream_t st) {
+                              double* stats, unsigned* bar, hipStream_t st) {
     const int N = (n + PB - 1) / PB * PB;
     const int nb = N / BW, np = nb / 2;
     const int tiles = np * (np + 1) / 2 + (N / PB) * np;
     int G = coop_grid((const void*)k_jacobi_coop, tiles < 128 ? tiles : 128);
     if (G < np) return hipErrorInvalidConfiguration;
-    void* args[] = {(void*)&task, (void*)&ubuf, (void*)&part, (void*)&ctrl};
+    hipError_t e = hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), st);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&task, (void*)&ubuf, (void*)&part, (void*)&ctrl, (void*)&stats, (void*)&bar};
     return hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3((unsigned)G), dim3(256), args, 0, st);
 }
 
 hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,
-                              double* d0, hipStream_t st) {
+                              double* d0, unsigned* bar, hipStream_t st) {
     const int kb = (k + PB - 1) / PB, mb = (m + PB - 1) / PB;
     int want = kb * (kb + 1) / 2;
     if (mb > want) want = mb;
     if (want > 64) want = 64;
     int G = coop_grid((const void*)k_cholqr_coop, want);
     if (G < 1) return hipErrorInvalidConfiguration;
-    void* args[] = {(void*)&task, (void*)&sy, (void*)&sq, (void*)&passes, (void*)&linv, (void*)&d0};
+    hipError_t e = hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), st);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&task, (void*)&sy, (void*)&sq, (void*)&passes, (void*)&linv, (void*)&d0, (void*)&bar};
     return hipLaunchCooperativeKernel((const void*)k_cholqr_coop, dim3((unsigned)G), dim3(256), args, 0, st);
 }
 

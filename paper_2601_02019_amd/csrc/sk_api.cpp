@@ -108,6 +108,71 @@ struct TaskArena {
     }
 };
 
+// ---------------------------------------------------------------- profiling
+static const int NSTAGE = 9;
+static const char* const STAGE_NAMES[NSTAGE] = {"ingest", "omega", "gram", "project", "cholqr",
+                                                "core_gemm", "eig", "threshold", "rebuild"};
+enum { ST_INGEST, ST_OMEGA, ST_GRAM, ST_PROJECT, ST_CHOLQR, ST_CORE, ST_EIG, ST_THRESH, ST_REBUILD };
+
+struct Prof {
+    uint32_t mask = 0;
+    struct Ev { int stage; hipEvent_t a, b; };
+    std::vector<Ev> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t calls[NSTAGE] = {};
+    double ms[NSTAGE] = {};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void drain() {
+        for (Ev& e : pending) {
+            float t = 0.f;
+            if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&t, e.a, e.b) == hipSuccess) {
+                calls[e.stage] += 1;
+                ms[e.stage] += t;
+            }
+            pool.push_back(e.a);
+            pool.push_back(e.b);
+        }
+        pending.clear();
+    }
+    void release() {
+        drain();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+// Records an event pair around the launches in its scope when the stage is
+// enabled.
+struct StageScope {
+    Prof* p;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageScope(Prof* p_, int stage_, hipStream_t st_) : p(p_), stage(stage_), st(st_) {
+        if (p && (p->mask & (1u << stage))) {
+            a = p->get();
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~StageScope() {
+        if (a) {
+            hipEvent_t b = p->get();
+            (void)hipEventRecord(b, st);
+            p->pending.push_back({stage, a, b});
+            if (p->pending.size() > 4096) p->drain();
+        }
+    }
+};
+
 // ------------------------------------------------------------------ sketch
 struct sketch_s {
     sketch_config cfg{};
@@ -133,6 +198,7 @@ struct sketch_s {
     bool counted = false;
     double* coop = nullptr;   // cooperative-kernel scratch (see coop_* offsets)
     int* coop_ctrl = nullptr;
+    Prof prof;
 
     sk_status device_fail(const std::string& msg) {
         sticky = true;
@@ -164,7 +230,8 @@ struct sketch_s {
 // Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
 // 256 workgroup partials, 16 inverse diagonal blocks of 32 x 32, 512 pivots.
 static const int64_t COOP_UBUF = 0, COOP_PART = 16 * 1024, COOP_LINV = COOP_PART + 256,
-                     COOP_D0 = COOP_LINV + 16 * 1024, COOP_DOUBLES = COOP_D0 + 512;
+                     COOP_D0 = COOP_LINV + 16 * 1024, COOP_STATS = COOP_D0 + 512,
+                     COOP_DOUBLES = COOP_STATS + 16;
 
 // Problem sizes from which one task alone runs the cooperative solvers.
 static int coop_min_n() {
@@ -260,6 +327,7 @@ struct Group {
     int q = 0, st = DT_F64, pj = DT_F64;
     double* coop = nullptr;
     int* coop_ctrl = nullptr;
+    Prof* prof = nullptr;
 };
 
 Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tasks, size_t first,
@@ -294,10 +362,11 @@ inline int dims(int M, int N, int K) { return M | (N << 2) | (K << 4); }  // 0 m
 
 hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hipStream_t st) {
     hipError_t e;
+    StageScope sc(g.prof, ST_CHOLQR, st);
     if (g.count == 1 && g.max_k >= coop_min_n()) {
         g_stage = "cholqr_coop";
         return launch_cholqr_coop(t, g.max_m, g.max_k, sy, sq, passes, g.coop + COOP_LINV,
-                                  g.coop + COOP_D0, st);
+                                  g.coop + COOP_D0, (unsigned*)(g.coop_ctrl + 8), st);
     }
     int src = sy;
     for (int pass = 0; pass < passes; ++pass) {
@@ -313,9 +382,11 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
 }
 
 hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
+    StageScope sc(g.prof, ST_EIG, st);
     if (g.count == 1 && g.max_n >= coop_min_n()) {
         g_stage = "jacobi_coop";
-        return launch_jacobi_coop(t, g.max_n, g.coop + COOP_UBUF, g.coop + COOP_PART, g.coop_ctrl, st);
+        return launch_jacobi_coop(t, g.max_n, g.coop + COOP_UBUF, g.coop + COOP_PART, g.coop_ctrl,
+                                  g.coop + COOP_STATS, (unsigned*)(g.coop_ctrl + 8), st);
     }
     g_stage = "jacobi";
     return launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
@@ -325,27 +396,28 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
 hipError_t run_shrinks(const Task* t, const Group& g, int kind, hipStream_t st) {
     hipError_t e;
     if (kind == T_SHRINK_RAND) {
-        if ((g_stage = "omega", e = launch_omega(t, g.count, g.max_d, g.max_k, g.pj, st))) return e;
-        if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e;
-        if ((g_stage = "project", e = launch_project(t, g.count, g.max_m, g.max_k, g.max_sp, g.st, g.pj, st))) return e;
+        { StageScope sc(g.prof, ST_OMEGA, st); if ((g_stage = "omega", e = launch_omega(t, g.count, g.max_d, g.max_k, g.pj, st))) return e; }
+        { StageScope sc(g.prof, ST_GRAM, st); if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e; }
+        { StageScope sc(g.prof, ST_PROJECT, st); if ((g_stage = "project", e = launch_project(t, g.count, g.max_m, g.max_k, g.max_sp, g.st, g.pj, st))) return e; }
         int cur = S_P;
         for (int it = 0; it < g.q; ++it) {
             // a well-conditioned basis of the iterate's span is enough between steps
             if ((e = cholqr(t, g, cur, S_Q, 1, st))) return e;
-            if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_Y, dims(0, 1, 0), st))) return e;
+            { StageScope sc(g.prof, ST_CORE, st); if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_Y, dims(0, 1, 0), st))) return e; }
             cur = S_Y;
         }
         if ((e = cholqr(t, g, cur, S_Q, 2, st))) return e;
-        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_T1, dims(0, 1, 0), st))) return e;
-        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q, S_T1, S_M, dims(1, 1, 0), st))) return e;
+        { StageScope sc(g.prof, ST_CORE, st); if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_G, S_Q, S_T1, dims(0, 1, 0), st))) return e; }
+        { StageScope sc(g.prof, ST_CORE, st); if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, S_Q, S_T1, S_M, dims(1, 1, 0), st))) return e; }
         if ((e = eig(t, g, st))) return e;
-        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_Q, S_U, S_Z, dims(0, 1, 1), st))) return e;
+        { StageScope sc(g.prof, ST_CORE, st); if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, false, S_Q, S_U, S_Z, dims(0, 1, 1), st))) return e; }
     } else {
-        if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e;
+        { StageScope sc(g.prof, ST_GRAM, st); if ((g_stage = "gram", e = launch_gram(t, g.count, g.max_m, g.max_sg, g.st, st))) return e; }
         if ((e = eig(t, g, st))) return e;
     }
-    if ((g_stage = "threshold", e = launch_threshold(t, g.count, g.max_ell, g.max_m, st))) return e;
+    { StageScope sc(g.prof, ST_THRESH, st); if ((g_stage = "threshold", e = launch_threshold(t, g.count, g.max_ell, g.max_m, st))) return e; }
     g_stage = "rebuild";
+    StageScope sc(g.prof, ST_REBUILD, st);
     return launch_rebuild(t, g.count, g.max_ell, g.max_d, g.st, kind == T_QUERY, st);
 }
 
@@ -368,10 +440,12 @@ static sk_status execute(sketch_t h, std::vector<sketch_t>& owners, std::vector<
             if (dup) break;
             ++j;
         }
-        const Group g = describe(owners, tasks, i, j - i);
+        Group g = describe(owners, tasks, i, j - i);
+        g.prof = &h->prof;
         if (tasks[i].kind == T_INGEST) {
             int max_rows = 0;
             for (size_t u = i; u < j; ++u) max_rows = std::max(max_rows, tasks[u].nrows);
+            StageScope sc(g.prof, ST_INGEST, h->stream);
             if (csr) HIP_TRY(h, launch_ingest_csr(dt + i, g.count, max_rows, g.max_d, g.st, h->stream));
             else HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
         } else {
@@ -606,6 +680,11 @@ static sk_status check_info(sketch_t h) {
     const int32_t* dinfo = h->win ? window_info_ptr(h) : h->host.info;
     HIP_TRY(h, hipMemcpy(info, dinfo, sizeof(info), hipMemcpyDeviceToHost));
     if (info[0] != 0) return h->device_fail("eigen-solver did not converge");
+    if (h->coop_ctrl) {
+        unsigned bar[2] = {0, 0};
+        HIP_TRY(h, hipMemcpy(bar, h->coop_ctrl + 8, sizeof(bar), hipMemcpyDeviceToHost));
+        if (bar[1] != 0) return h->device_fail("cooperative grid barrier timed out");
+    }
     return SK_OK;
 }
 
@@ -691,6 +770,7 @@ sk_status sketch_destroy(sketch_t h) {
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->stage) (void)hipFree(h->stage);
     h->arena.release();
+    h->prof.release();
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     if (h->counted) g_in_use -= h->bytes;
     delete h;
@@ -815,10 +895,12 @@ sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector
                owners[j]->st == owners[i]->st && owners[j]->pj == owners[i]->pj &&
                tasks[j].kind != T_QUERY)
             ++j;
-        const Group g = describe(owners, tasks, i, j - i);
+        Group g = describe(owners, tasks, i, j - i);
+        g.prof = &h->prof;
         if (tasks[i].kind == T_INGEST) {
             int max_rows = 0;
             for (size_t u = i; u < j; ++u) max_rows = std::max(max_rows, tasks[u].nrows);
+            StageScope sc(g.prof, ST_INGEST, h->stream);
             HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
         } else {
             HIP_TRY(h, run_shrinks(dt + i, g, tasks[i].kind, h->stream));
@@ -974,4 +1056,60 @@ extern "C" sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32
     }
     cleanup();
     return rc;
+}
+
+// ---------------------------------------------------------------- profiling
+extern "C" sk_status sketch_profile_enable(sketch_t h, uint32_t stage_mask) {
+    sk_status rc = check_handle(h, "sketch_profile_enable");
+    if (rc) return rc;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->prof.drain();
+    h->prof.mask = stage_mask & SK_STAGE_ALL;
+    for (int i = 0; i < NSTAGE; ++i) {
+        h->prof.calls[i] = 0;
+        h->prof.ms[i] = 0.0;
+    }
+    if (h->coop) HIP_TRY(h, hipMemset(h->coop + COOP_STATS, 0, 16 * sizeof(double)));
+    return SK_OK;
+}
+
+extern "C" sk_status sketch_profile_read(sketch_t h, sketch_stage_time* out, int32_t max_entries,
+                                         int32_t* n_out) {
+    sk_status rc = check_handle(h, "sketch_profile_read");
+    if (rc) return rc;
+    if (!n_out || (max_entries > 0 && !out)) return fail(SK_EINVAL, "sketch_profile_read: NULL argument");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->prof.drain();
+    int n = 0;
+    auto put = [&](const char* name, int64_t calls, double v) {
+        if (n < max_entries) {
+            std::memset(out[n].name, 0, sizeof(out[n].name));
+            std::strncpy(out[n].name, name, sizeof(out[n].name) - 1);
+            out[n].calls = calls;
+            out[n].total_ms = v;
+        }
+        ++n;
+    };
+    for (int i = 0; i < NSTAGE; ++i)
+        if (h->prof.calls[i] > 0) put(STAGE_NAMES[i], h->prof.calls[i], h->prof.ms[i]);
+    if (h->coop) {
+        double st[16];
+        HIP_TRY(h, hipMemcpy(st, h->coop + COOP_STATS, sizeof(st), hipMemcpyDeviceToHost));
+        if (st[6] > 0) {
+            int dev = 0, khz = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+            const double tick_ms = khz > 0 ? 1.0 / khz : 0.0;
+            put("eig_solves", 0, st[6]);
+            put("eig_sweeps", 0, st[0]);
+            put("eig_steps", 0, st[1]);
+            put("eig_phaseA_ms", 0, st[2] * tick_ms);
+            put("eig_syncA_ms", 0, st[3] * tick_ms);
+            put("eig_phaseB_ms", 0, st[4] * tick_ms);
+            put("eig_syncB_ms", 0, st[5] * tick_ms);
+            put("eig_workgroups", 0, st[7]);
+        }
+    }
+    *n_out = n;
+    return SK_OK;
 }

@@ -35,9 +35,9 @@ hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small
                          hipStream_t st);
 hipError_t launch_threshold(const Task* tasks, int count, int max_ell, int max_m, hipStream_t st);
 hipError_t launch_jacobi_coop(const Task* task, int n, double* ubuf, double* part, int* ctrl,
-                              hipStream_t st);
+                              double* stats, unsigned* bar, hipStream_t st);
 hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,
-                              double* d0, hipStream_t st);
+                              double* d0, unsigned* bar, hipStream_t st);
 int jacobi_lds_max();
 int chol_lds_max();
 
