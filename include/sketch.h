@@ -43,6 +43,12 @@
 #define SKETCH_H
 #include <stdint.h>
 
+#if defined(__GNUC__) || defined(__clang__)
+#define SK_EXPORT __attribute__((visibility("default")))
+#else
+#define SK_EXPORT
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -86,25 +92,25 @@ typedef struct {
 /* Fills *cfg with defaults: exact FP64 persistent sketch, q = 1, no
  * oversampling, seed 0, device 0, library-owned stream.  d and ell are 0 and
  * must be set by the caller. */
-sk_status sketch_config_init(sketch_config* cfg);
+SK_EXPORT sk_status sketch_config_init(sketch_config* cfg);
 
 /* Creates a sketch; allocates all device state up front.
  * SK_EINVAL for bad fields; SK_ENOMEM if allocation fails or the
  * library-wide memory budget (sketch_set_memory_budget) would be exceeded. */
-sk_status sketch_create(const sketch_config* cfg, sketch_t* out);
+SK_EXPORT sk_status sketch_create(const sketch_config* cfg, sketch_t* out);
 
 /* Appends n_rows rows (n_rows x d, leading dimension ld, element type dtype)
  * to the stream.  Rows are copied into the buffer (converted to the state
  * dtype, round-to-nearest-even); every time the buffer reaches 2*ell rows a
  * shrink runs (Algorithm "AeroSketch: Update" lines 1-6).  n_rows == 0 is a
  * no-op.  For SK_WINDOW sketches each row advances time by one. */
-sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld,
+SK_EXPORT sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld,
                         int32_t dtype, int32_t on_device);
 
 /* Same for sparse rows in CSR form: indptr (n_rows + 1, int64, indptr[0] may
  * be non-zero), column indices (int32, in [0, d)), values (float32).
  * Duplicate indices within a row are summed.  Persistent sketches only. */
-sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* indices,
+SK_EXPORT sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* indices,
                             const float* values, int64_t n_rows, int32_t on_device);
 
 /* Writes the ell x d sketch (row-major, dtype SK_F64 or SK_F32) to B_out.
@@ -112,33 +118,33 @@ sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* in
  * buffer when it holds >= ell rows (Algorithm "AeroSketch: Query" lines 5-7).
  * Window: the query of Algorithm "ML-AeroSketch" for the window (T-N, T].
  * Non-destructive. */
-sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device);
+SK_EXPORT sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device);
 
 /* SK_WINDOW only: moves time to t_now >= current time without rows and
  * expires what left the window.  SK_EUNSUPPORTED on persistent sketches,
  * SK_ESTATE if t_now is in the past. */
-sk_status window_advance(sketch_t h, int64_t t_now);
+SK_EXPORT sk_status window_advance(sketch_t h, int64_t t_now);
 
 /* dst absorbs each source sketch in order: the non-zero rows of the source's
  * query are appended to dst as ordinary rows (stack and re-shrink, Lemma
  * "Decomposability").  Sources are unchanged.  SK_ESHAPE if d differs;
  * persistent sketches only. */
-sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src);
+SK_EXPORT sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src);
 
 /* Binary-tree merge of n_src sketches (same d and ell) into dst, which must be
  * empty: level by level, pairs (2i, 2i+1) in index order are stacked and
  * shrunk; the shrinks of one level run as one batched launch. */
-sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32_t n_src);
+SK_EXPORT sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32_t n_src);
 
 /* Blocks until all work enqueued on h has finished; reports deferred device
  * errors (e.g. a non-converged eigen-solve). */
-sk_status sketch_sync(sketch_t h);
+SK_EXPORT sk_status sketch_sync(sketch_t h);
 
 /* Waits for outstanding work and frees the sketch.  NULL is a no-op. */
-sk_status sketch_destroy(sketch_t h);
+SK_EXPORT sk_status sketch_destroy(sketch_t h);
 
 /* Thread-local message of the last failing call ("" if none). */
-const char* sketch_last_error(void);
+SK_EXPORT const char* sketch_last_error(void);
 
 typedef struct {
     int64_t rows_seen;    /* rows appended so far (time for windows)              */
@@ -149,20 +155,25 @@ typedef struct {
     int32_t levels;       /* window levels (1 for persistent sketches)             */
 } sketch_info_t;
 
-sk_status sketch_info(sketch_t h, sketch_info_t* info);
+SK_EXPORT sk_status sketch_info(sketch_t h, sketch_info_t* info);
+
+/* SK_WINDOW only: counters of one level: [0] snapshots dumped, [1] raw rows
+ * stored, [2] directions dumped, [3] rows in the level's FD buffer, [4] queue
+ * length, [5] FD reduces. */
+SK_EXPORT sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6);
 
 /* Library-wide cap (bytes) on device memory held by live sketches; 0 = no
  * cap.  sketch_create returns SK_ENOMEM instead of exceeding it.  Used for
  * admission control by a serving loop. */
-sk_status sketch_set_memory_budget(int64_t bytes);
-int64_t sketch_memory_in_use(void);
+SK_EXPORT sk_status sketch_set_memory_budget(int64_t bytes);
+SK_EXPORT int64_t sketch_memory_in_use(void);
 
 /* Batched update: count sketches, each with its own device row block
  * (rows[i], n[i] rows, ld[i] = its d).  All sketches must share one HIP
  * stream and device.  Ingest and the shrinks that fall due are grouped
  * across sketches: one launch per pipeline stage serves every sketch whose
  * buffer filled at that point, whatever its d and ell. */
-sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
+SK_EXPORT sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
                               int32_t count, int32_t dtype);
 
 /* ---- profiling -------------------------------------------------------------
@@ -190,13 +201,13 @@ typedef struct {
 
 /* Enables (mask != 0) or disables event timing of the given stages for h and
  * clears the accumulated times. */
-sk_status sketch_profile_enable(sketch_t h, uint32_t stage_mask);
+SK_EXPORT sk_status sketch_profile_enable(sketch_t h, uint32_t stage_mask);
 
 /* Waits for h's stream and returns up to max_entries accumulated stage times
  * (only stages with at least one timed launch).  *n_out receives the count.
  * Entries after the stages report solver counters of the last cooperative
  * eigen-solve ("eig_sweeps" etc.) in total_ms with calls = 0. */
-sk_status sketch_profile_read(sketch_t h, sketch_stage_time* out, int32_t max_entries,
+SK_EXPORT sk_status sketch_profile_read(sketch_t h, sketch_stage_time* out, int32_t max_entries,
                               int32_t* n_out);
 
 #ifdef __cplusplus

@@ -56,6 +56,9 @@ def _load():
     lib.o_win_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.o_win_create.restype = ctypes.c_void_p
+    lib.o_win_create2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int]
+    lib.o_win_create2.restype = ctypes.c_void_p
     lib.o_win_destroy.argtypes = [ctypes.c_void_p]
     lib.o_win_update.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, ctypes.c_int64]
     lib.o_win_advance.argtypes = [ctypes.c_void_p, ctypes.c_int64]
@@ -209,9 +212,9 @@ class FD:
 class Window:
     """ML-AeroSketch over a sliding window of N rows."""
 
-    def __init__(self, d, ell, N, R, q=1, seed=0, stream=0):
+    def __init__(self, d, ell, N, R, q=1, seed=0, stream=0, fd="exact"):
         lib = _load()
-        self._h = lib.o_win_create(d, ell, N, float(R), q, seed, stream)
+        self._h = lib.o_win_create2(d, ell, N, float(R), q, seed, stream, {"exact": 0, "rand": 1}[fd])
         if not self._h:
             raise ValueError("bad window parameters")
         self.d, self.ell, self.N = d, ell, N

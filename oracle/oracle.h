@@ -85,6 +85,10 @@ typedef struct o_win o_win;
  * max(1, ceil(log2 R)) levels), q power steps of simul_iter. */
 o_win* o_win_create(int d, int ell, int64_t N, double R, int q,
                     uint64_t seed, uint64_t stream);
+/* The same with the FD reduce chosen: O_EXACT or O_RAND (simul_iter shrink,
+ * k = min(ell, d), q power steps, Philox key (seed, 64 stream + level + 1)). */
+o_win* o_win_create2(int d, int ell, int64_t N, double R, int q, uint64_t seed, uint64_t stream,
+                     int fd_mode);
 void o_win_destroy(o_win* w);
 int o_win_update(o_win* w, const double* rows, int64_t n, int64_t ld);
 /* Move time forward to t_now without rows (expires old entries). */

@@ -28,6 +28,9 @@
  *     dropped by the length cap; the smallest valid level is used (the last
  *     level if none is valid).
  *   - the FD over the stacked rows is one exact shrink of the whole stack.
+ *   - the FD reduce (Algorithm "AeroSketch: Update" lines 3-4) is the exact
+ *     SVD shrink or, with fd_mode O_RAND, the simul_iter shrink of the
+ *     persistent sketch (k = min(ell, d)), keyed per level.
  *   - random streams: power-iteration start vector of level j at time i uses
  *     counter (coordinate, 0, i, 0x100 + j); simul_iter's Omega at doubling
  *     step s uses counter (row, column/4, i, 0x200 + 32 j + s).
@@ -58,7 +61,7 @@ typedef struct {
 } wlevel;
 
 struct o_win {
-    int d, ell, L, q;
+    int d, ell, L, q, fd_mode;
     int64_t N, T;
     uint64_t seed, stream;
     wlevel* lv;
@@ -72,9 +75,16 @@ static void entry_free(wentry* e) {
 }
 
 o_win* o_win_create(int d, int ell, int64_t N, double R, int q, uint64_t seed, uint64_t stream) {
+    return o_win_create2(d, ell, N, R, q, seed, stream, O_EXACT);
+}
+
+o_win* o_win_create2(int d, int ell, int64_t N, double R, int q, uint64_t seed, uint64_t stream,
+                     int fd_mode) {
     if (d < 1 || ell < 2 || N < 1 || !(R >= 1.0) || q < 0) return NULL;
+    if (fd_mode != O_EXACT && fd_mode != O_RAND) return NULL;
     o_win* w = (o_win*)calloc(1, sizeof(o_win));
     w->d = d; w->ell = ell; w->N = N; w->q = q; w->seed = seed; w->stream = stream;
+    w->fd_mode = fd_mode;
     int L = (int)ceil(log2(R));
     if (L < 1) L = 1;
     w->L = L;
@@ -196,7 +206,14 @@ static int level_update(o_win* w, int j, const double* a, int64_t i) {
     memcpy(l->C + l->r * d, a, sizeof(double) * (size_t)d);
     l->r += 1;
     if (l->r == 2 * ell) {
-        int rc = o_shrink_exact(l->C, 2 * ell, d, d, ell);
+        /* FD reduce (line 4): exact SVD, or simul_iter with k = min(ell, d)
+         * keyed by (seed, 64 stream + j + 1) and the level's shrink count */
+        int rc;
+        if (w->fd_mode == O_EXACT)
+            rc = o_shrink_exact(l->C, 2 * ell, d, d, ell);
+        else
+            rc = o_shrink_rand(l->C, 2 * ell, d, d, ell, ell < d ? ell : d, w->q, w->seed,
+                               w->stream * 64u + (uint64_t)j + 1u, (uint64_t)l->shrinks);
         if (rc) return rc;
         for (int64_t e = ell - 1; e < 2 * ell; ++e) memset(l->C + e * d, 0, sizeof(double) * (size_t)d);
         l->r = ell - 1;

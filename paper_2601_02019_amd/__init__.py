@@ -102,6 +102,13 @@ def window_advance(h, t_now):
     _lib.check(_lib.load().window_advance(h, int(t_now)), "window_advance")
 
 
+def window_stats(h, level):
+    st = (ctypes.c_int64 * 6)()
+    _lib.check(_lib.load().window_stats(h, level, st), "window_stats")
+    keys = ["dumps", "raw", "dirs", "fill", "queue", "shrinks"]
+    return dict(zip(keys, list(st)))
+
+
 def _handles(srcs):
     arr = (ctypes.c_void_p * len(srcs))()
     for i, s in enumerate(srcs):
@@ -232,6 +239,9 @@ class Sketch:
 
     def advance(self, t_now):
         window_advance(self.handle, t_now)
+
+    def window_stats(self, level):
+        return window_stats(self.handle, level)
 
     def merge(self, srcs):
         sketch_merge(self.handle, srcs)

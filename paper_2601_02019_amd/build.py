@@ -11,7 +11,7 @@ SOURCES = ["k_stream.hip", "k_core.hip", "k_mfma.hip", "k_coop.hip", "k_window.h
            "sk_window.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result"]
+         "-Wno-unused-result", "-fvisibility=hidden"]
 
 
 def sources():

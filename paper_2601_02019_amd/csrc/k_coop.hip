@@ -151,19 +151,19 @@ __device__ __forceinline__ void lds_mm32(const double* X, const double* Y, doubl
     C[(r + 1) * PBL + c + 1] = a11;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* ubuf, double* part,
-                                                     int* ctrl, double* stats, unsigned* bar) {
-    GridBar grid{bar, gridDim.x, 0u};
-    const Task& t = tasks[0];
-    const SkDev* s = t.s;
-    const int n = eig_n(t);
-    const bool rnd = t.kind == T_SHRINK_RAND;
-    const double* Ain = s->slot[rnd ? S_M : S_G];
-    const int ldin = s->sld[rnd ? S_M : S_G];
+__global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
+    GridBar grid{args.bar, gridDim.x, 0u};
+    const int n = args.n;
+    const double* Ain = args.Ain;
+    const int ldin = args.ldin;
+    double* ubuf = args.ubuf;
+    double* part = args.part;
+    int* ctrl = args.ctrl;
+    double* stats = args.stats;
     const int N = (n + PB - 1) / PB * PB;
     const int nb = N / BW, np = nb / 2;
-    double* A = s->slot[S_EA];
-    double* V = s->slot[S_EV];
+    double* A = args.A;
+    double* V = args.V;
     const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
 
     __shared__ double sA[PB * PBL], sV[PB * PBL], sT[PB * PBL];
@@ -286,9 +286,9 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
         if (done) break;
     }
     // eigenvalues (real indices only) sorted descending, vectors permuted along
-    double* U = s->slot[S_U];
-    const int lu = s->sld[S_U];
-    double* lam = s->slot[S_LAM];
+    double* U = args.U;
+    const int lu = args.lu;
+    double* lam = args.lam;
     for (int i = wg * 256 + tid; i < n; i += G * 256) {
         const double li = A[(int64_t)i * N + i];
         int rank = 0;
@@ -300,8 +300,8 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(const Task* tasks, double* 
         for (int r = 0; r < n; ++r) U[(int64_t)r * lu + rank] = V[(int64_t)r * N + i];
     }
     if (wg == 0 && tid == 0) {
-        if (sweep >= COOP_MAX_SWEEPS) atomicAdd(&s->info[0], 1);
-        atomicMax(&s->info[1], sweep + 1);
+        if (sweep >= COOP_MAX_SWEEPS) atomicAdd(&args.info[0], 1);
+        atomicMax(&args.info[1], sweep + 1);
         stats[0] += (double)(sweep + 1);
         stats[1] += (double)steps_done;
         stats[2] += (double)tA;
@@ -548,17 +548,17 @@ static int coop_grid(const void* f, int want) {
     return want < cap ? want : cap;
 }
 
-hipError_t launch_jacobi_coop(const Task* task, int n, double* ubuf, double* part, int* ctrl,
-                              double* stats, unsigned* bar, hipStream_t st) {
-    const int N = (n + PB - 1) / PB * PB;
+hipError_t launch_jacobi_coop(const CoopEig& a, hipStream_t st) {
+    const int N = (a.n + PB - 1) / PB * PB;
     const int nb = N / BW, np = nb / 2;
     const int tiles = np * (np + 1) / 2 + (N / PB) * np;
     int G = coop_grid((const void*)k_jacobi_coop, tiles < 128 ? tiles : 128);
-    if (G < np) return hipErrorInvalidConfiguration;
-    hipError_t e = hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), st);
+    if (G < 1) return hipErrorInvalidConfiguration;
+    hipError_t e = hipMemsetAsync(a.bar, 0, 2 * sizeof(unsigned), st);
     if (e != hipSuccess) return e;
-    void* args[] = {(void*)&task, (void*)&ubuf, (void*)&part, (void*)&ctrl, (void*)&stats, (void*)&bar};
-    return hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3((unsigned)G), dim3(256), args, 0, st);
+    CoopEig args = a;
+    void* kargs[] = {(void*)&args};
+    return hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3((unsigned)G), dim3(256), kargs, 0, st);
 }
 
 hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,

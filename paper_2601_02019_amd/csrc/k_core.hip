@@ -111,19 +111,9 @@ __device__ __forceinline__ void tri_index(int e, int& a, int& b) {
 // dependent: its row and column of X are zero, so the basis Q = Y X^T gets a
 // zero column there and the spanned subspace keeps only the independent part.
 
-template <bool LDS>
-__global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int sx, int lds_max) {
-    extern __shared__ double lds[];
-    const Task& t = tasks[blockIdx.z];
-    if (t.kind != T_SHRINK_RAND) return;
-    const SkDev* s = t.s;
-    const int n = s->k;
-    if (LDS != (n <= lds_max)) return;
-    const double* W = s->slot[sw];
-    const int ldw = s->sld[sw];
-    double* X = s->slot[sx];
-    const int ldx = s->sld[sx];
-    double* L = LDS ? lds : s->slot[S_EA];
+// Cholesky-inverse of one n x n matrix by the whole workgroup; L is the
+// n x n work matrix (LDS or global).
+__device__ void cholinv_body(const double* W, int ldw, double* X, int ldx, int n, double* L) {
     const int ldl = n;
     __shared__ double diag0[512];
     __shared__ int drop[512];
@@ -179,6 +169,26 @@ __global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int
     }
 }
 
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int sx, int lds_max) {
+    extern __shared__ double lds[];
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind != T_SHRINK_RAND) return;
+    const SkDev* s = t.s;
+    const int n = s->k;
+    if (LDS != (n <= lds_max)) return;
+    cholinv_body(s->slot[sw], s->sld[sw], s->slot[sx], s->sld[sx], n, LDS ? lds : s->slot[S_EA]);
+}
+
+// Descriptor form: X = chol(W)^{-1} for each descriptor (blockIdx.z).
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_cholinv_desc(const SmallDesc* ds, int lds_max) {
+    extern __shared__ double lds[];
+    const SmallDesc& q = ds[blockIdx.z];
+    if (q.n <= 0 || LDS != (q.n <= lds_max)) return;
+    cholinv_body(q.A, q.lda, q.X, q.ldx, q.n, LDS ? lds : q.work);
+}
+
 // ------------------------------------------------------------ Jacobi
 // Parallel cyclic Jacobi, round-robin ("chess tournament") ordering: in each
 // of the ne-1 steps of a sweep the ne/2 index pairs are disjoint, so all
@@ -193,24 +203,14 @@ __device__ __forceinline__ int rr_player(int slot, int step, int ne) {
     return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ne - 1);
 }
 
-template <bool LDS>
-__global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max) {
-    extern __shared__ double lds[];
-    const Task& t = tasks[blockIdx.z];
-    if (t.kind == T_INGEST) return;
-    const SkDev* s = t.s;
-    const int n = eig_n(t);
-    if (LDS != (n <= lds_max)) return;
-    const bool rnd = t.kind == T_SHRINK_RAND;
-    const double* Ain = s->slot[rnd ? S_M : S_G];
-    const int ldin = s->sld[rnd ? S_M : S_G];
-    double* A = LDS ? lds : s->slot[S_EA];
+// Jacobi eigen-decomposition of one n x n symmetric matrix by the whole
+// workgroup.  A: n x n work matrix (LDS or global), V: n x n rotations,
+// U (ld lu) / lam: sorted output; info[0] counts non-converged solves,
+// info[1] keeps the largest sweep count.
+__device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, double* V, double* U,
+                            int lu, double* lam, int* info) {
     const int la = n;
-    double* V = s->slot[S_EV];
     const int lv = n;
-    double* U = s->slot[S_U];
-    const int lu = s->sld[S_U];
-    double* lam = s->slot[S_LAM];
 
     __shared__ double cs_c[2][256], cs_s[2][256];
     __shared__ int pp[2][256], qq[2][256];
@@ -331,9 +331,31 @@ __global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max)
         for (int r = 0; r < n; ++r) U[(int64_t)r * lu + rank] = V[(int64_t)r * lv + i];
     }
     if (tid == 0) {
-        if (!done) atomicAdd(&s->info[0], 1);
-        atomicMax(&s->info[1], sweep);
+        if (!done) atomicAdd(&info[0], 1);
+        atomicMax(&info[1], sweep);
     }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max) {
+    extern __shared__ double lds[];
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    const SkDev* s = t.s;
+    const int n = eig_n(t);
+    if (LDS != (n <= lds_max)) return;
+    const bool rnd = t.kind == T_SHRINK_RAND;
+    jacobi_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, LDS ? lds : s->slot[S_EA],
+                s->slot[S_EV], s->slot[S_U], s->sld[S_U], s->slot[S_LAM], s->info);
+}
+
+// Descriptor form: eigen-decomposition of A (n x n) into U / lam.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_jacobi_desc(const SmallDesc* ds, int lds_max) {
+    extern __shared__ double lds[];
+    const SmallDesc& q = ds[blockIdx.z];
+    if (q.n <= 0 || LDS != (q.n <= lds_max)) return;
+    jacobi_body(q.A, q.lda, q.n, LDS ? lds : q.work, q.work2, q.X, q.ldx, q.lam, q.info);
 }
 
 // ------------------------------------------------------------ threshold
@@ -395,8 +417,14 @@ static int lds_cap(const void* f) {
 }
 
 static void init_lds_caps() {
-    if (g_jac_lds < 0) g_jac_lds = lds_cap((const void*)k_jacobi<true>);
-    if (g_chol_lds < 0) g_chol_lds = lds_cap((const void*)k_cholinv<true>);
+    if (g_jac_lds < 0) {
+        const int a = lds_cap((const void*)k_jacobi<true>), b = lds_cap((const void*)k_jacobi_desc<true>);
+        g_jac_lds = a < b ? a : b;
+    }
+    if (g_chol_lds < 0) {
+        const int a = lds_cap((const void*)k_cholinv<true>), b = lds_cap((const void*)k_cholinv_desc<true>);
+        g_chol_lds = a < b ? a : b;
+    }
 }
 
 int jacobi_lds_max() {
@@ -444,6 +472,32 @@ hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small
         if (e != hipSuccess) return e;
     }
     if (any_large || cap == 0) hipLaunchKernelGGL((k_jacobi<false>), grid, dim3(1024), 0, st, tasks, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+    const int cap = chol_lds_max();
+    if (cap > 0) {
+        const int nn = max_n < cap ? max_n : cap;
+        hipLaunchKernelGGL((k_cholinv_desc<true>), dim3(1, 1, (unsigned)count), dim3(1024),
+                           sizeof(double) * (size_t)nn * nn, st, ds, cap);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (max_n > cap) hipLaunchKernelGGL((k_cholinv_desc<false>), dim3(1, 1, (unsigned)count), dim3(1024), 0, st, ds, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+    const int cap = jacobi_lds_max();
+    if (cap > 0) {
+        const int nn = max_n < cap ? max_n : cap;
+        hipLaunchKernelGGL((k_jacobi_desc<true>), dim3(1, 1, (unsigned)count), dim3(1024),
+                           sizeof(double) * (size_t)nn * nn, st, ds, cap);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (max_n > cap) hipLaunchKernelGGL((k_jacobi_desc<false>), dim3(1, 1, (unsigned)count), dim3(1024), 0, st, ds, cap);
     return hipGetLastError();
 }
 

@@ -68,6 +68,63 @@ struct Task {
     const float* values;
 };
 
+// Descriptor of one small dense FP64 problem for the pointer-driven kernels
+// (window sketches): Cholesky-inverse (A -> X) or eigen-decomposition
+// (A -> X = eigenvectors, lam).  work / work2: n x n scratch.
+struct SmallDesc {
+    const double* A;
+    double* X;
+    double* lam;
+    double* work;
+    double* work2;
+    int32_t* info;
+    int32_t n, lda, ldx, pad;
+};
+
+// Descriptor of one FP64 product C = alpha op(A) op(B) + beta C.
+struct GemmDesc {
+    const double* A;
+    const double* B;
+    double* C;
+    int32_t M, N, K;
+    int32_t lda, ldb, ldc;
+    int32_t ta, tb;
+    double alpha, beta;
+};
+
+// Gaussian matrix from Philox: M[t][c] = normal (c mod 4) of the block at
+// counter (t, c / 4, c2, c3), key (seed, stream).
+struct MatGenDesc {
+    double* M;
+    int32_t rows, cols, ld, pad;
+    uint64_t seed, stream, c2, c3;
+};
+
+// Power iteration of one window level on C (r x d).
+struct PiDesc {
+    const double* C;
+    double* out;
+    int64_t ldc;
+    int32_t r, d, steps, pad;
+    uint64_t seed, stream, c2, c3;
+};
+
+// Arguments of the cooperative block-Jacobi eigen-solver.
+struct CoopEig {
+    const double* Ain;   // n x n symmetric input (ld ldin)
+    double* A;           // N x N work (N = n rounded up to 32)
+    double* V;           // N x N rotations
+    double* U;           // n x n sorted eigenvectors (ld lu)
+    double* lam;         // n eigenvalues, descending
+    int32_t* info;       // [0] non-converged solves, [1] max sweeps
+    double* ubuf;        // (N / 32) x 32 x 32 pair-block rotations
+    double* part;        // >= gridDim doubles
+    int32_t* ctrl;       // 2 rotation counters
+    double* stats;       // 8 diagnostic accumulators
+    uint32_t* bar;       // grid barrier (2 words, zeroed before launch)
+    int32_t n, ldin, lu, pad;
+};
+
 // Eigen-problem size of a task: the buffer rows (exact shrink / query) or k.
 __host__ __device__ inline int eig_n(const Task& t) {
     return t.kind == T_SHRINK_RAND ? t.s->k : t.m;

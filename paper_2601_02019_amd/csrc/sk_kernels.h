@@ -34,10 +34,21 @@ hipError_t launch_cholinv(const Task* tasks, int count, int max_k, bool any_smal
 hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small, bool any_large,
                          hipStream_t st);
 hipError_t launch_threshold(const Task* tasks, int count, int max_ell, int max_m, hipStream_t st);
-hipError_t launch_jacobi_coop(const Task* task, int n, double* ubuf, double* part, int* ctrl,
-                              double* stats, unsigned* bar, hipStream_t st);
+hipError_t launch_jacobi_coop(const CoopEig& args, hipStream_t st);
+hipError_t launch_rownorm(const void* rows, int64_t ld, int dtype, int64_t n, int d, double* out,
+                          hipStream_t st);
+hipError_t launch_philox_mat(const void* descs, int count, int max_rows, int max_cols, hipStream_t st);
+hipError_t launch_win_pi(const void* descs, int count, int max_d, int max_r, hipStream_t st);
+hipError_t launch_blockmask(double* S, int ld, int D, const int32_t* ent, hipStream_t st);
+hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n, int ell, double* X,
+                              int64_t ldx, int d, hipStream_t st);
 hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,
                               double* d0, unsigned* bar, hipStream_t st);
+hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
+hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
+hipError_t launch_gemm_desc(const GemmDesc* ds, int count, int max_M, int max_N, hipStream_t st);
+hipError_t launch_transpose(const double* src, int lds, double* dst, int64_t ldd, int rows, int cols,
+                            hipStream_t st);
 int jacobi_lds_max();
 int chol_lds_max();
 

@@ -1,11 +1,614 @@
-// sk_window.cpp -- placeholder until the window engine lands.
+// sk_window.cpp -- sliding-window sketches: Algorithm "ML-AeroSketch" on the
+// GPU, behind the same C ABI.
+//
+// Levels j = 0 .. L-1 (L = max(1, ceil(log2 R))), threshold theta_j =
+// 2^j eps N with eps = 2 / ell.  Each level keeps
+//   - an FD buffer C (2 ell x d, FP64): a persistent sketch whose shrink is the
+//     window's shrink (exact SVD or simul_iter), so FD reduces of all levels
+//     run through the batched shrink pipeline;
+//   - a queue of snapshots (Z, Z^T C'^T C') and raw rows, metadata on the
+//     host, vectors in device rings.
+//
+// The host can plan everything that depends on row norms alone: for an
+// update call it reads |a|^2 of all rows once (one transfer), then knows for
+// each level which rows are stored raw and when the FD buffer fills (a dump
+// never changes the number of buffer rows).  What depends on the data is
+// decided per row from one small transfer: the power-iteration estimate of
+// every level (one launch for all levels), and, rarely, the doubling
+// simul_iter and the dump of a level.
+//
+// Readings shared with the FP64 oracle: simul_iter's test matrix is on the d
+// side; the dump at k = min(ell, d, rows) happens even if every estimate
+// reaches theta; s of an entry is the previous entry's t + 1; a level is
+// valid for a query when no in-window entry was dropped by the length cap;
+// random counters: power-iteration start (t, 0, i, 0x100 + j), simul_iter
+// (t, c / 4, i, 0x200 + 32 j + s), FD reduce of level j keyed (seed,
+// 64 stream + j + 1).
+#include <algorithm>
+#include <cmath>
+#include <deque>
+
+#include "sk_internal.h"
 #include "sk_window.h"
 
-sk_status window_create(sketch_t) { return SK_EUNSUPPORTED; }
-sk_status window_update(sketch_t, const char*, int64_t, int64_t, int) { return SK_EUNSUPPORTED; }
-sk_status window_query(sketch_t, const double**) { return SK_EUNSUPPORTED; }
-sk_status window_advance_impl(sketch_t, int64_t) { return SK_EUNSUPPORTED; }
-void window_destroy(sketch_t) {}
-const int32_t* window_info_ptr(sketch_t) { return nullptr; }
-int64_t window_time(sketch_t) { return 0; }
-int32_t window_levels(sketch_t) { return 1; }
+namespace {
+
+struct WinEntry {
+    int kind;        // 0 snapshot, 1 raw row
+    int xi;          // directions of a snapshot
+    int64_t s, t;
+    int64_t slot;    // first ring slot
+};
+
+struct WinLevel {
+    sketch_t sub = nullptr;
+    double theta = 0.0;
+    std::deque<WinEntry> q;
+    int64_t last_t = 0, dropped_t = 0;
+    double* Zp = nullptr;  // direction ring: z vectors (pcap x ld)
+    double* Wp = nullptr;  // rows of Z^T C'^T C' (pcap x ld)
+    int64_t pcap = 0, ptail = 0;
+    double* Rp = nullptr;  // raw-row ring (rcap x ld)
+    int64_t rcap = 0, rtail = 0;
+    int64_t ndumps = 0, nraw = 0, ndirs = 0, nsi = 0;
+};
+
+}  // namespace
+
+struct WindowState {
+    int L = 0, d = 0, ell = 0, q = 1, kmax = 0, steps = 0;
+    int64_t N = 0, T = 0, ld = 0;
+    uint64_t seed = 0, stream = 0;
+    std::vector<WinLevel> lv;
+    // per-row and simul_iter scratch
+    double* norms = nullptr;
+    int64_t norms_cap = 0;
+    double* h_norms = nullptr;   // pinned
+    double* pi_out = nullptr;
+    double* h_pi = nullptr;      // pinned
+    double *Kd = nullptr, *Q1d = nullptr, *Qd = nullptr, *Zd = nullptr;  // d x kmax
+    double *Y = nullptr, *CQ = nullptr, *CZ = nullptr;                   // 2 ell x kmax
+    double *Wk = nullptr, *Xk = nullptr, *Mk = nullptr, *Uk = nullptr, *lamk = nullptr;
+    double *w1 = nullptr, *w2 = nullptr;
+    double* h_est = nullptr;     // pinned
+    int32_t* info = nullptr;
+    // descriptor arena (device + pinned mirror), reset after every sync
+    char* darena = nullptr;
+    char* harena = nullptr;
+    size_t acap = 0, aoff = 0;
+    // query scratch
+    double *Bq = nullptr, *Eq = nullptr, *Vq = nullptr, *Uq = nullptr, *lamq = nullptr;
+    double *Zs = nullptr, *Ws = nullptr, *S = nullptr, *T2 = nullptr, *Rs = nullptr;
+    double *Xq = nullptr, *Xq2 = nullptr;
+    int32_t* ent = nullptr;
+    int chunk = 0;
+    double *ubuf = nullptr, *part = nullptr, *stats = nullptr;
+    int32_t* ctrl = nullptr;
+};
+
+static const int kWinDmax = 4096;  // LDS of the power-iteration kernel
+
+#define W_TRY(expr)                                                                         \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) return h->device_fail(std::string("window: ") + #expr + ": " + \
+                                                    hipGetErrorString(_e));                 \
+    } while (0)
+
+// Copies descriptors to the device arena (ordered on the stream); returns
+// the device address.
+template <typename D>
+static hipError_t put_desc(sketch_t h, const std::vector<D>& ds, const D** out) {
+    WindowState* w = h->win;
+    const size_t nb = sizeof(D) * ds.size();
+    const size_t off = (w->aoff + 255) / 256 * 256;
+    if (off + nb > w->acap) return hipErrorOutOfMemory;
+    std::memcpy(w->harena + off, ds.data(), nb);
+    hipError_t e = hipMemcpyAsync(w->darena + off, w->harena + off, nb, hipMemcpyHostToDevice, h->stream);
+    w->aoff = off + nb;
+    *out = (const D*)(w->darena + off);
+    return e;
+}
+
+static hipError_t sync_reset(sketch_t h) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    h->win->aoff = 0;
+    return e;
+}
+
+static GemmDesc gd(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
+                   int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0) {
+    GemmDesc g{};
+    g.A = A;
+    g.B = B;
+    g.C = C;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.ldc = ldc;
+    g.ta = ta;
+    g.tb = tb;
+    g.alpha = alpha;
+    g.beta = beta;
+    return g;
+}
+
+static sk_status gemm1(sketch_t h, const GemmDesc& g) {
+    if (g.M <= 0 || g.N <= 0) return SK_OK;
+    std::vector<GemmDesc> v{g};
+    const GemmDesc* dp = nullptr;
+    hipError_t e = put_desc(h, v, &dp);
+    if (e != hipSuccess) return h->device_fail(std::string("window desc: ") + hipGetErrorString(e));
+    e = launch_gemm_desc(dp, 1, g.M, g.N, h->stream);
+    if (e != hipSuccess) return h->device_fail(std::string("window gemm: ") + hipGetErrorString(e));
+    return SK_OK;
+}
+
+static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
+    std::vector<SmallDesc> v{q};
+    const SmallDesc* dp = nullptr;
+    hipError_t e = put_desc(h, v, &dp);
+    if (e == hipSuccess) e = eig ? launch_jacobi_desc(dp, 1, q.n, h->stream) : launch_cholinv_desc(dp, 1, q.n, h->stream);
+    if (e != hipSuccess) return h->device_fail(std::string("window small solve: ") + hipGetErrorString(e));
+    return SK_OK;
+}
+
+// In-place orthonormal basis of K (rows x k, ld kmax): `passes` CholeskyQR
+// passes through Q1d; the result is left in K.
+static sk_status cholqr_d(sketch_t h, double* K, int rows, int k, int passes) {
+    WindowState* w = h->win;
+    const int lk = w->kmax;
+    sk_status rc;
+    for (int p = 0; p < passes; ++p) {
+        if ((rc = gemm1(h, gd(K, lk, true, K, lk, false, w->Wk, lk, k, k, rows)))) return rc;
+        SmallDesc sd{};
+        sd.A = w->Wk;
+        sd.lda = lk;
+        sd.X = w->Xk;
+        sd.ldx = lk;
+        sd.n = k;
+        sd.work = w->w1;
+        if ((rc = small1(h, false, sd))) return rc;
+        if ((rc = gemm1(h, gd(K, lk, false, w->Xk, lk, true, w->Q1d, lk, rows, k, k)))) return rc;
+        W_TRY(hipMemcpyAsync(K, w->Q1d, sizeof(double) * (size_t)rows * lk, hipMemcpyDeviceToDevice, h->stream));
+    }
+    return SK_OK;
+}
+
+static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
+
+// Algorithm "Simultaneous Iteration" on A = C'^T with the test matrix on the
+// d side; leaves Z' = Q U in Zd (d x k) and the k estimates in h_est.
+static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) {
+    WindowState* w = h->win;
+    WinLevel& l = w->lv[(size_t)j];
+    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
+    const int ldc = (int)l.sub->ld;
+    const double* C = level_C(l);
+    sk_status rc;
+    MatGenDesc m{};
+    m.M = w->Kd;
+    m.rows = d;
+    m.cols = k;
+    m.ld = lk;
+    m.seed = w->seed;
+    m.stream = w->stream;
+    m.c2 = (uint64_t)ts;
+    m.c3 = tag;
+    {
+        std::vector<MatGenDesc> v{m};
+        const MatGenDesc* dp = nullptr;
+        W_TRY(put_desc(h, v, &dp));
+        W_TRY(launch_philox_mat(dp, 1, d, k, h->stream));
+    }
+    for (int it = 0; it <= w->q; ++it) {
+        if (it > 0 && (rc = cholqr_d(h, w->Kd, d, k, 1))) return rc;
+        if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->Y, lk, r, k, d)))) return rc;
+        if ((rc = gemm1(h, gd(C, ldc, true, w->Y, lk, false, w->Kd, lk, d, k, r)))) return rc;
+    }
+    if ((rc = cholqr_d(h, w->Kd, d, k, 2))) return rc;  // Kd now holds Q
+    if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->CQ, lk, r, k, d)))) return rc;
+    if ((rc = gemm1(h, gd(w->CQ, lk, true, w->CQ, lk, false, w->Mk, lk, k, k, r)))) return rc;
+    SmallDesc sd{};
+    sd.A = w->Mk;
+    sd.lda = lk;
+    sd.X = w->Uk;
+    sd.ldx = lk;
+    sd.lam = w->lamk;
+    sd.n = k;
+    sd.work = w->w1;
+    sd.work2 = w->w2;
+    sd.info = w->info;
+    if ((rc = small1(h, true, sd))) return rc;
+    if ((rc = gemm1(h, gd(w->Kd, lk, false, w->Uk, lk, false, w->Zd, lk, d, k, k)))) return rc;
+    W_TRY(hipMemcpyAsync(w->h_est, w->lamk, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
+    W_TRY(sync_reset(h));
+    l.nsi += 1;
+    return SK_OK;
+}
+
+// Snapshot (Z, Z^T C'^T C') of the first xi columns of Zd, then the residual
+// C <- C' - C' Z Z^T (Algorithm "AeroSketch: Update" lines 14-16).
+static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
+    WindowState* w = h->win;
+    WinLevel& l = w->lv[(size_t)j];
+    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
+    const int ldc = (int)l.sub->ld;
+    double* C = (double*)level_C(l);
+    if (l.ptail + xi > l.pcap) l.ptail = 0;
+    const int64_t slot = l.ptail;
+    for (const WinEntry& e : l.q)
+        if (e.kind == 0 && e.slot < slot + xi && slot < e.slot + e.xi)
+            return h->device_fail("window: snapshot ring overflow");
+    l.ptail += xi;
+    sk_status rc;
+    if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
+    if ((rc = gemm1(h, gd(w->CZ, lk, true, C, ldc, false, l.Wp + slot * w->ld, (int)w->ld, xi, d, r))))
+        return rc;
+    W_TRY(launch_transpose(w->Zd, lk, l.Zp + slot * w->ld, w->ld, d, xi, h->stream));
+    if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, C, ldc, r, d, xi, -1.0, 1.0)))) return rc;
+    WinEntry e{};
+    e.kind = 0;
+    e.xi = xi;
+    e.s = l.last_t + 1;
+    e.t = ts;
+    e.slot = slot;
+    l.q.push_back(e);
+    l.last_t = ts;
+    l.ndumps += 1;
+    l.ndirs += xi;
+    return SK_OK;
+}
+
+// Doubling loop of Algorithm "AeroSketch: Update" lines 9-17 for level j.
+static sk_status doubling(sketch_t h, int j, int64_t ts) {
+    WindowState* w = h->win;
+    WinLevel& l = w->lv[(size_t)j];
+    int kmax = std::min(w->ell, w->d);
+    if (kmax > l.sub->fill) kmax = (int)l.sub->fill;
+    if (kmax < 1) return SK_OK;
+    int nsteps = (int)std::ceil(std::log2((double)kmax));
+    if (nsteps < 1) nsteps = 1;
+    for (int s = 1; s <= nsteps; ++s) {
+        int k = 1 << s;
+        if (k > kmax) k = kmax;
+        sk_status rc = simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s);
+        if (rc) return rc;
+        if (w->h_est[k - 1] < l.theta || k == kmax) {
+            int xi = 0;
+            while (xi < k && w->h_est[xi] >= l.theta) ++xi;
+            if (xi > 0) {
+                if ((rc = dump(h, j, xi, ts))) return rc;
+            }
+            break;
+        }
+    }
+    return SK_OK;
+}
+
+static void expire(WindowState* w, WinLevel& l, int64_t i) {
+    const size_t cap = 4 * (size_t)w->ell;  // 8 / eps with eps = 2 / ell
+    while (!l.q.empty() && (l.q.size() > cap || l.q.front().t <= i - w->N)) {
+        const WinEntry& e = l.q.front();
+        if (e.t > i - w->N && e.t > l.dropped_t) l.dropped_t = e.t;
+        l.q.pop_front();
+    }
+}
+
+sk_status window_create(sketch_t h) {
+    const sketch_config& cfg = h->cfg;
+    if (cfg.d > kWinDmax) return fail(SK_EINVAL, "sketch_create: window sketches support d <= 4096");
+    WindowState* w = new WindowState();
+    h->win = w;
+    h->ld = round_up(cfg.d, 64);
+    w->d = cfg.d;
+    w->ell = cfg.ell;
+    w->q = cfg.q;
+    w->N = cfg.window_N;
+    w->ld = h->ld;
+    w->seed = cfg.seed;
+    w->stream = cfg.stream_id;
+    w->kmax = std::min(cfg.ell, cfg.d);
+    w->steps = (int)std::ceil(std::log2((double)cfg.d)) + 1;
+    int L = (int)std::ceil(std::log2(cfg.R));
+    w->L = L < 1 ? 1 : L;
+    const double eps = 2.0 / cfg.ell;
+    const int d = w->d, ell = w->ell, lk = w->kmax, n2 = 2 * ell;
+    w->lv.resize((size_t)w->L);
+    for (int j = 0; j < w->L; ++j) {
+        WinLevel& l = w->lv[(size_t)j];
+        l.theta = std::ldexp(1.0, j) * eps * (double)w->N;
+        sketch_config sc = cfg;
+        sc.kind = SK_PERSISTENT;
+        sc.state_dtype = SK_F64;
+        sc.proj_dtype = SK_F64;
+        sc.oversample = 0;
+        sc.stream_id = cfg.stream_id * 64u + (uint64_t)j + 1u;
+        sc.hip_stream = h->stream;
+        sc.use_given_stream = 1;
+        sk_status rc = sketch_create(&sc, &l.sub);
+        if (rc) return rc;
+        l.pcap = (4 * (int64_t)ell + 4) * lk;
+        l.rcap = 4 * (int64_t)ell + 2;
+        W_TRY(h->dalloc((void**)&l.Zp, sizeof(double) * (size_t)l.pcap * w->ld));
+        W_TRY(h->dalloc((void**)&l.Wp, sizeof(double) * (size_t)l.pcap * w->ld));
+        W_TRY(h->dalloc((void**)&l.Rp, sizeof(double) * (size_t)l.rcap * w->ld));
+    }
+    auto A = [&](double** p, size_t n) { return h->dalloc((void**)p, sizeof(double) * (n ? n : 1)); };
+    W_TRY(A(&w->pi_out, (size_t)w->L));
+    W_TRY(A(&w->Kd, (size_t)d * lk));
+    W_TRY(A(&w->Q1d, (size_t)d * lk));
+    W_TRY(A(&w->Qd, (size_t)d * lk));
+    W_TRY(A(&w->Zd, (size_t)d * lk));
+    W_TRY(A(&w->Y, (size_t)n2 * lk));
+    W_TRY(A(&w->CQ, (size_t)n2 * lk));
+    W_TRY(A(&w->CZ, (size_t)n2 * lk));
+    W_TRY(A(&w->Wk, (size_t)lk * lk));
+    W_TRY(A(&w->Xk, (size_t)lk * lk));
+    W_TRY(A(&w->Mk, (size_t)lk * lk));
+    W_TRY(A(&w->Uk, (size_t)lk * lk));
+    W_TRY(A(&w->lamk, (size_t)lk));
+    W_TRY(A(&w->w1, (size_t)lk * lk));
+    W_TRY(A(&w->w2, (size_t)lk * lk));
+    W_TRY(h->dalloc((void**)&w->info, 64));
+    W_TRY(hipMemset(w->info, 0, 64));
+    // query: d x d restore and eigen-solve, snapshot chunks of `chunk` directions
+    const int64_t N32 = round_up(d, 32);
+    w->chunk = 1024;
+    W_TRY(A(&w->Bq, (size_t)d * d));
+    W_TRY(A(&w->Eq, (size_t)(N32 * N32)));
+    W_TRY(A(&w->Vq, (size_t)(N32 * N32)));
+    W_TRY(A(&w->Uq, (size_t)d * d));
+    W_TRY(A(&w->lamq, (size_t)d));
+    W_TRY(A(&w->Zs, (size_t)w->chunk * w->ld));
+    W_TRY(A(&w->Ws, (size_t)w->chunk * w->ld));
+    W_TRY(A(&w->S, (size_t)w->chunk * w->chunk));
+    W_TRY(A(&w->T2, (size_t)d * w->chunk));
+    W_TRY(A(&w->Rs, (size_t)(4 * ell + 2) * w->ld));
+    W_TRY(A(&w->Xq, (size_t)ell * w->ld));
+    W_TRY(A(&w->Xq2, (size_t)ell * w->ld));
+    W_TRY(h->dalloc((void**)&w->ent, sizeof(int32_t) * (size_t)w->chunk));
+    W_TRY(A(&w->ubuf, (size_t)(N32 / 32) * 1024));
+    W_TRY(A(&w->part, 256));
+    W_TRY(A(&w->stats, 16));
+    W_TRY(h->dalloc((void**)&w->ctrl, 64 * sizeof(int32_t)));
+    w->acap = 1 << 20;
+    W_TRY(h->dalloc((void**)&w->darena, w->acap));
+    W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
+    W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
+    W_TRY(hipHostMalloc((void**)&w->h_est, sizeof(double) * (size_t)lk, hipHostMallocDefault));
+    return SK_OK;
+}
+
+void window_destroy(sketch_t h) {
+    WindowState* w = h->win;
+    if (!w) return;
+    for (WinLevel& l : w->lv)
+        if (l.sub) sketch_destroy(l.sub);
+    if (w->harena) (void)hipHostFree(w->harena);
+    if (w->h_pi) (void)hipHostFree(w->h_pi);
+    if (w->h_est) (void)hipHostFree(w->h_est);
+    if (w->h_norms) (void)hipHostFree(w->h_norms);
+    delete w;
+    h->win = nullptr;
+}
+
+sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int dtype) {
+    WindowState* w = h->win;
+    const int d = w->d;
+    if (n > w->norms_cap) {
+        W_TRY(hipStreamSynchronize(h->stream));
+        int64_t cap = std::max<int64_t>(n, 4096);
+        if (w->h_norms) (void)hipHostFree(w->h_norms);
+        w->h_norms = nullptr;
+        W_TRY(h->dalloc((void**)&w->norms, sizeof(double) * (size_t)cap));
+        W_TRY(hipHostMalloc((void**)&w->h_norms, sizeof(double) * (size_t)cap, hipHostMallocDefault));
+        w->norms_cap = cap;
+    }
+    W_TRY(launch_rownorm(rows, ld, dtype, n, d, w->norms, h->stream));
+    W_TRY(hipMemcpyAsync(w->h_norms, w->norms, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+    W_TRY(sync_reset(h));
+    const int64_t es = dtype_size(dtype);
+    std::vector<sketch_t> owners;
+    std::vector<Task> tasks;
+    std::vector<PiDesc> pis;
+    std::vector<int> pj;
+    for (int64_t e = 0; e < n; ++e) {
+        const int64_t i = w->T + 1;
+        w->T = i;
+        const char* row = rows + e * ld * es;
+        owners.clear();
+        tasks.clear();
+        pis.clear();
+        pj.clear();
+        for (int j = 0; j < w->L; ++j) {
+            WinLevel& l = w->lv[(size_t)j];
+            expire(w, l, i);
+            if (w->h_norms[e] >= l.theta) {
+                const int64_t slot = l.rtail;
+                l.rtail = (l.rtail + 1) % l.rcap;
+                W_TRY(launch_rows_to_f64(row, ld, dtype, l.Rp + slot * w->ld, w->ld, 1, d, h->stream));
+                WinEntry en{};
+                en.kind = 1;
+                en.s = l.last_t + 1;
+                en.t = i;
+                en.slot = slot;
+                l.q.push_back(en);
+                l.last_t = i;
+                l.nraw += 1;
+            } else {
+                plan_rows(l.sub, 1, row, ld, dtype, nullptr, nullptr, nullptr, owners, tasks);
+                pj.push_back(j);
+            }
+        }
+        if (!tasks.empty()) {
+            sk_status rc = execute_batched(h, owners, tasks, dtype);
+            if (rc) return rc;
+        }
+        if (pj.empty()) continue;
+        for (int j : pj) {
+            const WinLevel& l = w->lv[(size_t)j];
+            PiDesc p{};
+            p.C = level_C(l);
+            p.out = w->pi_out + j;
+            p.ldc = l.sub->ld;
+            p.r = (int)l.sub->fill;
+            p.d = d;
+            p.steps = w->steps;
+            p.seed = w->seed;
+            p.stream = w->stream;
+            p.c2 = (uint64_t)i;
+            p.c3 = 0x100u + (uint64_t)j;
+            pis.push_back(p);
+        }
+        const PiDesc* dp = nullptr;
+        W_TRY(put_desc(h, pis, &dp));
+        W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, h->stream));
+        W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
+        W_TRY(sync_reset(h));
+        for (int j : pj) {
+            if (w->h_pi[j] >= w->lv[(size_t)j].theta / 2.0) {
+                sk_status rc = doubling(h, j, i);
+                if (rc) return rc;
+            }
+        }
+    }
+    return SK_OK;
+}
+
+sk_status window_advance_impl(sketch_t h, int64_t t_now) {
+    WindowState* w = h->win;
+    if (t_now < w->T) return fail(SK_ESTATE, "window_advance: time moves backwards");
+    w->T = t_now;
+    for (WinLevel& l : w->lv)
+        while (!l.q.empty() && l.q.front().t <= t_now - w->N) l.q.pop_front();
+    return SK_OK;
+}
+
+// eigen-decomposition of the d x d matrix Bq into Uq / lamq
+static sk_status eig_d(sketch_t h) {
+    WindowState* w = h->win;
+    const int d = w->d;
+    if (d <= jacobi_lds_max()) {
+        SmallDesc sd{};
+        sd.A = w->Bq;
+        sd.lda = d;
+        sd.X = w->Uq;
+        sd.ldx = d;
+        sd.lam = w->lamq;
+        sd.n = d;
+        sd.work = w->Eq;
+        sd.work2 = w->Vq;
+        sd.info = w->info;
+        return small1(h, true, sd);
+    }
+    CoopEig a{};
+    a.Ain = w->Bq;
+    a.ldin = d;
+    a.n = d;
+    a.A = w->Eq;
+    a.V = w->Vq;
+    a.U = w->Uq;
+    a.lu = d;
+    a.lam = w->lamq;
+    a.info = w->info;
+    a.ubuf = w->ubuf;
+    a.part = w->part;
+    a.ctrl = w->ctrl;
+    a.stats = w->stats;
+    a.bar = (uint32_t*)(w->ctrl + 8);
+    W_TRY(launch_jacobi_coop(a, h->stream));
+    return SK_OK;
+}
+
+sk_status window_query(sketch_t h, const double** out) {
+    WindowState* w = h->win;
+    const int d = w->d, ell = w->ell;
+    const int64_t T = w->T, N = w->N, ld = w->ld;
+    int j = w->L - 1;
+    for (int c = 0; c < w->L; ++c)
+        if (w->lv[(size_t)c].dropped_t <= T - N) {
+            j = c;
+            break;
+        }
+    WinLevel& l = w->lv[(size_t)j];
+    const double* C = level_C(l);
+    const int r = (int)l.sub->fill;
+    sk_status rc;
+    W_TRY(sync_reset(h));
+    // B = C^T C + sum over in-window snapshots of Z W + W^T Z^T - Z (W Z) Z^T
+    if ((rc = gemm1(h, gd(C, (int)l.sub->ld, true, C, (int)l.sub->ld, false, w->Bq, d, d, d, r)))) return rc;
+    std::vector<const WinEntry*> snaps, raws;
+    for (const WinEntry& e : l.q) {
+        if (!(T - N < e.t && e.t <= T)) continue;
+        (e.kind == 0 ? snaps : raws).push_back(&e);
+    }
+    size_t si = 0;
+    std::vector<int32_t> ent;
+    while (si < snaps.size()) {
+        int D = 0;
+        ent.clear();
+        for (; si < snaps.size() && D + snaps[si]->xi <= w->chunk; ++si) {
+            const WinEntry& e = *snaps[si];
+            W_TRY(hipMemcpyAsync(w->Zs + (int64_t)D * ld, l.Zp + e.slot * ld, sizeof(double) * (size_t)e.xi * ld,
+                                 hipMemcpyDeviceToDevice, h->stream));
+            W_TRY(hipMemcpyAsync(w->Ws + (int64_t)D * ld, l.Wp + e.slot * ld, sizeof(double) * (size_t)e.xi * ld,
+                                 hipMemcpyDeviceToDevice, h->stream));
+            for (int c = 0; c < e.xi; ++c) ent.push_back((int32_t)si);
+            D += e.xi;
+        }
+        W_TRY(hipMemcpyAsync(w->ent, ent.data(), sizeof(int32_t) * ent.size(), hipMemcpyHostToDevice, h->stream));
+        const int li = (int)ld;
+        if ((rc = gemm1(h, gd(w->Zs, li, true, w->Ws, li, false, w->Bq, d, d, d, D, 1.0, 1.0)))) return rc;
+        if ((rc = gemm1(h, gd(w->Ws, li, true, w->Zs, li, false, w->Bq, d, d, d, D, 1.0, 1.0)))) return rc;
+        if ((rc = gemm1(h, gd(w->Ws, li, false, w->Zs, li, true, w->S, w->chunk, D, D, d)))) return rc;
+        W_TRY(launch_blockmask(w->S, w->chunk, D, w->ent, h->stream));
+        if ((rc = gemm1(h, gd(w->Zs, li, true, w->S, w->chunk, false, w->T2, w->chunk, d, D, D)))) return rc;
+        if ((rc = gemm1(h, gd(w->T2, w->chunk, false, w->Zs, li, false, w->Bq, d, d, d, D, -1.0, 1.0)))) return rc;
+        W_TRY(sync_reset(h));  // the host entry list of this chunk is reused
+    }
+    // eigen-decomposition and the shrink by lambda_ell (query lines 5-7)
+    if ((rc = eig_d(h))) return rc;
+    W_TRY(launch_shrink_rows(w->Uq, d, w->lamq, d, ell, w->Xq, ld, d, h->stream));
+    if (!raws.empty()) {
+        // FD over [B_hat; raw rows]: f_ell of B_hat^T B_hat + R^T R
+        int nr = 0;
+        for (const WinEntry* e : raws) {
+            W_TRY(hipMemcpyAsync(w->Rs + (int64_t)nr * ld, l.Rp + e->slot * ld, sizeof(double) * (size_t)ld,
+                                 hipMemcpyDeviceToDevice, h->stream));
+            ++nr;
+        }
+        const int li = (int)ld;
+        if ((rc = gemm1(h, gd(w->Xq, li, true, w->Xq, li, false, w->Bq, d, d, d, ell)))) return rc;
+        if ((rc = gemm1(h, gd(w->Rs, li, true, w->Rs, li, false, w->Bq, d, d, d, nr, 1.0, 1.0)))) return rc;
+        if ((rc = eig_d(h))) return rc;
+        W_TRY(launch_shrink_rows(w->Uq, d, w->lamq, d, ell, w->Xq, ld, d, h->stream));
+    }
+    W_TRY(sync_reset(h));
+    for (const WinLevel& lv : w->lv) {
+        int32_t inf[2] = {0, 0};
+        W_TRY(hipMemcpy(inf, lv.sub->host.info, sizeof(inf), hipMemcpyDeviceToHost));
+        if (inf[0] != 0) return h->device_fail("window: FD reduce eigen-solver did not converge");
+    }
+    *out = w->Xq;
+    return SK_OK;
+}
+
+const int32_t* window_info_ptr(sketch_t h) { return h->win->info; }
+int64_t window_time(sketch_t h) { return h->win->T; }
+int32_t window_levels(sketch_t h) { return h->win->L; }
+
+sk_status window_level_stats(sketch_t h, int32_t level, int64_t* st) {
+    WindowState* w = h->win;
+    if (level < 0 || level >= w->L) return fail(SK_EINVAL, "window_level_stats: bad level");
+    const WinLevel& l = w->lv[(size_t)level];
+    st[0] = l.ndumps;
+    st[1] = l.nraw;
+    st[2] = l.ndirs;
+    st[3] = l.sub->fill;
+    st[4] = (int64_t)l.q.size();
+    st[5] = l.sub->shrinks;
+    return SK_OK;
+}

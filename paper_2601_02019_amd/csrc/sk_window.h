@@ -15,3 +15,4 @@ void window_destroy(sketch_t h);
 const int32_t* window_info_ptr(sketch_t h);
 int64_t window_time(sketch_t h);
 int32_t window_levels(sketch_t h);
+sk_status window_level_stats(sketch_t h, int32_t level, int64_t* st);

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2601_02019_amd", "libsketch.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:sk_status|const char\*|int64_t)\s+(\w+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:SK_EXPORT\s+)?(?:sk_status|const char\*|int64_t)\s+(\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
