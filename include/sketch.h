@@ -176,6 +176,80 @@ SK_EXPORT int64_t sketch_memory_in_use(void);
 SK_EXPORT sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
                               int32_t count, int32_t dtype);
 
+/* ---- serving ---------------------------------------------------------------
+ * A request loop over many resident stream sketches on one GPU: streams are
+ * admitted while the device-memory budget allows (others wait, first come
+ * first served); bursts of rows are submitted with their arrival time; each
+ * server_tick polls finished work, admits waiting streams and launches one
+ * batched update (sketch_update_batch) for every stream that has pending
+ * rows, so bursts that arrive while the GPU is busy join the next tick while
+ * the host plans it.  A burst is complete -- its rows are queryable -- when
+ * the batch holding its last rows has finished on the device.  Not
+ * thread-safe: one driver thread per server. */
+typedef struct sk_server_s* sk_server_t;
+
+typedef struct {
+    int32_t device;
+    int32_t max_inflight;         /* ticks in flight at once (>= 1; default 2)   */
+    int64_t memory_budget;        /* device bytes for admitted streams, 0 = none */
+    int64_t max_rows_per_tick;    /* rows of one burst per tick, 0 = unlimited   */
+    void* hip_stream;             /* stream for all work (see use_given_stream)  */
+    double (*clock)(void* ctx);   /* seconds; NULL: steady clock + HIP events    */
+    void* clock_ctx;
+    int32_t use_given_stream;     /* 1: hip_stream as given, also NULL (the null
+                                     stream); 0: NULL means a server-owned one   */
+} sk_server_config;
+
+typedef struct {
+    int64_t ticket;
+    int64_t stream;               /* server stream id                            */
+    int64_t rows;
+    double arrival;               /* as submitted                                */
+    double launched;              /* clock when its first rows were launched     */
+    double done;                  /* clock when its last rows finished           */
+} sk_completion;
+
+typedef struct {
+    int64_t admitted, waiting, closed;
+    int64_t bytes_in_use;
+    int64_t ticks, batches, pending_bursts, inflight;
+    int64_t rows_done;
+} sk_server_stats;
+
+SK_EXPORT sk_status server_config_init(sk_server_config* cfg);
+SK_EXPORT sk_status server_create(const sk_server_config* cfg, sk_server_t* out);
+/* Registers a stream with the given sketch configuration (its stream and
+ * device fields are overridden by the server's).  The stream is admitted at
+ * once if the budget allows, else it waits; *id is valid either way and
+ * bursts may be submitted to a waiting stream. */
+SK_EXPORT sk_status server_open(sk_server_t s, const sketch_config* cfg, int64_t* id);
+/* Queues a burst of n device rows (dtype, leading dimension = the stream's
+ * d).  The rows must stay valid until the burst completes. */
+SK_EXPORT sk_status server_submit(sk_server_t s, int64_t id, const void* rows, int64_t n,
+                                  int32_t dtype, double arrival, int64_t* ticket);
+/* One scheduling step (non-blocking unless max_inflight ticks are on the
+ * device).  *launched receives the number of bursts that got rows. */
+SK_EXPORT sk_status server_tick(sk_server_t s, int32_t* launched);
+/* Completed bursts since the last poll (up to max). */
+SK_EXPORT sk_status server_poll(sk_server_t s, sk_completion* out, int32_t max, int32_t* n);
+/* Runs ticks until every submitted burst of admitted streams has completed. */
+SK_EXPORT sk_status server_drain(sk_server_t s);
+/* Query of an admitted stream (blocks). */
+SK_EXPORT sk_status server_query(sk_server_t s, int64_t id, void* B_out, int32_t dtype,
+                                 int32_t on_device);
+/* Ends a stream.  New bursts are refused at once; queued bursts still run,
+ * and the sketch is released when they have completed (a waiting stream is
+ * dropped with its bursts, which are reported with done = -1).  A released
+ * sketch's memory is reused for the next admitted stream of the same shape
+ * (d, ell, kind, dtypes, q, oversample) or freed when a waiting stream of
+ * another shape needs the budget. */
+SK_EXPORT sk_status server_close(sk_server_t s, int64_t id);
+SK_EXPORT sk_status server_stats(sk_server_t s, sk_server_stats* out);
+/* The server's clock in seconds (the fake clock when one is configured);
+ * arrival times are given in this time base. */
+SK_EXPORT double server_now(sk_server_t s);
+SK_EXPORT sk_status server_destroy(sk_server_t s);
+
 /* ---- profiling -------------------------------------------------------------
  * Per-stage GPU time of the pipeline, measured with HIP events recorded on
  * the sketch's stream around every launch of the enabled stages.  Disabled by

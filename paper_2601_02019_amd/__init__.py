@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     SK_BF16, SK_EDEVICE, SK_EINVAL, SK_ENOMEM, SK_ESHAPE, SK_ESTATE, SK_EUNSUPPORTED, SK_F32,
     SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
-    sketch_config, sketch_info_t,
+    sk_completion, sk_server_config, sk_server_stats, sketch_config, sketch_info_t,
 )
 
 _TORCH_DT = {torch.float64: SK_F64, torch.float32: SK_F32, torch.bfloat16: SK_BF16}
@@ -189,21 +189,185 @@ def sketch_profile_read(h):
     return {buf[i].name.decode(): (buf[i].calls, buf[i].total_ms) for i in range(min(n.value, 64))}
 
 
+def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", proj_dtype="f64", q=1,
+                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0):
+    cfg = sketch_config_init()
+    cfg.d, cfg.ell = d, ell
+    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW}[kind]
+    cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
+    cfg.state_dtype = _dt(state_dtype)
+    cfg.proj_dtype = _dt(proj_dtype)
+    cfg.q, cfg.oversample = q, oversample
+    cfg.window_N, cfg.R = int(window_N), float(R)
+    cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
+    return cfg
+
+
+# ------------------------------------------------------------------ serving
+def server_config_init():
+    cfg = sk_server_config()
+    _lib.check(_lib.load().server_config_init(ctypes.byref(cfg)), "server_config_init")
+    return cfg
+
+
+def server_create(cfg):
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().server_create(ctypes.byref(cfg), ctypes.byref(h)), "server_create")
+    return h
+
+
+def server_open(s, cfg):
+    sid = ctypes.c_int64()
+    _lib.check(_lib.load().server_open(s, ctypes.byref(cfg), ctypes.byref(sid)), "server_open")
+    return sid.value
+
+
+def server_submit(s, sid, rows, arrival):
+    assert isinstance(rows, torch.Tensor) and rows.is_cuda and rows.is_contiguous() and rows.dim() == 2
+    t = ctypes.c_int64()
+    _lib.check(_lib.load().server_submit(s, sid, ctypes.c_void_p(rows.data_ptr()), rows.shape[0],
+                                         _TORCH_DT[rows.dtype], float(arrival), ctypes.byref(t)),
+               "server_submit")
+    return t.value
+
+
+def server_tick(s):
+    n = ctypes.c_int32()
+    _lib.check(_lib.load().server_tick(s, ctypes.byref(n)), "server_tick")
+    return n.value
+
+
+_POLL_FIELDS = [f for f, _ in sk_completion._fields_]
+
+
+def server_poll(s, max_n=1024, buf=None):
+    if buf is None:
+        buf = (sk_completion * max_n)()
+    n = ctypes.c_int32()
+    _lib.check(_lib.load().server_poll(s, buf, len(buf), ctypes.byref(n)), "server_poll")
+    return [{f: getattr(buf[i], f) for f in _POLL_FIELDS} for i in range(n.value)]
+
+
+def server_drain(s):
+    _lib.check(_lib.load().server_drain(s), "server_drain")
+
+
+def server_query(s, sid, out):
+    assert isinstance(out, torch.Tensor) and out.is_contiguous()
+    _lib.check(_lib.load().server_query(s, sid, ctypes.c_void_p(out.data_ptr()), _TORCH_DT[out.dtype],
+                                        int(out.is_cuda)), "server_query")
+    return out
+
+
+def server_close(s, sid):
+    _lib.check(_lib.load().server_close(s, sid), "server_close")
+
+
+def server_stats(s):
+    st = sk_server_stats()
+    _lib.check(_lib.load().server_stats(s, ctypes.byref(st)), "server_stats")
+    return {f: getattr(st, f) for f, _ in sk_server_stats._fields_}
+
+
+def server_now(s):
+    return _lib.load().server_now(s)
+
+
+def server_destroy(s):
+    _lib.check(_lib.load().server_destroy(s), "server_destroy")
+
+
+class Server:
+    """Owning wrapper of a serving loop.  Keeps each submitted tensor alive
+    until its burst has been reported complete by ``poll``.  ``clock``: an
+    optional Python callable returning seconds (a fake clock for tests).
+    ``stream``: a torch stream for all of the server's work (default: the
+    current one), or False for a stream of the server's own."""
+
+    def __init__(self, device=0, max_inflight=2, memory_budget=0, max_rows_per_tick=0, clock=None,
+                 stream=None):
+        cfg = server_config_init()
+        cfg.device, cfg.max_inflight = device, max_inflight
+        cfg.memory_budget, cfg.max_rows_per_tick = int(memory_budget), int(max_rows_per_tick)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        if stream is not False:
+            # all work on the torch stream, ordered after the tensors' producers
+            cfg.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+            cfg.use_given_stream = 1
+        self._clock = None
+        if clock is not None:
+            self._clock = _lib.CLOCK_FN(lambda ctx: float(clock()))
+            cfg.clock = self._clock
+        self.device = device
+        self.handle = server_create(cfg)
+        self._rows = {}
+        self._shape = {}
+        self._pollbuf = (sk_completion * 1024)()
+
+    def open(self, d, ell, **kw):
+        sid = server_open(self.handle, make_config(d, ell, device=self.device, **kw))
+        self._shape[sid] = (d, ell)
+        return sid
+
+    def submit(self, sid, rows, arrival=None):
+        if arrival is None:
+            arrival = self.now()
+        t = server_submit(self.handle, sid, rows, arrival)
+        self._rows[t] = rows
+        return t
+
+    def tick(self):
+        return server_tick(self.handle)
+
+    def poll(self):
+        out = []
+        while True:
+            got = server_poll(self.handle, buf=self._pollbuf)
+            for c in got:
+                self._rows.pop(c["ticket"], None)
+            out.extend(got)
+            if len(got) < len(self._pollbuf):
+                return out
+
+    def drain(self):
+        server_drain(self.handle)
+
+    def query(self, sid, dtype=torch.float64):
+        d, ell = self._shape[sid]
+        out = torch.empty((ell, d), dtype=dtype, device=f"cuda:{self.device}")
+        return server_query(self.handle, sid, out)
+
+    def close_stream(self, sid):
+        server_close(self.handle, sid)
+
+    def stats(self):
+        return server_stats(self.handle)
+
+    def now(self):
+        return server_now(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            server_destroy(self.handle)
+            self.handle = None
+            self._rows.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Sketch:
     """Owning wrapper of one sketch handle."""
 
     def __init__(self, d, ell, kind="persistent", shrink="exact", state_dtype="f64",
                  proj_dtype="f64", q=1, oversample=0, window_N=0, R=1.0, seed=0, stream_id=0,
                  device=0, stream=None):
-        cfg = sketch_config_init()
-        cfg.d, cfg.ell = d, ell
-        cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW}[kind]
-        cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
-        cfg.state_dtype = _dt(state_dtype)
-        cfg.proj_dtype = _dt(proj_dtype)
-        cfg.q, cfg.oversample = q, oversample
-        cfg.window_N, cfg.R = int(window_N), float(R)
-        cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
+        cfg = make_config(d, ell, kind, shrink, state_dtype, proj_dtype, q, oversample, window_N, R,
+                          seed, stream_id, device)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         if stream is not False:

@@ -44,6 +44,29 @@ class sketch_stage_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("calls", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+CLOCK_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p)
+
+
+class sk_server_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
+        ("max_rows_per_tick", ctypes.c_int64), ("hip_stream", ctypes.c_void_p), ("clock", CLOCK_FN),
+        ("clock_ctx", ctypes.c_void_p), ("use_given_stream", ctypes.c_int32),
+    ]
+
+
+class sk_completion(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64), ("stream", ctypes.c_int64), ("rows", ctypes.c_int64),
+        ("arrival", ctypes.c_double), ("launched", ctypes.c_double), ("done", ctypes.c_double),
+    ]
+
+
+class sk_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("admitted", "waiting", "closed", "bytes_in_use", "ticks",
+                                               "batches", "pending_bursts", "inflight", "rows_done")]
+
+
 SK_STAGE = {"ingest": 1 << 0, "omega": 1 << 1, "gram": 1 << 2, "project": 1 << 3, "cholqr": 1 << 4,
             "core_gemm": 1 << 5, "eig": 1 << 6, "threshold": 1 << 7, "rebuild": 1 << 8}
 SK_STAGE_ALL = 0x1FF
@@ -53,6 +76,8 @@ EXPORTS = [
     "window_advance", "sketch_merge", "sketch_merge_tree", "sketch_sync", "sketch_destroy",
     "sketch_last_error", "sketch_info", "sketch_set_memory_budget", "sketch_memory_in_use",
     "sketch_update_batch", "sketch_profile_enable", "sketch_profile_read", "window_stats",
+    "server_config_init", "server_create", "server_open", "server_submit", "server_tick", "server_poll",
+    "server_drain", "server_query", "server_close", "server_stats", "server_now", "server_destroy",
 ]
 
 _lib = None
@@ -88,8 +113,21 @@ def load():
     lib.window_stats.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.sketch_profile_enable.argtypes = [vp, ctypes.c_uint32]
     lib.sketch_profile_read.argtypes = [vp, ctypes.POINTER(sketch_stage_time), i32, ctypes.POINTER(i32)]
+    lib.server_config_init.argtypes = [ctypes.POINTER(sk_server_config)]
+    lib.server_create.argtypes = [ctypes.POINTER(sk_server_config), ctypes.POINTER(vp)]
+    lib.server_open.argtypes = [vp, ctypes.POINTER(sketch_config), ctypes.POINTER(i64)]
+    lib.server_submit.argtypes = [vp, i64, vp, i64, i32, ctypes.c_double, ctypes.POINTER(i64)]
+    lib.server_tick.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.server_poll.argtypes = [vp, ctypes.POINTER(sk_completion), i32, ctypes.POINTER(i32)]
+    lib.server_drain.argtypes = [vp]
+    lib.server_query.argtypes = [vp, i64, vp, i32, i32]
+    lib.server_close.argtypes = [vp, i64]
+    lib.server_stats.argtypes = [vp, ctypes.POINTER(sk_server_stats)]
+    lib.server_now.argtypes = [vp]
+    lib.server_now.restype = ctypes.c_double
+    lib.server_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("sketch_last_error", "sketch_memory_in_use"):
+        if name not in ("sketch_last_error", "sketch_memory_in_use", "server_now"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

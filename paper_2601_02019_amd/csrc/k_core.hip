@@ -173,7 +173,7 @@ template <bool LDS>
 __global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int sx, int lds_max) {
     extern __shared__ double lds[];
     const Task& t = tasks[blockIdx.z];
-    if (t.kind != T_SHRINK_RAND) return;
+    if (t.kind != T_SHRINK_RAND || (t.flags & TF_COOP_CHOL)) return;
     const SkDev* s = t.s;
     const int n = s->k;
     if (LDS != (n <= lds_max)) return;
@@ -204,31 +204,37 @@ __device__ __forceinline__ int rr_player(int slot, int step, int ne) {
 }
 
 // Jacobi eigen-decomposition of one n x n symmetric matrix by the whole
-// workgroup.  A: n x n work matrix (LDS or global), V: n x n rotations,
-// U (ld lu) / lam: sorted output; info[0] counts non-converged solves,
-// info[1] keeps the largest sweep count.
-__device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, double* V, double* U,
-                            int lu, double* lam, int* info) {
+// workgroup.  A: n x n work matrix (LDS or global).  The rotations are
+// accumulated in Vt = V^T (n x n, rows = eigenvectors), so that a pair's
+// update rotates two contiguous rows; Vt lives in LDS after A when both fit
+// (vt_lds), else in the global scratch Vg.  U (ld lu) / lam: sorted output;
+// info[0] counts non-converged solves, info[1] keeps the largest sweep count.
+__device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, double* Vg, double* U,
+                            int lu, double* lam, int* info, double* vt_lds) {
     const int la = n;
-    const int lv = n;
-
-    __shared__ double cs_c[2][256], cs_s[2][256];
-    __shared__ int pp[2][256], qq[2][256];
+    double* Vt = vt_lds ? vt_lds : Vg;
+    __shared__ double cs_c[256], cs_s[256];
+    __shared__ int pp[256], qq[256];
     __shared__ int rot_count[2];
     __shared__ double red[32];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int ne = (n + 1) & ~1;
     const int np = ne / 2;
+    // threads per row-pair of A (a power of two <= np) and per pair of Vt rows
+    int tpr = 1;
+    while (tpr * 2 <= np && tpr * 2 * np <= nth * 2 && tpr < 64) tpr *= 2;
+    if (tpr > nth) tpr = nth;
+    int tpv = 1;
+    while (tpv * 2 <= n && tpv < 64) tpv *= 2;
 
     double loc = 0.0;
     for (int e = tid; e < n * n; e += nth) {
-        const int i = e / n, j = e % n;
+        const int i = e / n, j = e - (e / n) * n;
         const double v = 0.5 * (Ain[(int64_t)i * ldin + j] + Ain[(int64_t)j * ldin + i]);
         A[(int64_t)i * la + j] = v;
-        V[(int64_t)i * lv + j] = (i == j) ? 1.0 : 0.0;
+        Vt[(int64_t)i * n + j] = (i == j) ? 1.0 : 0.0;
         loc += v * v;
     }
-    // block reduction of ||A||_F^2 in a fixed order
     for (int off = 32; off > 0; off >>= 1) loc += __shfl_down(loc, off, 64);
     if ((tid & 63) == 0) red[tid >> 6] = loc;
     if (tid < 2) rot_count[tid] = 0;
@@ -244,7 +250,6 @@ __device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, doubl
         if (tid == 0) rot_count[sb] = 0;
         __syncthreads();
         for (int step = 0; step < ne - 1; ++step) {
-            const int b = step & 1;
             for (int m = tid; m < np; m += nth) {
                 int p = rr_player(m, step, ne), q = rr_player(ne - 1 - m, step, ne);
                 if (p > q) {
@@ -258,61 +263,60 @@ __device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, doubl
                     const double app = A[(int64_t)p * la + p];
                     const double aqq = A[(int64_t)q * la + q];
                     if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        // symmetric Schur rotation (Golub & Van Loan 8.5.2), tan from the hypot
+                        const double dd = aqq - app, bb = 2.0 * apq;
+                        const double hyp = sqrt(dd * dd + bb * bb);
+                        const double tt = (dd >= 0.0 ? bb : -bb) / (fabs(dd) + hyp);
                         c = 1.0 / sqrt(1.0 + tt * tt);
                         sn = tt * c;
-                        atomicAdd(&rot_count[sb], 1);
+                        rot_count[sb] = 1;  // any rotation: another sweep follows
                     }
                 }
-                cs_c[b][m] = c;
-                cs_s[b][m] = sn;
-                pp[b][m] = p;
-                qq[b][m] = q;
+                cs_c[m] = c;
+                cs_s[m] = sn;
+                pp[m] = p;
+                qq[m] = q;
             }
             __syncthreads();
-            // A <- J^T A J on the 2 x 2 blocks (m1, m2), m1 <= m2; mirrors written
-            const int nblk = np * (np + 1) / 2;
-            for (int e = tid; e < nblk; e += nth) {
-                int m1, m2;
-                tri_index(e, m1, m2);
-                const int p1 = pp[b][m1], q1 = qq[b][m1], p2 = pp[b][m2], q2 = qq[b][m2];
-                const double c1 = cs_c[b][m1], s1 = cs_s[b][m1], c2 = cs_c[b][m2], s2 = cs_s[b][m2];
-                const bool hq1 = q1 < n, hq2 = q2 < n;
-                const double a00 = A[(int64_t)p1 * la + p2];
-                const double a01 = hq2 ? A[(int64_t)p1 * la + q2] : 0.0;
-                const double a10 = hq1 ? A[(int64_t)q1 * la + p2] : 0.0;
-                const double a11 = (hq1 && hq2) ? A[(int64_t)q1 * la + q2] : 0.0;
-                // rows: [p1; q1] <- [c1 -s1; s1 c1] [p1; q1]
-                const double r00 = c1 * a00 - s1 * a10, r01 = c1 * a01 - s1 * a11;
-                const double r10 = s1 * a00 + c1 * a10, r11 = s1 * a01 + c1 * a11;
-                // columns: [p2 q2] <- [p2 q2] [c2 s2; -s2 c2]
-                double n00 = r00 * c2 - r01 * s2, n01 = r00 * s2 + r01 * c2;
-                double n10 = r10 * c2 - r11 * s2, n11 = r10 * s2 + r11 * c2;
-                if (m1 == m2) {
-                    n01 = 0.0;
-                    n10 = 0.0;
-                }
-                A[(int64_t)p1 * la + p2] = n00;
-                if (hq2) A[(int64_t)p1 * la + q2] = n01;
-                if (hq1) A[(int64_t)q1 * la + p2] = n10;
-                if (hq1 && hq2) A[(int64_t)q1 * la + q2] = n11;
-                if (m1 != m2) {
-                    A[(int64_t)p2 * la + p1] = n00;
-                    if (hq2) A[(int64_t)q2 * la + p1] = n01;
-                    if (hq1) A[(int64_t)p2 * la + q1] = n10;
-                    if (hq1 && hq2) A[(int64_t)q2 * la + q1] = n11;
+            // A <- J^T A J: every 2 x 2 block (m1, m2) by one thread, no mirrors;
+            // a thread walks one m1 and strided m2, keeping m1's rotation in registers
+            for (int m1 = tid / tpr; m1 < np; m1 += nth / tpr) {
+                const int p1 = pp[m1], q1 = qq[m1];
+                const double c1 = cs_c[m1], s1 = cs_s[m1];
+                const bool hq1 = q1 < n;
+                for (int m2 = tid % tpr; m2 < np; m2 += tpr) {
+                    const int p2 = pp[m2], q2 = qq[m2];
+                    const double c2 = cs_c[m2], s2 = cs_s[m2];
+                    const bool hq2 = q2 < n;
+                    const double a00 = A[(int64_t)p1 * la + p2];
+                    const double a01 = hq2 ? A[(int64_t)p1 * la + q2] : 0.0;
+                    const double a10 = hq1 ? A[(int64_t)q1 * la + p2] : 0.0;
+                    const double a11 = (hq1 && hq2) ? A[(int64_t)q1 * la + q2] : 0.0;
+                    const double r00 = c1 * a00 - s1 * a10, r01 = c1 * a01 - s1 * a11;
+                    const double r10 = s1 * a00 + c1 * a10, r11 = s1 * a01 + c1 * a11;
+                    double n00 = r00 * c2 - r01 * s2, n01 = r00 * s2 + r01 * c2;
+                    double n10 = r10 * c2 - r11 * s2, n11 = r10 * s2 + r11 * c2;
+                    if (m1 == m2) {
+                        n01 = 0.0;
+                        n10 = 0.0;
+                    }
+                    A[(int64_t)p1 * la + p2] = n00;
+                    if (hq2) A[(int64_t)p1 * la + q2] = n01;
+                    if (hq1) A[(int64_t)q1 * la + p2] = n10;
+                    if (hq1 && hq2) A[(int64_t)q1 * la + q2] = n11;
                 }
             }
-            // V <- V J
-            for (int e = tid; e < n * np; e += nth) {
-                const int i = e / np, mm = e % np;
-                const int p = pp[b][mm], q = qq[b][mm];
+            // Vt <- J^T Vt: rows p and q of every pair, contiguous along the row
+            for (int mm = tid / tpv; mm < np; mm += nth / tpv) {
+                const int p = pp[mm], q = qq[mm];
                 if (q >= n) continue;
-                const double c = cs_c[b][mm], sn = cs_s[b][mm];
-                const double vp = V[(int64_t)i * lv + p], vq = V[(int64_t)i * lv + q];
-                V[(int64_t)i * lv + p] = c * vp - sn * vq;
-                V[(int64_t)i * lv + q] = sn * vp + c * vq;
+                const double cc = cs_c[mm], sn = cs_s[mm];
+                if (cc == 1.0 && sn == 0.0) continue;
+                for (int c = tid % tpv; c < n; c += tpv) {
+                    const double vp = Vt[(int64_t)p * n + c], vq = Vt[(int64_t)q * n + c];
+                    Vt[(int64_t)p * n + c] = cc * vp - sn * vq;
+                    Vt[(int64_t)q * n + c] = sn * vp + cc * vq;
+                }
             }
             __syncthreads();
         }
@@ -328,7 +332,7 @@ __device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, doubl
             rank += (lj > li) || (lj == li && j < i);
         }
         lam[rank] = li;
-        for (int r = 0; r < n; ++r) U[(int64_t)r * lu + rank] = V[(int64_t)r * lv + i];
+        for (int r = 0; r < n; ++r) U[(int64_t)r * lu + rank] = Vt[(int64_t)i * n + r];
     }
     if (tid == 0) {
         if (!done) atomicAdd(&info[0], 1);
@@ -337,25 +341,28 @@ __device__ void jacobi_body(const double* Ain, int ldin, int n, double* A, doubl
 }
 
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max) {
+__global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max, int lds_doubles) {
     extern __shared__ double lds[];
     const Task& t = tasks[blockIdx.z];
-    if (t.kind == T_INGEST) return;
+    if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
     const SkDev* s = t.s;
     const int n = eig_n(t);
     if (LDS != (n <= lds_max)) return;
     const bool rnd = t.kind == T_SHRINK_RAND;
+    // Vt joins A in LDS only when both fit in what this launch allocated
+    double* vt = (LDS && 2 * n * n <= lds_doubles) ? lds + n * n : nullptr;
     jacobi_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, LDS ? lds : s->slot[S_EA],
-                s->slot[S_EV], s->slot[S_U], s->sld[S_U], s->slot[S_LAM], s->info);
+                s->slot[S_EV], s->slot[S_U], s->sld[S_U], s->slot[S_LAM], s->info, vt);
 }
 
 // Descriptor form: eigen-decomposition of A (n x n) into U / lam.
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_jacobi_desc(const SmallDesc* ds, int lds_max) {
+__global__ __launch_bounds__(1024) void k_jacobi_desc(const SmallDesc* ds, int lds_max, int lds_doubles) {
     extern __shared__ double lds[];
     const SmallDesc& q = ds[blockIdx.z];
     if (q.n <= 0 || LDS != (q.n <= lds_max)) return;
-    jacobi_body(q.A, q.lda, q.n, LDS ? lds : q.work, q.work2, q.X, q.ldx, q.lam, q.info);
+    double* vt = (LDS && 2 * q.n * q.n <= lds_doubles) ? lds + q.n * q.n : nullptr;
+    jacobi_body(q.A, q.lda, q.n, LDS ? lds : q.work, q.work2, q.X, q.ldx, q.lam, q.info, vt);
 }
 
 // ------------------------------------------------------------ threshold
@@ -467,11 +474,12 @@ hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small
     const dim3 grid(1, 1, (unsigned)count);
     if (any_small && cap > 0) {
         const int nn = max_n < cap ? max_n : cap;
-        hipLaunchKernelGGL((k_jacobi<true>), grid, dim3(1024), sizeof(double) * (size_t)nn * nn, st, tasks, cap);
+        const int ldsd = 2 * nn * nn <= cap * cap ? 2 * nn * nn : nn * nn;
+        hipLaunchKernelGGL((k_jacobi<true>), grid, dim3(1024), sizeof(double) * (size_t)ldsd, st, tasks, cap, ldsd);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (any_large || cap == 0) hipLaunchKernelGGL((k_jacobi<false>), grid, dim3(1024), 0, st, tasks, cap);
+    if (any_large || cap == 0) hipLaunchKernelGGL((k_jacobi<false>), grid, dim3(1024), 0, st, tasks, cap, 0);
     return hipGetLastError();
 }
 
@@ -492,12 +500,13 @@ hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStre
     const int cap = jacobi_lds_max();
     if (cap > 0) {
         const int nn = max_n < cap ? max_n : cap;
-        hipLaunchKernelGGL((k_jacobi_desc<true>), dim3(1, 1, (unsigned)count), dim3(1024),
-                           sizeof(double) * (size_t)nn * nn, st, ds, cap);
+        const int ldsd = 2 * nn * nn <= cap * cap ? 2 * nn * nn : nn * nn;
+        hipLaunchKernelGGL((k_jacobi_desc<true>), dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)ldsd,
+                           st, ds, cap, ldsd);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (max_n > cap) hipLaunchKernelGGL((k_jacobi_desc<false>), dim3(1, 1, (unsigned)count), dim3(1024), 0, st, ds, cap);
+    if (max_n > cap) hipLaunchKernelGGL((k_jacobi_desc<false>), dim3(1, 1, (unsigned)count), dim3(1024), 0, st, ds, cap, 0);
     return hipGetLastError();
 }
 

@@ -30,9 +30,19 @@ static int coop_min_n() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_COOP_MIN_N");
-        v = e ? atoi(e) : 96;
+        v = e ? atoi(e) : 129;
     }
     return v;
+}
+
+// Marks the stages of a shrink / query task that the cooperative solvers
+// take: a property of the task alone, so a sketch computes the same thing
+// whatever else shares its launches.
+static void mark_coop(Task& t, const sketch_s* h) {
+    const int n = (t.kind == T_SHRINK_RAND) ? h->k : t.m;
+    t.flags = 0;
+    if (n >= coop_min_n()) t.flags |= TF_COOP_EIG;
+    if (t.kind == T_SHRINK_RAND && h->k >= coop_min_n()) t.flags |= TF_COOP_CHOL;
 }
 
 // Split-K plan: about 512 workgroups in total for a launch.
@@ -67,12 +77,12 @@ static sk_status build_device_state(sketch_t h) {
     const size_t es = (size_t)dtype_size(h->st);
     for (int b = 0; b < 2; ++b) {
         HIP_TRY(h, h->dalloc(&s.buf[b], es * (size_t)n2 * (size_t)h->ld));
-        HIP_TRY(h, hipMemset(s.buf[b], 0, es * (size_t)n2 * (size_t)h->ld));
+        HIP_TRY(h, h->dzero(s.buf[b], es * (size_t)n2 * (size_t)h->ld));
     }
     if (h->rnd) {
         const size_t ps = (size_t)dtype_size(h->pj);
         HIP_TRY(h, h->dalloc(&s.omegaT, ps * (size_t)k * (size_t)h->ld));
-        HIP_TRY(h, hipMemset(s.omegaT, 0, ps * (size_t)k * (size_t)h->ld));
+        HIP_TRY(h, h->dzero(s.omegaT, ps * (size_t)k * (size_t)h->ld));
     }
     struct Sz { int slot; int64_t rows, cols; };
     const int64_t mk = h->rnd ? kk : 1;
@@ -97,15 +107,15 @@ static sk_status build_device_state(sketch_t h) {
         HIP_TRY(h, h->dalloc(&p, sizeof(double) * COOP_DOUBLES));
         h->coop = (double*)p;
         HIP_TRY(h, h->dalloc(&p, 64 * sizeof(int)));
-        HIP_TRY(h, hipMemset(p, 0, 64 * sizeof(int)));
+        HIP_TRY(h, h->dzero(p, 64 * sizeof(int)));
         h->coop_ctrl = (int*)p;
     }
     void* info = nullptr;
     HIP_TRY(h, h->dalloc(&info, 64));
-    HIP_TRY(h, hipMemset(info, 0, 64));
+    HIP_TRY(h, h->dzero(info, 64));
     s.info = (int32_t*)info;
     HIP_TRY(h, h->dalloc((void**)&h->dev, sizeof(SkDev)));
-    HIP_TRY(h, hipMemcpy(h->dev, &s, sizeof(SkDev), hipMemcpyHostToDevice));
+    if (!h->dry) HIP_TRY(h, hipMemcpy(h->dev, &s, sizeof(SkDev), hipMemcpyHostToDevice));
     return SK_OK;
 }
 
@@ -122,6 +132,11 @@ struct Group {
     Prof* prof = nullptr;
     const SkDev* hs = nullptr;   // host mirror of the (single) task's sketch
     int kind = 0;
+    // tasks (offsets in the group) whose eigen-solve / CholeskyQR is cooperative
+    std::vector<int> coop_eig, coop_chol;
+    std::vector<sketch_t> own;
+    std::vector<int> ns;          // eigen-problem size of each task
+    bool any_plain_eig = false, any_plain_chol = false;
 };
 
 Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tasks, size_t first,
@@ -150,6 +165,12 @@ Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tas
         g.coop_ctrl = h->coop_ctrl;
         g.hs = &h->host;
         g.kind = t.kind;
+        g.own.push_back(h);
+        g.ns.push_back(n);
+        if (t.flags & TF_COOP_EIG) g.coop_eig.push_back((int)(i - first));
+        else g.any_plain_eig = true;
+        if (t.flags & TF_COOP_CHOL) g.coop_chol.push_back((int)(i - first));
+        else if (t.kind == T_SHRINK_RAND) g.any_plain_chol = true;
     }
     return g;
 }
@@ -159,49 +180,59 @@ inline int dims(int M, int N, int K) { return M | (N << 2) | (K << 4); }  // 0 m
 hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hipStream_t st) {
     hipError_t e;
     StageScope sc(g.prof, ST_CHOLQR, st);
-    if (g.count == 1 && g.max_k >= coop_min_n()) {
-        g_stage = "cholqr_coop";
-        return launch_cholqr_coop(t, g.max_m, g.max_k, sy, sq, passes, g.coop + COOP_LINV,
-                                  g.coop + COOP_D0, (unsigned*)(g.coop_ctrl + 8), st);
+    if (g.any_plain_chol) {
+        // batched CholeskyQR; k_cholinv skips the cooperative tasks, whose
+        // outputs are then rewritten below from the unchanged input sy
+        int src = sy;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int dst = (pass == passes - 1) ? sq : S_Q1;
+            if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, src, src, S_W, dims(1, 1, 0), st))) return e;
+            if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
+            if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
+            src = dst;
+        }
     }
-    int src = sy;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int dst = (pass == passes - 1) ? sq : S_Q1;
-        if (dst == src) return hipErrorInvalidValue;
-        // W = Y^T Y, X = chol(W)^{-1}, dst = Y X^T
-        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, src, src, S_W, dims(1, 1, 0), st))) return e;
-        if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
-        if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
-        src = dst;
+    for (int off : g.coop_chol) {
+        const sketch_t h = g.own[(size_t)off];
+        g_stage = "cholqr_coop";
+        if ((e = launch_cholqr_coop(t + off, h->n2, h->k, sy, sq, passes, h->coop + COOP_LINV,
+                                    h->coop + COOP_D0, (unsigned*)(h->coop_ctrl + 8), st)))
+            return e;
     }
     return hipSuccess;
 }
 
 hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
     StageScope sc(g.prof, ST_EIG, st);
-    if (g.count == 1 && g.max_n >= coop_min_n()) {
-        g_stage = "jacobi_coop";
-        const SkDev& hs = *g.hs;
+    if (g.any_plain_eig) {
+        g_stage = "jacobi";
+        hipError_t e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int off : g.coop_eig) {
+        const sketch_t h = g.own[(size_t)off];
+        const SkDev& hs = h->host;
         const bool rnd = g.kind == T_SHRINK_RAND;
         CoopEig a{};
         a.Ain = hs.slot[rnd ? S_M : S_G];
         a.ldin = hs.sld[rnd ? S_M : S_G];
-        a.n = g.max_n;
+        a.n = g.ns[(size_t)off];
         a.A = hs.slot[S_EA];
         a.V = hs.slot[S_EV];
         a.U = hs.slot[S_U];
         a.lu = hs.sld[S_U];
         a.lam = hs.slot[S_LAM];
         a.info = hs.info;
-        a.ubuf = g.coop + COOP_UBUF;
-        a.part = g.coop + COOP_PART;
-        a.ctrl = g.coop_ctrl;
-        a.stats = g.coop + COOP_STATS;
-        a.bar = (uint32_t*)(g.coop_ctrl + 8);
-        return launch_jacobi_coop(a, st);
+        a.ubuf = h->coop + COOP_UBUF;
+        a.part = h->coop + COOP_PART;
+        a.ctrl = h->coop_ctrl;
+        a.stats = h->coop + COOP_STATS;
+        a.bar = (uint32_t*)(h->coop_ctrl + 8);
+        g_stage = "jacobi_coop";
+        hipError_t e = launch_jacobi_coop(a, st);
+        if (e != hipSuccess) return e;
     }
-    g_stage = "jacobi";
-    return launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
+    return hipSuccess;
 }
 
 // Runs the shrink stages for `count` tasks of one kind starting at t.
@@ -301,6 +332,7 @@ void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dt
             s.par = h->par;
             s.m = h->n2;
             s.shrink_idx = h->shrinks;
+            mark_coop(s, h);
             owners.push_back(h);
             tasks.push_back(s);
             h->par ^= 1;
@@ -320,6 +352,76 @@ sk_status check_handle(sketch_t h, const char* what) {
 }
 
 // ---------------------------------------------------------------- C ABI
+static sk_status validate_config(const sketch_config* cfg) {
+    if (cfg->d < 1 || cfg->ell < 2) return fail(SK_EINVAL, "sketch_create: need d >= 1 and ell >= 2");
+    if (cfg->ell > 256) return fail(SK_EINVAL, "sketch_create: ell > 256 is not supported");
+    if (cfg->state_dtype != SK_F64 && cfg->state_dtype != SK_F32)
+        return fail(SK_EINVAL, "sketch_create: state_dtype must be SK_F64 or SK_F32");
+    if (cfg->proj_dtype < SK_F64 || cfg->proj_dtype > SK_BF16)
+        return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
+    if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
+        return fail(SK_EINVAL, "sketch_create: bad shrink");
+    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW)
+        return fail(SK_EINVAL, "sketch_create: bad kind");
+    if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
+        return fail(SK_EINVAL, "sketch_create: bad q or oversample");
+    if (cfg->kind == SK_WINDOW && (cfg->window_N < 1 || !(cfg->R >= 1.0)))
+        return fail(SK_EINVAL, "sketch_create: window needs window_N >= 1 and R >= 1");
+    if (cfg->d > (1 << 20)) return fail(SK_EINVAL, "sketch_create: d too large");
+    return SK_OK;
+}
+
+static void init_fields(sketch_t h, const sketch_config* cfg) {
+    h->cfg = *cfg;
+    h->d = cfg->d;
+    h->ell = cfg->ell;
+    h->n2 = 2 * cfg->ell;
+    h->rnd = cfg->kind == SK_PERSISTENT && cfg->shrink == SK_SHRINK_RAND;
+    h->k = h->rnd ? std::min(std::min(cfg->ell + cfg->oversample, 2 * cfg->ell), cfg->d) : 0;
+    h->q = cfg->q;
+    h->st = cfg->state_dtype;
+    h->pj = cfg->proj_dtype;
+    h->ld = round_up(cfg->d, 64);
+}
+
+int64_t sketch_state_bytes(const sketch_config* cfg) {
+    if (!cfg || validate_config(cfg) != SK_OK || cfg->kind != SK_PERSISTENT) return -1;
+    sketch_s tmp;
+    tmp.dry = true;
+    init_fields(&tmp, cfg);
+    if (build_device_state(&tmp) != SK_OK) return -1;
+    return tmp.bytes;
+}
+
+sk_status sketch_reset(sketch_t h, uint64_t seed, uint64_t stream_id) {
+    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_reset: window sketch");
+    h->cfg.seed = seed;
+    h->cfg.stream_id = stream_id;
+    h->host.seed = seed;
+    h->host.stream = stream_id;
+    h->fill = 0;
+    h->shrinks = 0;
+    h->rows_seen = 0;
+    h->par = 0;
+    h->sticky = false;
+    h->sticky_msg.clear();
+    h->prof.drain();
+    for (int i = 0; i < NSTAGE; ++i) {
+        h->prof.calls[i] = 0;
+        h->prof.ms[i] = 0.0;
+    }
+    h->prof.mask = 0;
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    // stream-ordered: kernels queued later read the new seed; the zeroed
+    // buffer rows keep a query of the empty sketch exact
+    HIP_TRY(h, hipMemsetAsync(h->host.buf[0], 0, (size_t)dtype_size(h->st) * (size_t)h->n2 * (size_t)h->ld,
+                              h->stream));
+    // h->host is not written again before the sketch is next idle, so the
+    // asynchronous copy may read it late
+    HIP_TRY(h, hipMemcpyAsync(h->dev, &h->host, sizeof(SkDev), hipMemcpyHostToDevice, h->stream));
+    return SK_OK;
+}
+
 extern "C" {
 
 sk_status sketch_config_init(sketch_config* cfg) {
@@ -337,32 +439,10 @@ sk_status sketch_config_init(sketch_config* cfg) {
 sk_status sketch_create(const sketch_config* cfg, sketch_t* out) {
     if (!cfg || !out) return fail(SK_EINVAL, "sketch_create: NULL argument");
     *out = nullptr;
-    if (cfg->d < 1 || cfg->ell < 2) return fail(SK_EINVAL, "sketch_create: need d >= 1 and ell >= 2");
-    if (cfg->ell > 256) return fail(SK_EINVAL, "sketch_create: ell > 256 is not supported");
-    if (cfg->state_dtype != SK_F64 && cfg->state_dtype != SK_F32)
-        return fail(SK_EINVAL, "sketch_create: state_dtype must be SK_F64 or SK_F32");
-    if (cfg->proj_dtype < SK_F64 || cfg->proj_dtype > SK_BF16)
-        return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
-    if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
-        return fail(SK_EINVAL, "sketch_create: bad shrink");
-    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW)
-        return fail(SK_EINVAL, "sketch_create: bad kind");
-    if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
-        return fail(SK_EINVAL, "sketch_create: bad q or oversample");
-    if (cfg->kind == SK_WINDOW && (cfg->window_N < 1 || !(cfg->R >= 1.0)))
-        return fail(SK_EINVAL, "sketch_create: window needs window_N >= 1 and R >= 1");
-    if (cfg->d > (1 << 20)) return fail(SK_EINVAL, "sketch_create: d too large");
+    sk_status vr = validate_config(cfg);
+    if (vr) return vr;
     sketch_t h = new sketch_s();
-    h->cfg = *cfg;
-    h->d = cfg->d;
-    h->ell = cfg->ell;
-    h->n2 = 2 * cfg->ell;
-    h->rnd = cfg->kind == SK_PERSISTENT && cfg->shrink == SK_SHRINK_RAND;
-    h->k = h->rnd ? std::min(std::min(cfg->ell + cfg->oversample, 2 * cfg->ell), cfg->d) : 0;
-    h->q = cfg->q;
-    h->st = cfg->state_dtype;
-    h->pj = cfg->proj_dtype;
-    h->ld = round_up(cfg->d, 64);
+    init_fields(h, cfg);
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) {
         delete h;
@@ -480,6 +560,7 @@ static sk_status query_to_qout(sketch_t h) {
         t.kind = T_QUERY;
         t.par = h->par;
         t.m = (int32_t)r;
+        mark_coop(t, h);
         std::vector<Task> tasks{t};
         return execute(h, owners, tasks, DT_F64, false);
     }
@@ -575,10 +656,9 @@ sk_status sketch_sync(sketch_t h) {
     return check_info(h);
 }
 
-sk_status sketch_destroy(sketch_t h) {
-    if (!h) return SK_OK;
+static void destroy_impl(sketch_t h, bool sync) {
     (void)hipSetDevice(h->cfg.device);
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (sync && h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->win) window_destroy(h);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->stage) (void)hipFree(h->stage);
@@ -587,6 +667,10 @@ sk_status sketch_destroy(sketch_t h) {
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     if (h->counted) g_in_use -= h->bytes;
     delete h;
+}
+
+sk_status sketch_destroy(sketch_t h) {
+    if (h) destroy_impl(h, true);
     return SK_OK;
 }
 
@@ -672,6 +756,7 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
                 s.par = h->par;
                 s.m = h->n2;
                 s.shrink_idx = h->shrinks;
+                mark_coop(s, h);
                 shr.push_back({h, s});
                 h->par ^= 1;
                 h->fill = h->ell - 1;
@@ -701,6 +786,11 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
 }
 
 }  // extern "C"
+
+sk_status sketch_destroy_idle(sketch_t h) {
+    if (h) destroy_impl(h, false);
+    return SK_OK;
+}
 
 // Batched execution: like execute(), but a group also breaks where the shrink
 // flavour (q, dtypes) changes.
@@ -834,6 +924,7 @@ extern "C" sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32
                 s.par = node->par;
                 s.m = (int32_t)node->fill;
                 s.shrink_idx = 0;
+                mark_coop(s, node);
                 oi.push_back(node);
                 ti.push_back(s);
                 node->par ^= 1;

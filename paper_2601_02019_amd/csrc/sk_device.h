@@ -50,6 +50,8 @@ struct SkDev {
     uint64_t seed, stream;
 };
 
+enum TaskFlags : int32_t { TF_COOP_EIG = 1, TF_COOP_CHOL = 2 };
+
 enum TaskKind : int32_t { T_INGEST = 0, T_SHRINK_EXACT = 1, T_SHRINK_RAND = 2, T_QUERY = 3 };
 
 struct Task {
@@ -60,6 +62,8 @@ struct Task {
     int32_t row0;              // ingest: first destination row
     int32_t nrows;             // ingest: rows to copy
     int32_t src_dtype;         // ingest: dtype of src
+    int32_t flags;             // TF_COOP_EIG / TF_COOP_CHOL: solved by the cooperative kernels
+    int32_t pad0;
     int64_t shrink_idx;        // Philox counter word of this shrink
     int64_t src_ld;            // ingest: leading dimension of src
     const void* src;           // ingest: source rows (device)

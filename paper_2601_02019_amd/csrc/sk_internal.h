@@ -38,16 +38,18 @@ inline int dtype_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2)
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // --------------------------------------------------------------- task arena
-// Pinned host mirror + device array of Task records, used as two halves in
-// alternation; a half is rewritten only after the event recorded behind the
-// last launch that read it has completed.
+// Pinned host mirror + device array of Task records, used as a ring of NSLOT
+// slots; a slot is rewritten only after the event recorded behind the last
+// launch that read it has completed, so NSLOT - 1 batched calls can be queued
+// on the device while the host plans the next.
 struct TaskArena {
+    static const int NSLOT = 4;
     Task* host = nullptr;
     Task* dev = nullptr;
-    int cap = 0;  // per half
-    int half = 0;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    bool used[2] = {false, false};
+    int cap = 0;  // per slot
+    int slot = 0;
+    hipEvent_t ev[NSLOT] = {};
+    bool used[NSLOT] = {};
 
     hipError_t reserve(int n, hipStream_t st) {
         if (n <= cap) return hipSuccess;
@@ -55,11 +57,11 @@ struct TaskArena {
         if (e != hipSuccess) return e;
         release();
         int c = std::max(n, 256);
-        e = hipHostMalloc((void**)&host, sizeof(Task) * 2 * (size_t)c, hipHostMallocDefault);
+        e = hipHostMalloc((void**)&host, sizeof(Task) * NSLOT * (size_t)c, hipHostMallocDefault);
         if (e != hipSuccess) return e;
-        e = hipMalloc((void**)&dev, sizeof(Task) * 2 * (size_t)c);
+        e = hipMalloc((void**)&dev, sizeof(Task) * NSLOT * (size_t)c);
         if (e != hipSuccess) return e;
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < NSLOT; ++i) {
             e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
             if (e != hipSuccess) return e;
             used[i] = false;
@@ -67,17 +69,17 @@ struct TaskArena {
         cap = c;
         return hipSuccess;
     }
-    // Copies tasks to the next half; returns its device pointer.
+    // Copies tasks to the next slot; returns its device pointer.
     hipError_t upload(const std::vector<Task>& tasks, hipStream_t st, Task** out) {
         hipError_t e = reserve((int)tasks.size(), st);
         if (e != hipSuccess) return e;
-        half ^= 1;
-        if (used[half]) {
-            e = hipEventSynchronize(ev[half]);
+        slot = (slot + 1) % NSLOT;
+        if (used[slot]) {
+            e = hipEventSynchronize(ev[slot]);
             if (e != hipSuccess) return e;
         }
-        Task* h = host + (size_t)half * cap;
-        Task* d = dev + (size_t)half * cap;
+        Task* h = host + (size_t)slot * cap;
+        Task* d = dev + (size_t)slot * cap;
         std::memcpy(h, tasks.data(), sizeof(Task) * tasks.size());
         e = hipMemcpyAsync(d, h, sizeof(Task) * tasks.size(), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return e;
@@ -85,17 +87,18 @@ struct TaskArena {
         return hipSuccess;
     }
     hipError_t done(hipStream_t st) {
-        used[half] = true;
-        return hipEventRecord(ev[half], st);
+        used[slot] = true;
+        return hipEventRecord(ev[slot], st);
     }
     void release() {
         if (host) (void)hipHostFree(host);
         if (dev) (void)hipFree(dev);
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NSLOT; ++i) {
             if (ev[i]) (void)hipEventDestroy(ev[i]);
+            ev[i] = nullptr;
+        }
         host = nullptr;
         dev = nullptr;
-        ev[0] = ev[1] = nullptr;
         cap = 0;
     }
 };
@@ -188,6 +191,7 @@ struct sketch_s {
     TaskArena arena;
     WindowState* win = nullptr;
     bool counted = false;
+    bool dry = false;         // size computation only: dalloc counts, allocates nothing
     double* coop = nullptr;   // cooperative-kernel scratch (see coop_* offsets)
     int* coop_ctrl = nullptr;
     Prof prof;
@@ -199,6 +203,11 @@ struct sketch_s {
     }
     hipError_t dalloc(void** p, size_t n) {
         if (n == 0) n = 8;
+        if (dry) {
+            *p = nullptr;
+            bytes += (int64_t)n;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(p, n);
         if (e == hipSuccess) {
             allocs.push_back(*p);
@@ -206,6 +215,7 @@ struct sketch_s {
         }
         return e;
     }
+    hipError_t dzero(void* p, size_t n) { return dry ? hipSuccess : hipMemset(p, 0, n); }
     hipError_t ensure_stage(size_t n) {
         if (n <= stage_bytes) return hipSuccess;
         hipError_t e = hipStreamSynchronize(stream);
@@ -232,3 +242,12 @@ void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dt
 sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
                           int in_dtype);
 sk_status check_handle(sketch_t h, const char* what);
+// Device bytes sketch_create would allocate for cfg (persistent sketches);
+// negative on a configuration sketch_create rejects.
+int64_t sketch_state_bytes(const sketch_config* cfg);
+// Returns an idle persistent sketch (no work in flight on its stream) to its
+// empty state with a new seed and stream id, without reallocating.
+sk_status sketch_reset(sketch_t h, uint64_t seed, uint64_t stream_id);
+// sketch_destroy without the stream synchronisation, for a sketch whose work
+// the caller knows to have completed.
+sk_status sketch_destroy_idle(sketch_t h);
