@@ -41,9 +41,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-shrinks", type=int, default=1,
                     help="shrinks of the CPU oracle sample")
-    ap.add_argument("--workload", choices=["persistent", "serving"], default="persistent",
-                    help="persistent: the tight-error single stream (default); serving: many "
-                         "concurrent streams with Poisson bursts through the serving loop")
+    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving"],
+                    default="persistent",
+                    help="persistent: the tight-error single stream (default); small: the FP64 exact "
+                         "small stream; window: the sliding-window stream; sites: 64 CSR sites with "
+                         "tree merges; serving: many concurrent streams with Poisson bursts")
+    ap.add_argument("--window-rows", type=int, default=200_000, help="rows of the window stream")
+    ap.add_argument("--site-rows", type=int, default=100_000, help="rows per site")
+    ap.add_argument("--sites", type=int, default=64)
     ap.add_argument("--streams", type=int, default=512)
     ap.add_argument("--bursts", type=int, default=2000, help="bursts per load point")
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9",
@@ -223,14 +228,233 @@ def serving_main(args):
     print(json.dumps(out))
 
 
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def base_line(args, value, unit, ms_per_step, workload, extra):
+    out = {
+        "metric": "rows/sec sketch update at matched cov-err vs exact-SVD FD; batched p99 lat",
+        "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": extra.pop("dtype"), "data": "synthetic", "config": {"workload": workload},
+    }
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def small_main(args):
+    """Persistent stream, exact FP64 shrink: n = 10,000, d = 256, ell = 32."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2601_02019_amd import Sketch
+    n, d, ell = 10_000, 256, 32
+    A = synth.persistent_small(n, d, seed=0)
+    At = torch.from_numpy(A).cuda()
+    for _ in range(args.warmup):
+        s = Sketch(d, ell)
+        s.update(At)
+        s.query()
+        s.close()
+    times = []
+    for _ in range(args.steps):
+        s = Sketch(d, ell)
+        s.profile("all")
+        B, t = timed(lambda: (s.update(At), s.query())[1])
+        times.append(t)
+        prof = s.profile_read()
+        s.close()
+    ms = 1e3 * float(np.median(times))
+    AtA = A.T @ A
+    Bn = B.cpu().numpy()
+    err = float(np.max(np.abs(np.linalg.eigvalsh(AtA - Bn.T @ Bn)))) / float(np.trace(AtA))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        o = oracle.FD(d, ell)
+        t = time.perf_counter()
+        o.update(A)
+        o.query()
+        tc = time.perf_counter() - t
+        cpu = {"value": n / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole stream ({n} rows, {o.shrinks} exact shrinks), FP64 plain C, one "
+                         f"thread, {tc:.1f}s"}
+    stages = {k: v for k, v in prof.items() if v[0] > 0}
+    base_line(args, n / (ms / 1e3), "rows/s", ms,
+              "persistent stream, exact FP64 shrink: n=10000, d=256, ell=32, rank-20 signal "
+              "10*0.8^i + N(0, 0.1^2)",
+              {"dtype": "f64", "us_per_shrink": 1e3 * ms / 302, "cov_err_rel": err, "bound_rel": 1 / ell,
+               "cpu_baseline": cpu, "stage_ms_per_step": {k: v[1] for k, v in stages.items()}})
+
+
+def window_main(args):
+    """Sliding window: d = 1024, ell = 128, N = 100,000, FP32 rows, queries
+    every 10,000 rows; the first --window-rows rows of the stream."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2601_02019_amd import Sketch
+    d, ell, N, R = 1024, 128, 100_000, 64.0
+    n = args.window_rows
+    t0 = time.time()
+    A = synth.window_stream(n, d=d, seed=2)
+    At = torch.from_numpy(A).cuda()
+    print(f"[bench] window stream {n} x {d} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    w = Sketch(d, ell, kind="window", shrink="rand", window_N=N, R=R, q=1, seed=9, stream_id=0)
+    # warm-up on a separate sketch
+    ww = Sketch(d, ell, kind="window", shrink="rand", window_N=N, R=R, q=1, seed=9, stream_id=1)
+    ww.update(At[:2000])
+    ww.query()
+    ww.close()
+    upd, qry, errs = 0.0, [], []
+    for r0 in range(0, n, 10_000):
+        blk = At[r0:r0 + 10_000]
+        _, t = timed(lambda: w.update(blk))
+        upd += t
+        B, tq = timed(lambda: w.query(torch.float64))
+        qry.append(tq)
+        lo = max(0, r0 + blk.shape[0] - N)
+        W = At[lo:r0 + blk.shape[0]].double()
+        G = W.T @ W
+        D = G - B.T @ B
+        errs.append(float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / torch.trace(G)))
+        print(f"[bench] window rows {r0 + blk.shape[0]}: update {t:.2f}s query {1e3 * tq:.0f} ms "
+              f"err {errs[-1]:.2e}", file=sys.stderr, flush=True)
+    lv = w.info()["levels"]
+    stats = [w.window_stats(j) for j in range(lv)]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        m = 3000
+        o = oracle.Window(d, ell, N, R, q=1, seed=9, stream=0, fd="rand")
+        t = time.perf_counter()
+        o.update(A[:m].astype(np.float64))
+        tc = time.perf_counter() - t
+        cpu = {"value": m / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} rows of the window stream, FP64 plain C, one thread, {tc:.1f}s"}
+    base_line(args, n / upd, "rows/s", None,
+              "sliding window: d=1024, ell=128, N=100000, FP32 rows, rank-64 spectrum 0.95^j rotating "
+              "by a Givens sweep every 50000 rows; first %d rows, query every 10000" % n,
+              {"dtype": "f32 rows, f64 state", "rows": n, "update_s": upd,
+               "query_ms_median": 1e3 * float(np.median(qry)), "query_ms_max": 1e3 * float(np.max(qry)),
+               "cov_err_rel_max": max(errs), "bound_rel_25_over_ell": 25.0 / ell,
+               "level_stats": stats, "cpu_baseline": cpu})
+
+
+def sites_main(args):
+    """64 logical sites, each 100,000 CSR rows (d = 2048, 1 % density, values
+    N(0,1) * j^-0.5), ell = 128 per site; every 10,000 rows per site the
+    coordinator re-merges the current site sketches by a binary tree."""
+    import numpy as np
+    import torch
+    from paper_2601_02019_amd import Sketch, sketch_update_csr_batch
+    d, ell, S, n = 2048, 128, args.sites, args.site_rows
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4)
+    w = torch.arange(1, d + 1, device=dev, dtype=torch.float32) ** -0.5
+    t0 = time.time()
+    sites = []
+    for s in range(S):
+        ips, ixs, vvs = [torch.zeros(1, dtype=torch.int64, device=dev)], [], []
+        base = 0
+        for r0 in range(0, n, 10_000):
+            m = min(10_000, n - r0)
+            mask = torch.rand(m, d, device=dev, generator=gen) < 0.01
+            cnt = mask.sum(1)
+            idx = mask.nonzero()[:, 1].to(torch.int32)
+            vals = torch.randn(idx.shape[0], device=dev, generator=gen) * w[idx.long()]
+            ips.append(base + torch.cumsum(cnt, 0))
+            base += int(cnt.sum())
+            ixs.append(idx)
+            vvs.append(vals)
+        sites.append((torch.cat(ips).contiguous(), torch.cat(ixs).contiguous(), torch.cat(vvs).contiguous()))
+    torch.cuda.synchronize()
+    nnz = sum(int(x[1].shape[0]) for x in sites)
+    print(f"[bench] {S} sites x {n} CSR rows ({nnz / (S * n):.1f} nnz/row) in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def run():
+        sk = [Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=1, seed=4, stream_id=s)
+              for s in range(S)]
+        coord = None
+        t_upd = t_mrg = 0.0
+        for r0 in range(0, n, 10_000):
+            m = min(10_000, n - r0)
+            chunk = [(x[0][r0:r0 + m + 1].contiguous(), x[1], x[2]) for x in sites]
+            _, t = timed(lambda: sketch_update_csr_batch(sk, chunk))
+            t_upd += t
+            if coord is not None:
+                coord.close()
+            coord = Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=1, seed=4,
+                           stream_id=1000 + r0 // 10_000)
+            _, t = timed(lambda: coord.merge_tree(sk))
+            t_mrg += t
+        B = coord.query()
+        for x in sk:
+            x.close()
+        return B, t_upd, t_mrg
+
+    if args.warmup:  # load the kernels on a small piece of the work
+        wk = [Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=1, seed=4, stream_id=s)
+              for s in range(2)]
+        sketch_update_csr_batch(wk, [(x[0][:1001].contiguous(), x[1], x[2]) for x in sites[:2]])
+        wc = Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=1, seed=4, stream_id=99)
+        wc.merge_tree(wk)
+        wc.query()
+        for x in wk + [wc]:
+            x.close()
+    B, t_upd, t_mrg = run()
+    total = t_upd + t_mrg
+    # error of the final merged sketch against the union of all site rows
+    G = torch.zeros(d, d, device=dev, dtype=torch.float64)
+    for ip, ix, vv in sites:
+        for r0 in range(0, n, 20_000):
+            m = min(20_000, n - r0)
+            X = torch.zeros(m, d, device=dev, dtype=torch.float64)
+            a, b = int(ip[r0]), int(ip[r0 + m])
+            rows = torch.repeat_interleave(torch.arange(m, device=dev), (ip[r0 + 1:r0 + m + 1] - ip[r0:r0 + m]))
+            X[rows, ix[a:b].long()] = vv[a:b].double()
+            G += X.T @ X
+    D = G - B.double().T @ B.double()
+    err = float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / torch.trace(G))
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        import synth
+        m = 2 * ell + 2 * (ell + 1)
+        ip, ix, vv = synth.streams.sparse_sites(m, d=d, density=0.01, seed=4, site=0)
+        Xd = synth.streams.csr_to_dense(ip, ix, vv, d)
+        o = oracle.FD(d, ell, "rand", k=ell, q=1, seed=4, stream=0)
+        t = time.perf_counter()
+        o.update(Xd)
+        tc = time.perf_counter() - t
+        cpu = {"value": m / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} rows of one site densified ({o.shrinks} randomized shrinks), FP64 "
+                         f"plain C, one thread, {tc:.1f}s"}
+    base_line(args, S * n / total, "rows/s", None,
+              "distributed sites on one GPU: %d sites x %d CSR rows, d=2048, 1%% density, values N(0,1) "
+              "j^-0.5, ell=128 per site, tree merge every 10000 rows per site" % (S, n),
+              {"dtype": "f32 state + bf16 projection (FP64 core)", "update_s": t_upd, "merge_s": t_mrg,
+               "update_rows_per_s": S * n / t_upd, "cov_err_rel_merged": err, "bound_rel": 1 / ell,
+               "cpu_baseline": cpu})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} "
               f"requested). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "serving":
-        return serving_main(args)
+    if args.workload != "persistent":
+        return {"serving": serving_main, "small": small_main, "window": window_main,
+                "sites": sites_main}[args.workload](args)
     import torch
     from paper_2601_02019_amd import Sketch
 

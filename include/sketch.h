@@ -6,7 +6,7 @@
  * buffer is factorised, the ell-th largest squared singular value is
  * subtracted from every squared singular value (clamped at zero) and an
  * (ell-1)-row sketch is rebuilt (paper Sec. 2.3 "Frequent Directions";
- * Algorithm "AeroSketch: Update" lines 1-6).  With SK_SHRINK_RAND the exact
+ * the FD reduce of Algorithm "AeroSketch: Update").  With SK_SHRINK_RAND the exact
  * SVD is replaced by the randomized factorisation of Algorithm "Simultaneous
  * Iteration" (Sec. 2.2) applied to the buffer, with the Gaussian test matrix
  * on the d side (Omega, d x k) drawn from Philox4x64-10.
@@ -102,7 +102,7 @@ SK_EXPORT sk_status sketch_create(const sketch_config* cfg, sketch_t* out);
 /* Appends n_rows rows (n_rows x d, leading dimension ld, element type dtype)
  * to the stream.  Rows are copied into the buffer (converted to the state
  * dtype, round-to-nearest-even); every time the buffer reaches 2*ell rows a
- * shrink runs (Algorithm "AeroSketch: Update" lines 1-6).  n_rows == 0 is a
+ * shrink runs (the FD reduce of Algorithm "AeroSketch: Update").  n_rows == 0 is a
  * no-op.  For SK_WINDOW sketches each row advances time by one. */
 SK_EXPORT sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld,
                         int32_t dtype, int32_t on_device);
@@ -115,7 +115,7 @@ SK_EXPORT sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const i
 
 /* Writes the ell x d sketch (row-major, dtype SK_F64 or SK_F32) to B_out.
  * Persistent: f_ell of the buffer rows, i.e. one exact shrink of the current
- * buffer when it holds >= ell rows (Algorithm "AeroSketch: Query" lines 5-7).
+ * buffer when it holds >= ell rows (the final step of Algorithm "AeroSketch: Query").
  * Window: the query of Algorithm "ML-AeroSketch" for the window (T-N, T].
  * Non-destructive. */
 SK_EXPORT sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device);
@@ -175,6 +175,14 @@ SK_EXPORT int64_t sketch_memory_in_use(void);
  * buffer filled at that point, whatever its d and ell. */
 SK_EXPORT sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n,
                               int32_t count, int32_t dtype);
+/* The same for CSR rows on the device (as sketch_update_csr with
+ * on_device = 1): sketch i takes n[i] rows from indptr[i] (n[i] + 1 int64
+ * offsets into indices[i] / values[i]; int32 column indices < d, FP32
+ * values).  Used for many sites of a distributed stream on one GPU; each
+ * sketch's result is bitwise the same as with its own sketch_update_csr. */
+SK_EXPORT sk_status sketch_update_csr_batch(sketch_t* hs, const int64_t* const* indptr,
+                                            const int32_t* const* indices, const float* const* values,
+                                            const int64_t* n, int32_t count);
 
 /* ---- serving ---------------------------------------------------------------
  * A request loop over many resident stream sketches on one GPU: streams are

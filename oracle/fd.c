@@ -3,25 +3,26 @@
  * TEST INFRASTRUCTURE ONLY.
  *
  * Exact shrink: Sec. 2.3 "Frequent Directions" and Algorithm "AeroSketch:
- * Update" lines 1-6: when the 2*ell-row buffer is full, take its SVD, subtract
+ * Update" (its FD reduce): when the 2*ell-row buffer is full, take its SVD, subtract
  * the ell-th largest squared singular value from every squared singular value
  * (clamped at zero) and keep Sigma' V^T, which has at least ell+1 zero rows.
  *
  * Randomized shrink: the SVD of the full buffer is replaced by Algorithm
  * "Simultaneous Iteration" (Sec. 2.2) applied to the buffer C (2*ell x d):
- *   K = (C C^T)^q C Omega   (Omega d x k Gaussian)            -- line 2
- *       computed as K <- C C^T QR(K), q times (same span; the orthonormal
- *       basis between steps keeps the small directions in floating point)
- *   Q = QR(K)                                                 -- line 3
- *   M = Q^T C C^T Q                                           -- line 4
- *   M = U Sigma^2 U^T                                         -- line 5
- *   Z = Q U                                                   -- line 6
+ *   sketch      K = (C C^T)^q C Omega   (Omega d x k Gaussian),
+ *               computed as K <- C C^T QR(K), q times (same span; the
+ *               orthonormal basis between steps keeps the small directions
+ *               in floating point)
+ *   range       Q = QR(K)
+ *   projection  M = Q^T C C^T Q
+ *   core        M = U Sigma^2 U^T
+ *   lift        Z = Q U
  * and the FD shrink is taken with the estimated singular values and the rows
  * z_i^T C / sigma_i as right singular vectors.  The test matrix sits on the
  * d side (Omega d x k) so that the result depends only on C^T C and Omega.
  *
- * Query: Algorithm "AeroSketch: Query" lines 5-7 (eigen-decomposition and a
- * shrink by the ell-th eigenvalue), non-destructive.
+ * Query: the final step of Algorithm "AeroSketch: Query" (eigen-decomposition
+ * and a shrink by the ell-th eigenvalue), non-destructive.
  * Merge: Lemma "Decomposability": stacking sketches of disjoint row sets and
  * sketching the stack keeps the errors additive.
  */
@@ -81,9 +82,9 @@ int o_shrink_rand(double* X, int m, int d, int ld, int ell, int k, int q,
     double* Z = dalloc((int64_t)m * k);
     double* Bn = dalloc((int64_t)m * d);
     int rc = 0;
-    /* line 1: Omega ~ N(0,1)^{d x k} from the counter stream of shrink b */
+    /* Omega ~ N(0,1)^{d x k} from the counter stream of shrink b */
     o_omega(seed, stream, b, 0, d, k, Om);
-    /* line 2: K = C Omega, then q times K <- C (C^T K) */
+    /* sketch: K = C Omega, then q times K <- C (C^T K) */
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < k; ++j) {
             double s = 0;
@@ -109,10 +110,10 @@ int o_shrink_rand(double* X, int m, int d, int ld, int ell, int k, int q,
                 K[(int64_t)i * k + j] = s;
             }
     }
-    /* line 3: Q = QR(K) */
+    /* range: Q = QR(K) */
     rc = o_qr_householder(K, m, k, Q);
     if (rc) goto out;
-    /* line 4: M = Q^T C C^T Q = V^T V with V = C^T Q */
+    /* projection: M = Q^T C C^T Q = V^T V with V = C^T Q */
     for (int t = 0; t < d; ++t)
         for (int j = 0; j < k; ++j) {
             double s = 0;
@@ -125,10 +126,10 @@ int o_shrink_rand(double* X, int m, int d, int ld, int ell, int k, int q,
             for (int t = 0; t < d; ++t) s += V[(int64_t)t * k + a] * V[(int64_t)t * k + c];
             M[(int64_t)a * k + c] = s;
         }
-    /* line 5: eigen-decomposition of M (sigma_hat^2 = w) */
+    /* core: eigen-decomposition of M (sigma_hat^2 = w) */
     rc = o_sym_eig(M, k, w, U);
     if (rc) goto out;
-    /* line 6: Z = Q U */
+    /* lift: Z = Q U */
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < k; ++j) {
             double s = 0;

@@ -4,8 +4,8 @@
  * TEST INFRASTRUCTURE ONLY -- deliberately plain loops, no blocking.
  *
  * The paper treats SVD, eigen-decomposition and QR as black boxes (Sec. 2.2,
- * Algorithm "Simultaneous Iteration" lines 3 and 5; Sec. 2.3 FD; Algorithm
- * "AeroSketch: Query" line 5).  These are the textbook algorithms
+ * the QR and eigen steps of Algorithm "Simultaneous Iteration"; Sec. 2.3 FD;
+ * the eigen step of Algorithm "AeroSketch: Query").  These are the textbook algorithms
  * (Hestenes 1958; Jacobi/Rutishauser; Householder), see Golub & Van Loan,
  * "Matrix Computations", Sec. 8.5 (Jacobi) and 5.2 (Householder QR).
  */

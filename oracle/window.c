@@ -14,7 +14,7 @@
  *     k-th estimate falls below theta, dump the xi directions whose estimate
  *     reaches theta as a snapshot (Z, Z^T C'^T C') and remove them from C'.
  * Query: restore B = C^T C + sum over in-window snapshots of
- *   Z W + W^T Z^T - Z (W Z) Z^T  (Algorithm "AeroSketch: Query" lines 1-4),
+ *   Z W + W^T Z^T - Z (W Z) Z^T  (the restore of Algorithm "AeroSketch: Query"),
  * eigen-decompose, shrink by the ell-th eigenvalue, then FD over that sketch
  * stacked with the in-window raw rows.
  *
@@ -28,7 +28,7 @@
  *     dropped by the length cap; the smallest valid level is used (the last
  *     level if none is valid).
  *   - the FD over the stacked rows is one exact shrink of the whole stack.
- *   - the FD reduce (Algorithm "AeroSketch: Update" lines 3-4) is the exact
+ *   - the FD reduce of Algorithm "AeroSketch: Update" is the exact
  *     SVD shrink or, with fd_mode O_RAND, the simul_iter shrink of the
  *     persistent sketch (k = min(ell, d)), keyed per level.
  *   - random streams: power-iteration start vector of level j at time i uses
@@ -206,7 +206,7 @@ static int level_update(o_win* w, int j, const double* a, int64_t i) {
     memcpy(l->C + l->r * d, a, sizeof(double) * (size_t)d);
     l->r += 1;
     if (l->r == 2 * ell) {
-        /* FD reduce (line 4): exact SVD, or simul_iter with k = min(ell, d)
+        /* FD reduce: exact SVD, or simul_iter with k = min(ell, d)
          * keyed by (seed, 64 stream + j + 1) and the level's shrink count */
         int rc;
         if (w->fd_mode == O_EXACT)
@@ -335,7 +335,7 @@ int o_win_stats(const o_win* w, int level, int64_t* st) {
     return 0;
 }
 
-/* B_T of Algorithm "AeroSketch: Query" lines 1-4 for a level, window (T-N, T]. */
+/* B_T of the restore in Algorithm "AeroSketch: Query" for a level, window (T-N, T]. */
 static void level_restore(const o_win* w, int j, double* G) {
     const wlevel* l = &w->lv[j];
     const int d = w->d;

@@ -168,6 +168,21 @@ def sketch_update_batch(sketches, rows_list, dtype=None):
                "sketch_update_batch")
 
 
+def sketch_update_csr_batch(sketches, csr_list):
+    """Batched CSR update: csr_list[i] = (indptr int64, indices int32, values
+    float32), contiguous CUDA tensors; sketch i takes indptr.shape[0] - 1 rows."""
+    n = len(sketches)
+    hs = _handles(sketches)
+    ip, ix, vv = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+    ns = (ctypes.c_int64 * n)()
+    for i, (a, b, c) in enumerate(csr_list):
+        assert a.is_cuda and a.dtype == torch.int64 and b.dtype == torch.int32 and c.dtype == torch.float32
+        assert a.is_contiguous() and b.is_contiguous() and c.is_contiguous()
+        ip[i], ix[i], vv[i] = a.data_ptr(), b.data_ptr(), c.data_ptr()
+        ns[i] = a.shape[0] - 1
+    _lib.check(_lib.load().sketch_update_csr_batch(hs, ip, ix, vv, ns, n), "sketch_update_csr_batch")
+
+
 def sketch_profile_enable(h, stages="all"):
     """Event-times the given stages (names of _lib.SK_STAGE, or "all")."""
     if stages == "all":

@@ -6,11 +6,11 @@
 //                 then L^{-1} (CholeskyQR: Q = Y L^{-T})
 //   k_jacobi      symmetric eigen-decomposition by parallel-ordered cyclic
 //                 Jacobi: G = C C^T (exact shrink, size m) or the k x k
-//                 Rayleigh-Ritz matrix (Algorithm "Simultaneous Iteration"
-//                 line 5); eigenvalues sorted descending with vectors
+//                 Rayleigh-Ritz matrix (the eigen step of Algorithm
+//                 "Simultaneous Iteration"); eigenvalues sorted descending with vectors
 //   k_threshold   delta = ell-th eigenvalue; T = diag(f) Z^T with
 //                 f_i = sqrt(max(lambda_i - delta, 0) / lambda_i)
-//                 (Sec. 2.3 FD shrink; Algorithm "AeroSketch: Update" line 4)
+//                 (Sec. 2.3 FD shrink; the FD reduce of Algorithm "AeroSketch: Update")
 //
 // All arithmetic is FP64; reductions are in a fixed order, so results do not
 // depend on how many tasks share a launch.

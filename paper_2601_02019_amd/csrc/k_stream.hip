@@ -3,12 +3,12 @@
 // stage serves every task of a batch.
 //
 //   k_ingest       rows -> buffer rows [row0, row0 + n) with dtype conversion
-//                  (Algorithm "AeroSketch: Update" line 1)
+//                  (the insert of Algorithm "AeroSketch: Update")
 //   k_ingest_csr   the same for CSR rows
 //   k_omega        Omega^T (k x d) from Philox4x64-10 + Box-Muller
-//                  (Algorithm "Simultaneous Iteration" line 1)
+//                  (the test matrix of Algorithm "Simultaneous Iteration")
 //   k_nt_partial   split-K partial products C C^T (Gram of the buffer) and
-//                  C Omega (line 2's first product), FP64 accumulation
+//                  C Omega (the first product of the sketch step), FP64 accumulation
 //   k_reduce       fixed-order sum of the split-K partials (deterministic)
 //   k_rebuild      B' = T C: the FD rebuild diag(f) Z^T C (Sec. 2.3)
 //   k_convert_rows FP64 staging -> caller dtype

@@ -7,14 +7,14 @@
 //                 start vector, simul_iter test matrix)
 //   k_win_pi      Algorithm "Power Iteration" on C'^T C' for one level:
 //                 ceil(log2 d) + 1 normalised steps x <- C'^T C' x, then the
-//                 Rayleigh quotient |C' x|^2 (Algorithm "AeroSketch: Update"
-//                 line 7)
+//                 Rayleigh quotient |C' x|^2 (the power-iteration test of
+//                 Algorithm "AeroSketch: Update")
 //   k_gemm_desc   FP64 C = alpha op(A) op(B) + beta C for snapshot, residual
 //                 and restore products
-//   k_blockmask   zeroes the off-entry blocks of W Z (restore of Algorithm
-//                 "AeroSketch: Query" line 4 is per snapshot)
-//   k_shrink_rows rows sqrt(max(lambda_i - lambda_ell, 0)) v_i^T (query
-//                 lines 5-7)
+//   k_blockmask   zeroes the off-entry blocks of W Z (the restore of Algorithm
+//                 "AeroSketch: Query" is per snapshot)
+//   k_shrink_rows rows sqrt(max(lambda_i - lambda_ell, 0)) v_i^T (the query's
+//                 final shrink)
 #include "sk_device.h"
 #include "sk_kernels.h"
 

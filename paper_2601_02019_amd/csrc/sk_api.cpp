@@ -1,7 +1,7 @@
 // sk_api.cpp -- host engine and C ABI (include/sketch.h).
 //
 // The host owns each sketch's state machine: it knows from row counts alone
-// when the buffer fills (Algorithm "AeroSketch: Update" line 2), so a whole
+// when the buffer fills (Algorithm "AeroSketch: Update"), so a whole
 // update call is planned on the host as a list of Task records (ingest
 // segments and shrinks), uploaded once, and executed as a stream-ordered
 // sequence of task-list launches without any device-to-host round trip.
@@ -341,9 +341,6 @@ void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dt
         }
     }
 }
-
-sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
-                          int in_dtype);
 
 sk_status check_handle(sketch_t h, const char* what) {
     if (!h) return fail(SK_EINVAL, std::string(what) + ": NULL handle");
@@ -703,28 +700,35 @@ sk_status sketch_set_memory_budget(int64_t bytes) {
 
 int64_t sketch_memory_in_use(void) { return g_in_use.load(); }
 
-sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n, int32_t count,
-                              int32_t dtype) {
-    if (count < 0 || (count > 0 && (!hs || !rows || !n))) return fail(SK_EINVAL, "sketch_update_batch: bad arguments");
+// Lock-step rounds: round r holds every sketch's r-th ingest segment, then the
+// shrinks those segments triggered, grouped by shrink flavour.  Dense rows
+// (rows[i], dtype) or CSR rows (indptr[i], indices[i], values[i]).
+static sk_status update_batch_impl(const char* what, sketch_t* hs, const void* const* rows,
+                                   const int64_t* const* indptr, const int32_t* const* indices,
+                                   const float* const* values, const int64_t* n, int32_t count,
+                                   int32_t dtype) {
+    const bool csr = indptr != nullptr;
+    if (count < 0 || (count > 0 && (!hs || !n || (!csr && !rows) || (csr && (!indices || !values)))))
+        return fail(SK_EINVAL, std::string(what) + ": bad arguments");
     if (count == 0) return SK_OK;
-    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, "sketch_update_batch: bad dtype");
+    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, std::string(what) + ": bad dtype");
     sk_status rc;
     for (int i = 0; i < count; ++i) {
-        if ((rc = check_handle(hs[i], "sketch_update_batch"))) return rc;
-        if (hs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_update_batch: window sketch");
+        if ((rc = check_handle(hs[i], what))) return rc;
+        if (hs[i]->win) return fail(SK_EUNSUPPORTED, std::string(what) + ": window sketch");
         if (hs[i]->stream != hs[0]->stream || hs[i]->cfg.device != hs[0]->cfg.device)
-            return fail(SK_EINVAL, "sketch_update_batch: sketches must share stream and device");
-        if (n[i] < 0) return fail(SK_EINVAL, "sketch_update_batch: negative row count");
-        if (n[i] > 0 && !rows[i]) return fail(SK_EINVAL, "sketch_update_batch: NULL rows");
+            return fail(SK_EINVAL, std::string(what) + ": sketches must share stream and device");
+        if (n[i] < 0) return fail(SK_EINVAL, std::string(what) + ": negative row count");
+        if (n[i] > 0 && !csr && !rows[i]) return fail(SK_EINVAL, std::string(what) + ": NULL rows");
+        if (n[i] > 0 && csr && (!indptr[i] || !indices[i] || !values[i]))
+            return fail(SK_EINVAL, std::string(what) + ": NULL CSR array");
+        if (csr && hs[i]->d > 16384) return fail(SK_EUNSUPPORTED, std::string(what) + ": d > 16384");
         for (int j = 0; j < i; ++j)
-            if (hs[j] == hs[i]) return fail(SK_EINVAL, "sketch_update_batch: a sketch is listed twice");
+            if (hs[j] == hs[i]) return fail(SK_EINVAL, std::string(what) + ": a sketch is listed twice");
     }
     sketch_t h0 = hs[0];
     HIP_TRY(h0, hipSetDevice(h0->cfg.device));
-    // Lock-step rounds: round r holds every sketch's r-th ingest segment, then
-    // the shrinks those segments triggered, grouped by shrink flavour.
-    struct Cursor { int64_t pos = 0; };
-    std::vector<Cursor> cur((size_t)count);
+    std::vector<int64_t> cur((size_t)count, 0);
     std::vector<sketch_t> owners;
     std::vector<Task> tasks;
     const int64_t es = dtype_size(dtype);
@@ -734,8 +738,8 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
         std::vector<std::pair<sketch_t, Task>> ing, shr;
         for (int i = 0; i < count; ++i) {
             sketch_t h = hs[i];
-            if (cur[i].pos >= n[i]) continue;
-            const int64_t take = std::min<int64_t>(n[i] - cur[i].pos, h->n2 - h->fill);
+            if (cur[i] >= n[i]) continue;
+            const int64_t take = std::min<int64_t>(n[i] - cur[i], h->n2 - h->fill);
             Task t{};
             t.s = h->dev;
             t.kind = T_INGEST;
@@ -744,11 +748,17 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
             t.nrows = (int32_t)take;
             t.src_dtype = dtype;
             t.src_ld = h->d;
-            t.src = (const char*)rows[i] + cur[i].pos * h->d * es;
+            if (csr) {
+                t.indptr = indptr[i] + cur[i];
+                t.indices = indices[i];
+                t.values = values[i];
+            } else {
+                t.src = (const char*)rows[i] + cur[i] * h->d * es;
+            }
             ing.push_back({h, t});
             h->fill += take;
             h->rows_seen += take;
-            cur[i].pos += take;
+            cur[i] += take;
             if (h->fill == h->n2) {
                 Task s{};
                 s.s = h->dev;
@@ -762,7 +772,7 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
                 h->fill = h->ell - 1;
                 h->shrinks += 1;
             }
-            if (cur[i].pos < n[i]) more = true;
+            if (cur[i] < n[i]) more = true;
         }
         for (auto& p : ing) {
             owners.push_back(p.first);
@@ -782,7 +792,19 @@ sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64
             tasks.push_back(p.second);
         }
     }
-    return execute_batched(h0, owners, tasks, dtype);
+    return execute_batched(h0, owners, tasks, csr ? DT_F32 : dtype, csr);
+}
+
+sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n, int32_t count,
+                              int32_t dtype) {
+    return update_batch_impl("sketch_update_batch", hs, rows, nullptr, nullptr, nullptr, n, count, dtype);
+}
+
+sk_status sketch_update_csr_batch(sketch_t* hs, const int64_t* const* indptr, const int32_t* const* indices,
+                                  const float* const* values, const int64_t* n, int32_t count) {
+    if (!indptr) return fail(SK_EINVAL, "sketch_update_csr_batch: NULL indptr list");
+    return update_batch_impl("sketch_update_csr_batch", hs, nullptr, indptr, indices, values, n, count,
+                             SK_F32);
 }
 
 }  // extern "C"
@@ -795,7 +817,7 @@ sk_status sketch_destroy_idle(sketch_t h) {
 // Batched execution: like execute(), but a group also breaks where the shrink
 // flavour (q, dtypes) changes.
 sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
-                          int in_dtype) {
+                          int in_dtype, bool csr) {
     if (tasks.empty()) return SK_OK;
     Task* dt = nullptr;
     HIP_TRY(h, h->arena.upload(tasks, h->stream, &dt));
@@ -812,7 +834,8 @@ sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector
             int max_rows = 0;
             for (size_t u = i; u < j; ++u) max_rows = std::max(max_rows, tasks[u].nrows);
             StageScope sc(g.prof, ST_INGEST, h->stream);
-            HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
+            if (csr) HIP_TRY(h, launch_ingest_csr(dt + i, g.count, max_rows, g.max_d, g.st, h->stream));
+            else HIP_TRY(h, launch_ingest(dt + i, g.count, max_rows, g.max_d, in_dtype, g.st, h->stream));
         } else {
             HIP_TRY(h, run_shrinks(dt + i, g, tasks[i].kind, h->stream));
         }

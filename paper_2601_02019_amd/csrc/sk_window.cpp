@@ -230,7 +230,7 @@ static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) 
 }
 
 // Snapshot (Z, Z^T C'^T C') of the first xi columns of Zd, then the residual
-// C <- C' - C' Z Z^T (Algorithm "AeroSketch: Update" lines 14-16).
+// C <- C' - C' Z Z^T (the dump of Algorithm "AeroSketch: Update").
 static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
     WindowState* w = h->win;
     WinLevel& l = w->lv[(size_t)j];
@@ -262,7 +262,7 @@ static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
     return SK_OK;
 }
 
-// Doubling loop of Algorithm "AeroSketch: Update" lines 9-17 for level j.
+// Doubling loop of Algorithm "AeroSketch: Update" (k = 2, 4, ...) for level j.
 static sk_status doubling(sketch_t h, int j, int64_t ts) {
     WindowState* w = h->win;
     WinLevel& l = w->lv[(size_t)j];
@@ -569,7 +569,7 @@ sk_status window_query(sketch_t h, const double** out) {
         if ((rc = gemm1(h, gd(w->T2, w->chunk, false, w->Zs, li, false, w->Bq, d, d, d, D, -1.0, 1.0)))) return rc;
         W_TRY(sync_reset(h));  // the host entry list of this chunk is reused
     }
-    // eigen-decomposition and the shrink by lambda_ell (query lines 5-7)
+    // eigen-decomposition and the shrink by lambda_ell (the query's final step)
     if ((rc = eig_d(h))) return rc;
     W_TRY(launch_shrink_rows(w->Uq, d, w->lamq, d, ell, w->Xq, ld, d, h->stream));
     if (!raws.empty()) {

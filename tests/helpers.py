@@ -3,7 +3,7 @@
 f_ell(X) = sum_i max(lambda_i - lambda_ell, 0) v_i v_i^T (lambda_ell := 0 when X
 has fewer than ell eigenvalues), written with numpy's LAPACK eigh.  This is
 the Gram-domain form of the FD shrink (Sec. 2.3) and of the query shrink
-(Algorithm "AeroSketch: Query" line 6).
+(the final step of Algorithm "AeroSketch: Query").
 """
 import numpy as np
 

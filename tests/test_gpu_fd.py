@@ -260,6 +260,30 @@ def test_csr_ingest_equals_dense():
     assert torch.equal(s3.query(), B1)
 
 
+def test_csr_batch_equals_individual_csr_bitwise():
+    from paper_2601_02019_amd import sketch_update_csr_batch
+    shapes = [(256, 16, "rand"), (256, 16, "rand"), (128, 8, "exact"), (300, 20, "rand")]
+    sites = [synth.streams.sparse_sites(150 + 70 * i, d=d, density=0.03, seed=6, site=i)
+             for i, (d, ell, _) in enumerate(shapes)]
+    dev = [tuple(torch.from_numpy(a).cuda() for a in site) for site in sites]
+    alone, mixed = [], []
+    for i, (d, ell, mode) in enumerate(shapes):
+        a = make(d, ell, shrink=mode, state_dtype="f32", proj_dtype="bf16", seed=2, stream_id=i)
+        a.update_csr(*dev[i])
+        alone.append(a.query())
+        mixed.append(make(d, ell, shrink=mode, state_dtype="f32", proj_dtype="bf16", seed=2, stream_id=i))
+    sketch_update_csr_batch(mixed, dev)
+    for i in range(len(shapes)):
+        assert torch.equal(mixed[i].query(), alone[i]), i
+    # and the FP64 exact site against the oracle on the densified rows
+    d, ell = 128, 8
+    s = make(d, ell)
+    sketch_update_csr_batch([s], [dev[2]])
+    o = oracle.FD(d, ell)
+    o.update(synth.streams.csr_to_dense(*sites[2], d))
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
 # ------------------------------------------------------------------ errors
 def test_error_paths_leave_state_unchanged():
     from paper_2601_02019_amd import SketchError, sketch_update
