@@ -27,34 +27,6 @@ constexpr int PB = 32;    // pair-block size (two blocks)
 constexpr int PBL = 33;   // padded LDS leading dimension
 constexpr int COOP_MAX_SWEEPS = 40;
 
-// Grid barrier for a cooperative launch: an arrival counter (zeroed by the
-// host before the launch) with agent-scope release on arrival and acquire
-// while waiting.  Every workgroup is resident (cooperative launch), so every
-// wait ends; the spin is bounded all the same and records a timeout in
-// bar[1] instead of hanging.
-struct GridBar {
-    unsigned* bar;
-    unsigned nblk;
-    unsigned epoch;
-    __device__ void sync() {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            ++epoch;
-            const unsigned target = epoch * nblk;
-            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned spins = 0;
-            while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 26)) {
-                    __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-        }
-        __syncthreads();
-    }
-};
-
 __device__ __forceinline__ int rrp(int slot, int step, int ne) {
     return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ne - 1);
 }

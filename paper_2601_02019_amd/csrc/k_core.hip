@@ -182,9 +182,9 @@ __global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int
 
 // Descriptor form: X = chol(W)^{-1} for each descriptor (blockIdx.z).
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_cholinv_desc(const SmallDesc* ds, int lds_max) {
+__global__ __launch_bounds__(1024) void k_cholinv_desc(DescArg<SmallDesc> ds, int lds_max) {
     extern __shared__ double lds[];
-    const SmallDesc& q = ds[blockIdx.z];
+    const SmallDesc q = ds.get();
     if (q.n <= 0 || LDS != (q.n <= lds_max)) return;
     cholinv_body(q.A, q.lda, q.X, q.ldx, q.n, LDS ? lds : q.work);
 }
@@ -357,9 +357,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(const Task* tasks, int lds_max,
 
 // Descriptor form: eigen-decomposition of A (n x n) into U / lam.
 template <bool LDS>
-__global__ __launch_bounds__(1024) void k_jacobi_desc(const SmallDesc* ds, int lds_max, int lds_doubles) {
+__global__ __launch_bounds__(1024) void k_jacobi_desc(DescArg<SmallDesc> ds, int lds_max, int lds_doubles) {
     extern __shared__ double lds[];
-    const SmallDesc& q = ds[blockIdx.z];
+    const SmallDesc q = ds.get();
     if (q.n <= 0 || LDS != (q.n <= lds_max)) return;
     double* vt = (LDS && 2 * q.n * q.n <= lds_doubles) ? lds + q.n * q.n : nullptr;
     jacobi_body(q.A, q.lda, q.n, LDS ? lds : q.work, q.work2, q.X, q.ldx, q.lam, q.info, vt);
@@ -483,7 +483,7 @@ hipError_t launch_jacobi(const Task* tasks, int count, int max_n, bool any_small
     return hipGetLastError();
 }
 
-hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+static hipError_t cholinv_desc_impl(DescArg<SmallDesc> ds, int count, int max_n, hipStream_t st) {
     const int cap = chol_lds_max();
     if (cap > 0) {
         const int nn = max_n < cap ? max_n : cap;
@@ -496,7 +496,7 @@ hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+static hipError_t jacobi_desc_impl(DescArg<SmallDesc> ds, int count, int max_n, hipStream_t st) {
     const int cap = jacobi_lds_max();
     if (cap > 0) {
         const int nn = max_n < cap ? max_n : cap;
@@ -508,6 +508,19 @@ hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStre
     }
     if (max_n > cap) hipLaunchKernelGGL((k_jacobi_desc<false>), dim3(1, 1, (unsigned)count), dim3(1024), 0, st, ds, cap, 0);
     return hipGetLastError();
+}
+
+hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+    return cholinv_desc_impl(DescArg<SmallDesc>{ds, {}}, count, max_n, st);
+}
+hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+    return jacobi_desc_impl(DescArg<SmallDesc>{ds, {}}, count, max_n, st);
+}
+hipError_t launch_cholinv1(const SmallDesc& q, hipStream_t st) {
+    return cholinv_desc_impl(DescArg<SmallDesc>{nullptr, q}, 1, q.n, st);
+}
+hipError_t launch_jacobi1(const SmallDesc& q, hipStream_t st) {
+    return jacobi_desc_impl(DescArg<SmallDesc>{nullptr, q}, 1, q.n, st);
 }
 
 hipError_t launch_threshold(const Task* tasks, int count, int max_ell, int max_m, hipStream_t st) {

@@ -80,8 +80,8 @@ __global__ __launch_bounds__(256) void k_rownorm(const T* rows, int64_t ld, int6
 
 
 // M[t][c] = normal (c mod 4) of the block at counter (t, c / 4, c2, c3)
-__global__ __launch_bounds__(256) void k_philox_mat(const MatGenDesc* ds) {
-    const MatGenDesc& q = ds[blockIdx.z];
+__global__ __launch_bounds__(256) void k_philox_mat(DescArg<MatGenDesc> ds) {
+    const MatGenDesc q = ds.get();
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
     if (t >= q.rows || c >= q.cols) return;
@@ -97,74 +97,97 @@ __device__ double block_sum(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// One workgroup per level; x (d) and y (r) live in LDS.
-__global__ __launch_bounds__(256) void k_win_pi(const PiDesc* ds) {
+// Power iteration of all levels in one cooperative launch: blockIdx.y is the
+// level, its G workgroups own column slabs of C (r x d) and of x.  One level
+// barrier per step: each workgroup writes the partial y = C x of its slab
+// (x not yet normalised) and its slab's |x|^2; after the barrier every
+// workgroup sums the G partials in a fixed order, scales y by 1 / |x| and
+// forms its slab of the next x = C^T y.  The partial buffers alternate, so a
+// buffer is rewritten only two barriers after it was read.
+__global__ __launch_bounds__(256) void k_win_pi_coop(const PiDesc* ds, int G, int rmax, double* part,
+                                                    unsigned* bars) {
     extern __shared__ double sm[];
     __shared__ double red[4];
-    const PiDesc& q = ds[blockIdx.z];
-    const int r = q.r, d = q.d, tid = threadIdx.x;
-    double* x = sm;
-    double* y = sm + d;
+    const int lv = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+    const PiDesc& q = ds[lv];
+    const int r = q.r, d = q.d;
     if (r <= 0) {
-        if (tid == 0) *q.out = 0.0;
+        if (w == 0 && tid == 0) *q.out = 0.0;
         return;
     }
-    double loc = 0.0;
-    for (int t = tid; t < d; t += 256) {
-        x[t] = w_gauss(q.seed, q.stream, (uint64_t)t, 0ull, q.c2, q.c3, 0);
-        loc = fma(x[t], x[t], loc);
-    }
-    double nrm = sqrt(block_sum(loc, red));
-    if (nrm > 0.0)
-        for (int t = tid; t < d; t += 256) x[t] /= nrm;
+    GridBar bar{bars + 2 * lv, (unsigned)G, 0u};
+    const int sw = (d + G - 1) / G;
+    const int c0 = min(d, w * sw), c1 = min(d, c0 + sw), nc = c1 - c0;
+    double* xs = sm;            // slab of x (sw)
+    double* y = sm + sw;        // r
+    double* colp = y + rmax;    // 4 x 64 column partials
+    // per level: py[2][G][rmax], pn[2][G]
+    double* py = part + (int64_t)lv * 2 * G * (rmax + 1);
+    double* pn = py + (int64_t)2 * G * rmax;
+    const int64_t ldc = q.ldc;
+    const double* C = q.C;
+
+    // y = C x / |x| in LDS; returns |x|^2 (the same value in every workgroup)
+    auto apply_C = [&](int b) {
+        for (int i = tid; i < r; i += 256) {
+            const double* Ci = C + (int64_t)i * ldc + c0;
+            double acc = 0.0;
+            for (int c = 0; c < nc; ++c) acc = fma(Ci[c], xs[c], acc);
+            py[((int64_t)b * G + w) * rmax + i] = acc;
+        }
+        double loc = 0.0;
+        for (int c = tid; c < nc; c += 256) loc = fma(xs[c], xs[c], loc);
+        const double s2 = block_sum(loc, red);
+        if (tid == 0) pn[b * G + w] = s2;
+        bar.sync();
+        double tot = 0.0;
+        for (int ww = 0; ww < G; ++ww) tot += pn[b * G + ww];
+        const double inv = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+        for (int i = tid; i < r; i += 256) {
+            double acc = 0.0;
+            for (int ww = 0; ww < G; ++ww) acc += py[((int64_t)b * G + ww) * rmax + i];
+            y[i] = acc * inv;
+        }
+        __syncthreads();
+        return tot;
+    };
+
+    for (int c = tid; c < nc; c += 256) xs[c] = w_gauss(q.seed, q.stream, (uint64_t)(c0 + c), 0ull, q.c2, q.c3, 0);
     __syncthreads();
-    const int wave = tid >> 6, lane = tid & 63;
+    const int lane = tid & 63, grp = tid >> 6;
     bool zero = false;
-    for (int it = 0; it < q.steps && !zero; ++it) {
-        for (int i = wave; i < r; i += 4) {  // y = C x
-            double acc = 0.0;
-            for (int t = lane; t < d; t += 64) acc = fma(q.C[(int64_t)i * q.ldc + t], x[t], acc);
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-            if (lane == 0) y[i] = acc;
-        }
-        __syncthreads();
-        loc = 0.0;
-        for (int t = tid; t < d; t += 256) {  // x = C^T y
-            double acc = 0.0;
-            for (int i = 0; i < r; ++i) acc = fma(q.C[(int64_t)i * q.ldc + t], y[i], acc);
-            x[t] = acc;
-            loc = fma(acc, acc, loc);
-        }
-        nrm = sqrt(block_sum(loc, red));
-        if (nrm == 0.0) {
+    for (int it = 0; it < q.steps; ++it) {
+        if (apply_C(it & 1) == 0.0) {  // uniform across the level's workgroups
             zero = true;
-        } else {
-            for (int t = tid; t < d; t += 256) x[t] /= nrm;
+            break;
         }
-        __syncthreads();
+        for (int u = 0; u * 64 < nc; ++u) {  // x slab = C^T y, four row groups per column
+            const int c = u * 64 + lane;
+            double acc = 0.0;
+            if (c < nc)
+                for (int i = grp; i < r; i += 4) acc = fma(C[(int64_t)i * ldc + c0 + c], y[i], acc);
+            colp[grp * 64 + lane] = acc;
+            __syncthreads();
+            if (grp == 0 && c < nc) xs[c] = (colp[lane] + colp[64 + lane]) + (colp[128 + lane] + colp[192 + lane]);
+            __syncthreads();
+        }
     }
-    if (zero) {
-        if (tid == 0) *q.out = 0.0;
-        return;
+    double rq = 0.0;
+    if (!zero && apply_C(q.steps & 1) > 0.0 && w == 0) {
+        double loc = 0.0;
+        for (int i = tid; i < r; i += 256) loc = fma(y[i], y[i], loc);
+        rq = block_sum(loc, red);
     }
-    for (int i = wave; i < r; i += 4) {
-        double acc = 0.0;
-        for (int t = lane; t < d; t += 64) acc = fma(q.C[(int64_t)i * q.ldc + t], x[t], acc);
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if (lane == 0) y[i] = acc;
+    if (w == 0 && tid == 0) {
+        const bool timed_out = __hip_atomic_load(bars + 2 * lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        *q.out = timed_out ? __builtin_nan("") : rq;
     }
-    __syncthreads();
-    loc = 0.0;
-    for (int i = tid; i < r; i += 256) loc = fma(y[i], y[i], loc);
-    const double rq = block_sum(loc, red);
-    if (tid == 0) *q.out = rq;
 }
 
 // ---------------------------------------------------------------- GEMM
-__global__ __launch_bounds__(256) void k_gemm_desc(const GemmDesc* ds) {
-    const GemmDesc& g = ds[blockIdx.z];
+// One 64 x 64 tile (r0, c0) of C = alpha op(A) op(B) + beta C, 256 threads.
+__device__ void gemm_tile(const GemmDesc& g, int r0, int c0) {
     const int M = g.M, N = g.N, K = g.K;
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
     if (r0 >= M || c0 >= N) return;
     __shared__ double As[16][64 + 2];
     __shared__ double Bs[16][64 + 2];
@@ -223,6 +246,40 @@ __global__ __launch_bounds__(256) void k_gemm_desc(const GemmDesc* ds) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_gemm_desc(DescArg<GemmDesc> ds) {
+    gemm_tile(ds.get(), blockIdx.y * 64, blockIdx.x * 64);
+}
+
+// Split-K partial of one GEMM descriptor: blockIdx.z = split, blockIdx.y/x
+// = 64 x 64 tile; part[split] = op(A)[:, chunk] op(B)[chunk, :].
+__global__ __launch_bounds__(256) void k_gemm_part(DescArg<GemmDesc> dp) {
+    GemmDesc g = dp.one;
+    const int s = blockIdx.z;
+    const int kb = s * g.kchunk, ke = min(g.K, kb + g.kchunk);
+    if (kb >= ke) return;
+    // shift A and B to the chunk and compute an ordinary product into part[s]
+    g.A = g.ta ? g.A + (int64_t)kb * g.lda : g.A + kb;
+    g.B = g.tb ? g.B + kb : g.B + (int64_t)kb * g.ldb;
+    g.K = ke - kb;
+    g.C = g.part + (int64_t)s * g.M * g.N;
+    g.ldc = g.N;
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    gemm_tile(g, blockIdx.y * 64, blockIdx.x * 64);
+}
+
+// C = alpha * (sum of the splits in order) + beta C.
+__global__ __launch_bounds__(256) void k_gemm_reduce(DescArg<GemmDesc> dp) {
+    const GemmDesc g = dp.one;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)g.M * g.N) return;
+    double acc = 0.0;
+    for (int s = 0; s < g.nsplit; ++s) acc += g.part[(int64_t)s * g.M * g.N + e];
+    const int r = (int)(e / g.N), c = (int)(e % g.N);
+    double* p = g.C + (int64_t)r * g.ldc + c;
+    *p = (g.beta == 0.0) ? g.alpha * acc : fma(g.alpha, acc, g.beta * *p);
+}
+
 // S (D x D): keep S[a][b] only when directions a and b belong to one snapshot
 __global__ __launch_bounds__(256) void k_blockmask(double* S, int ld, int D, const int32_t* ent) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -255,20 +312,59 @@ hipError_t launch_rownorm(const void* rows, int64_t ld, int dtype, int64_t n, in
 }
 
 hipError_t launch_philox_mat(const void* descs, int count, int max_rows, int max_cols, hipStream_t st) {
+    DescArg<MatGenDesc> a{(const MatGenDesc*)descs, {}};
     hipLaunchKernelGGL(k_philox_mat, dim3((unsigned)((max_rows + 255) / 256), (unsigned)max_cols, (unsigned)count),
-                       dim3(256), 0, st, (const MatGenDesc*)descs);
+                       dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_win_pi(const void* descs, int count, int max_d, int max_r, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)(max_d + max_r);
-    hipLaunchKernelGGL(k_win_pi, dim3(1, 1, (unsigned)count), dim3(256), lds, st, (const PiDesc*)descs);
+hipError_t launch_philox_mat1(const MatGenDesc& m, hipStream_t st) {
+    DescArg<MatGenDesc> a{nullptr, m};
+    hipLaunchKernelGGL(k_philox_mat, dim3((unsigned)((m.rows + 255) / 256), (unsigned)m.cols, 1u), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int win_pi_groups(int d) {
+    int g = (d + 63) / 64;
+    return g < 1 ? 1 : (g > 32 ? 32 : g);
+}
+
+hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double* part, unsigned* bars,
+                         hipStream_t st) {
+    const int G = win_pi_groups(d);
+    const int sw = (d + G - 1) / G;
+    const size_t lds = sizeof(double) * (size_t)(sw + max_r + 256);
+    hipError_t e = hipMemsetAsync(bars, 0, sizeof(unsigned) * 2 * (size_t)count, st);
+    if (e != hipSuccess) return e;
+    const PiDesc* dp = (const PiDesc*)descs;
+    int gg = G, rm = max_r;
+    void* kargs[] = {(void*)&dp, (void*)&gg, (void*)&rm, (void*)&part, (void*)&bars};
+    return hipLaunchCooperativeKernel((const void*)k_win_pi_coop, dim3((unsigned)G, (unsigned)count), dim3(256),
+                                      kargs, (unsigned)lds, st);
+}
+
+hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st) {
+    DescArg<GemmDesc> a{nullptr, g};
+    hipLaunchKernelGGL(k_gemm_part, dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)g.nsplit),
+                       dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t tot = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_desc(const GemmDesc* ds, int count, int max_M, int max_N, hipStream_t st) {
+    DescArg<GemmDesc> a{ds, {}};
     hipLaunchKernelGGL(k_gemm_desc, dim3((unsigned)((max_N + 63) / 64), (unsigned)((max_M + 63) / 64), (unsigned)count),
-                       dim3(256), 0, st, ds);
+                       dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm1(const GemmDesc& g, hipStream_t st) {
+    DescArg<GemmDesc> a{nullptr, g};
+    hipLaunchKernelGGL(k_gemm_desc, dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), 1u), dim3(256), 0,
+                       st, a);
     return hipGetLastError();
 }
 

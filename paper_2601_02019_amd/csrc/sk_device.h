@@ -86,6 +86,9 @@ struct SmallDesc {
 };
 
 // Descriptor of one FP64 product C = alpha op(A) op(B) + beta C.
+// With nsplit > 1 the K range is cut into nsplit chunks of kchunk: the
+// partial products go to part (nsplit x M x N) and a fixed-order reduction
+// writes C, so the result does not depend on the launch shape.
 struct GemmDesc {
     const double* A;
     const double* B;
@@ -94,6 +97,8 @@ struct GemmDesc {
     int32_t lda, ldb, ldc;
     int32_t ta, tb;
     double alpha, beta;
+    double* part;
+    int32_t nsplit, kchunk;
 };
 
 // Gaussian matrix from Philox: M[t][c] = normal (c mod 4) of the block at
@@ -104,7 +109,9 @@ struct MatGenDesc {
     uint64_t seed, stream, c2, c3;
 };
 
-// Power iteration of one window level on C (r x d).
+// Power iteration of one window level on C (r x d).  out receives the
+// Rayleigh quotient, or NaN when a grid barrier of the cooperative kernel
+// timed out.
 struct PiDesc {
     const double* C;
     double* out;
@@ -127,6 +134,44 @@ struct CoopEig {
     double* stats;       // 8 diagnostic accumulators
     uint32_t* bar;       // grid barrier (2 words, zeroed before launch)
     int32_t n, ldin, lu, pad;
+};
+
+// Grid barrier for a cooperative launch: an arrival counter (zeroed by the
+// host before the launch) with agent-scope release on arrival and acquire
+// while waiting.  Every workgroup is resident (cooperative launch), so every
+// wait ends; the spin is bounded all the same and records a timeout in
+// bar[1] instead of hanging.
+struct GridBar {
+    unsigned* bar;
+    unsigned nblk;
+    unsigned epoch;
+    __device__ void sync() {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ++epoch;
+            const unsigned target = epoch * nblk;
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned spins = 0;
+            while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1u << 26)) {
+                    __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// Descriptor argument of the pointer-driven kernels: a device list indexed by
+// blockIdx.z, or (list == nullptr) one descriptor passed by value, which
+// saves the host-to-device copy of a single descriptor.
+template <typename D>
+struct DescArg {
+    const D* list;
+    D one;
+    __device__ D get() const { return list ? list[blockIdx.z] : one; }
 };
 
 // Eigen-problem size of a task: the buffer rows (exact shrink / query) or k.

@@ -38,7 +38,18 @@ hipError_t launch_jacobi_coop(const CoopEig& args, hipStream_t st);
 hipError_t launch_rownorm(const void* rows, int64_t ld, int dtype, int64_t n, int d, double* out,
                           hipStream_t st);
 hipError_t launch_philox_mat(const void* descs, int count, int max_rows, int max_cols, hipStream_t st);
-hipError_t launch_win_pi(const void* descs, int count, int max_d, int max_r, hipStream_t st);
+// Workgroups per level of the cooperative power iteration for dimension d.
+int win_pi_groups(int d);
+// part: count * 2 * win_pi_groups(d) * (max_r + 1) doubles; bars: 2 * count words.
+hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double* part, unsigned* bars,
+                         hipStream_t st);
+// One split-K product (descriptor by value, with part, nsplit, kchunk set).
+hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st);
+// Single-descriptor launches with the descriptor passed by value.
+hipError_t launch_gemm1(const GemmDesc& g, hipStream_t st);
+hipError_t launch_philox_mat1(const MatGenDesc& m, hipStream_t st);
+hipError_t launch_cholinv1(const SmallDesc& q, hipStream_t st);
+hipError_t launch_jacobi1(const SmallDesc& q, hipStream_t st);
 hipError_t launch_blockmask(double* S, int ld, int D, const int32_t* ent, hipStream_t st);
 hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n, int ell, double* X,
                               int64_t ldx, int d, hipStream_t st);

@@ -84,9 +84,15 @@ struct WindowState {
     int chunk = 0;
     double *ubuf = nullptr, *part = nullptr, *stats = nullptr;
     int32_t* ctrl = nullptr;
+    // cooperative power iteration: slab partials and per-level barriers
+    double* pi_part = nullptr;
+    unsigned* pi_bars = nullptr;
+    // split-K partials of the skinny products (long K, few output tiles)
+    double* gpart = nullptr;
+    int64_t gpart_cap = 0;
 };
 
-static const int kWinDmax = 4096;  // LDS of the power-iteration kernel
+static const int kWinDmax = 4096;  // largest d of a window sketch
 
 #define W_TRY(expr)                                                                         \
     do {                                                                                    \
@@ -135,34 +141,47 @@ static GemmDesc gd(const double* A, int lda, bool ta, const double* B, int ldb, 
     return g;
 }
 
-static sk_status gemm1(sketch_t h, const GemmDesc& g) {
-    if (g.M <= 0 || g.N <= 0) return SK_OK;
-    std::vector<GemmDesc> v{g};
-    const GemmDesc* dp = nullptr;
-    hipError_t e = put_desc(h, v, &dp);
-    if (e != hipSuccess) return h->device_fail(std::string("window desc: ") + hipGetErrorString(e));
-    e = launch_gemm_desc(dp, 1, g.M, g.N, h->stream);
+static sk_status gemm1(sketch_t h, const GemmDesc& g0) {
+    if (g0.M <= 0 || g0.N <= 0) return SK_OK;
+    WindowState* w = h->win;
+    GemmDesc g = g0;
+    // products with few output tiles and a long K (C' Omega, K^T K, C' Z ...)
+    // are cut along K so that enough workgroups take part; the cut depends
+    // on the shape alone and the partials are summed in a fixed order
+    const int64_t tiles = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
+    hipError_t e;
+    if (tiles < 64 && g.K >= 128) {
+        int ns = (int)std::min<int64_t>((g.K + 31) / 32, std::max<int64_t>(2, 256 / tiles));
+        const int kc = (int)round_up((g.K + ns - 1) / ns, 16);
+        ns = (g.K + kc - 1) / kc;
+        if (ns > 1 && (int64_t)ns * g.M * g.N <= w->gpart_cap) {
+            g.part = w->gpart;
+            g.nsplit = ns;
+            g.kchunk = kc;
+            e = launch_gemm_split(g, h->stream);
+            if (e != hipSuccess) return h->device_fail(std::string("window split gemm: ") + hipGetErrorString(e));
+            return SK_OK;
+        }
+    }
+    e = launch_gemm1(g, h->stream);
     if (e != hipSuccess) return h->device_fail(std::string("window gemm: ") + hipGetErrorString(e));
     return SK_OK;
 }
 
 static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
-    std::vector<SmallDesc> v{q};
-    const SmallDesc* dp = nullptr;
-    hipError_t e = put_desc(h, v, &dp);
-    if (e == hipSuccess) e = eig ? launch_jacobi_desc(dp, 1, q.n, h->stream) : launch_cholinv_desc(dp, 1, q.n, h->stream);
+    hipError_t e = eig ? launch_jacobi1(q, h->stream) : launch_cholinv1(q, h->stream);
     if (e != hipSuccess) return h->device_fail(std::string("window small solve: ") + hipGetErrorString(e));
     return SK_OK;
 }
 
-// In-place orthonormal basis of K (rows x k, ld kmax): `passes` CholeskyQR
-// passes through Q1d; the result is left in K.
-static sk_status cholqr_d(sketch_t h, double* K, int rows, int k, int passes) {
+// Orthonormal basis of Kd (rows x k, ld kmax) by `passes` CholeskyQR passes;
+// each pass writes Q1d and swaps the two buffers, so the basis ends in Kd.
+static sk_status cholqr_d(sketch_t h, int rows, int k, int passes) {
     WindowState* w = h->win;
     const int lk = w->kmax;
     sk_status rc;
     for (int p = 0; p < passes; ++p) {
-        if ((rc = gemm1(h, gd(K, lk, true, K, lk, false, w->Wk, lk, k, k, rows)))) return rc;
+        if ((rc = gemm1(h, gd(w->Kd, lk, true, w->Kd, lk, false, w->Wk, lk, k, k, rows)))) return rc;
         SmallDesc sd{};
         sd.A = w->Wk;
         sd.lda = lk;
@@ -171,8 +190,8 @@ static sk_status cholqr_d(sketch_t h, double* K, int rows, int k, int passes) {
         sd.n = k;
         sd.work = w->w1;
         if ((rc = small1(h, false, sd))) return rc;
-        if ((rc = gemm1(h, gd(K, lk, false, w->Xk, lk, true, w->Q1d, lk, rows, k, k)))) return rc;
-        W_TRY(hipMemcpyAsync(K, w->Q1d, sizeof(double) * (size_t)rows * lk, hipMemcpyDeviceToDevice, h->stream));
+        if ((rc = gemm1(h, gd(w->Kd, lk, false, w->Xk, lk, true, w->Q1d, lk, rows, k, k)))) return rc;
+        std::swap(w->Kd, w->Q1d);
     }
     return SK_OK;
 }
@@ -197,18 +216,13 @@ static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) 
     m.stream = w->stream;
     m.c2 = (uint64_t)ts;
     m.c3 = tag;
-    {
-        std::vector<MatGenDesc> v{m};
-        const MatGenDesc* dp = nullptr;
-        W_TRY(put_desc(h, v, &dp));
-        W_TRY(launch_philox_mat(dp, 1, d, k, h->stream));
-    }
+    W_TRY(launch_philox_mat1(m, h->stream));
     for (int it = 0; it <= w->q; ++it) {
-        if (it > 0 && (rc = cholqr_d(h, w->Kd, d, k, 1))) return rc;
+        if (it > 0 && (rc = cholqr_d(h, d, k, 1))) return rc;
         if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->Y, lk, r, k, d)))) return rc;
         if ((rc = gemm1(h, gd(C, ldc, true, w->Y, lk, false, w->Kd, lk, d, k, r)))) return rc;
     }
-    if ((rc = cholqr_d(h, w->Kd, d, k, 2))) return rc;  // Kd now holds Q
+    if ((rc = cholqr_d(h, d, k, 2))) return rc;  // Kd now holds Q
     if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->CQ, lk, r, k, d)))) return rc;
     if ((rc = gemm1(h, gd(w->CQ, lk, true, w->CQ, lk, false, w->Mk, lk, k, k, r)))) return rc;
     SmallDesc sd{};
@@ -374,6 +388,10 @@ sk_status window_create(sketch_t h) {
     W_TRY(A(&w->part, 256));
     W_TRY(A(&w->stats, 16));
     W_TRY(h->dalloc((void**)&w->ctrl, 64 * sizeof(int32_t)));
+    W_TRY(A(&w->pi_part, (size_t)w->L * 2 * win_pi_groups(d) * (n2 + 1)));
+    W_TRY(h->dalloc((void**)&w->pi_bars, sizeof(unsigned) * 2 * (size_t)w->L));
+    w->gpart_cap = (int64_t)1 << 21;
+    W_TRY(A(&w->gpart, (size_t)w->gpart_cap));
     w->acap = 1 << 20;
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
@@ -465,9 +483,12 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
         }
         const PiDesc* dp = nullptr;
         W_TRY(put_desc(h, pis, &dp));
-        W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, h->stream));
+        W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, w->pi_part, w->pi_bars, h->stream));
         W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
         W_TRY(sync_reset(h));
+        for (int j : pj)
+            if (std::isnan(w->h_pi[j]))
+                return h->device_fail("window: power iteration failed (barrier timeout or non-finite rows)");
         for (int j : pj) {
             if (w->h_pi[j] >= w->lv[(size_t)j].theta / 2.0) {
                 sk_status rc = doubling(h, j, i);
