@@ -39,13 +39,16 @@ def parse():
                     help="prefix of the stream on which the exact-SVD FD path is timed")
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-err", action="store_true",
+                    help="skip the covariance-error evaluation (torch eigvalsh) of the timed sketch")
     ap.add_argument("--cpu-shrinks", type=int, default=1,
                     help="shrinks of the CPU oracle sample")
-    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving"],
+    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy"],
                     default="persistent",
                     help="persistent: the tight-error single stream (default); small: the FP64 exact "
                          "small stream; window: the sliding-window stream; sites: 64 CSR sites with "
-                         "tree merges; serving: many concurrent streams with Poisson bursts")
+                         "tree merges; serving: many concurrent streams with Poisson bursts; copy: a "
+                         "plain device copy of known size (HBM reference and counter calibration)")
     ap.add_argument("--window-rows", type=int, default=200_000, help="rows of the window stream")
     ap.add_argument("--site-rows", type=int, default=100_000, help="rows per site")
     ap.add_argument("--sites", type=int, default=64)
@@ -93,6 +96,22 @@ def cov_err(AtA, B):
     D = (D + D.T) / 2
     ev = torch.linalg.eigvalsh(D)
     return float(ev.abs().max())
+
+
+def measured_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known size), or None
+    when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, source), "rb").read()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def jacobi_flops(n, sweeps):
@@ -446,6 +465,29 @@ def sites_main(args):
                "cpu_baseline": cpu})
 
 
+def copy_main(args):
+    """A plain device-to-device copy of 1 GiB, args.steps times: the measured
+    HBM rate, and a kernel of known traffic for calibrating the FETCH_SIZE /
+    WRITE_SIZE counters (2^30 bytes read and 2^30 written per launch)."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(max(1, args.warmup)):
+        dst.copy_(src)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gbs = 2 * 4 * n / (ms / 1e3) / 1e9
+    base_line(args, gbs, "GB/s", ms, "device copy of 2^30 bytes (read + write)",
+              {"dtype": "f32", "bytes_per_launch": 2 * 4 * n, "frac_of_8TBs": gbs / PEAK_HBM_GBS})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -454,7 +496,7 @@ def main():
         sys.exit(2)
     if args.workload != "persistent":
         return {"serving": serving_main, "small": small_main, "window": window_main,
-                "sites": sites_main}[args.workload](args)
+                "sites": sites_main, "copy": copy_main}[args.workload](args)
     import torch
     from paper_2601_02019_amd import Sketch
 
@@ -500,7 +542,8 @@ def main():
         achieved = flops / (avg_ms / 1e3) / 1e12
         roofline = {"bound": "alu", "kernel": "k_jacobi_coop (FP64 block Jacobi, n=%d)" % ell,
                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                    "frac": achieved / PEAK_FP64_TFLOPS,
+                    "traffic": measured_traffic("k_jacobi_coop", "paper_2601_02019_amd/csrc/k_coop.hip"),
                     "avg_launch_ms": avg_ms, "sweeps_per_solve": sweeps,
                     "algorithmic_flops_per_launch": flops}
     else:
@@ -535,11 +578,13 @@ def main():
         ra.close()
 
     # full-stream error of the timed sketch
-    AtA = gram_f64(A)
-    fro2 = float(torch.trace(AtA))
-    # the sketch saw the stream (warmup + steps) times: compare with that many copies
-    passes = args.warmup + args.steps
-    err_full = cov_err(passes * AtA, B) / (passes * fro2)
+    err_full = None
+    if not args.no_err:
+        AtA = gram_f64(A)
+        fro2 = float(torch.trace(AtA))
+        # the sketch saw the stream (warmup + steps) times: compare with that many copies
+        passes = args.warmup + args.steps
+        err_full = cov_err(passes * AtA, B) / (passes * fro2)
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample
     cpu = None
