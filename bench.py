@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--bursts", type=int, default=2000, help="bursts per load point")
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9",
                     help="offered loads as fractions of the measured saturation rate")
-    ap.add_argument("--row-cap", type=int, default=1024, help="rows of one stream per serving tick")
+    ap.add_argument("--row-cap", type=int, default=4096, help="rows of one stream per serving tick")
+    ap.add_argument("--shrink-cap", type=int, default=1,
+                    help="shrinks of one stream per serving tick (more for ell < 64)")
     ap.add_argument("--pool-rows", type=int, default=4096, help="resident rows per stream")
     return ap.parse_args()
 
@@ -199,7 +201,7 @@ def serving_main(args):
     torch.cuda.synchronize()
     print(f"[bench] {args.streams} stream pools generated in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
-    srv = Server(max_inflight=2, max_rows_per_tick=args.row_cap)
+    srv = Server(max_inflight=2, max_rows_per_tick=args.row_cap, max_shrinks_per_tick=args.shrink_cap)
     ids = [srv.open(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=1, seed=5,
                     stream_id=i) for i, (d, ell) in enumerate(zip(ds, ells))]
     st = srv.stats()
@@ -237,7 +239,8 @@ def serving_main(args):
                                "U{16..256}, rank 2 ell low-rank + noise, log-uniform bursts 1-4096 "
                                "rows, Poisson arrivals; randomized shrink, bf16 projection, q=1"
                                % args.streams,
-                   "streams": args.streams, "bursts_per_point": args.bursts, "row_cap": args.row_cap},
+                   "streams": args.streams, "bursts_per_point": args.bursts, "row_cap": args.row_cap,
+                   "shrink_cap": args.shrink_cap},
         "saturation": {"rows_per_s": sat_rows, "bursts_per_s": sat_bursts},
         "latency": points,
         "p99_ms_at_highest_load": hi["p99_ms"] if hi else None,

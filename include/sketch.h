@@ -206,6 +206,11 @@ typedef struct {
     void* clock_ctx;
     int32_t use_given_stream;     /* 1: hip_stream as given, also NULL (the null
                                      stream); 0: NULL means a server-owned one   */
+    int32_t max_shrinks_per_tick; /* rows of one stream per tick are also capped
+                                     at this many shrinks' worth ((ell + 1) rows
+                                     each; 64 / ell times as many for ell < 64),
+                                     0 = no cap: keeps ticks short, so small
+                                     bursts do not wait behind large ones      */
 } sk_server_config;
 
 typedef struct {

@@ -300,10 +300,11 @@ class Server:
     current one), or False for a stream of the server's own."""
 
     def __init__(self, device=0, max_inflight=2, memory_budget=0, max_rows_per_tick=0, clock=None,
-                 stream=None):
+                 stream=None, max_shrinks_per_tick=0):
         cfg = server_config_init()
         cfg.device, cfg.max_inflight = device, max_inflight
         cfg.memory_budget, cfg.max_rows_per_tick = int(memory_budget), int(max_rows_per_tick)
+        cfg.max_shrinks_per_tick = int(max_shrinks_per_tick)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         if stream is not False:

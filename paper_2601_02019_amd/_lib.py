@@ -52,6 +52,7 @@ class sk_server_config(ctypes.Structure):
         ("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
         ("max_rows_per_tick", ctypes.c_int64), ("hip_stream", ctypes.c_void_p), ("clock", CLOCK_FN),
         ("clock_ctx", ctypes.c_void_p), ("use_given_stream", ctypes.c_int32),
+        ("max_shrinks_per_tick", ctypes.c_int32),
     ]
 
 

@@ -123,8 +123,12 @@ __device__ __forceinline__ void lds_mm32(const double* X, const double* Y, doubl
     C[(r + 1) * PBL + c + 1] = a11;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
-    GridBar grid{args.bar, gridDim.x, 0u};
+// The solve of one problem by G workgroups (wg = 0 .. G-1).  Every value
+// computed depends on the problem alone, not on G: tiles and pair problems
+// are independent of which workgroup takes them, and the norm used for the
+// rotation floor is summed over a fixed set of 64 chunks.
+__device__ void jacobi_coop_body(const CoopEig& args, int wg, int G) {
+    GridBar grid{args.bar, (unsigned)G, 0u};
     const int n = args.n;
     const double* Ain = args.Ain;
     const int ldin = args.ldin;
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
     const int nb = N / BW, np = nb / 2;
     double* A = args.A;
     double* V = args.V;
-    const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+    const int tid = threadIdx.x;
 
     __shared__ double sA[PB * PBL], sV[PB * PBL], sT[PB * PBL];
     __shared__ double cs[PB];
@@ -144,27 +148,32 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
     __shared__ int sh_rot;
     __shared__ double red[4];
 
-    // A = sym(Ain) zero-padded to N x N, V = I; per-workgroup ||A||_F^2 partials
-    double loc = 0.0;
-    for (int64_t e = (int64_t)wg * 256 + tid; e < (int64_t)N * N; e += (int64_t)G * 256) {
-        const int i = (int)(e / N), j = (int)(e % N);
-        double v = 0.0;
-        if (i < n && j < n) v = 0.5 * (Ain[(int64_t)i * ldin + j] + Ain[(int64_t)j * ldin + i]);
-        A[e] = v;
-        V[e] = (i == j) ? 1.0 : 0.0;
-        loc += v * v;
+    // A = sym(Ain) zero-padded to N x N, V = I; ||A||_F^2 by 64 fixed chunks
+    const int64_t NN = (int64_t)N * N;
+    for (int ch = wg; ch < 64; ch += G) {
+        const int64_t e0 = NN * ch / 64, e1 = NN * (ch + 1) / 64;
+        double loc = 0.0;
+        for (int64_t e = e0 + tid; e < e1; e += 256) {
+            const int i = (int)(e / N), j = (int)(e % N);
+            double v = 0.0;
+            if (i < n && j < n) v = 0.5 * (Ain[(int64_t)i * ldin + j] + Ain[(int64_t)j * ldin + i]);
+            A[e] = v;
+            V[e] = (i == j) ? 1.0 : 0.0;
+            loc += v * v;
+        }
+        for (int off = 32; off > 0; off >>= 1) loc += __shfl_down(loc, off, 64);
+        __syncthreads();
+        if ((tid & 63) == 0) red[tid >> 6] = loc;
+        __syncthreads();
+        if (tid == 0) part[ch] = red[0] + red[1] + red[2] + red[3];
     }
-    for (int off = 32; off > 0; off >>= 1) loc += __shfl_down(loc, off, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = loc;
-    __syncthreads();
-    if (tid == 0) part[wg] = red[0] + red[1] + red[2] + red[3];
     if (wg == 0 && tid == 0) {
         ctrl[0] = 0;
         ctrl[1] = 0;
     }
     grid.sync();
     double fro2 = 0.0;
-    for (int w = 0; w < G; ++w) fro2 += part[w];
+    for (int ch = 0; ch < 64; ++ch) fro2 += part[ch];
     // off-diagonal entries below eps ||A||_F are rounding noise: not rotated
     const double floor_abs = 1e-300 + 1.1e-16 * sqrt(fro2);
 
@@ -285,6 +294,49 @@ __global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_jacobi_coop(CoopEig args) {
+    jacobi_coop_body(args, blockIdx.x, gridDim.x);
+}
+
+// Problem of a shrink / query task: the Rayleigh-Ritz matrix (randomized) or
+// the buffer Gram (exact), into the sketch's slots and cooperative scratch.
+__device__ CoopEig coop_eig_of(const Task& t) {
+    const SkDev* s = t.s;
+    const bool rnd = t.kind == T_SHRINK_RAND;
+    CoopEig a{};
+    a.Ain = s->slot[rnd ? S_M : S_G];
+    a.ldin = s->sld[rnd ? S_M : S_G];
+    a.n = eig_n(t);
+    a.A = s->slot[S_EA];
+    a.V = s->slot[S_EV];
+    a.U = s->slot[S_U];
+    a.lu = s->sld[S_U];
+    a.lam = s->slot[S_LAM];
+    a.info = s->info;
+    a.ubuf = s->coop + COOP_UBUF;
+    a.part = s->coop + COOP_PART;
+    a.ctrl = s->coop_ctrl;
+    a.stats = s->coop + COOP_STATS;
+    a.bar = (uint32_t*)(s->coop_ctrl + 8);
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_coop_tasks(CoopList L) {
+    const int i = blockIdx.x / L.gper;
+    const CoopEig a = coop_eig_of(L.tasks[L.idx[i]]);
+    jacobi_coop_body(a, blockIdx.x % L.gper, L.gper);
+}
+
+// Zeroes the grid-barrier words of every task of a multi-task launch.
+__global__ void k_coop_zero_bars(CoopList L) {
+    const int i = threadIdx.x;
+    if (i < L.count) {
+        int32_t* c = L.tasks[L.idx[i]].s->coop_ctrl;
+        c[8] = 0;
+        c[9] = 0;
+    }
+}
+
 // ------------------------------------------------------------ CholeskyQR
 // Factor the 32 x 32 diagonal block in LDS (lower, with rank dropping against
 // the original diagonal d0), then its lower inverse.  drop[] per column.
@@ -332,16 +384,17 @@ __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, d
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_cholqr_coop(const Task* tasks, int sy, int sq, int passes,
-                                                     double* linv, double* d0g, unsigned* bar) {
-    GridBar grid{bar, gridDim.x, 0u};
-    const Task& t = tasks[0];
+// CholeskyQR of one task by G workgroups; every value is independent of G.
+__device__ void cholqr_coop_body(const Task& t, int sy, int sq, int passes, int wg, int G) {
     const SkDev* s = t.s;
+    double* linv = s->coop + COOP_LINV;
+    double* d0g = s->coop + COOP_D0;
+    GridBar grid{(unsigned*)(s->coop_ctrl + 8), (unsigned)G, 0u};
     const int m = t.m, k = s->k;
     const int K = (k + PB - 1) / PB * PB;   // padded rank
     const int kb = K / PB;
     const int mb = (m + PB - 1) / PB;
-    const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+    const int tid = threadIdx.x;
     double* W = s->slot[S_EA];              // K x K (ld K)
     const int ldk = s->sld[S_Q];
 
@@ -510,6 +563,11 @@ __global__ __launch_bounds__(256) void k_cholqr_coop(const Task* tasks, int sy, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_cholqr_coop_tasks(CoopList L) {
+    const int i = blockIdx.x / L.gper;
+    cholqr_coop_body(L.tasks[L.idx[i]], L.sy, L.sq, L.passes, blockIdx.x % L.gper, L.gper);
+}
+
 // ------------------------------------------------------------ launchers
 static int coop_grid(const void* f, int want) {
     int dev = 0, cus = 0, per = 0;
@@ -533,18 +591,60 @@ hipError_t launch_jacobi_coop(const CoopEig& a, hipStream_t st) {
     return hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3((unsigned)G), dim3(256), kargs, 0, st);
 }
 
-hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,
-                              double* d0, unsigned* bar, hipStream_t st) {
+// Runs the listed tasks in as few cooperative launches as residency allows;
+// want = workgroups per task that keep every tile busy.
+static hipError_t launch_multi(const void* kern, const Task* tasks, const int* idx, int count, int want,
+                               int sy, int sq, int passes, hipStream_t st) {
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0);
+    if (e != hipSuccess) return e;
+    const int cap = cus * per;
+    if (cap < 1) return hipErrorInvalidConfiguration;
+    int done = 0;
+    while (done < count) {
+        // tasks of this launch: at least 16 workgroups each while they fit
+        int batch = count - done;
+        if (batch > COOP_MAX_TASKS) batch = COOP_MAX_TASKS;
+        while (batch > 1 && cap / batch < 16) --batch;
+        int gper = cap / batch;
+        if (gper > want) gper = want;
+        if (gper < 1) return hipErrorInvalidConfiguration;
+        CoopList L{};
+        L.tasks = tasks;
+        L.count = batch;
+        L.gper = gper;
+        L.sy = sy;
+        L.sq = sq;
+        L.passes = passes;
+        for (int i = 0; i < batch; ++i) L.idx[i] = idx[done + i];
+        hipLaunchKernelGGL(k_coop_zero_bars, dim3(1), dim3(COOP_MAX_TASKS), 0, st, L);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        void* kargs[] = {(void*)&L};
+        e = hipLaunchCooperativeKernel(kern, dim3((unsigned)(batch * gper)), dim3(256), kargs, 0, st);
+        if (e != hipSuccess) return e;
+        done += batch;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st) {
+    const int N = (max_n + PB - 1) / PB * PB;
+    const int nb = N / BW, np = nb / 2;
+    int want = np * (np + 1) / 2 + (N / PB) * np;
+    if (want > 128) want = 128;
+    return launch_multi((const void*)k_jacobi_coop_tasks, tasks, idx, count, want, 0, 0, 0, st);
+}
+
+hipError_t launch_cholqr_coop_tasks(const Task* tasks, const int* idx, int count, int m, int k, int sy, int sq,
+                                    int passes, hipStream_t st) {
     const int kb = (k + PB - 1) / PB, mb = (m + PB - 1) / PB;
     int want = kb * (kb + 1) / 2;
     if (mb > want) want = mb;
     if (want > 64) want = 64;
-    int G = coop_grid((const void*)k_cholqr_coop, want);
-    if (G < 1) return hipErrorInvalidConfiguration;
-    hipError_t e = hipMemsetAsync(bar, 0, 2 * sizeof(unsigned), st);
-    if (e != hipSuccess) return e;
-    void* args[] = {(void*)&task, (void*)&sy, (void*)&sq, (void*)&passes, (void*)&linv, (void*)&d0, (void*)&bar};
-    return hipLaunchCooperativeKernel((const void*)k_cholqr_coop, dim3((unsigned)G), dim3(256), args, 0, st);
+    return launch_multi((const void*)k_cholqr_coop_tasks, tasks, idx, count, want, sy, sq, passes, st);
 }
 
 }  // namespace sk

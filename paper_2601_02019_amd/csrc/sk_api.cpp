@@ -109,6 +109,8 @@ static sk_status build_device_state(sketch_t h) {
         HIP_TRY(h, h->dalloc(&p, 64 * sizeof(int)));
         HIP_TRY(h, h->dzero(p, 64 * sizeof(int)));
         h->coop_ctrl = (int*)p;
+        s.coop = h->coop;
+        s.coop_ctrl = h->coop_ctrl;
     }
     void* info = nullptr;
     HIP_TRY(h, h->dalloc(&info, 64));
@@ -192,11 +194,16 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
             src = dst;
         }
     }
-    for (int off : g.coop_chol) {
-        const sketch_t h = g.own[(size_t)off];
+    if (!g.coop_chol.empty()) {
+        // every cooperative CholeskyQR of the group in one launch (same m and k
+        // within a task; the launch is sized by the largest)
+        int m = 0, k = 0;
+        for (int off : g.coop_chol) {
+            m = std::max(m, g.own[(size_t)off]->n2);
+            k = std::max(k, g.own[(size_t)off]->k);
+        }
         g_stage = "cholqr_coop";
-        if ((e = launch_cholqr_coop(t + off, h->n2, h->k, sy, sq, passes, h->coop + COOP_LINV,
-                                    h->coop + COOP_D0, (unsigned*)(h->coop_ctrl + 8), st)))
+        if ((e = launch_cholqr_coop_tasks(t, g.coop_chol.data(), (int)g.coop_chol.size(), m, k, sy, sq, passes, st)))
             return e;
     }
     return hipSuccess;
@@ -209,27 +216,12 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
         hipError_t e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
         if (e != hipSuccess) return e;
     }
-    for (int off : g.coop_eig) {
-        const sketch_t h = g.own[(size_t)off];
-        const SkDev& hs = h->host;
-        const bool rnd = g.kind == T_SHRINK_RAND;
-        CoopEig a{};
-        a.Ain = hs.slot[rnd ? S_M : S_G];
-        a.ldin = hs.sld[rnd ? S_M : S_G];
-        a.n = g.ns[(size_t)off];
-        a.A = hs.slot[S_EA];
-        a.V = hs.slot[S_EV];
-        a.U = hs.slot[S_U];
-        a.lu = hs.sld[S_U];
-        a.lam = hs.slot[S_LAM];
-        a.info = hs.info;
-        a.ubuf = h->coop + COOP_UBUF;
-        a.part = h->coop + COOP_PART;
-        a.ctrl = h->coop_ctrl;
-        a.stats = h->coop + COOP_STATS;
-        a.bar = (uint32_t*)(h->coop_ctrl + 8);
+    if (!g.coop_eig.empty()) {
+        // every cooperative eigen-solve of the group in one launch
+        int max_n = 0;
+        for (int off : g.coop_eig) max_n = std::max(max_n, g.ns[(size_t)off]);
         g_stage = "jacobi_coop";
-        hipError_t e = launch_jacobi_coop(a, st);
+        hipError_t e = launch_jacobi_coop_tasks(t, g.coop_eig.data(), (int)g.coop_eig.size(), max_n, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

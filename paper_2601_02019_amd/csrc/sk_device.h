@@ -48,7 +48,16 @@ struct SkDev {
     int32_t sld[NSLOT];        // leading dimension of each slot
     int32_t* info;             // [0]: non-converged eigen-solves, [1]: max sweeps
     uint64_t seed, stream;
+    double* coop;              // cooperative-solver scratch (COOP_* layout)
+    int32_t* coop_ctrl;        // [0..1] rotation counters, [8..9] grid barrier
 };
+
+// Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
+// 256 partial sums, 16 inverse diagonal blocks of 32 x 32, 512 pivots, stats.
+constexpr int64_t COOP_UBUF = 0, COOP_PART = 16 * 1024, COOP_LINV = COOP_PART + 256,
+                  COOP_D0 = COOP_LINV + 16 * 1024, COOP_STATS = COOP_D0 + 512,
+                  COOP_DOUBLES = COOP_STATS + 16;
+
 
 enum TaskFlags : int32_t { TF_COOP_EIG = 1, TF_COOP_CHOL = 2 };
 
@@ -70,6 +79,16 @@ struct Task {
     const int64_t* indptr;     // CSR ingest (src == nullptr)
     const int32_t* indices;
     const float* values;
+};
+
+// Task list of one multi-task cooperative launch: task idx[i] of `tasks`
+// owns workgroups [i * gper, (i + 1) * gper).
+constexpr int COOP_MAX_TASKS = 64;
+struct CoopList {
+    const Task* tasks;
+    int32_t count, gper;
+    int32_t sy, sq, passes, pad;   // CholeskyQR: input / output slots, passes
+    int32_t idx[COOP_MAX_TASKS];
 };
 
 // Descriptor of one small dense FP64 problem for the pointer-driven kernels

@@ -229,11 +229,6 @@ struct sketch_s {
     }
 };
 
-// Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
-// 256 workgroup partials, 16 inverse diagonal blocks of 32 x 32, 512 pivots.
-static const int64_t COOP_UBUF = 0, COOP_PART = 16 * 1024, COOP_LINV = COOP_PART + 256,
-                     COOP_D0 = COOP_LINV + 16 * 1024, COOP_STATS = COOP_D0 + 512,
-                     COOP_DOUBLES = COOP_STATS + 16;
 
 // Planning and execution helpers of sk_api.cpp.
 void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dtype,

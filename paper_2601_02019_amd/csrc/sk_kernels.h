@@ -53,8 +53,11 @@ hipError_t launch_jacobi1(const SmallDesc& q, hipStream_t st);
 hipError_t launch_blockmask(double* S, int ld, int D, const int32_t* ent, hipStream_t st);
 hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n, int ell, double* X,
                               int64_t ldx, int d, hipStream_t st);
-hipError_t launch_cholqr_coop(const Task* task, int m, int k, int sy, int sq, int passes, double* linv,
-                              double* d0, unsigned* bar, hipStream_t st);
+// Multi-task cooperative solvers: tasks[idx[i]] for i < count, each by its
+// own group of workgroups (several launches when residency requires).
+hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st);
+hipError_t launch_cholqr_coop_tasks(const Task* tasks, const int* idx, int count, int m, int k, int sy, int sq,
+                                    int passes, hipStream_t st);
 hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
 hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
 hipError_t launch_gemm_desc(const GemmDesc* ds, int count, int max_M, int max_N, hipStream_t st);

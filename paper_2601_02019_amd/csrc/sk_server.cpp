@@ -220,8 +220,8 @@ sk_status server_create(const sk_server_config* cfg, sk_server_t* out) {
     *out = nullptr;
     if (cfg->max_inflight < 1 || cfg->max_inflight > 64)
         return fail(SK_EINVAL, "server_create: max_inflight must be in [1, 64]");
-    if (cfg->memory_budget < 0 || cfg->max_rows_per_tick < 0)
-        return fail(SK_EINVAL, "server_create: negative budget or row cap");
+    if (cfg->memory_budget < 0 || cfg->max_rows_per_tick < 0 || cfg->max_shrinks_per_tick < 0)
+        return fail(SK_EINVAL, "server_create: negative budget or cap");
     hipError_t e = hipSetDevice(cfg->device);
     if (e != hipSuccess) return fail(SK_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     sk_server_t s = new sk_server_s();
@@ -307,6 +307,13 @@ sk_status server_tick(sk_server_t s, int32_t* launched) {
         SStream& st = s->streams[i];
         if (st.state != ST_ADMITTED || st.q.empty()) continue;
         int64_t budget = cap > 0 ? cap : INT64_MAX;
+        if (s->cfg.max_shrinks_per_tick > 0) {
+            // rows up to the buffer's next shrink plus (cap - 1) more shrinks;
+            // sketches with ell < 64 take 64 / ell times as many (cheaper) shrinks
+            const int64_t cap_s = (int64_t)s->cfg.max_shrinks_per_tick * std::max(1, 64 / st.cfg.ell);
+            const int64_t to_first = 2 * (int64_t)st.cfg.ell - st.h->fill;
+            budget = std::min(budget, to_first + (cap_s - 1) * (st.cfg.ell + 1));
+        }
         size_t r = 0;
         for (size_t b = 0; b < st.q.size() && budget > 0; ++b, ++r) {
             Burst& bu = st.q[b];

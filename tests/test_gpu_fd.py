@@ -260,6 +260,31 @@ def test_csr_ingest_equals_dense():
     assert torch.equal(s3.query(), B1)
 
 
+def test_batched_cooperative_solvers_bitwise_and_parity():
+    # several large cores in one batch share multi-task cooperative launches;
+    # each sketch's result is bitwise its result alone (the work split over
+    # workgroups does not change any value) and matches the oracle
+    from paper_2601_02019_amd import sketch_update_batch
+    shapes = [(300, 136, "rand", 0), (300, 136, "rand", 1), (260, 140, "rand", 2), (280, 70, "exact", 3)]
+    rows = [torch.from_numpy(synth.lowrank_rows(2 * ell + 2 * (ell + 1) + 7, d, np.geomspace(4, 0.05, 180),
+                                                 0.05, seed=70 + i)).cuda()
+            for i, (d, ell, _, _) in enumerate(shapes)]
+    alone, mixed = [], []
+    for i, (d, ell, mode, sid) in enumerate(shapes):
+        a = make(d, ell, shrink=mode, seed=5, stream_id=sid)
+        a.update(rows[i])
+        alone.append(a.query())
+        mixed.append(make(d, ell, shrink=mode, seed=5, stream_id=sid))
+    note("batched cooperative solvers: 3 randomized cores k >= 136, one exact 2 ell = 140")
+    sketch_update_batch(mixed, rows)
+    for i in range(len(shapes)):
+        assert torch.equal(mixed[i].query(), alone[i]), i
+    d, ell, _, sid = shapes[0]
+    o = oracle.FD(d, ell, "rand", k=ell, q=1, seed=5, stream=sid)
+    o.update(rows[0].cpu().numpy())
+    assert rel_fro(gram(alone[0]), gram(o.query())) <= 1e-9
+
+
 def test_csr_batch_equals_individual_csr_bitwise():
     from paper_2601_02019_amd import sketch_update_csr_batch
     shapes = [(256, 16, "rand"), (256, 16, "rand"), (128, 8, "exact"), (300, 20, "rand")]

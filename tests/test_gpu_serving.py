@@ -37,8 +37,8 @@ STREAMS = [  # (d, ell, shrink, state, proj)
 ]
 
 
-@pytest.mark.parametrize("row_cap,inflight", [(0, 2), (96, 1), (200, 3)])
-def test_mix_equals_alone_bitwise(row_cap, inflight):
+@pytest.mark.parametrize("row_cap,inflight,shrink_cap", [(0, 2, 0), (96, 1, 0), (200, 3, 0), (0, 2, 1)])
+def test_mix_equals_alone_bitwise(row_cap, inflight, shrink_cap):
     sk = _lib()
     rng = np.random.default_rng(7)
     note(f"serving mix row_cap={row_cap} inflight={inflight}")
@@ -49,7 +49,7 @@ def test_mix_equals_alone_bitwise(row_cap, inflight):
         dt = torch.float64 if STREAMS[i][3] == "f64" else torch.float32
         data.append(torch.from_numpy(A).to("cuda", dt))
         bursts.append(_bursts(n, rng, 300))
-    srv = sk.Server(max_inflight=inflight, max_rows_per_tick=row_cap)
+    srv = sk.Server(max_inflight=inflight, max_rows_per_tick=row_cap, max_shrinks_per_tick=shrink_cap)
     ids = []
     for i, (d, ell, shr, st, pj) in enumerate(STREAMS):
         ids.append(srv.open(d, ell, shrink=shr, state_dtype=st, proj_dtype=pj, seed=11, stream_id=i))
