@@ -35,6 +35,18 @@ static int coop_min_n() {
     return v;
 }
 
+// The one-workgroup eigen-solver: the tridiagonal solver, or the Jacobi
+// method with SK_EIG_SOLVER=jacobi (both exact to rounding; the choice is
+// fixed for the process, so results do not depend on batch composition).
+bool eig_solver_jacobi() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_EIG_SOLVER");
+        v = (e && std::string(e) == "jacobi") ? 1 : 0;
+    }
+    return v == 1;
+}
+
 // Marks the stages of a shrink / query task that the cooperative solvers
 // take: a property of the task alone, so a sketch computes the same thing
 // whatever else shares its launches.
@@ -212,8 +224,14 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
 hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
     StageScope sc(g.prof, ST_EIG, st);
     if (g.any_plain_eig) {
-        g_stage = "jacobi";
-        hipError_t e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
+        hipError_t e;
+        if (eig_solver_jacobi()) {
+            g_stage = "jacobi";
+            e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
+        } else {
+            g_stage = "tridiagonal eig";
+            e = launch_tri_eig(t, g.count, st);
+        }
         if (e != hipSuccess) return e;
     }
     if (!g.coop_eig.empty()) {

@@ -237,6 +237,7 @@ void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dt
 sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
                           int in_dtype, bool csr = false);
 sk_status check_handle(sketch_t h, const char* what);
+bool eig_solver_jacobi();
 // Device bytes sketch_create would allocate for cfg (persistent sketches);
 // negative on a configuration sketch_create rejects.
 int64_t sketch_state_bytes(const sketch_config* cfg);

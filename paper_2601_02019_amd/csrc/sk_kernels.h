@@ -53,6 +53,11 @@ hipError_t launch_jacobi1(const SmallDesc& q, hipStream_t st);
 hipError_t launch_blockmask(double* S, int ld, int D, const int32_t* ent, hipStream_t st);
 hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n, int ell, double* X,
                               int64_t ldx, int d, hipStream_t st);
+// Tridiagonal eigen-solver, one workgroup per problem (n <= 512): the
+// non-cooperative tasks of a list, or one descriptor by value.
+hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st);
+hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st);
+int tri_lds_doubles();
 // Multi-task cooperative solvers: tasks[idx[i]] for i < count, each by its
 // own group of workgroups (several launches when residency requires).
 hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st);

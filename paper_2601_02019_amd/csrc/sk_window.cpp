@@ -169,7 +169,8 @@ static sk_status gemm1(sketch_t h, const GemmDesc& g0) {
 }
 
 static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
-    hipError_t e = eig ? launch_jacobi1(q, h->stream) : launch_cholinv1(q, h->stream);
+    hipError_t e = !eig ? launch_cholinv1(q, h->stream)
+                        : (eig_solver_jacobi() ? launch_jacobi1(q, h->stream) : launch_tri_eig1(q, h->stream));
     if (e != hipSuccess) return h->device_fail(std::string("window small solve: ") + hipGetErrorString(e));
     return SK_OK;
 }
