@@ -25,12 +25,27 @@ thread_local const char* g_stage = "";
 std::atomic<int64_t> g_in_use{0};
 std::atomic<int64_t> g_budget{0};
 
-// Problem sizes from which one task alone runs the cooperative solvers.
+// Problem sizes from which one task alone runs the cooperative solvers:
+// CholeskyQR from k = 129 (SK_COOP_MIN_N), the eigen-solve from n = 257
+// (SK_COOP_EIG_MIN_N; below it the one-workgroup tridiagonal solver is as
+// fast and leaves the other compute units to the rest of the batch; with
+// SK_EIG_SOLVER=jacobi the one-workgroup Jacobi solver stops at 128).
 static int coop_min_n() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_COOP_MIN_N");
         v = e ? atoi(e) : 129;
+    }
+    return v;
+}
+
+bool eig_solver_jacobi();
+
+static int coop_eig_min_n() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_COOP_EIG_MIN_N");
+        v = e ? atoi(e) : (eig_solver_jacobi() ? 129 : 257);
     }
     return v;
 }
@@ -53,7 +68,7 @@ bool eig_solver_jacobi() {
 static void mark_coop(Task& t, const sketch_s* h) {
     const int n = (t.kind == T_SHRINK_RAND) ? h->k : t.m;
     t.flags = 0;
-    if (n >= coop_min_n()) t.flags |= TF_COOP_EIG;
+    if (n >= coop_eig_min_n()) t.flags |= TF_COOP_EIG;
     if (t.kind == T_SHRINK_RAND && h->k >= coop_min_n()) t.flags |= TF_COOP_CHOL;
 }
 
@@ -230,7 +245,7 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
             e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
         } else {
             g_stage = "tridiagonal eig";
-            e = launch_tri_eig(t, g.count, st);
+            e = launch_tri_eig(t, g.count, g.max_n, st);
         }
         if (e != hipSuccess) return e;
     }
@@ -1054,6 +1069,11 @@ extern "C" sk_status sketch_profile_read(sketch_t h, sketch_stage_time* out, int
             put("eig_syncB_ms", 0, st[5] * tick_ms);
             put("eig_workgroups", 0, st[7]);
         }
+    }
+    if (!h->win) {  // eigen-solves that went from the tridiagonal solver to the Jacobi method
+        int32_t inf[4] = {0, 0, 0, 0};
+        HIP_TRY(h, hipMemcpy(inf, h->host.info, sizeof(inf), hipMemcpyDeviceToHost));
+        put("eig_fallbacks", 0, (double)inf[2]);
     }
     *n_out = n;
     return SK_OK;
