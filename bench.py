@@ -116,6 +116,14 @@ def measured_traffic(kernel, source):
     return rec.get("traffic_bytes_per_launch")
 
 
+def tri_flops(n):
+    """Dense arithmetic of k_tri_eig (FP64 flops): the Householder reduction
+    to tridiagonal form (a symmetric product and a rank-2 update per column,
+    4 n^3 / 3 in all); the bisection and the O(n^2) eigenvector recurrences
+    are not counted.  The back-transformation (2 n^3) is the next kernel."""
+    return 4.0 * n ** 3 / 3.0
+
+
 def jacobi_flops(n, sweeps):
     """Arithmetic of the block Jacobi solver per solve (FP64 flops): per block
     step, one 31-step rotation sweep of every 32 x 32 pair sub-problem and the
@@ -538,7 +546,17 @@ def main():
     dom_calls, dom_ms = stages[dom]
     avg_ms = dom_ms / dom_calls
     roofline = None
-    if dom == "eig":
+    if dom == "eig" and ell <= 256 and os.environ.get("SK_EIG_SOLVER") != "jacobi":
+        # k x k Rayleigh-Ritz eigen-solve on one workgroup (k = ell <= 256)
+        flops = tri_flops(ell)
+        achieved = flops / (avg_ms / 1e3) / 1e12
+        roofline = {"bound": "alu", "kernel": "k_tri_eig (FP64 tridiagonal eigen-solver, one workgroup, n=%d)" % ell,
+                    "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP64_TFLOPS,
+                    "traffic": measured_traffic("k_tri_eig", "paper_2601_02019_amd/csrc/k_tri.hip"),
+                    "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops,
+                    "fallbacks_to_jacobi": prof.get("eig_fallbacks", (0, 0.0))[1]}
+    elif dom == "eig":
         solves = prof.get("eig_solves", (0, 0.0))[1]
         sweeps = prof.get("eig_sweeps", (0, 0.0))[1] / max(solves, 1)
         flops = jacobi_flops(ell, sweeps)

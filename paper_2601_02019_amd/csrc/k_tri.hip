@@ -421,13 +421,16 @@ __device__ void tri_body(const double* Ain, int ldin, int n, double* W, double* 
 }
 
 // U = Q U for the reflectors in W (row j: v_j beyond the super-diagonal,
-// W[j][j] = tau_j), one wavefront per 64-column strip; the strip lives in
-// LDS when it fits.  Skipped when the Jacobi fallback produced U.
+// W[j][j] = tau_j): a workgroup of four wavefronts per 64-column strip (lane
+// = column), the rows of each reflector split between the wavefronts; the
+// strip lives in LDS when it fits.  Skipped when the Jacobi fallback
+// produced U.
 __device__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n, double* lds,
                               int lds_doubles) {
     __shared__ double vs[TRI_NMAX];
+    __shared__ double part[2][4][64];
     if (Dm[0] != 0.0) return;
-    const int lane = threadIdx.x, c0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c0 = blockIdx.x * 64;
     if (c0 >= n) return;
     const int nc = min(64, n - c0);
     const bool act = lane < nc;
@@ -437,31 +440,35 @@ __device__ void tri_back_body(const double* W, const double* Dm, double* U, int 
     double* Z = inl ? lds : U + c0;
     const int lz = inl ? 64 : lu;
     const int col = inl ? lane : (act ? lane : 0);
+    const bool wr = inl || act;
     if (inl)
-        for (int i = 0; i < n; ++i) Z[i * 64 + lane] = act ? U[(int64_t)i * lu + c0 + lane] : 0.0;
+        for (int i = wave; i < n; i += 4) Z[i * 64 + lane] = act ? U[(int64_t)i * lu + c0 + lane] : 0.0;
+    int buf = 0;
     for (int j = n - 2; j >= 0; --j) {
         const double tau = W[(int64_t)j * n + j];
         if (tau == 0.0) continue;
         const int L = n - j - 1;
-        __syncthreads();  // one wave: orders the reuse of vs
-        for (int i = lane; i < L; i += 64) vs[i] = (i == 0) ? 1.0 : W[(int64_t)j * n + j + 1 + i];
+        __syncthreads();  // the previous reflector is done with vs
+        for (int i = tid; i < L; i += 256) vs[i] = (i == 0) ? 1.0 : W[(int64_t)j * n + j + 1 + i];
         __syncthreads();
         double* z = Z + (int64_t)(j + 1) * lz + col;
-        double y0 = 0.0, y1 = 0.0, y2 = 0.0, y3 = 0.0;
-        int i = 0;
-        for (; i + 4 <= L; i += 4) {
+        double y0 = 0.0, y1 = 0.0;
+        int i = wave;
+        for (; i + 4 < L; i += 8) {
             y0 = fma(vs[i], z[(int64_t)i * lz], y0);
-            y1 = fma(vs[i + 1], z[(int64_t)(i + 1) * lz], y1);
-            y2 = fma(vs[i + 2], z[(int64_t)(i + 2) * lz], y2);
-            y3 = fma(vs[i + 3], z[(int64_t)(i + 3) * lz], y3);
+            y1 = fma(vs[i + 4], z[(int64_t)(i + 4) * lz], y1);
         }
-        for (; i < L; ++i) y0 = fma(vs[i], z[(int64_t)i * lz], y0);
-        const double y = tau * ((y0 + y1) + (y2 + y3));
-        if (inl || act)
-            for (int r = 0; r < L; ++r) z[(int64_t)r * lz] = fma(-vs[r], y, z[(int64_t)r * lz]);
+        for (; i < L; i += 4) y0 = fma(vs[i], z[(int64_t)i * lz], y0);
+        part[buf][wave][lane] = y0 + y1;
+        __syncthreads();
+        const double y = tau * ((part[buf][0][lane] + part[buf][1][lane]) + (part[buf][2][lane] + part[buf][3][lane]));
+        buf ^= 1;  // the next reflector writes the other buffer: no barrier before its partials
+        if (wr)
+            for (int r = wave; r < L; r += 4) z[(int64_t)r * lz] = fma(-vs[r], y, z[(int64_t)r * lz]);
     }
+    __syncthreads();
     if (inl && act)
-        for (int i = 0; i < n; ++i) U[(int64_t)i * lu + c0 + lane] = Z[i * 64 + lane];
+        for (int i = wave; i < n; i += 4) U[(int64_t)i * lu + c0 + lane] = Z[i * 64 + lane];
 }
 
 // Task form: the eigen-problem of a shrink / query task (not the
@@ -478,7 +485,7 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks, int lds_dou
              s->sld[S_U], s->slot[S_LAM], s->info, lds, lds_doubles);
 }
 
-__global__ __launch_bounds__(64) void k_tri_back(const Task* tasks, int lds_doubles) {
+__global__ __launch_bounds__(256) void k_tri_back(const Task* tasks, int lds_doubles) {
     extern __shared__ double lds[];
     const Task& t = tasks[blockIdx.z];
     if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(64) void k_tri_back(const Task* tasks, int lds_doub
     tri_back_body(s->slot[S_EA], s->slot[S_EV], s->slot[S_U], s->sld[S_U], eig_n(t), lds, lds_doubles);
 }
 
-__global__ __launch_bounds__(64) void k_tri_back_desc(DescArg<SmallDesc> ds, int lds_doubles) {
+__global__ __launch_bounds__(256) void k_tri_back_desc(DescArg<SmallDesc> ds, int lds_doubles) {
     extern __shared__ double lds[];
     const SmallDesc q = ds.get();
     if (q.n < 1) return;
@@ -539,15 +546,17 @@ static int back_lds(int max_n) {
     return want <= g_back_lds ? want : 0;
 }
 
-hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
+hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st, tasks,
                        dbl);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int bl = back_lds(max_n);
-    hipLaunchKernelGGL(k_tri_back, dim3((unsigned)((max_n + 63) / 64), 1, (unsigned)count), dim3(64),
+    hipLaunchKernelGGL(k_tri_back, dim3((unsigned)((max_n + 63) / 64), 1, (unsigned)count), dim3(256),
                        sizeof(double) * (size_t)bl, st, tasks, bl);
     return hipGetLastError();
 }
@@ -560,7 +569,7 @@ hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int bl = back_lds(q.n);
-    hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((q.n + 63) / 64), 1, 1), dim3(64), sizeof(double) * (size_t)bl,
+    hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((q.n + 63) / 64), 1, 1), dim3(256), sizeof(double) * (size_t)bl,
                        st, a, bl);
     return hipGetLastError();
 }

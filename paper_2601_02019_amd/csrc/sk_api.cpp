@@ -237,19 +237,28 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
 }
 
 hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
-    StageScope sc(g.prof, ST_EIG, st);
     if (g.any_plain_eig) {
         hipError_t e;
         if (eig_solver_jacobi()) {
+            StageScope sc(g.prof, ST_EIG, st);
             g_stage = "jacobi";
             e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
         } else {
-            g_stage = "tridiagonal eig";
-            e = launch_tri_eig(t, g.count, g.max_n, st);
+            {
+                StageScope sc(g.prof, ST_EIG, st);
+                g_stage = "tridiagonal eig";
+                e = launch_tri_eig(t, g.count, st);
+            }
+            if (e == hipSuccess) {
+                StageScope sc(g.prof, ST_EIG_BACK, st);
+                g_stage = "eig back-transformation";
+                e = launch_tri_back(t, g.count, g.max_n, st);
+            }
         }
         if (e != hipSuccess) return e;
     }
     if (!g.coop_eig.empty()) {
+        StageScope sc(g.prof, ST_EIG, st);
         // every cooperative eigen-solve of the group in one launch
         int max_n = 0;
         for (int off : g.coop_eig) max_n = std::max(max_n, g.ns[(size_t)off]);

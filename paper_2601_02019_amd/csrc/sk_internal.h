@@ -104,10 +104,10 @@ struct TaskArena {
 };
 
 // ---------------------------------------------------------------- profiling
-static const int NSTAGE = 9;
+static const int NSTAGE = 10;
 static const char* const STAGE_NAMES[NSTAGE] = {"ingest", "omega", "gram", "project", "cholqr",
-                                                "core_gemm", "eig", "threshold", "rebuild"};
-enum { ST_INGEST, ST_OMEGA, ST_GRAM, ST_PROJECT, ST_CHOLQR, ST_CORE, ST_EIG, ST_THRESH, ST_REBUILD };
+                                                "core_gemm", "eig", "threshold", "rebuild", "eig_back"};
+enum { ST_INGEST, ST_OMEGA, ST_GRAM, ST_PROJECT, ST_CHOLQR, ST_CORE, ST_EIG, ST_THRESH, ST_REBUILD, ST_EIG_BACK };
 
 struct Prof {
     uint32_t mask = 0;
