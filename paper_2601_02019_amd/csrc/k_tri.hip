@@ -1,21 +1,21 @@
 // k_tri.hip -- symmetric eigen-decomposition of the shrink's core (the eigen
 // step of Algorithm "Simultaneous Iteration" on the k x k Rayleigh-Ritz
 // matrix; the exact FD shrink's eigen-decomposition of the 2 ell x 2 ell
-// buffer Gram, Sec. 2.3) by one workgroup per problem:
+// buffer Gram, Sec. 2.3) by one workgroup per problem, in three kernels:
 //
-//   1. Householder tridiagonalisation A = Q T Q^T (unblocked; A in LDS when
-//      it fits, else in the global work matrix, which then stays in L2);
-//   2. eigenvalues of T by bisection on Sturm counts, one eigenvalue per
-//      thread, to absolute accuracy eps ||T||;
-//   3. eigenvectors of T by a twisted factorisation at each eigenvalue (the
-//      forward and backward pivots of T - lambda I meet at the index where
-//      the twist is smallest; the vector follows from one pass each way),
-//      one eigenvector per thread;
-//   4. U = Q Z by a second kernel: one wavefront per 64-column strip of Z
-//      applies the reflectors from the last to the first (lane = column, so
-//      the products with v_j need no cross-lane reduction).
+//   1. k_tri_reduce: Householder tridiagonalisation A = Q T Q^T (A in LDS
+//      when it fits; else in the global work matrix, which stays in L2, and
+//      for n <= 256 blocked by panels so that each column reads the matrix
+//      once and the panel updates it once);
+//   2. k_tri_eig: eigenvalues of T by multisection on Sturm counts to
+//      absolute accuracy eps ||T||, then eigenvectors of T by a twisted
+//      factorisation at each eigenvalue (the forward and backward pivots of
+//      T - lambda I meet at the index where the twist is smallest; the vector
+//      follows from one pass each way), one eigenvector per thread;
+//   3. k_tri_back: U = Q Z, four wavefronts per 64-column strip of Z
+//      applying the reflectors from the last to the first.
 //
-// Eigenvectors from step 3 are accurate to eps ||T|| / gap.  Within clusters
+// Eigenvectors from step 2 are accurate to eps ||T|| / gap.  Within clusters
 // of close eigenvalues the vectors are made orthogonal by Gram-Schmidt, with
 // other twist indices where they coincide; more than 8 equal eigenvalues, or
 // a vector that is not finite, send the problem to the Jacobi method.  Every
@@ -34,21 +34,10 @@ constexpr int TRI_NMAX = 512;
 struct TriShared {
     double d[TRI_NMAX], e[TRI_NMAX];
     double v[TRI_NMAX], w[TRI_NMAX];
-    double red[16];
+    double red[32];
     double y[1024];
     int flag, ncl;
 };
-
-__device__ __forceinline__ double tri_block_sum(double x, double* red) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-    __syncthreads();
-    double s = 0.0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) s += red[w];
-    return s;
-}
 
 // a / b from the hardware reciprocal refined by two Newton steps and a
 // residual correction (a few ulp; the recurrences below are backward stable
@@ -148,15 +137,27 @@ __device__ bool twisted_vec(const double* d, const double* e, const double* e2, 
     return true;
 }
 
-// Returns true when the problem was solved by the Jacobi fallback.
-// W: n x n global work (ld n): A when it does not fit LDS, then the
-// reflectors (row j holds v_j beyond the super-diagonal, W[j][j] = tau_j).
-// Dm: n x n global scratch.  lds: dynamic LDS of lds_doubles doubles.
-__device__ void tri_body(const double* Ain, int ldin, int n, double* W, double* Dm, double* U, int lu,
-                         double* lam, int* info, double* lds, int lds_doubles) {
+// Householder reduction of the symmetric n x n matrix (Ain, symmetrised) to
+// tridiagonal form T = Q^T A Q.  Output: the reflectors in W (row j holds v_j
+// beyond the super-diagonal, v_j[j + 1] = 1 implied, W[j][j] = tau_j), the
+// diagonal of T in row 0 of U and its off-diagonal in row 1 (read back by the
+// eigenpair kernel before it writes U).  lds: dynamic LDS of lds_doubles.
+//
+//  * n (n + 1) <= lds_doubles: A in LDS (row stride n + 1), unblocked;
+//  * n <= 256: A in W, blocked by panels of TRI_NB columns (below);
+//  * otherwise A in W, unblocked.
+constexpr int TRI_NB = 32;
+typedef __attribute__((address_space(1))) double gdouble;
+
+__device__ __forceinline__ double tri_wave_sum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldin, int n, double* W, double* U, int lu,
+                                                double* lds, int lds_doubles) {
     __shared__ TriShared S;
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
-    // A in LDS (row stride n + 1: the rows of a column map to different banks)
     const bool inl = (n + 1) * n <= lds_doubles;
     const int la = inl ? n + 1 : n;
     double* A = inl ? lds : W;
@@ -273,7 +274,6 @@ __device__ void tri_body(const double* Ain, int ldin, int n, double* W, double* 
     if (tid == 0) {
         S.d[n - 1] = A[(int64_t)(n - 1) * la + n - 1];
         A[(int64_t)(n - 1) * la + n - 1] = 0.0;
-        S.flag = 0;
     }
     __syncthreads();
     if (inl)  // the reflectors (ld n) for the back-transformation
@@ -281,6 +281,280 @@ __device__ void tri_body(const double* Ain, int ldin, int n, double* W, double* 
             const int i = e / n, k = e - i * n;
             W[e] = lds[(int64_t)i * la + k];
         }
+    for (int i = tid; i < n; i += nth) {
+        U[i] = S.d[i];
+        if (i + 1 < n) U[lu + i] = S.e[i];
+    }
+}
+
+// The blocked reduction (A in W, 128 < n <= 256, 1024 threads); a kernel of
+// its own so that its product loop keeps its loads in registers.
+//
+// Within a panel of TRI_NB columns the matrix is not updated: column j uses
+// the panel-start matrix minus sum_{c<jc} (v_c w_c^T + w_c v_c^T), with the
+// panel's vectors in LDS, and after the panel its 2 TRI_NB vectors update the
+// trailing matrix at once.  Nothing is stored to global memory inside a panel
+// (a barrier would wait for the stores): the reflectors go to W with the
+// update.  Four barriers per column:
+//   X  effective column j and |x|^2 (4 lanes per entry);
+//   Y  W^T v, V^T v (16 lanes per product), then A22 v (lanes along columns,
+//      waves along row stripes, batches of independent loads);
+//   P  p = tau (A22 v - V W^T v - W V^T v) and p . v (4 lanes per entry);
+//   S  v and w = p - (tau/2)(p . v) v into the panel.
+// v_i = x_i * scal is recomputed from x where needed (same rounding).  The
+// product leaves row j + 1 (panel-start) in d[j + 1 ..], the part of d not
+// yet written, for the next column.  The panel vectors are stored entry-major
+// (row g holds entry g of every vector), so a lane's walk over the vectors
+// has constant offsets.
+struct TriBlkShared {
+    double d[256], e[256], v[256];
+    double y[1024];
+    double red[32];
+};
+
+constexpr int TRI_NBP = TRI_NB + 1;  // row stride of the panel (bank spread)
+
+// Dynamic LDS (doubles) of the blocked reduction at size n.
+__host__ __device__ constexpr int tri_blk_lds(int n) { return 2 * n * TRI_NBP + 128; }
+
+__device__ __forceinline__ bool tri_blocked(int n, int blk_ok) { return blk_ok && n > 128 && n <= 256; }
+
+__device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin, int n, double* W, double* U, int lu,
+                                                    double* lds) {
+    __shared__ TriBlkShared S;
+    constexpr int NW = 16;  // wavefronts (1024 threads)
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < n * n; e += nth) {
+        const int i = e / n, j = e - i * n;
+        W[(int64_t)i * n + j] = 0.5 * (Ain[(int64_t)i * ldin + j] + Ain[(int64_t)j * ldin + i]);
+    }
+    double* Vt = lds;                  // [n][TRI_NBP], zero outside each vector's range
+    double* Wt = lds + n * TRI_NBP;    // [n][TRI_NBP]
+    double* pan = lds + 2 * n * TRI_NBP;
+    double* dW = pan;                  // W^T v (zero beyond the panel's columns so far)
+    double* dV = pan + TRI_NB;         // V^T v
+    double* taus = pan + 64;
+    gdouble* Ag = (gdouble*)W;
+    const int quad = tid >> 2, q = tid & 3;
+    bool row_ok = false;  // d[j ..] holds row j of the panel-start matrix
+    __syncthreads();
+    for (int j0 = 0; j0 + 1 < n; j0 += TRI_NB) {
+        const int jb = min(TRI_NB, n - 1 - j0);
+        for (int e = tid; e < 2 * n * TRI_NBP + 2 * TRI_NB; e += nth) lds[e] = 0.0;
+        __syncthreads();
+        for (int jc = 0; jc < jb; ++jc) {
+            const int j = j0 + jc, L = n - j - 1;
+            const bool pre = jc > 0 && row_ok;
+            // X: entry quad of column j below the diagonal (quad 255: the
+            // diagonal; L <= 254 whenever jc > 0); lane q takes the vectors
+            // c = q (mod 4)
+            {
+                const bool diag = quad == 255;
+                const bool act = quad < L || diag;
+                const int g = diag ? j : j + 1 + (act ? quad : 0);
+                const double* vg = Vt + g * TRI_NBP + q;
+                const double* wg = Wt + g * TRI_NBP + q;
+                const double* vj = Vt + j * TRI_NBP + q;
+                const double* wj = Wt + j * TRI_NBP + q;
+                double sub = 0.0;
+                const int tmax = (jc - q + 3) >> 2;  // vectors c = q + 4 t < jc
+#pragma unroll
+                for (int t = 0; t < TRI_NB / 4; ++t)
+                    if (t < tmax) sub += vg[4 * t] * wj[4 * t] + wg[4 * t] * vj[4 * t];
+                sub += __shfl_xor(sub, 1, 64);
+                sub += __shfl_xor(sub, 2, 64);
+                double x2 = 0.0;
+                if (act && q == 0) {
+                    const double a = pre ? S.d[g] : (double)Ag[j * n + g];
+                    const double x = a - sub;
+                    if (diag) {
+                        pan[97] = x;
+                    } else {
+                        S.v[quad] = x;
+                        if (quad == 0) pan[96] = x;
+                        else x2 = x * x;
+                    }
+                }
+                x2 = tri_wave_sum(x2);
+                if (lane == 0) S.red[wave] = x2;
+            }
+            __syncthreads();
+            double xn2 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) xn2 += S.red[w];
+            const double alpha = pan[96];
+            double beta = alpha, tau = 0.0, scal = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            row_ok = tau != 0.0;
+            if (tid == 0) {
+                S.d[j] = pan[97];
+                S.e[j] = beta;
+                taus[jc] = tau;
+            }
+            if (tau != 0.0) {
+                // Y: products of v with the panel vectors (slot c < 32: w_c,
+                // 32 + c: v_c; 16 lanes each, rows j + 1 + part + 16 t)
+                {
+                    const int slot = tid >> 4, part = tid & 15, cc = slot & 31;
+                    const double* P = (slot < 32 ? Wt : Vt) + (j + 1 + part) * TRI_NBP + cc;
+                    const double* vp = S.v + part;
+                    const int rem = L - part;  // rows t with 16 t < rem
+                    double ds = 0.0;
+                    if (cc < jc) {
+#pragma unroll
+                        for (int t = 0; t < 16; ++t)
+                            if (16 * t < rem) {
+                                const double vi = (part == 0 && t == 0) ? 1.0 : vp[16 * t] * scal;
+                                ds = fma(P[16 * t * TRI_NBP], vi, ds);
+                            }
+                    }
+                    ds += __shfl_xor(ds, 8, 64);
+                    ds += __shfl_xor(ds, 4, 64);
+                    ds += __shfl_xor(ds, 2, 64);
+                    ds += __shfl_xor(ds, 1, 64);
+                    if (part == 0 && cc < jc) pan[slot] = ds;
+                }
+                const int cb = (L + 63) >> 6, nst = NW / cb, Lp = cb << 6;
+                if (wave < cb * nst) {
+                    const int st = wave / cb, k = ((wave - st * cb) << 6) + lane;
+                    double acc = 0.0;
+                    if (k < L) {
+                        const gdouble* colp = Ag + (j + 1) * n + j + 1 + k;
+                        const int step = nst * n;
+                        int i = st;
+                        constexpr int B = 16;
+                        for (; i + (B - 1) * nst < L; i += B * nst) {
+                            const gdouble* p0 = colp + i * n;
+                            double av[B];
+#pragma unroll
+                            for (int u = 0; u < B; ++u) av[u] = p0[u * step];
+                            if (i == 0) S.d[j + 1 + k] = av[0];
+#pragma unroll
+                            for (int u = 0; u < B; ++u) {
+                                const int r = i + u * nst;
+                                acc = fma(av[u], r == 0 ? 1.0 : S.v[r] * scal, acc);
+                            }
+                        }
+                        for (; i < L; i += nst) {
+                            const double a = colp[i * n];
+                            if (i == 0) S.d[j + 1 + k] = a;
+                            acc = fma(a, i == 0 ? 1.0 : S.v[i] * scal, acc);
+                        }
+                    }
+                    S.y[st * Lp + k] = acc;
+                }
+                __syncthreads();
+                // P: entry quad; lane q takes the stripes and vectors = q (mod 4)
+                const bool act = quad < L;
+                const int ic = act ? quad : 0, g = j + 1 + ic;
+                double pp = 0.0;
+                {
+                    const double* yp = S.y + q * Lp + ic;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (q + 4 * t < nst) pp += yp[4 * t * Lp];
+                    const double* vg = Vt + g * TRI_NBP + q;
+                    const double* wg = Wt + g * TRI_NBP + q;
+                    const int tmax = (jc - q + 3) >> 2;
+#pragma unroll
+                    for (int t = 0; t < TRI_NB / 4; ++t)
+                        if (t < tmax) pp -= vg[4 * t] * dW[q + 4 * t] + wg[4 * t] * dV[q + 4 * t];
+                }
+                pp += __shfl_xor(pp, 1, 64);
+                pp += __shfl_xor(pp, 2, 64);
+                const double vi = act ? (quad == 0 ? 1.0 : S.v[quad] * scal) : 0.0;
+                const double pi = tau * pp;
+                double pv = (act && q == 0) ? pi * vi : 0.0;
+                pv = tri_wave_sum(pv);
+                if (lane == 0) S.red[16 + wave] = pv;
+                __syncthreads();
+                // S: w = p - K v, K = tau / 2 (p . v)
+                double pvs = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) pvs += S.red[16 + w];
+                const double K = 0.5 * tau * pvs;
+                if (act && q == 0) {
+                    Vt[g * TRI_NBP + jc] = vi;
+                    Wt[g * TRI_NBP + jc] = fma(-K, vi, pi);
+                }
+            }
+            __syncthreads();
+        }
+        // reflectors to W; trailing matrix (rows and columns >= j0 + jb)
+        // -= V W^T + W V^T in 4 x 4 tiles
+        for (int e = tid; e < jb * n; e += nth) {
+            const int cc = e / n, g = e - cc * n, j = j0 + cc;
+            if (g == j) Ag[j * n + j] = taus[cc];
+            else if (g > j + 1) Ag[j * n + g] = Vt[g * TRI_NBP + cc];
+        }
+        const int t0 = j0 + jb, Lt = n - t0;
+        const int nt = (Lt + 3) / 4;
+        for (int tile = tid; tile < nt * nt; tile += nth) {
+            const int ti = tile / nt, tk = tile - ti * nt;
+            const int i0 = t0 + 4 * ti, k0 = t0 + 4 * tk;
+            const double* vr[4];
+            const double* wr[4];
+            const double* vc[4];
+            const double* wc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ii = min(i0 + u, n - 1), kk = min(k0 + u, n - 1);
+                vr[u] = Vt + ii * TRI_NBP;
+                wr[u] = Wt + ii * TRI_NBP;
+                vc[u] = Vt + kk * TRI_NBP;
+                wc[u] = Wt + kk * TRI_NBP;
+            }
+            double acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int cc = 0; cc < jb; ++cc) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = fma(vr[a][cc], wc[b][cc], fma(wr[a][cc], vc[b][cc], acc[a][b]));
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (i0 + a < n && k0 + b < n) Ag[(i0 + a) * n + k0 + b] -= acc[a][b];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.d[n - 1] = W[(int64_t)(n - 1) * n + n - 1];
+        W[(int64_t)(n - 1) * n + n - 1] = 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += nth) {
+        U[i] = S.d[i];
+        if (i + 1 < n) U[lu + i] = S.e[i];
+    }
+}
+
+// Eigenpairs of the tridiagonal T left by the reduction (diagonal in row 0
+// of U, off-diagonal in row 1) into lam (descending) and U (eigenvectors of
+// T; the back-transformation applies Q).  On clusters it cannot separate,
+// the problem is solved again from Ain by the Jacobi method (info[2] counts
+// these; Dm[0] = 1 then tells the back-transformation to skip).
+// Dm: n x n global scratch.
+__device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n, double* W, double* Dm, double* U,
+                                             int lu, double* lam, int* info) {
+    __shared__ TriShared S;
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
+    for (int i = tid; i < n; i += nth) {
+        S.d[i] = U[i];
+        if (i + 1 < n) S.e[i] = U[lu + i];
+    }
+    if (tid == 0) S.flag = 0;
+    __syncthreads();
 
     // ---- 2. eigenvalues by bisection
     double emax2 = 0.0;
@@ -425,7 +699,7 @@ __device__ void tri_body(const double* Ain, int ldin, int n, double* W, double* 
 // = column), the rows of each reflector split between the wavefronts; the
 // strip lives in LDS when it fits.  Skipped when the Jacobi fallback
 // produced U.
-__device__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n, double* lds,
+__device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n, double* lds,
                               int lds_doubles) {
     __shared__ double vs[TRI_NMAX];
     __shared__ double part[2][4][64];
@@ -473,24 +747,62 @@ __device__ void tri_back_body(const double* W, const double* Dm, double* U, int 
 
 // Task form: the eigen-problem of a shrink / query task (not the
 // cooperative ones).
-__global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks, int lds_doubles) {
+#define TRI_TASK_PROLOGUE                                                   \
+    const Task& t = tasks[blockIdx.z];                                      \
+    if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;              \
+    const SkDev* s = t.s;                                                   \
+    const int n = eig_n(t);                                                 \
+    if (n < 1) return;                                                      \
+    const bool rnd = t.kind == T_SHRINK_RAND;                               \
+    (void)rnd;
+
+__global__ __launch_bounds__(1024) void k_tri_reduce(const Task* tasks, int lds_doubles, int blk_ok) {
     extern __shared__ double lds[];
-    const Task& t = tasks[blockIdx.z];
-    if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
-    const SkDev* s = t.s;
-    const int n = eig_n(t);
-    if (n < 1) return;
-    const bool rnd = t.kind == T_SHRINK_RAND;
-    tri_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_EV], s->slot[S_U],
-             s->sld[S_U], s->slot[S_LAM], s->info, lds, lds_doubles);
+    TRI_TASK_PROLOGUE
+    if (tri_blocked(n, blk_ok)) return;
+    tri_reduce_unblk_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U],
+                          s->sld[S_U], lds, lds_doubles);
+}
+
+__global__ __launch_bounds__(1024) void k_tri_reduce_blk(const Task* tasks) {
+    extern __shared__ double lds[];
+    TRI_TASK_PROLOGUE
+    if (!tri_blocked(n, 1)) return;
+    tri_reduce_blk_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U],
+                        s->sld[S_U], lds);
+}
+
+__global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks) {
+    TRI_TASK_PROLOGUE
+    tri_eig_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_EV], s->slot[S_U],
+                 s->sld[S_U], s->slot[S_LAM], s->info);
 }
 
 __global__ __launch_bounds__(256) void k_tri_back(const Task* tasks, int lds_doubles) {
     extern __shared__ double lds[];
-    const Task& t = tasks[blockIdx.z];
-    if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
-    const SkDev* s = t.s;
-    tri_back_body(s->slot[S_EA], s->slot[S_EV], s->slot[S_U], s->sld[S_U], eig_n(t), lds, lds_doubles);
+    TRI_TASK_PROLOGUE
+    tri_back_body(s->slot[S_EA], s->slot[S_EV], s->slot[S_U], s->sld[S_U], n, lds, lds_doubles);
+}
+
+// Descriptor form (window sketches): A (n x n) -> X (eigenvectors), lam.
+__global__ __launch_bounds__(1024) void k_tri_reduce_desc(DescArg<SmallDesc> ds, int lds_doubles, int blk_ok) {
+    extern __shared__ double lds[];
+    const SmallDesc q = ds.get();
+    if (q.n < 1 || tri_blocked(q.n, blk_ok)) return;
+    tri_reduce_unblk_body(q.A, q.lda, q.n, q.work, q.X, q.ldx, lds, lds_doubles);
+}
+
+__global__ __launch_bounds__(1024) void k_tri_reduce_blk_desc(DescArg<SmallDesc> ds) {
+    extern __shared__ double lds[];
+    const SmallDesc q = ds.get();
+    if (!tri_blocked(q.n, 1)) return;
+    tri_reduce_blk_body(q.A, q.lda, q.n, q.work, q.X, q.ldx, lds);
+}
+
+__global__ __launch_bounds__(1024) void k_tri_eig_desc(DescArg<SmallDesc> ds) {
+    const SmallDesc q = ds.get();
+    if (q.n < 1) return;
+    tri_eig_body(q.A, q.lda, q.n, q.work, q.work2, q.X, q.ldx, q.lam, q.info);
 }
 
 __global__ __launch_bounds__(256) void k_tri_back_desc(DescArg<SmallDesc> ds, int lds_doubles) {
@@ -500,15 +812,7 @@ __global__ __launch_bounds__(256) void k_tri_back_desc(DescArg<SmallDesc> ds, in
     tri_back_body(q.work, q.work2, q.X, q.ldx, q.n, lds, lds_doubles);
 }
 
-// Descriptor form (window sketches): A (n x n) -> X (eigenvectors), lam.
-__global__ __launch_bounds__(1024) void k_tri_eig_desc(DescArg<SmallDesc> ds, int lds_doubles) {
-    extern __shared__ double lds[];
-    const SmallDesc q = ds.get();
-    if (q.n < 1) return;
-    tri_body(q.A, q.lda, q.n, q.work, q.work2, q.X, q.ldx, q.lam, q.info, lds, lds_doubles);
-}
-
-static int g_tri_lds = -1, g_back_lds = -1;
+static int g_tri_lds = -1, g_back_lds = -1, g_blk_ok = 0;
 
 static int set_dyn_lds(const void* f, int want_doubles) {
     int dev = 0, maxl = 0;
@@ -525,13 +829,17 @@ static int set_dyn_lds(const void* f, int want_doubles) {
     return dbl;
 }
 
-// Dynamic LDS (doubles) of the tridiagonalisation kernels: up to a 128 x 129
-// matrix; of the back-transformation kernels: up to a 256 x 64 strip.
+// Dynamic LDS (doubles): the unblocked reduction up to a 128 x 129 matrix;
+// the blocked one its panels at n = 256 (else the unblocked reduction takes
+// every size); the back-transformation up to a 256 x 64 strip.
 int tri_lds_doubles() {
     if (g_tri_lds < 0) {
-        const int a = set_dyn_lds((const void*)k_tri_eig, 128 * 129);
-        const int b = set_dyn_lds((const void*)k_tri_eig_desc, 128 * 129);
-        g_tri_lds = a < b ? a : b;
+        const int a = set_dyn_lds((const void*)k_tri_reduce, 128 * 129);
+        const int b = set_dyn_lds((const void*)k_tri_reduce_desc, 128 * 129);
+        g_tri_lds = std::min(a, b);
+        const int c0 = set_dyn_lds((const void*)k_tri_reduce_blk, tri_blk_lds(256));
+        const int c1 = set_dyn_lds((const void*)k_tri_reduce_blk_desc, tri_blk_lds(256));
+        g_blk_ok = std::min(c0, c1) >= tri_blk_lds(256) ? 1 : 0;
         const int c = set_dyn_lds((const void*)k_tri_back, 256 * 64);
         const int d = set_dyn_lds((const void*)k_tri_back_desc, 256 * 64);
         g_back_lds = c < d ? c : d;
@@ -546,11 +854,20 @@ static int back_lds(int max_n) {
     return want <= g_back_lds ? want : 0;
 }
 
-hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st) {
+hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st, tasks,
-                       dbl);
+    hipLaunchKernelGGL(k_tri_reduce, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st, tasks,
+                       dbl, g_blk_ok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g_blk_ok && max_n > 128) {
+        hipLaunchKernelGGL(k_tri_reduce_blk, dim3(1, 1, (unsigned)count), dim3(1024),
+                           sizeof(double) * (size_t)tri_blk_lds(std::min(max_n, 256)), st, tasks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks);
     return hipGetLastError();
 }
 
@@ -565,8 +882,18 @@ hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;
     DescArg<SmallDesc> a{nullptr, q};
-    hipLaunchKernelGGL(k_tri_eig_desc, dim3(1, 1, 1), dim3(1024), sizeof(double) * (size_t)dbl, st, a, dbl);
+    hipLaunchKernelGGL(k_tri_reduce_desc, dim3(1, 1, 1), dim3(1024), sizeof(double) * (size_t)dbl, st, a, dbl,
+                       g_blk_ok);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g_blk_ok && q.n > 128 && q.n <= 256) {
+        hipLaunchKernelGGL(k_tri_reduce_blk_desc, dim3(1, 1, 1), dim3(1024), sizeof(double) * (size_t)tri_blk_lds(q.n),
+                           st, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tri_eig_desc, dim3(1, 1, 1), dim3(1024), 0, st, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int bl = back_lds(q.n);
     hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((q.n + 63) / 64), 1, 1), dim3(256), sizeof(double) * (size_t)bl,

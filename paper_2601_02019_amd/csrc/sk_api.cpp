@@ -247,7 +247,7 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
             {
                 StageScope sc(g.prof, ST_EIG, st);
                 g_stage = "tridiagonal eig";
-                e = launch_tri_eig(t, g.count, st);
+                e = launch_tri_eig(t, g.count, g.max_n, st);
             }
             if (e == hipSuccess) {
                 StageScope sc(g.prof, ST_EIG_BACK, st);

@@ -285,6 +285,25 @@ def test_batched_cooperative_solvers_bitwise_and_parity():
     assert rel_fro(gram(alone[0]), gram(o.query())) <= 1e-9
 
 
+@pytest.mark.parametrize("copies", [2, 12])
+def test_exact_fp64_repeated_eigenvalues(copies):
+    # rows that repeat a few orthogonal directions with equal weights give
+    # buffers whose Gram has repeated eigenvalues: pairs go through the
+    # cluster re-orthogonalisation of the eigen-solver, a dozen equal ones
+    # through its Jacobi fallback; the sketch must still match the oracle
+    d, ell = 96, 24
+    rng = np.random.default_rng(copies)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, 3 * copies)))
+    A = np.concatenate([np.tile(Q.T, (4, 1)), 0.5 * Q.T[:copies]], axis=0) * 2.0
+    A = A[rng.permutation(A.shape[0])]
+    note(f"exact fp64 repeated eigenvalues copies={copies} rows={A.shape[0]}")
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    o = oracle.FD(d, ell)
+    o.update(A)
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
 def test_csr_batch_equals_individual_csr_bitwise():
     from paper_2601_02019_amd import sketch_update_csr_batch
     shapes = [(256, 16, "rand"), (256, 16, "rand"), (128, 8, "exact"), (300, 20, "rand")]
