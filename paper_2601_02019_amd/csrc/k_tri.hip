@@ -695,54 +695,96 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
 }
 
 // U = Q U for the reflectors in W (row j: v_j beyond the super-diagonal,
-// W[j][j] = tau_j): a workgroup of four wavefronts per 64-column strip (lane
-// = column), the rows of each reflector split between the wavefronts; the
-// strip lives in LDS when it fits.  Skipped when the Jacobi fallback
-// produced U.
-__device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n, double* lds,
-                              int lds_doubles) {
-    __shared__ double vs[TRI_NMAX];
-    __shared__ double part[2][4][64];
+// W[j][j] = tau_j), skipped when the Jacobi fallback produced U.  One
+// wavefront per 4-column strip of U, held in LDS; sixteen lanes per column
+// split the rows (the product with v_j ends in four shuffles), so the
+// reflectors follow one another without a barrier.  The reflectors arrive in
+// blocks of TRI_RB(n) rows of W through LDS; the next block's loads are issued
+// before the current block is applied, so their latency is hidden.
+constexpr int TRI_SC = 4;
+__host__ __device__ constexpr int tri_rb(int n) { return n <= 256 ? 8 : 4; }
+__host__ __device__ constexpr int tri_back_lds(int n) { return (TRI_SC + tri_rb(n)) * n; }
+
+__device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n,
+                                              double* lds) {
     if (Dm[0] != 0.0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c0 = blockIdx.x * 64;
+    const int lane = threadIdx.x, c = lane & (TRI_SC - 1), p = lane >> 2;  // p: row phase (16)
+    const int c0 = blockIdx.x * TRI_SC;
     if (c0 >= n) return;
-    const int nc = min(64, n - c0);
-    const bool act = lane < nc;
-    const bool inl = n * 64 <= lds_doubles;
-    // the strip: LDS when it fits, else the columns of U in place (idle lanes
-    // then work on a clamped column and do not write it)
-    double* Z = inl ? lds : U + c0;
-    const int lz = inl ? 64 : lu;
-    const int col = inl ? lane : (act ? lane : 0);
-    const bool wr = inl || act;
-    if (inl)
-        for (int i = wave; i < n; i += 4) Z[i * 64 + lane] = act ? U[(int64_t)i * lu + c0 + lane] : 0.0;
-    int buf = 0;
-    for (int j = n - 2; j >= 0; --j) {
-        const double tau = W[(int64_t)j * n + j];
-        if (tau == 0.0) continue;
-        const int L = n - j - 1;
-        __syncthreads();  // the previous reflector is done with vs
-        for (int i = tid; i < L; i += 256) vs[i] = (i == 0) ? 1.0 : W[(int64_t)j * n + j + 1 + i];
-        __syncthreads();
-        double* z = Z + (int64_t)(j + 1) * lz + col;
-        double y0 = 0.0, y1 = 0.0;
-        int i = wave;
-        for (; i + 4 < L; i += 8) {
-            y0 = fma(vs[i], z[(int64_t)i * lz], y0);
-            y1 = fma(vs[i + 4], z[(int64_t)(i + 4) * lz], y1);
+    const bool act = c0 + c < n;
+    const int RB = tri_rb(n);
+    double* Z = lds;                // [n][TRI_SC]
+    double* vb = lds + n * TRI_SC;  // RB rows of W
+    for (int i = p; i < n; i += 16) Z[i * TRI_SC + c] = act ? U[(int64_t)i * lu + c0 + c] : 0.0;
+    double pf[32];  // RB * n <= 2048 = 32 per lane
+    int jhi = n - 2;
+    if (jhi >= 0) {
+        const int jl = max(0, jhi - RB + 1), cnt = (jhi - jl + 1) * n;
+        const double* src = W + (int64_t)jl * n;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            const int e = lane + 64 * t;
+            pf[t] = e < cnt ? src[e] : 0.0;
         }
-        for (; i < L; i += 4) y0 = fma(vs[i], z[(int64_t)i * lz], y0);
-        part[buf][wave][lane] = y0 + y1;
-        __syncthreads();
-        const double y = tau * ((part[buf][0][lane] + part[buf][1][lane]) + (part[buf][2][lane] + part[buf][3][lane]));
-        buf ^= 1;  // the next reflector writes the other buffer: no barrier before its partials
-        if (wr)
-            for (int r = wave; r < L; r += 4) z[(int64_t)r * lz] = fma(-vs[r], y, z[(int64_t)r * lz]);
     }
-    __syncthreads();
-    if (inl && act)
-        for (int i = wave; i < n; i += 4) U[(int64_t)i * lu + c0 + lane] = Z[i * 64 + lane];
+    while (jhi >= 0) {
+        const int jlo = max(0, jhi - RB + 1), cnt = (jhi - jlo + 1) * n;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            const int e = lane + 64 * t;
+            if (e < cnt) vb[e] = pf[t];
+        }
+        __syncthreads();
+        if (jlo > 0) {  // the next block, in flight while this one is applied
+            const int jh = jlo - 1, jl = max(0, jh - RB + 1), cn = (jh - jl + 1) * n;
+            const double* src = W + (int64_t)jl * n;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const int e = lane + 64 * t;
+                pf[t] = e < cn ? src[e] : 0.0;
+            }
+        }
+        for (int j = jhi; j >= jlo; --j) {
+            const double* row = vb + (j - jlo) * n;
+            const double tau = row[j];
+            if (tau == 0.0) continue;
+            const int L = n - j - 1;
+            const double* v = row + j + 1;  // v[0] = 1 implied
+            double* z = Z + (j + 1) * TRI_SC + c;
+            // eight independent partial sums and eight rows per step, so a
+            // lane keeps eight LDS loads in flight
+            double acc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+            int i = p;
+            for (; i + 112 < L; i += 128) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int r = i + 16 * u;
+                    acc[u] = fma(r == 0 ? 1.0 : v[r], z[r * TRI_SC], acc[u]);
+                }
+            }
+            for (; i < L; i += 16) acc[0] = fma(i == 0 ? 1.0 : v[i], z[i * TRI_SC], acc[0]);
+            double y = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+            y += __shfl_xor(y, 4, 64);
+            y += __shfl_xor(y, 8, 64);
+            y += __shfl_xor(y, 16, 64);
+            y += __shfl_xor(y, 32, 64);
+            y *= tau;
+            for (i = p; i + 112 < L; i += 128) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int r = i + 16 * u;
+                    z[r * TRI_SC] = fma(-(r == 0 ? 1.0 : v[r]), y, z[r * TRI_SC]);
+                }
+            }
+            for (; i < L; i += 16) z[i * TRI_SC] = fma(-(i == 0 ? 1.0 : v[i]), y, z[i * TRI_SC]);
+        }
+        jhi = jlo - 1;
+        __syncthreads();
+    }
+    if (act)
+        for (int i = p; i < n; i += 16) U[(int64_t)i * lu + c0 + c] = Z[i * TRI_SC + c];
 }
 
 // Task form: the eigen-problem of a shrink / query task (not the
@@ -778,10 +820,10 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks) {
                  s->sld[S_U], s->slot[S_LAM], s->info);
 }
 
-__global__ __launch_bounds__(256) void k_tri_back(const Task* tasks, int lds_doubles) {
+__global__ __launch_bounds__(64) void k_tri_back(const Task* tasks) {
     extern __shared__ double lds[];
     TRI_TASK_PROLOGUE
-    tri_back_body(s->slot[S_EA], s->slot[S_EV], s->slot[S_U], s->sld[S_U], n, lds, lds_doubles);
+    tri_back_body(s->slot[S_EA], s->slot[S_EV], s->slot[S_U], s->sld[S_U], n, lds);
 }
 
 // Descriptor form (window sketches): A (n x n) -> X (eigenvectors), lam.
@@ -805,14 +847,14 @@ __global__ __launch_bounds__(1024) void k_tri_eig_desc(DescArg<SmallDesc> ds) {
     tri_eig_body(q.A, q.lda, q.n, q.work, q.work2, q.X, q.ldx, q.lam, q.info);
 }
 
-__global__ __launch_bounds__(256) void k_tri_back_desc(DescArg<SmallDesc> ds, int lds_doubles) {
+__global__ __launch_bounds__(64) void k_tri_back_desc(DescArg<SmallDesc> ds) {
     extern __shared__ double lds[];
     const SmallDesc q = ds.get();
     if (q.n < 1) return;
-    tri_back_body(q.work, q.work2, q.X, q.ldx, q.n, lds, lds_doubles);
+    tri_back_body(q.work, q.work2, q.X, q.ldx, q.n, lds);
 }
 
-static int g_tri_lds = -1, g_back_lds = -1, g_blk_ok = 0;
+static int g_tri_lds = -1, g_back_ok = 0, g_blk_ok = 0;
 
 static int set_dyn_lds(const void* f, int want_doubles) {
     int dev = 0, maxl = 0;
@@ -840,18 +882,20 @@ int tri_lds_doubles() {
         const int c0 = set_dyn_lds((const void*)k_tri_reduce_blk, tri_blk_lds(256));
         const int c1 = set_dyn_lds((const void*)k_tri_reduce_blk_desc, tri_blk_lds(256));
         g_blk_ok = std::min(c0, c1) >= tri_blk_lds(256) ? 1 : 0;
-        const int c = set_dyn_lds((const void*)k_tri_back, 256 * 64);
-        const int d = set_dyn_lds((const void*)k_tri_back_desc, 256 * 64);
-        g_back_lds = c < d ? c : d;
+        const int want = std::max(tri_back_lds(256), tri_back_lds(TRI_NMAX));
+        const int c = set_dyn_lds((const void*)k_tri_back, want);
+        const int d = set_dyn_lds((const void*)k_tri_back_desc, want);
+        g_back_ok = std::min(c, d) >= want ? 1 : 0;
         (void)hipGetLastError();
     }
     return g_tri_lds;
 }
 
+// LDS of a back-transformation launch covering sizes up to max_n
 static int back_lds(int max_n) {
-    tri_lds_doubles();
-    const int want = max_n * 64;
-    return want <= g_back_lds ? want : 0;
+    int w = 0;
+    for (int m : {std::min(max_n, 256), max_n}) w = std::max(w, tri_back_lds(m));
+    return w;
 }
 
 hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
@@ -872,9 +916,10 @@ hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t s
 }
 
 hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t st) {
-    const int bl = back_lds(max_n);
-    hipLaunchKernelGGL(k_tri_back, dim3((unsigned)((max_n + 63) / 64), 1, (unsigned)count), dim3(256),
-                       sizeof(double) * (size_t)bl, st, tasks, bl);
+    tri_lds_doubles();
+    if (!g_back_ok || max_n > TRI_NMAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_tri_back, dim3((unsigned)((max_n + TRI_SC - 1) / TRI_SC), 1, (unsigned)count), dim3(64),
+                       sizeof(double) * (size_t)back_lds(max_n), st, tasks);
     return hipGetLastError();
 }
 
@@ -895,9 +940,9 @@ hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st) {
     hipLaunchKernelGGL(k_tri_eig_desc, dim3(1, 1, 1), dim3(1024), 0, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int bl = back_lds(q.n);
-    hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((q.n + 63) / 64), 1, 1), dim3(256), sizeof(double) * (size_t)bl,
-                       st, a, bl);
+    if (!g_back_ok || q.n > TRI_NMAX) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((q.n + TRI_SC - 1) / TRI_SC), 1, 1), dim3(64),
+                       sizeof(double) * (size_t)tri_back_lds(q.n), st, a);
     return hipGetLastError();
 }
 
