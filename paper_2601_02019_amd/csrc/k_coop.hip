@@ -340,45 +340,46 @@ __global__ void k_coop_zero_bars(CoopList L) {
 // ------------------------------------------------------------ CholeskyQR
 // Factor the 32 x 32 diagonal block in LDS (lower, with rank dropping against
 // the original diagonal d0), then its lower inverse.  drop[] per column.
+// One barrier per column: column j's final values go to Li while the trailing
+// update reads the unscaled column from L (scaled by 1 / L_jj on the fly).
+// The inverse: eight lanes per column split each substitution's sum (the
+// column's rows follow one another inside one wavefront, no barrier).
 __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, double* piv) {
+    __shared__ double rd[PB];
     const int tid = threadIdx.x;
+    (void)piv;
     for (int j = 0; j < PB; ++j) {
-        if (tid == 0) {
-            const double p = L[j * PBL + j];
-            const bool ok = p > 1e-14 * d0[j] && p > 1e-300;
-            drop[j] = ok ? 0 : 1;
-            *piv = ok ? sqrt(p) : 0.0;
-            L[j * PBL + j] = *piv;
-        }
-        __syncthreads();
-        const double dj = *piv;
-        const bool dr = drop[j] != 0;
-        if (tid > j && tid < PB) L[tid * PBL + j] = dr ? 0.0 : L[tid * PBL + j] / dj;
-        __syncthreads();
-        if (!dr) {
+        const double p = L[j * PBL + j];
+        const bool ok = p > 1e-14 * d0[j] && p > 1e-300;
+        const double dj = ok ? sqrt(p) : 0.0;
+        const double r = ok ? 1.0 / dj : 0.0;
+        if (tid < PB) Li[tid * PBL + j] = tid < j ? 0.0 : (tid == j ? dj : L[tid * PBL + j] * r);
+        if (tid == 0) drop[j] = ok ? 0 : 1;
+        if (ok)
             for (int e = tid; e < PB * PB; e += 256) {
                 const int i = e / PB, l = e % PB;
-                if (l > j && l <= i) L[i * PBL + l] -= L[i * PBL + j] * L[l * PBL + j];
+                if (l > j && l <= i) L[i * PBL + l] -= (L[i * PBL + j] * r) * (L[l * PBL + j] * r);
             }
-        }
         __syncthreads();
     }
-    // zero the strict upper part, then Li = L^{-1} by columns (thread c: column c)
+    // L = the factor (strict upper part zero); rd = 1 / L_ii (0 when dropped)
     for (int e = tid; e < PB * PB; e += 256) {
         const int i = e / PB, l = e % PB;
-        if (l > i) L[i * PBL + l] = 0.0;
+        L[i * PBL + l] = l <= i ? Li[i * PBL + l] : 0.0;
     }
+    if (tid < PB) rd[tid] = drop[tid] ? 0.0 : 1.0 / Li[tid * PBL + tid];
     __syncthreads();
-    if (tid < PB) {
-        const int c = tid;
+    {
+        const int c = tid >> 3, sl = tid & 7;
         for (int i = 0; i < PB; ++i) {
-            double v = 0.0;
-            if (i >= c && !drop[i]) {
-                double acc = (i == c) ? 1.0 : 0.0;
-                for (int l = c; l < i; ++l) acc -= L[i * PBL + l] * Li[l * PBL + c];
-                v = acc / L[i * PBL + i];
-            }
-            Li[i * PBL + c] = v;
+            double acc = 0.0;
+            if (i > c)
+                for (int l = c + sl; l < i; l += 8) acc = fma(L[i * PBL + l], Li[l * PBL + c], acc);
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            acc += __shfl_xor(acc, 4, 64);
+            if (sl == 0) Li[i * PBL + c] = (i < c) ? 0.0 : ((i == c ? 1.0 : 0.0) - acc) * rd[i];
+            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
