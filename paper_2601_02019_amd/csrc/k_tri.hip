@@ -87,14 +87,23 @@ __device__ bool twisted_vec(const double* d, const double* e, const double* e2, 
     Pm[(int64_t)(n - 1) * sm] = qb;
     int r = n - 1;
     double gbest = fabs(Pp[(int64_t)(n - 1) * sp] + qb - (d[n - 1] - x));
-    for (int i = n - 2; i >= 0; --i) {
-        qb = (d[i] - x) - tri_div(e2[i], qb);
-        if (fabs(qb) < pivmin) qb = -pivmin;
-        Pm[(int64_t)i * sm] = qb;
-        const double g = fabs(Pp[(int64_t)i * sp] + qb - (d[i] - x));
-        if (g < gbest) {
-            gbest = g;
-            r = i;
+    // the stored pivots are read in batches of 8 ahead of the recurrence
+    for (int i0 = n - 2; i0 >= 0; i0 -= 8) {
+        double pp[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pp[u] = Pp[(int64_t)max(i0 - u, 0) * sp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 - u;
+            if (i < 0) break;
+            qb = (d[i] - x) - tri_div(e2[i], qb);
+            if (fabs(qb) < pivmin) qb = -pivmin;
+            Pm[(int64_t)i * sm] = qb;
+            const double g = fabs(pp[u] + qb - (d[i] - x));
+            if (g < gbest) {
+                gbest = g;
+                r = i;
+            }
         }
     }
     if (rank > 0) {  // the rank-th smallest |gamma|: rank + 1 passes with exclusion
@@ -119,20 +128,37 @@ __device__ bool twisted_vec(const double* d, const double* e, const double* e2, 
     }
     // z_r = 1; upwards with the forward pivots, downwards with the backward ones
     double z = 1.0, nrm2 = 1.0;
-    for (int i = r - 1; i >= 0; --i) {
-        z = -tri_div(e[i], Pp[(int64_t)i * sp]) * z;
-        Z[(int64_t)i * sz] = z;
-        nrm2 = fma(z, z, nrm2);
+    for (int i0 = r - 1; i0 >= 0; i0 -= 8) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pv[u] = Pp[(int64_t)max(i0 - u, 0) * sp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 - u;
+            if (i < 0) break;
+            z = -tri_div(e[i], pv[u]) * z;
+            Z[(int64_t)i * sz] = z;
+            nrm2 = fma(z, z, nrm2);
+        }
     }
     Z[(int64_t)r * sz] = 1.0;
     z = 1.0;
-    for (int i = r + 1; i < n; ++i) {
-        z = -tri_div(e[i - 1], Pm[(int64_t)i * sm]) * z;
-        Z[(int64_t)i * sz] = z;
-        nrm2 = fma(z, z, nrm2);
+    for (int i0 = r + 1; i0 < n; i0 += 8) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pv[u] = Pm[(int64_t)min(i0 + u, n - 1) * sm];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u;
+            if (i >= n) break;
+            z = -tri_div(e[i - 1], pv[u]) * z;
+            Z[(int64_t)i * sz] = z;
+            nrm2 = fma(z, z, nrm2);
+        }
     }
     if (!(nrm2 < 1e300)) return false;
     const double inv = 1.0 / sqrt(nrm2);
+#pragma unroll 8
     for (int i = 0; i < n; ++i) Z[(int64_t)i * sz] *= inv;
     return true;
 }
@@ -576,8 +602,11 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
     // multisection: tpe threads (contiguous lanes) per eigenvalue count at the
     // tpe interior points that cut the interval into tpe + 1 parts; the first
     // point with more than m eigenvalues below it bounds the next interval
-    int tpe = 1;  // tpe * n <= nth: one eigenvalue per group of lanes
-    while (tpe < 32 && tpe * 2 * n <= nth) tpe *= 2;
+#ifndef TRI_BISECT_LANES
+#define TRI_BISECT_LANES 768
+#endif
+    int tpe = 1;  // tpe * n <= TRI_BISECT_LANES: one eigenvalue per group of lanes
+    while (tpe < 32 && tpe * 2 * n <= min(nth, TRI_BISECT_LANES)) tpe *= 2;
     {
         const int sub = lane % tpe, k = tid / tpe;
         const unsigned long long gmask = (1ull << tpe) - 1ull;
