@@ -117,11 +117,16 @@ def measured_traffic(kernel, source):
 
 
 def tri_flops(n):
-    """Dense arithmetic of k_tri_eig (FP64 flops): the Householder reduction
-    to tridiagonal form (a symmetric product and a rank-2 update per column,
-    4 n^3 / 3 in all); the bisection and the O(n^2) eigenvector recurrences
-    are not counted.  The back-transformation (2 n^3) is the next kernel."""
+    """Dense arithmetic of the tridiagonal reduction (FP64 flops): a symmetric
+    product and a rank-2 update per column, 4 n^3 / 3 in all."""
     return 4.0 * n ** 3 / 3.0
+
+
+def tri_product_bytes(n):
+    """Bytes the blocked reduction reads per launch for its products with the
+    panel-start matrix (column j reads the (n - j - 1)^2 trailing block once,
+    FP64), about 8 n^3 / 3; the once-per-panel trailing updates add little."""
+    return 8.0 * sum((n - j - 1) ** 2 for j in range(n - 1))
 
 
 def jacobi_flops(n, sweeps):
@@ -361,7 +366,8 @@ def window_main(args):
     cpu = None
     if not args.no_cpu:
         import oracle
-        m = 3000
+        m = 600  # about 20-30 s of the FP64 oracle
+        print(f"[bench] CPU oracle on the first {m} rows", file=sys.stderr, flush=True)
         o = oracle.Window(d, ell, N, R, q=1, seed=9, stream=0, fd="rand")
         t = time.perf_counter()
         o.update(A[:m].astype(np.float64))
@@ -546,17 +552,22 @@ def main():
     dom_calls, dom_ms = stages[dom]
     avg_ms = dom_ms / dom_calls
     roofline = None
-    if dom == "eig" and ell <= 256 and os.environ.get("SK_EIG_SOLVER") != "jacobi":
-        # k x k Rayleigh-Ritz eigen-solve on one workgroup (k = ell <= 256)
+    if dom == "eig_reduce":
+        # Householder reduction of the k x k Rayleigh-Ritz matrix (k = ell) on
+        # one workgroup: blocked, with the matrix in L2, for 128 < n <= 256
+        kern = "k_tri_reduce_blk" if 128 < ell <= 256 else "k_tri_reduce"
         flops = tri_flops(ell)
         achieved = flops / (avg_ms / 1e3) / 1e12
-        roofline = {"bound": "alu", "kernel": "k_tri_eig (FP64 tridiagonal eigen-solver, one workgroup, n=%d)" % ell,
+        roofline = {"bound": "alu", "kernel": "%s (FP64 Householder tridiagonalisation, one workgroup, n=%d)"
+                    % (kern, ell),
                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_FP64_TFLOPS,
-                    "traffic": measured_traffic("k_tri_eig", "paper_2601_02019_amd/csrc/k_tri.hip"),
+                    "traffic": measured_traffic(kern, "paper_2601_02019_amd/csrc/k_tri.hip"),
                     "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops,
+                    "l2_product_bytes_per_launch": tri_product_bytes(ell),
+                    "l2_product_gbps": tri_product_bytes(ell) / (avg_ms / 1e3) / 1e9,
                     "fallbacks_to_jacobi": prof.get("eig_fallbacks", (0, 0.0))[1]}
-    elif dom == "eig":
+    elif dom == "eig" and (ell > 256 or os.environ.get("SK_EIG_SOLVER") == "jacobi"):
         solves = prof.get("eig_solves", (0, 0.0))[1]
         sweeps = prof.get("eig_sweeps", (0, 0.0))[1] / max(solves, 1)
         flops = jacobi_flops(ell, sweeps)

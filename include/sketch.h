@@ -278,7 +278,8 @@ enum {
     SK_STAGE_THRESHOLD = 1u << 7, /* delta and the rebuild matrix                 */
     SK_STAGE_REBUILD = 1u << 8,   /* B' = T C                                     */
     SK_STAGE_EIG_BACK = 1u << 9,  /* eigenvectors back to the matrix's basis      */
-    SK_STAGE_ALL = 0x3ffu
+    SK_STAGE_EIG_REDUCE = 1u << 10, /* tridiagonal reduction of the eigen-solve   */
+    SK_STAGE_ALL = 0x7ffu
 };
 
 typedef struct {

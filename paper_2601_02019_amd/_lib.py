@@ -69,8 +69,9 @@ class sk_server_stats(ctypes.Structure):
 
 
 SK_STAGE = {"ingest": 1 << 0, "omega": 1 << 1, "gram": 1 << 2, "project": 1 << 3, "cholqr": 1 << 4,
-            "core_gemm": 1 << 5, "eig": 1 << 6, "threshold": 1 << 7, "rebuild": 1 << 8, "eig_back": 1 << 9}
-SK_STAGE_ALL = 0x3FF
+            "core_gemm": 1 << 5, "eig": 1 << 6, "threshold": 1 << 7, "rebuild": 1 << 8, "eig_back": 1 << 9,
+            "eig_reduce": 1 << 10}
+SK_STAGE_ALL = 0x7FF
 
 EXPORTS = [
     "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query",

@@ -340,8 +340,46 @@ struct TriBlkShared {
 
 constexpr int TRI_NBP = TRI_NB + 1;  // row stride of the panel (bank spread)
 
-// Dynamic LDS (doubles) of the blocked reduction at size n.
-__host__ __device__ constexpr int tri_blk_lds(int n) { return 2 * n * TRI_NBP + 128; }
+// Dynamic LDS (doubles) of the blocked reduction at size n: the panels, 128
+// scalars, and 16 rows of slack that the products with v may read (and
+// discard) past the last row.
+__host__ __device__ constexpr int tri_blk_lds(int n) { return 2 * n * TRI_NBP + 128 + 16 * TRI_NBP; }
+
+// Product of a panel vector with v on 16 lanes: rows part + 16 t, t < T, of
+// which those past the column (16 t >= rem) are read and discarded.
+template <int T>
+__device__ __forceinline__ double tri_vdot(const double* P, const double* vp, int rem, bool first, double scal) {
+    double ds = 0.0;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const bool in = 16 * t < rem;
+        const double pt = P[16 * t * TRI_NBP], vt = vp[16 * t];
+        const double vi = in ? ((first && t == 0) ? 1.0 : vt * scal) : 0.0;
+        ds = fma(in ? pt : 0.0, vi, ds);
+    }
+    return ds;
+}
+__device__ __forceinline__ double tri_vdot_n(int T, const double* P, const double* vp, int rem, bool first,
+                                             double scal) {
+    switch (T) {
+        case 1: return tri_vdot<1>(P, vp, rem, first, scal);
+        case 2: return tri_vdot<2>(P, vp, rem, first, scal);
+        case 3: return tri_vdot<3>(P, vp, rem, first, scal);
+        case 4: return tri_vdot<4>(P, vp, rem, first, scal);
+        case 5: return tri_vdot<5>(P, vp, rem, first, scal);
+        case 6: return tri_vdot<6>(P, vp, rem, first, scal);
+        case 7: return tri_vdot<7>(P, vp, rem, first, scal);
+        case 8: return tri_vdot<8>(P, vp, rem, first, scal);
+        case 9: return tri_vdot<9>(P, vp, rem, first, scal);
+        case 10: return tri_vdot<10>(P, vp, rem, first, scal);
+        case 11: return tri_vdot<11>(P, vp, rem, first, scal);
+        case 12: return tri_vdot<12>(P, vp, rem, first, scal);
+        case 13: return tri_vdot<13>(P, vp, rem, first, scal);
+        case 14: return tri_vdot<14>(P, vp, rem, first, scal);
+        case 15: return tri_vdot<15>(P, vp, rem, first, scal);
+        default: return tri_vdot<16>(P, vp, rem, first, scal);
+    }
+}
 
 __device__ __forceinline__ bool tri_blocked(int n, int blk_ok) { return blk_ok && n > 128 && n <= 256; }
 
@@ -430,14 +468,7 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
                     const double* vp = S.v + part;
                     const int rem = L - part;  // rows t with 16 t < rem
                     double ds = 0.0;
-                    if (cc < jc) {
-#pragma unroll
-                        for (int t = 0; t < 16; ++t)
-                            if (16 * t < rem) {
-                                const double vi = (part == 0 && t == 0) ? 1.0 : vp[16 * t] * scal;
-                                ds = fma(P[16 * t * TRI_NBP], vi, ds);
-                            }
-                    }
+                    if (cc < jc) ds = tri_vdot_n((L + 15) >> 4, P, vp, rem, part == 0, scal);
                     ds += __shfl_xor(ds, 8, 64);
                     ds += __shfl_xor(ds, 4, 64);
                     ds += __shfl_xor(ds, 2, 64);
@@ -927,19 +958,26 @@ static int back_lds(int max_n) {
     return w;
 }
 
-hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
+hipError_t launch_tri_reduce(const Task* tasks, int count, int min_n, int max_n, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_tri_reduce, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st, tasks,
-                       dbl, g_blk_ok);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (g_blk_ok && max_n > 128) {
+    const bool any_blk = g_blk_ok && max_n > 128 && min_n <= 256;
+    const bool any_unblk = !g_blk_ok || min_n <= 128 || max_n > 256;
+    hipError_t e = hipSuccess;
+    if (any_unblk) {
+        hipLaunchKernelGGL(k_tri_reduce, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st,
+                           tasks, dbl, g_blk_ok);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (any_blk) {
         hipLaunchKernelGGL(k_tri_reduce_blk, dim3(1, 1, (unsigned)count), dim3(1024),
                            sizeof(double) * (size_t)tri_blk_lds(std::min(max_n, 256)), st, tasks);
         e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
+    return e;
+}
+
+hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st) {
     hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks);
     return hipGetLastError();
 }

@@ -153,7 +153,7 @@ namespace {
 
 struct Group {
     int count = 0;
-    int max_m = 0, max_k = 0, max_d = 0, max_ell = 0, max_sg = 1, max_sp = 1, max_n = 0;
+    int max_m = 0, max_k = 0, max_d = 0, max_ell = 0, max_sg = 1, max_sp = 1, max_n = 0, min_n = 1 << 30;
     bool small = false, large = false, small_k = false, large_k = false;
     int q = 0, st = DT_F64, pj = DT_F64;
     double* coop = nullptr;
@@ -183,6 +183,7 @@ Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tas
         g.max_sp = std::max(g.max_sp, h->host.sp);
         const int n = (t.kind == T_SHRINK_RAND) ? h->k : t.m;
         g.max_n = std::max(g.max_n, n);
+        g.min_n = std::min(g.min_n, n);
         if (n <= jacobi_lds_max()) g.small = true;
         else g.large = true;
         if (h->k <= chol_lds_max()) g.small_k = true;
@@ -245,9 +246,14 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
             e = launch_jacobi(t, g.count, g.max_n, g.small, g.large, st);
         } else {
             {
+                StageScope sc(g.prof, ST_EIG_REDUCE, st);
+                g_stage = "tridiagonal reduction";
+                e = launch_tri_reduce(t, g.count, g.min_n, g.max_n, st);
+            }
+            if (e == hipSuccess) {
                 StageScope sc(g.prof, ST_EIG, st);
                 g_stage = "tridiagonal eig";
-                e = launch_tri_eig(t, g.count, g.max_n, st);
+                e = launch_tri_eig(t, g.count, st);
             }
             if (e == hipSuccess) {
                 StageScope sc(g.prof, ST_EIG_BACK, st);

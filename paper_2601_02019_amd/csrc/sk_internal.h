@@ -104,10 +104,12 @@ struct TaskArena {
 };
 
 // ---------------------------------------------------------------- profiling
-static const int NSTAGE = 10;
+static const int NSTAGE = 11;
 static const char* const STAGE_NAMES[NSTAGE] = {"ingest", "omega", "gram", "project", "cholqr",
-                                                "core_gemm", "eig", "threshold", "rebuild", "eig_back"};
-enum { ST_INGEST, ST_OMEGA, ST_GRAM, ST_PROJECT, ST_CHOLQR, ST_CORE, ST_EIG, ST_THRESH, ST_REBUILD, ST_EIG_BACK };
+                                                "core_gemm", "eig", "threshold", "rebuild", "eig_back",
+                                                "eig_reduce"};
+enum { ST_INGEST, ST_OMEGA, ST_GRAM, ST_PROJECT, ST_CHOLQR, ST_CORE, ST_EIG, ST_THRESH, ST_REBUILD, ST_EIG_BACK,
+       ST_EIG_REDUCE };
 
 struct Prof {
     uint32_t mask = 0;

@@ -55,7 +55,10 @@ hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n
                               int64_t ldx, int d, hipStream_t st);
 // Tridiagonal eigen-solver, one workgroup per problem (n <= 512): the
 // non-cooperative tasks of a list, or one descriptor by value.
-hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st);
+// The tridiagonal solver in three launches: the reduction (tasks' sizes in
+// [min_n, max_n]), the eigenpairs of T, the back-transformation.
+hipError_t launch_tri_reduce(const Task* tasks, int count, int min_n, int max_n, hipStream_t st);
+hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st);
 hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t st);
 hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st);
 int tri_lds_doubles();
