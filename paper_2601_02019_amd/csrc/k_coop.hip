@@ -338,49 +338,73 @@ __global__ void k_coop_zero_bars(CoopList L) {
 }
 
 // ------------------------------------------------------------ CholeskyQR
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // Factor the 32 x 32 diagonal block in LDS (lower, with rank dropping against
 // the original diagonal d0), then its lower inverse.  drop[] per column.
-// One barrier per column: column j's final values go to Li while the trailing
-// update reads the unscaled column from L (scaled by 1 / L_jj on the fly).
-// The inverse: eight lanes per column split each substitution's sum (the
-// column's rows follow one another inside one wavefront, no barrier).
+// One wavefront, lane i holding row i in registers: per column the pivot
+// comes by a lane read, 1/sqrt by the hardware estimate and two Newton steps,
+// and the scaled column reaches the other lanes through LDS; no barrier.  The
+// inverse: lane c holds column c and substitutes row by row.
 __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, double* piv) {
+    __shared__ double colj[PB];
     __shared__ double rd[PB];
     const int tid = threadIdx.x;
     (void)piv;
-    for (int j = 0; j < PB; ++j) {
-        const double p = L[j * PBL + j];
-        const bool ok = p > 1e-14 * d0[j] && p > 1e-300;
-        const double dj = ok ? sqrt(p) : 0.0;
-        const double r = ok ? 1.0 / dj : 0.0;
-        if (tid < PB) Li[tid * PBL + j] = tid < j ? 0.0 : (tid == j ? dj : L[tid * PBL + j] * r);
-        if (tid == 0) drop[j] = ok ? 0 : 1;
-        if (ok)
-            for (int e = tid; e < PB * PB; e += 256) {
-                const int i = e / PB, l = e % PB;
-                if (l > j && l <= i) L[i * PBL + l] -= (L[i * PBL + j] * r) * (L[l * PBL + j] * r);
+    if (tid < PB) {
+        const int i = tid;
+        double a[PB];
+#pragma unroll
+        for (int t = 0; t < PB; ++t) a[t] = L[i * PBL + t];
+        double rdi = 0.0;
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const double p = lane_bcast(a[j], j);
+            const bool ok = p > 1e-14 * d0[j] && p > 1e-300;
+            double r = 0.0, dj = 0.0;
+            if (ok) {
+                r = __builtin_amdgcn_rsq(p);
+                r = r * fma(-0.5 * p * r, r, 1.5);
+                r = r * fma(-0.5 * p * r, r, 1.5);
+                dj = p * r;
             }
-        __syncthreads();
-    }
-    // L = the factor (strict upper part zero); rd = 1 / L_ii (0 when dropped)
-    for (int e = tid; e < PB * PB; e += 256) {
-        const int i = e / PB, l = e % PB;
-        L[i * PBL + l] = l <= i ? Li[i * PBL + l] : 0.0;
-    }
-    if (tid < PB) rd[tid] = drop[tid] ? 0.0 : 1.0 / Li[tid * PBL + tid];
-    __syncthreads();
-    {
-        const int c = tid >> 3, sl = tid & 7;
-        for (int i = 0; i < PB; ++i) {
-            double acc = 0.0;
-            if (i > c)
-                for (int l = c + sl; l < i; l += 8) acc = fma(L[i * PBL + l], Li[l * PBL + c], acc);
-            acc += __shfl_xor(acc, 1, 64);
-            acc += __shfl_xor(acc, 2, 64);
-            acc += __shfl_xor(acc, 4, 64);
-            if (sl == 0) Li[i * PBL + c] = (i < c) ? 0.0 : ((i == c ? 1.0 : 0.0) - acc) * rd[i];
+            const double ci = a[j] * r;
+            colj[i] = ci;
+            __builtin_amdgcn_wave_barrier();
+            if (ok) {
+#pragma unroll
+                for (int l = j + 1; l < PB; ++l)
+                    if (l <= i) a[l] -= ci * colj[l];
+            }
+            a[j] = (i > j) ? ci : (i == j ? dj : 0.0);
+            if (i == j) rdi = r;
+            if (i == 0) drop[j] = ok ? 0 : 1;
             __builtin_amdgcn_wave_barrier();
         }
+#pragma unroll
+        for (int t = 0; t < PB; ++t) L[i * PBL + t] = t <= i ? a[t] : 0.0;
+        rd[i] = rdi;
+    }
+    __syncthreads();
+    if (tid < PB) {
+        const int c = tid;
+        double x[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+            for (int l = 0; l < i; l += 2) {
+                s0 = fma(-L[i * PBL + l], x[l], s0);
+                if (l + 1 < i) s1 = fma(-L[i * PBL + l + 1], x[l + 1], s1);
+            }
+            x[i] = (i >= c) ? (s0 + s1) * rd[i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) Li[i * PBL + c] = x[i];
     }
     __syncthreads();
 }
