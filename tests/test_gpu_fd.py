@@ -304,6 +304,35 @@ def test_exact_fp64_repeated_eigenvalues(copies):
     assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
 
 
+@pytest.mark.parametrize("d,ell,n", [(300, 72, 500), (260, 100, 420), (400, 128, 700)])
+def test_exact_fp64_blocked_reduction_sizes(d, ell, n):
+    # 2 ell in (128, 256]: the eigen-solve takes the panel-blocked Householder
+    # reduction (several 32-column panels, a ragged last panel, and the
+    # largest size, 256)
+    note(f"exact fp64 blocked reduction d={d} ell={ell} n={n}")
+    A = synth.lowrank_rows(n, d, np.geomspace(6, 0.02, min(d, 3 * ell)), 0.05, seed=d + ell)
+    o = run_oracle(A, d, ell)
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
+@pytest.mark.parametrize("copies", [3, 10])
+def test_exact_fp64_repeated_eigenvalues_blocked(copies):
+    # repeated eigenvalues at 2 ell = 160 (blocked reduction, cluster path)
+    d, ell = 200, 80
+    rng = np.random.default_rng(100 + copies)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, 12 * copies)))
+    A = np.concatenate([np.tile(Q.T, (3, 1)), 0.5 * Q.T[:copies], rng.standard_normal((40, d)) * 0.01], axis=0)
+    A = A[rng.permutation(A.shape[0])]
+    note(f"exact fp64 repeated eigenvalues (blocked) copies={copies} rows={A.shape[0]}")
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    o = oracle.FD(d, ell)
+    o.update(A)
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+
+
 def test_csr_batch_equals_individual_csr_bitwise():
     from paper_2601_02019_amd import sketch_update_csr_batch
     shapes = [(256, 16, "rand"), (256, 16, "rand"), (128, 8, "exact"), (300, 20, "rand")]
