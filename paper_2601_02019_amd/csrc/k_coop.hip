@@ -346,12 +346,11 @@ __device__ __forceinline__ double lane_bcast(double x, int lane) {
 
 // Factor the 32 x 32 diagonal block in LDS (lower, with rank dropping against
 // the original diagonal d0), then its lower inverse.  drop[] per column.
-// One wavefront, lane i holding row i in registers: per column the pivot
-// comes by a lane read, 1/sqrt by the hardware estimate and two Newton steps,
-// and the scaled column reaches the other lanes through LDS; no barrier.  The
+// One wavefront, lane i holding row i in registers: per column the pivot and
+// the scaled column come by lane reads, 1/sqrt by the hardware estimate and
+// two Newton steps; no LDS traffic and no barrier.  The
 // inverse: lane c holds column c and substitutes row by row.
 __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, double* piv) {
-    __shared__ double colj[PB];
     __shared__ double rd[PB];
     const int tid = threadIdx.x;
     (void)piv;
@@ -373,12 +372,12 @@ __device__ void lds_chol32(double* L, double* Li, const double* d0, int* drop, d
                 dj = p * r;
             }
             const double ci = a[j] * r;
-            colj[i] = ci;
-            __builtin_amdgcn_wave_barrier();
             if (ok) {
 #pragma unroll
-                for (int l = j + 1; l < PB; ++l)
-                    if (l <= i) a[l] -= ci * colj[l];
+                for (int l = j + 1; l < PB; ++l) {
+                    const double cl = lane_bcast(ci, l);
+                    if (l <= i) a[l] -= ci * cl;
+                }
             }
             a[j] = (i > j) ? ci : (i == j ? dj : 0.0);
             if (i == j) rdi = r;
