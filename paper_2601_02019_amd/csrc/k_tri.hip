@@ -175,8 +175,37 @@ __device__ bool twisted_vec(const double* d, const double* e, const double* e2, 
 constexpr int TRI_NB = 32;
 typedef __attribute__((address_space(1))) double gdouble;
 
+// Lane exchanges inside rows of 16 lanes by DPP (no trip through the LDS
+// crossbar): CTRL 0xB1 / 0x4E swap lanes 1 and 2 apart within quads, 0x141
+// mirrors each half-row, 0x140 each row.
+template <int CTRL>
+__device__ __forceinline__ double tri_dpp(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each quad, every lane of the quad getting the same value (the
+// same operations as exchanges with lane ^ 1, then lane ^ 2).
+__device__ __forceinline__ double tri_quad_sum(double x) {
+    x += tri_dpp<0xB1>(x);
+    x += tri_dpp<0x4E>(x);
+    return x;
+}
+
+// Sum over each row of 16 lanes: after the quad sums every quad is uniform,
+// so the half-row and row mirrors pair quads as lane ^ 4 and lane ^ 8 would.
+__device__ __forceinline__ double tri_row_sum(double x) {
+    x = tri_quad_sum(x);
+    x += tri_dpp<0x141>(x);
+    x += tri_dpp<0x140>(x);
+    return x;
+}
+
 __device__ __forceinline__ double tri_wave_sum(double x) {
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    x = tri_row_sum(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
 }
 
@@ -198,7 +227,7 @@ __device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldi
     if (wave == 0) {  // |x|^2 of the first column below its first entry
         double acc = 0.0;
         for (int k = 2 + lane; k < n; k += 64) acc = fma(A[k], A[k], acc);
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        acc = tri_wave_sum(acc);
         if (lane == 0) S.red[1] = acc;
     }
     __syncthreads();
@@ -233,8 +262,7 @@ __device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldi
                 double acc = 0.0;
                 if (i < L)
                     for (int k = sub; k < L; k += 4) acc = fma(A22[(int64_t)i * la + k], S.v[k], acc);
-                acc += __shfl_xor(acc, 1, 64);
-                acc += __shfl_xor(acc, 2, 64);
+                acc = tri_quad_sum(acc);
                 if (i < L && sub == 0) {
                     S.w[i] = tau * acc;
                     S.y[i] = tau * acc * S.v[i];
@@ -244,7 +272,7 @@ __device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldi
                     const double* Ai = A22 + (int64_t)i * la;
                     double acc = 0.0;
                     for (int k = lane; k < L; k += 64) acc = fma(Ai[k], S.v[k], acc);
-                    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+                    acc = tri_wave_sum(acc);
                     if (lane == 0) {
                         S.w[i] = tau * acc;
                         S.y[i] = tau * acc * S.v[i];
@@ -255,7 +283,7 @@ __device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldi
             if (wave == 0) {  // K = tau / 2 (p . v)
                 double acc = 0.0;
                 for (int i = lane; i < L; i += 64) acc += S.y[i];
-                for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+                acc = tri_wave_sum(acc);
                 if (lane == 0) S.red[0] = 0.5 * tau * acc;
             }
             __syncthreads();
@@ -286,13 +314,13 @@ __device__ __forceinline__ void tri_reduce_unblk_body(const double* Ain, int ldi
                 }
             }
             if (wave == 0) {
-                for (int off = 32; off > 0; off >>= 1) nx += __shfl_xor(nx, off, 64);
+                nx = tri_wave_sum(nx);
                 if (lane == 0) S.red[1] = nx;
             }
         } else if (wave == 0) {  // no reflection: the next column as it stands
             double acc = 0.0;
             for (int k = 2 + lane; k < L; k += 64) acc = fma(A22[k], A22[k], acc);
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            acc = tri_wave_sum(acc);
             if (lane == 0) S.red[1] = acc;
         }
         __syncthreads();
@@ -425,8 +453,7 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
 #pragma unroll
                 for (int t = 0; t < TRI_NB / 4; ++t)
                     if (t < tmax) sub += vg[4 * t] * wj[4 * t] + wg[4 * t] * vj[4 * t];
-                sub += __shfl_xor(sub, 1, 64);
-                sub += __shfl_xor(sub, 2, 64);
+                sub = tri_quad_sum(sub);
                 double x2 = 0.0;
                 if (act && q == 0) {
                     const double a = pre ? S.d[g] : (double)Ag[j * n + g];
@@ -469,10 +496,7 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
                     const int rem = L - part;  // rows t with 16 t < rem
                     double ds = 0.0;
                     if (cc < jc) ds = tri_vdot_n((L + 15) >> 4, P, vp, rem, part == 0, scal);
-                    ds += __shfl_xor(ds, 8, 64);
-                    ds += __shfl_xor(ds, 4, 64);
-                    ds += __shfl_xor(ds, 2, 64);
-                    ds += __shfl_xor(ds, 1, 64);
+                    ds = tri_row_sum(ds);
                     if (part == 0 && cc < jc) pan[slot] = ds;
                 }
                 const int cb = (L + 63) >> 6, nst = NW / cb, Lp = cb << 6;
@@ -521,8 +545,7 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
                     for (int t = 0; t < TRI_NB / 4; ++t)
                         if (t < tmax) pp -= vg[4 * t] * dW[q + 4 * t] + wg[4 * t] * dV[q + 4 * t];
                 }
-                pp += __shfl_xor(pp, 1, 64);
-                pp += __shfl_xor(pp, 2, 64);
+                pp = tri_quad_sum(pp);
                 const double vi = act ? (quad == 0 ? 1.0 : S.v[quad] * scal) : 0.0;
                 const double pi = tau * pp;
                 double pv = (act && q == 0) ? pi * vi : 0.0;
@@ -720,13 +743,13 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
                                 double dot = 0.0;
                                 for (int i = lane; i < n; i += 64)
                                     dot = fma(U[(int64_t)i * lu + q], zm[(int64_t)i * lu], dot);
-                                for (int off = 32; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 64);
+                                dot = tri_wave_sum(dot);
                                 for (int i = lane; i < n; i += 64)
                                     zm[(int64_t)i * lu] = fma(-dot, U[(int64_t)i * lu + q], zm[(int64_t)i * lu]);
                             }
                         double nrm2 = 0.0;
                         for (int i = lane; i < n; i += 64) nrm2 = fma(zm[(int64_t)i * lu], zm[(int64_t)i * lu], nrm2);
-                        for (int off = 32; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
+                        nrm2 = tri_wave_sum(nrm2);
                         if (nrm2 > 0.25) {
                             const double inv = 1.0 / sqrt(nrm2);
                             for (int i = lane; i < n; i += 64) zm[(int64_t)i * lu] *= inv;
