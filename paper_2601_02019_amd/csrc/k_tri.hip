@@ -779,9 +779,10 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
 
 // U = Q U for the reflectors in W (row j: v_j beyond the super-diagonal,
 // W[j][j] = tau_j), skipped when the Jacobi fallback produced U.  One
-// wavefront per 4-column strip of U, held in LDS; sixteen lanes per column
-// split the rows (the product with v_j ends in four shuffles), so the
-// reflectors follow one another without a barrier.  The reflectors arrive in
+// wavefront per 4-column strip of U, held in LDS; the sixteen lanes of a row
+// of the wavefront take one column and split its rows (the product with v_j
+// ends in a DPP row sum), so the reflectors follow one another without a
+// barrier.  The reflectors arrive in
 // blocks of TRI_RB(n) rows of W through LDS; the next block's loads are issued
 // before the current block is applied, so their latency is hidden.
 constexpr int TRI_SC = 4;
@@ -791,7 +792,7 @@ __host__ __device__ constexpr int tri_back_lds(int n) { return (TRI_SC + tri_rb(
 __device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n,
                                               double* lds) {
     if (Dm[0] != 0.0) return;
-    const int lane = threadIdx.x, c = lane & (TRI_SC - 1), p = lane >> 2;  // p: row phase (16)
+    const int lane = threadIdx.x, c = lane >> 4, p = lane & 15;  // a row of 16 lanes per column
     const int c0 = blockIdx.x * TRI_SC;
     if (c0 >= n) return;
     const bool act = c0 + c < n;
@@ -849,10 +850,7 @@ __device__ __forceinline__ void tri_back_body(const double* W, const double* Dm,
             }
             for (; i < L; i += 16) acc[0] = fma(i == 0 ? 1.0 : v[i], z[i * TRI_SC], acc[0]);
             double y = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-            y += __shfl_xor(y, 4, 64);
-            y += __shfl_xor(y, 8, 64);
-            y += __shfl_xor(y, 16, 64);
-            y += __shfl_xor(y, 32, 64);
+            y = tri_row_sum(y);
             y *= tau;
             for (i = p; i + 112 < L; i += 128) {
 #pragma unroll
