@@ -363,6 +363,7 @@ def window_main(args):
               f"err {errs[-1]:.2e}", file=sys.stderr, flush=True)
     lv = w.info()["levels"]
     stats = [w.window_stats(j) for j in range(lv)]
+    w.close()
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -433,6 +434,7 @@ def sites_main(args):
             _, t = timed(lambda: coord.merge_tree(sk))
             t_mrg += t
         B = coord.query()
+        coord.close()
         for x in sk:
             x.close()
         return B, t_upd, t_mrg
@@ -543,6 +545,7 @@ def main():
         times.append(time.perf_counter() - t)
         print(f"[bench] step {k}: {times[-1]:.3f}s", file=sys.stderr, flush=True)
     prof = sk.profile_read()
+    sk.close()
     ms_per_step = 1e3 * sum(times) / len(times)
     rows_per_s = n / (ms_per_step / 1e3)
 

@@ -109,7 +109,9 @@ SK_EXPORT sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, 
 
 /* Same for sparse rows in CSR form: indptr (n_rows + 1, int64, indptr[0] may
  * be non-zero), column indices (int32, in [0, d)), values (float32).
- * Duplicate indices within a row are summed.  Persistent sketches only. */
+ * Duplicate indices within a row are summed in the order they appear in
+ * the row (FP64 sum, then one rounding to the state dtype); the result does
+ * not depend on thread timing.  Persistent sketches only. */
 SK_EXPORT sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* indices,
                             const float* values, int64_t n_rows, int32_t on_device);
 
@@ -122,7 +124,7 @@ SK_EXPORT sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t
 
 /* SK_WINDOW only: moves time to t_now >= current time without rows and
  * expires what left the window.  SK_EUNSUPPORTED on persistent sketches,
- * SK_ESTATE if t_now is in the past. */
+ * SK_EINVAL (state unchanged) if t_now is in the past. */
 SK_EXPORT sk_status window_advance(sketch_t h, int64_t t_now);
 
 /* dst absorbs each source sketch in order: the non-zero rows of the source's
@@ -262,6 +264,17 @@ SK_EXPORT sk_status server_stats(sk_server_t s, sk_server_stats* out);
  * arrival times are given in this time base. */
 SK_EXPORT double server_now(sk_server_t s);
 SK_EXPORT sk_status server_destroy(sk_server_t s);
+
+/* ---- failure injection (tests of the error paths) ---------------------------
+ * Records one non-converged eigen-solve in the sketch's device status words,
+ * in stream order after the work queued so far, exactly as a failing solver
+ * would; nothing else changes.  The next sketch_sync / sketch_query then
+ * returns SK_EDEVICE and the handle turns sticky.  Persistent sketches only
+ * (SK_EUNSUPPORTED otherwise).  The server form acts on an admitted stream's
+ * sketch (SK_ESTATE if the stream is not admitted).  Lets a test exercise
+ * the failure path without making a kernel fail. */
+SK_EXPORT sk_status sketch_debug_fail_solver(sketch_t h);
+SK_EXPORT sk_status server_debug_fail_solver(sk_server_t s, int64_t id);
 
 /* ---- profiling -------------------------------------------------------------
  * Per-stage GPU time of the pipeline, measured with HIP events recorded on

@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "liboracle.so")
+# SKETCH_ORACLE_LIB selects another build of the same sources (the mutation
+# tests load deliberately broken copies through it)
+_LIBPATH = os.environ.get("SKETCH_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -66,6 +68,12 @@ def _load():
     lib.o_win_levels.argtypes = [ctypes.c_void_p]
     lib.o_win_stats.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p]
     lib.o_win_level_gram.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+    lib.o_win_counters.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p]
+    lib.o_win_entry.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, _i64p, _dp, _dp, _dp]
+    lib.o_win_buffer.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+    lib.o_aero_dump.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int64, ctypes.c_int64, _dp, _dp,
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
     _lib = lib
     return lib
 
@@ -152,6 +160,23 @@ def shrink_rand(X, ell, k, q, seed, stream, b):
     m, d = X.shape
     _check(lib.o_shrink_rand(_p(X), m, d, d, ell, k, q, seed, stream, b), "shrink_rand")
     return X
+
+
+def aero_dump(C, theta, ell, q=1, seed=0, stream=0, level=0, i=1):
+    """The window's dump step on the buffer C (r x d).  Returns a dict with
+    the power-iteration estimate ``pi``, the simul_iter call count ``nsi``,
+    ``xi``, the snapshot ``Z`` (d x xi) and ``W`` (xi x d) and the residual
+    buffer ``C`` (C - C Z Z^T)."""
+    lib = _load()
+    C = _f64(np.atleast_2d(C)).copy()
+    r, d = C.shape
+    Z = np.zeros((d, ell))
+    W = np.zeros((ell, d))
+    xi, nsi, pi = ctypes.c_int(0), ctypes.c_int(0), np.zeros(1)
+    _check(lib.o_aero_dump(d, ell, q, seed, stream, level, float(theta), _p(C), r, i, _p(Z), _p(W),
+                           ctypes.byref(xi), ctypes.byref(nsi), _p(pi)), "aero_dump")
+    x = xi.value
+    return {"pi": float(pi[0]), "nsi": nsi.value, "xi": x, "Z": Z[:, :x].copy(), "W": W[:x].copy(), "C": C}
 
 
 def power_iteration(C, x0, steps):
@@ -253,3 +278,36 @@ class Window:
         G = np.zeros((self.d, self.d))
         _check(_lib.o_win_level_gram(self._h, level, _p(G)), "win_level_gram")
         return G
+
+    def counters(self, level):
+        st = np.zeros(8, dtype=np.int64)
+        _check(_lib.o_win_counters(self._h, level, st.ctypes.data_as(_i64p)), "win_counters")
+        keys = ["dumps", "raw", "dirs", "fill", "queue", "shrinks", "simul_iters", "dropped_t"]
+        return dict(zip(keys, st.tolist()))
+
+    def entries(self, level):
+        """Queue of a level, oldest first: dicts with kind ('dump'/'raw'), s,
+        t and Z, W (dumps) or a (raw rows)."""
+        out = []
+        q = self.counters(level)["queue"]
+        meta = np.zeros(4, dtype=np.int64)
+        for e in range(q):
+            _check(_lib.o_win_entry(self._h, level, e, meta.ctypes.data_as(_i64p), None, None, None),
+                   "win_entry")
+            xi = int(meta[1])
+            Z, W, a = np.zeros((self.d, max(xi, 1))), np.zeros((max(xi, 1), self.d)), np.zeros(self.d)
+            _check(_lib.o_win_entry(self._h, level, e, meta.ctypes.data_as(_i64p), _p(Z), _p(W), _p(a)),
+                   "win_entry")
+            if meta[0] == 0:
+                out.append({"kind": "dump", "xi": xi, "s": int(meta[2]), "t": int(meta[3]),
+                            "Z": Z[:, :xi].copy(), "W": W[:xi].copy()})
+            else:
+                out.append({"kind": "raw", "s": int(meta[2]), "t": int(meta[3]), "a": a})
+        return out
+
+    def buffer(self, level):
+        C = np.zeros((2 * self.ell, self.d))
+        r = _lib.o_win_buffer(self._h, level, _p(C))
+        if r < 0:
+            raise RuntimeError("oracle win_buffer failed")
+        return C[:r].copy()

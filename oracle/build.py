@@ -11,15 +11,15 @@ SOURCES = ["philox.c", "linalg.c", "fd.c", "window.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src_dir: str = HERE, out: str = LIB) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-           "-ffp-contract=off", "-o", LIB]
-    cmd += [os.path.join(HERE, s) for s in SOURCES]
+           "-ffp-contract=off", "-I", HERE, "-o", out]
+    cmd += [os.path.join(src_dir, s) for s in SOURCES]
     cmd += ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

@@ -99,9 +99,30 @@ int o_win_levels(const o_win* w);
 /* Diagnostics of one level: counts of dumps, raw rows, dumped directions,
  * residual rows and queue length. */
 int o_win_stats(const o_win* w, int level, int64_t* stats /* [6] */);
-/* Gram of the level's restored matrix B_T (d x d), Algorithm "Query" lines
- * 1-4, with the in-window raw rows added. */
+/* Gram of the level's restored matrix B_T (d x d): the restore of Algorithm
+ * "AeroSketch: Query" over the in-window snapshots, with the in-window raw
+ * rows added. */
 int o_win_level_gram(const o_win* w, int level, double* G);
+/* Counters of one level: the six of o_win_stats, then [6] simul_iter calls
+ * and [7] the largest in-window timestamp dropped by the length cap. */
+int o_win_counters(const o_win* w, int level, int64_t* st /* [8] */);
+/* Queue entry e (0 = oldest) of a level: meta = {kind (0 snapshot, 1 raw
+ * row), xi, s, t}; Z (d x xi), W (xi x d) of a snapshot or a (d) of a raw
+ * row are copied where the pointer is non-NULL. */
+int o_win_entry(const o_win* w, int level, int64_t e, int64_t* meta /* [4] */, double* Z, double* W,
+                double* a);
+/* The level's residual buffer rows (r x d) into C; returns r. */
+int o_win_buffer(const o_win* w, int level, double* C);
+/* The dump step of Algorithm "AeroSketch: Update" on a level buffer C (r x d,
+ * row-major, ld d), as the window runs it for the row with timestamp i at
+ * level `level` with threshold theta: power iteration on C^T C (ceil(log2 d)
+ * + 1 steps); if its estimate (*pi) reaches theta / 2, simul_iter with
+ * k = 2, 4, ... up to min(ell, d, r) until the k-th estimate falls below
+ * theta (*nsi calls); the *xi directions whose estimate reaches theta are the
+ * snapshot: Z (d x ell, first *xi columns), W = Z^T C^T C (ell x d, first *xi
+ * rows), and C becomes C - C Z Z^T. */
+int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
+                int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi);
 
 #ifdef __cplusplus
 }

@@ -136,9 +136,15 @@ static void expire(o_win* w, wlevel* l, int64_t i) {
     }
 }
 
+/* Parameters of one level's dump step. */
+typedef struct {
+    int d, ell, q;
+    uint64_t seed, stream;
+} dump_par;
+
 /* simul_iter on A = C'^T (reading: Omega on the d side), returns Z' (d x k)
  * and the estimates w (descending). */
-static int simul_iter_window(const o_win* w, const double* C, int64_t r, int k, uint64_t ts,
+static int simul_iter_window(const dump_par* w, const double* C, int64_t r, int k, uint64_t ts,
                              uint64_t tag, double* Zp, double* est) {
     const int d = w->d;
     double* Om = walloc((int64_t)d * k);
@@ -199,6 +205,86 @@ out:
     return rc;
 }
 
+/* The dump step of Algorithm "AeroSketch: Update" on the level buffer C
+ * (r x d, after the FD reduce) for the row with timestamp i at level j:
+ * power iteration on C^T C with ceil(log2 d) + 1 steps (start vector from
+ * Philox counter (coordinate, 0, i, 0x100 + j)); if its estimate reaches
+ * theta / 2, simul_iter with k = 2, 4, ... (capped at min(ell, d, r)) until the
+ * k-th estimate falls below theta or k reaches the cap; the xi leading
+ * directions whose estimate reaches theta form the snapshot Z (d x xi, the
+ * first xi of the ell columns of Z) and W = Z^T C^T C (the first xi rows of
+ * W), and C becomes C - C Z Z^T.  *pi: the power-iteration estimate; *nsi:
+ * simul_iter calls. */
+static int aero_dump(const dump_par* w, int j, double theta, double* C, int64_t r, int64_t i, double* Zout,
+                     double* Wout, int* xi_out, int* nsi, double* pi) {
+    const int d = w->d, ell = w->ell;
+    *xi_out = 0;
+    *nsi = 0;
+    int steps = (int)ceil(log2((double)d)) + 1;
+    double* x0 = walloc(d);
+    o_omega(w->seed, w->stream, (uint64_t)i, 0x100u + (uint64_t)j, d, 1, x0);
+    double s1 = o_power_iteration(C, (int)r, d, d, x0, steps, NULL);
+    free(x0);
+    *pi = s1;
+    if (!(s1 >= theta / 2.0)) return 0;
+    int kmax = (ell < d) ? ell : d;
+    if (kmax > (int)r) kmax = (int)r;
+    if (kmax < 1) return 0;
+    int nsteps = (int)ceil(log2((double)kmax));
+    if (nsteps < 1) nsteps = 1;
+    for (int s = 1; s <= nsteps; ++s) {
+        int k = 1 << s;
+        if (k > kmax) k = kmax;
+        double* Zp = walloc((int64_t)d * k);
+        double* est = walloc(k);
+        int rc = simul_iter_window(w, C, r, k, (uint64_t)i, 0x200u + 32u * (uint64_t)j + (uint64_t)s, Zp, est);
+        *nsi += 1;
+        if (rc) { free(Zp); free(est); return rc; }
+        if (est[k - 1] < theta || k == kmax) {
+            int xi = 0;
+            while (xi < k && est[xi] >= theta) ++xi;
+            if (xi > 0) {
+                for (int t = 0; t < d; ++t)
+                    for (int c = 0; c < xi; ++c) Zout[(int64_t)t * ell + c] = Zp[(int64_t)t * k + c];
+                /* CZ = C' Z (r x xi); W = (C'Z)^T C' */
+                double* CZ = walloc(r * xi);
+                for (int64_t rr = 0; rr < r; ++rr)
+                    for (int c = 0; c < xi; ++c) {
+                        double acc = 0;
+                        for (int t = 0; t < d; ++t) acc += C[rr * d + t] * Zout[(int64_t)t * ell + c];
+                        CZ[rr * xi + c] = acc;
+                    }
+                for (int c = 0; c < xi; ++c)
+                    for (int t = 0; t < d; ++t) {
+                        double acc = 0;
+                        for (int64_t rr = 0; rr < r; ++rr) acc += CZ[rr * xi + c] * C[rr * d + t];
+                        Wout[(int64_t)c * d + t] = acc;
+                    }
+                /* C <- C' - C' Z Z^T */
+                for (int64_t rr = 0; rr < r; ++rr)
+                    for (int t = 0; t < d; ++t) {
+                        double acc = 0;
+                        for (int c = 0; c < xi; ++c) acc += CZ[rr * xi + c] * Zout[(int64_t)t * ell + c];
+                        C[rr * d + t] -= acc;
+                    }
+                free(CZ);
+            }
+            *xi_out = xi;
+            free(Zp); free(est);
+            break;
+        }
+        free(Zp); free(est);
+    }
+    return 0;
+}
+
+int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
+                int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi) {
+    if (d < 1 || ell < 2 || q < 0 || r < 0 || !C || !Z || !W || !xi || !nsi || !pi) return -1;
+    dump_par par = {d, ell, q, seed, stream};
+    return aero_dump(&par, level, theta, C, r, i, Z, W, xi, nsi, pi);
+}
+
 /* Algorithm "AeroSketch: Update" for one level. */
 static int level_update(o_win* w, int j, const double* a, int64_t i) {
     wlevel* l = &w->lv[j];
@@ -219,71 +305,30 @@ static int level_update(o_win* w, int j, const double* a, int64_t i) {
         l->r = ell - 1;
         l->shrinks += 1;
     }
-    /* power iteration on C'^T C' with ceil(log2 d) + 1 steps */
-    int steps = (int)ceil(log2((double)d)) + 1;
-    double* x0 = walloc(d);
-    o_omega(w->seed, w->stream, (uint64_t)i, 0x100u + (uint64_t)j, d, 1, x0);
-    double s1 = o_power_iteration(l->C, (int)l->r, d, d, x0, steps, NULL);
-    free(x0);
-    if (!(s1 >= l->theta / 2.0)) return 0;
-    int kmax = (ell < d) ? ell : d;
-    if (kmax > (int)l->r) kmax = (int)l->r;
-    if (kmax < 1) return 0;
-    int nsteps = (int)ceil(log2((double)kmax));
-    if (nsteps < 1) nsteps = 1;
-    for (int s = 1; s <= nsteps; ++s) {
-        int k = 1 << s;
-        if (k > kmax) k = kmax;
-        double* Zp = walloc((int64_t)d * k);
-        double* est = walloc(k);
-        int rc = simul_iter_window(w, l->C, l->r, k, (uint64_t)i, 0x200u + 32u * (uint64_t)j + (uint64_t)s, Zp, est);
-        l->nsi += 1;
-        if (rc) { free(Zp); free(est); return rc; }
-        if (est[k - 1] < l->theta || k == kmax) {
-            int xi = 0;
-            while (xi < k && est[xi] >= l->theta) ++xi;
-            if (xi > 0) {
-                wentry* e = qpush(l);
-                e->kind = 0;
-                e->xi = xi;
-                e->Z = walloc((int64_t)d * xi);
-                e->W = walloc((int64_t)xi * d);
-                for (int t = 0; t < d; ++t)
-                    for (int c = 0; c < xi; ++c) e->Z[(int64_t)t * xi + c] = Zp[(int64_t)t * k + c];
-                /* CZ = C' Z (r x xi); W = (C'Z)^T C' */
-                double* CZ = walloc(l->r * xi);
-                for (int64_t rr = 0; rr < l->r; ++rr)
-                    for (int c = 0; c < xi; ++c) {
-                        double acc = 0;
-                        for (int t = 0; t < d; ++t) acc += l->C[rr * d + t] * e->Z[(int64_t)t * xi + c];
-                        CZ[rr * xi + c] = acc;
-                    }
-                for (int c = 0; c < xi; ++c)
-                    for (int t = 0; t < d; ++t) {
-                        double acc = 0;
-                        for (int64_t rr = 0; rr < l->r; ++rr) acc += CZ[rr * xi + c] * l->C[rr * d + t];
-                        e->W[(int64_t)c * d + t] = acc;
-                    }
-                e->s = l->last_t + 1;
-                e->t = i;
-                l->last_t = i;
-                /* C <- C' - C' Z Z^T */
-                for (int64_t rr = 0; rr < l->r; ++rr)
-                    for (int t = 0; t < d; ++t) {
-                        double acc = 0;
-                        for (int c = 0; c < xi; ++c) acc += CZ[rr * xi + c] * e->Z[(int64_t)t * xi + c];
-                        l->C[rr * d + t] -= acc;
-                    }
-                free(CZ);
-                l->ndumps += 1;
-                l->ndirs += xi;
-            }
-            free(Zp); free(est);
-            break;
-        }
-        free(Zp); free(est);
+    double* Z = walloc((int64_t)d * ell);
+    double* W = walloc((int64_t)ell * d);
+    int xi = 0, nsi = 0;
+    double pi = 0.0;
+    dump_par par = {d, ell, w->q, w->seed, w->stream};
+    int rc = aero_dump(&par, j, l->theta, l->C, l->r, i, Z, W, &xi, &nsi, &pi);
+    l->nsi += nsi;
+    if (rc == 0 && xi > 0) {
+        wentry* e = qpush(l);
+        e->kind = 0;
+        e->xi = xi;
+        e->Z = walloc((int64_t)d * xi);
+        e->W = walloc((int64_t)xi * d);
+        for (int t = 0; t < d; ++t)
+            for (int c = 0; c < xi; ++c) e->Z[(int64_t)t * xi + c] = Z[(int64_t)t * ell + c];
+        memcpy(e->W, W, sizeof(double) * (size_t)xi * d);
+        e->s = l->last_t + 1;
+        e->t = i;
+        l->last_t = i;
+        l->ndumps += 1;
+        l->ndirs += xi;
     }
-    return 0;
+    free(Z); free(W);
+    return rc;
 }
 
 int o_win_update(o_win* w, const double* rows, int64_t n, int64_t ld) {
@@ -426,4 +471,34 @@ int o_win_query(const o_win* w, double* out, int* level_out) {
     memcpy(out, X, sizeof(double) * (size_t)ell * d);
     free(G); free(V); free(lam); free(X);
     return rc;
+}
+
+int o_win_counters(const o_win* w, int level, int64_t* st) {
+    if (!w || level < 0 || level >= w->L) return -1;
+    const wlevel* l = &w->lv[level];
+    st[0] = l->ndumps; st[1] = l->nraw; st[2] = l->ndirs; st[3] = l->r; st[4] = l->len; st[5] = l->shrinks;
+    st[6] = l->nsi; st[7] = l->dropped_t;
+    return 0;
+}
+
+int o_win_entry(const o_win* w, int level, int64_t e, int64_t* meta, double* Z, double* W, double* a) {
+    if (!w || level < 0 || level >= w->L) return -1;
+    const wlevel* l = &w->lv[level];
+    if (e < 0 || e >= l->len) return -1;
+    const wentry* en = &l->q[(l->head + e) % l->capq];
+    meta[0] = en->kind; meta[1] = en->xi; meta[2] = en->s; meta[3] = en->t;
+    if (en->kind == 0) {
+        if (Z) memcpy(Z, en->Z, sizeof(double) * (size_t)w->d * en->xi);
+        if (W) memcpy(W, en->W, sizeof(double) * (size_t)en->xi * w->d);
+    } else if (a) {
+        memcpy(a, en->a, sizeof(double) * (size_t)w->d);
+    }
+    return 0;
+}
+
+int o_win_buffer(const o_win* w, int level, double* C) {
+    if (!w || level < 0 || level >= w->L) return -1;
+    const wlevel* l = &w->lv[level];
+    memcpy(C, l->C, sizeof(double) * (size_t)l->r * w->d);
+    return (int)l->r;
 }

@@ -5,7 +5,10 @@ have the C names and only marshal arguments; the ``Sketch`` class wraps a
 handle for convenience.  Device rows are torch tensors on the sketch's GPU;
 host rows may be numpy arrays or CPU tensors.
 """
+import atexit
 import ctypes
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -20,6 +23,29 @@ from ._lib import (  # noqa: F401
 _TORCH_DT = {torch.float64: SK_F64, torch.float32: SK_F32, torch.bfloat16: SK_BF16}
 _NP_DT = {np.dtype(np.float64): SK_F64, np.dtype(np.float32): SK_F32}
 _NAME_DT = {"f64": SK_F64, "f32": SK_F32, "bf16": SK_BF16}
+
+
+# Live owning wrappers.  They are closed from an atexit hook, which runs
+# before the interpreter tears down modules and before the HIP runtime's own
+# exit handlers: a handle destroyed later (from __del__ during finalisation)
+# would synchronise streams and free memory while the runtime, and any
+# profiler attached to it, are already shutting down.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    objs = list(_LIVE)
+    # servers first: they own their streams' sketches
+    for o in sorted(objs, key=lambda o: 0 if isinstance(o, Server) else 1):
+        try:
+            o.close()
+        except Exception:
+            pass
+
+
+def _finalizing():
+    return sys.is_finalizing()
 
 
 def _dt(x):
@@ -130,6 +156,14 @@ def sketch_sync(h):
 
 def sketch_destroy(h):
     _lib.check(_lib.load().sketch_destroy(h), "sketch_destroy")
+
+
+def sketch_debug_fail_solver(h):
+    _lib.check(_lib.load().sketch_debug_fail_solver(h), "sketch_debug_fail_solver")
+
+
+def server_debug_fail_solver(s, sid):
+    _lib.check(_lib.load().server_debug_fail_solver(s, sid), "server_debug_fail_solver")
 
 
 def sketch_last_error():
@@ -317,6 +351,7 @@ class Server:
             cfg.clock = self._clock
         self.device = device
         self.handle = server_create(cfg)
+        _LIVE.add(self)
         self._rows = {}
         self._shape = {}
         self._pollbuf = (sk_completion * 1024)()
@@ -357,6 +392,9 @@ class Server:
     def close_stream(self, sid):
         server_close(self.handle, sid)
 
+    def debug_fail_solver(self, sid):
+        server_debug_fail_solver(self.handle, sid)
+
     def stats(self):
         return server_stats(self.handle)
 
@@ -370,10 +408,18 @@ class Server:
             self._rows.clear()
 
     def __del__(self):
+        if _finalizing():  # the atexit hook has closed every live handle
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Sketch:
@@ -394,6 +440,7 @@ class Sketch:
         self.d, self.ell = d, ell
         self.device = device
         self.handle = sketch_create(cfg)
+        _LIVE.add(self)
         self._keep = []
 
     def update(self, rows):
@@ -449,7 +496,15 @@ class Sketch:
             self._keep.clear()
 
     def __del__(self):
+        if _finalizing():  # the atexit hook has closed every live handle
+            return
         try:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

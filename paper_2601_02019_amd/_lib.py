@@ -80,6 +80,7 @@ EXPORTS = [
     "sketch_update_batch", "sketch_update_csr_batch", "sketch_profile_enable", "sketch_profile_read", "window_stats",
     "server_config_init", "server_create", "server_open", "server_submit", "server_tick", "server_poll",
     "server_drain", "server_query", "server_close", "server_stats", "server_now", "server_destroy",
+    "sketch_debug_fail_solver", "server_debug_fail_solver",
 ]
 
 _lib = None
@@ -130,6 +131,8 @@ def load():
     lib.server_now.argtypes = [vp]
     lib.server_now.restype = ctypes.c_double
     lib.server_destroy.argtypes = [vp]
+    lib.sketch_debug_fail_solver.argtypes = [vp]
+    lib.server_debug_fail_solver.argtypes = [vp, i64]
     for name in EXPORTS:
         if name not in ("sketch_last_error", "sketch_memory_in_use", "server_now"):
             getattr(lib, name).restype = ctypes.c_int

@@ -94,26 +94,48 @@ __global__ __launch_bounds__(256) void k_ingest(const Task* tasks) {
     }
 }
 
-// One workgroup per sparse row: the row is assembled in LDS (duplicates
-// summed) and written out densely.
+// One workgroup per sparse row, written out densely.  Duplicate column
+// indices within a row are summed in the order they appear in the row: the
+// first position of every column is found with an integer atomicMin in LDS
+// (exact, order-free), duplicates set bit 31 of that entry, and the thread of
+// a column with duplicates adds them up sequentially from its first
+// position.  No floating-point atomics: the result does not depend on thread
+// timing.  Columns without duplicates cost one store.
 template <typename Tst>
 __global__ __launch_bounds__(256) void k_ingest_csr(const Task* tasks) {
-    extern __shared__ double rowbuf[];
+    extern __shared__ int first[];
     const Task& t = tasks[blockIdx.z];
     const int row = blockIdx.y;
     if (t.kind != T_INGEST || row >= t.nrows) return;
     const SkDev* s = t.s;
     const int d = s->d;
-    for (int c = threadIdx.x; c < d; c += 256) rowbuf[c] = 0.0;
+    constexpr int NONE = 0x7fffffff;
+    for (int c = threadIdx.x; c < d; c += 256) first[c] = NONE;
     __syncthreads();
     const int64_t b = t.indptr[row], e = t.indptr[row + 1];
     for (int64_t p = b + threadIdx.x; p < e; p += 256) {
         const int j = t.indices[p];
-        if (j >= 0 && j < d) atomicAdd(&rowbuf[j], (double)t.values[p]);
+        if (j >= 0 && j < d) atomicMin(&first[j], (int)(p - b));
+    }
+    __syncthreads();
+    for (int64_t p = b + threadIdx.x; p < e; p += 256) {
+        const int j = t.indices[p];
+        if (j >= 0 && j < d && (first[j] & NONE) != (int)(p - b)) atomicOr(&first[j], (int)0x80000000);
     }
     __syncthreads();
     Tst* dst = (Tst*)s->buf[t.par] + (int64_t)(t.row0 + row) * s->ld;
-    for (int c = threadIdx.x; c < d; c += 256) dst[c] = from_f64<Tst>(rowbuf[c]);
+    for (int c = threadIdx.x; c < d; c += 256) {
+        const int f = first[c];
+        double v = 0.0;
+        if (f != NONE) {
+            const int64_t p0 = b + (f & NONE);
+            v = (double)t.values[p0];
+            if (f < 0)  // duplicates: the later positions in row order
+                for (int64_t p = p0 + 1; p < e; ++p)
+                    if (t.indices[p] == c) v += (double)t.values[p];
+        }
+        dst[c] = from_f64<Tst>(v);
+    }
 }
 
 // ---------------------------------------------------------------- Omega^T
@@ -360,7 +382,7 @@ hipError_t launch_ingest(const Task* tasks, int count, int max_rows, int max_d, 
 hipError_t launch_ingest_csr(const Task* tasks, int count, int max_rows, int max_d, int st_dtype,
                              hipStream_t st) {
     const dim3 grid = g3(1, max_rows, count);
-    const size_t lds = sizeof(double) * (size_t)max_d;
+    const size_t lds = sizeof(int) * (size_t)max_d;
     if (st_dtype == DT_F64) hipLaunchKernelGGL((k_ingest_csr<double>), grid, dim3(256), lds, st, tasks);
     else hipLaunchKernelGGL((k_ingest_csr<float>), grid, dim3(256), lds, st, tasks);
     return hipGetLastError();

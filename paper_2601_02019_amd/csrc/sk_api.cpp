@@ -453,6 +453,9 @@ sk_status sketch_reset(sketch_t h, uint64_t seed, uint64_t stream_id) {
     // buffer rows keep a query of the empty sketch exact
     HIP_TRY(h, hipMemsetAsync(h->host.buf[0], 0, (size_t)dtype_size(h->st) * (size_t)h->n2 * (size_t)h->ld,
                               h->stream));
+    // the solver status words (non-convergence counts) belong to the previous
+    // stream: a reused sketch starts with a clean record
+    HIP_TRY(h, hipMemsetAsync(h->host.info, 0, 64, h->stream));
     // h->host is not written again before the sketch is next idle, so the
     // asynchronous copy may read it late
     HIP_TRY(h, hipMemcpyAsync(h->dev, &h->host, sizeof(SkDev), hipMemcpyHostToDevice, h->stream));
@@ -682,6 +685,19 @@ sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src) {
         if ((rc = execute(dst, owners, tasks, DT_F64, false))) return rc;
         HIP_TRY(dst, hipStreamSynchronize(dst->stream));
     }
+    return SK_OK;
+}
+
+sk_status sketch_debug_fail_solver(sketch_t h) {
+    sk_status rc = check_handle(h, "sketch_debug_fail_solver");
+    if (rc) return rc;
+    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_debug_fail_solver: window sketch");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    // one failed solve, stream-ordered after the work queued so far (a
+    // host-to-device copy: the library's kernels are not involved)
+    static const int32_t one = 1;
+    HIP_TRY(h, hipMemcpyAsync(h->host.info, &one, sizeof(one), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return SK_OK;
 }
 

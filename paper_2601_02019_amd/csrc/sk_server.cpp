@@ -145,8 +145,13 @@ void release_closed(sk_server_t s) {
         SStream& st = s->streams[i];
         if (st.state != ST_ADMITTED || !st.closing || !st.q.empty() || st.last_seq > s->completed_seq)
             continue;
-        s->idle.emplace(shape_of(st.cfg), st.h);
-        s->idle_bytes += st.bytes;
+        if (st.h->sticky) {  // a failed sketch is not handed to another stream
+            sketch_destroy_idle(st.h);
+            s->bytes -= st.bytes;
+        } else {
+            s->idle.emplace(shape_of(st.cfg), st.h);
+            s->idle_bytes += st.bytes;
+        }
         st.h = nullptr;
         st.state = ST_CLOSED;
         s->n_admitted -= 1;
@@ -425,6 +430,15 @@ sk_status server_query(sk_server_t s, int64_t id, void* B_out, int32_t dtype, in
     SStream& st = s->streams[(size_t)id];
     if (st.state != ST_ADMITTED) return fail(SK_ESTATE, "server_query: stream is not admitted");
     return sketch_query(st.h, B_out, dtype, on_device);
+}
+
+sk_status server_debug_fail_solver(sk_server_t s, int64_t id) {
+    sk_status rc = check_server(s, "server_debug_fail_solver");
+    if (rc) return rc;
+    if (id < 0 || id >= (int64_t)s->streams.size()) return fail(SK_EINVAL, "server_debug_fail_solver: bad stream id");
+    SStream& st = s->streams[(size_t)id];
+    if (st.state != ST_ADMITTED) return fail(SK_ESTATE, "server_debug_fail_solver: stream is not admitted");
+    return sketch_debug_fail_solver(st.h);
 }
 
 sk_status server_close(sk_server_t s, int64_t id) {

@@ -502,7 +502,7 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
 
 sk_status window_advance_impl(sketch_t h, int64_t t_now) {
     WindowState* w = h->win;
-    if (t_now < w->T) return fail(SK_ESTATE, "window_advance: time moves backwards");
+    if (t_now < w->T) return fail(SK_EINVAL, "window_advance: time moves backwards");
     w->T = t_now;
     for (WinLevel& l : w->lv)
         while (!l.q.empty() && l.q.front().t <= t_now - w->N) l.q.pop_front();

@@ -223,3 +223,59 @@ def test_serving_argument_errors():
         sk.server_submit(srv.handle, 99, torch.ones(2, 64, device="cuda"), 0.0)
     assert e.value.code == sk.SK_EINVAL
     srv.close()
+
+
+def test_reused_sketch_does_not_inherit_a_failed_solve():
+    """A released sketch that recorded a failed eigen-solve (injected from the
+    host, no kernel fails) is reset before reuse, so the next stream of the
+    same shape queries cleanly; a sketch whose failure was reported (sticky)
+    is freed instead of reused."""
+    sk = _lib()
+    d, ell = 128, 16
+    A = torch.from_numpy(synth.lowrank_rows(200, d, np.linspace(1.0, 0.1, 20), 0.1, seed=5)).to("cuda", torch.float32)
+    srv = sk.Server(max_inflight=1)
+    # 1. failure recorded but never observed: the stream is closed, its sketch idles
+    a = srv.open(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=0)
+    srv.submit(a, A)
+    srv.drain()
+    srv.debug_fail_solver(a)
+    srv.close_stream(a)
+    srv.drain()
+    srv.tick()
+    b = srv.open(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=0)
+    srv.submit(b, A)
+    srv.drain()
+    assert srv.stats()["admitted"] == 1
+    Bb = srv.query(b)  # no SK_EDEVICE from the previous stream's record
+    alone = sk.Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=0)
+    alone.update(A)
+    assert torch.equal(alone.query(), Bb)
+    alone.close()
+    # 2. failure observed: the handle turns sticky and is not reused
+    srv.debug_fail_solver(b)
+    with pytest.raises(sk.SketchError) as e:
+        srv.query(b)
+    assert e.value.code == sk.SK_EDEVICE
+    srv.close_stream(b)
+    srv.drain()
+    srv.tick()
+    c = srv.open(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", seed=1, stream_id=0)
+    srv.submit(c, A)
+    srv.drain()
+    assert torch.equal(srv.query(c), Bb)
+    srv.close()
+
+
+def test_debug_fail_solver_makes_the_sketch_sticky():
+    sk = _lib()
+    s = sk.Sketch(64, 8, shrink="exact")
+    s.update(torch.randn(40, 64, dtype=torch.float64, device="cuda"))
+    s.query()
+    sk.sketch_debug_fail_solver(s.handle)
+    with pytest.raises(sk.SketchError) as e:
+        s.sync()
+    assert e.value.code == sk.SK_EDEVICE
+    with pytest.raises(sk.SketchError) as e:
+        s.query()
+    assert e.value.code == sk.SK_EDEVICE
+    s.close()

@@ -107,5 +107,9 @@ def test_window_advance_backwards_is_rejected():
     from paper_2601_02019_amd import SketchError
     g = make(8, 4, 10, 2.0, "exact")
     g.update(torch.ones(5, 8, dtype=torch.float64, device="cuda") * 0.1)
-    with pytest.raises(SketchError):
+    from paper_2601_02019_amd import SK_EINVAL
+    with pytest.raises(SketchError) as e:
         g.advance(3)
+    assert e.value.code == SK_EINVAL
+    assert g.info()["rows_seen"] == 5  # state unchanged
+    g.close()

@@ -1,0 +1,77 @@
+"""Mutation check of the oracle's pins: each case plants one plausible mistake
+in a copy of the oracle sources (on the CPU, in a temporary directory), builds
+that copy and runs the pin suites against it; at least one pin must fail.
+
+The mistakes are the ones a reader of the algorithms could plausibly make:
+a threshold compared against theta instead of theta / 2, strict instead of
+inclusive comparisons, an off-by-one count of dumped directions, a residual
+that is not downdated, a wrong Philox key for a level's FD reduce, a wrong
+level threshold, and in the persistent oracle a wrong shrink threshold index
+or a missing power step.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+# (file, original text, mutated text, pin files expected to catch it)
+WINDOW_PINS = ["tests/test_oracle_window_pins.py", "tests/test_oracle_window.py"]
+FD_PINS = ["tests/test_oracle_pins.py"]
+MUTANTS = {
+    "pi_threshold_theta": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
+                           "if (!(s1 >= theta)) return 0;", WINDOW_PINS),
+    "pi_threshold_strict": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
+                            "if (!(s1 > theta / 2.0)) return 0;", WINDOW_PINS),
+    "xi_strict": ("window.c", "while (xi < k && est[xi] >= theta) ++xi;",
+                  "while (xi < k && est[xi] > theta) ++xi;", WINDOW_PINS),
+    "xi_plus_one": ("window.c", "while (xi < k && est[xi] >= theta) ++xi;",
+                    "while (xi < k && est[xi] >= theta) ++xi;\n            if (xi > 0 && xi < k) ++xi;",
+                    WINDOW_PINS),
+    "xi_minus_one": ("window.c", "while (xi < k && est[xi] >= theta) ++xi;",
+                     "while (xi < k && est[xi] >= theta) ++xi;\n            if (xi > 1) --xi;", WINDOW_PINS),
+    "no_residual_downdate": ("window.c", "C[rr * d + t] -= acc;", "C[rr * d + t] -= 0.0 * acc;",
+                             WINDOW_PINS),
+    "raw_strict": ("window.c", "if (nrm >= l->theta) {", "if (nrm > l->theta) {", WINDOW_PINS),
+    "level_key": ("window.c", "w->stream * 64u + (uint64_t)j + 1u", "w->stream * 64u + (uint64_t)j",
+                  WINDOW_PINS),
+    "level_theta": ("window.c", "l->theta = ldexp(1.0, j) * eps * (double)N;",
+                    "l->theta = ldexp(1.0, j + 1) * eps * (double)N;", WINDOW_PINS),
+    "exact_delta_index": ("fd.c", "double delta = (m >= ell) ? sigma[ell - 1] * sigma[ell - 1] : 0.0;",
+                          "double delta = (m > ell) ? sigma[ell] * sigma[ell] : 0.0;", FD_PINS),
+    "rand_delta_index": ("fd.c", "double delta = (k >= ell) ? fmax(w[ell - 1], 0.0) : 0.0;",
+                         "double delta = (k > ell) ? fmax(w[ell], 0.0) : fmax(w[k - 1], 0.0);", FD_PINS),
+    "rand_power_step_dropped": ("fd.c", "for (int it = 0; it < q; ++it) {", "for (int it = 1; it < q; ++it) {",
+                                FD_PINS),
+    "rand_omega_shrink_counter": ("fd.c", "o_omega(seed, stream, b, 0, d, k, Om);",
+                                  "o_omega(seed, stream, 0, 0, d, k, Om);", FD_PINS),
+    "fill_after_shrink": ("fd.c", "s->r = s->ell - 1;", "s->r = s->ell;", FD_PINS),
+    "power_iteration_step": ("fd.c", "for (int it = 0; it < steps; ++it) {", "for (int it = 1; it < steps; ++it) {",
+                             FD_PINS + WINDOW_PINS),
+}
+
+
+def _build_mutant(tmp, name):
+    fname, old, new, pins = MUTANTS[name]
+    src = os.path.join(tmp, "src")
+    shutil.copytree(ORACLE, src, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    path = os.path.join(src, fname)
+    text = open(path).read()
+    assert text.count(old) >= 1, f"{name}: pattern not found in {fname}"
+    open(path, "w").write(text.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle import build as ob
+    return ob.build(src_dir=src, out=os.path.join(tmp, "liboracle_mutant.so")), pins
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    lib, pins = _build_mutant(str(tmp_path), name)
+    env = dict(os.environ, SKETCH_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
+                       + pins, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

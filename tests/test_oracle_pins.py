@@ -117,6 +117,22 @@ def test_power_iteration_converges_to_top_eigenvalue():
     assert abs(np.linalg.norm(v) - 1) < 1e-12
 
 
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_power_iteration_after_a_given_number_of_steps_is_the_spectral_closed_form(steps):
+    # s steps of x <- C^T C x / |C^T C x| from x0 give x_s ~ V diag(lambda^s) V^T x0,
+    # and the returned estimate is the Rayleigh quotient x_s^T C^T C x_s
+    rng = np.random.default_rng(steps)
+    C = rng.standard_normal((6, 9))
+    x0 = rng.standard_normal(9)
+    lam, V = np.linalg.eigh(C.T @ C)
+    xs = V @ (lam ** steps * (V.T @ x0))
+    xs /= np.linalg.norm(xs)
+    expect = xs @ (C.T @ C) @ xs
+    s, v = oracle.power_iteration(C, x0, steps)
+    assert abs(s - expect) < 1e-12 * lam[-1]
+    assert abs(abs(v @ xs) - 1.0) < 1e-12
+
+
 # ------------------------------------------------------------- exact FD -----
 @pytest.mark.parametrize("d,ell,n", [(40, 6, 100), (16, 4, 57), (12, 8, 80), (64, 16, 300),
                                      (8, 8, 40), (30, 3, 31)])
