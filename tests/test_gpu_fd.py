@@ -275,7 +275,7 @@ def test_batched_cooperative_solvers_bitwise_and_parity():
         a.update(rows[i])
         alone.append(a.query())
         mixed.append(make(d, ell, shrink=mode, seed=5, stream_id=sid))
-    note("batched cooperative solvers: 3 randomized cores k >= 136, one exact 2 ell = 140")
+    note("batched cooperative CholeskyQR: 3 randomized cores k >= 136, one exact 2 ell = 140 (tridiagonal)")
     sketch_update_batch(mixed, rows)
     for i in range(len(shapes)):
         assert torch.equal(mixed[i].query(), alone[i]), i
@@ -379,7 +379,8 @@ def test_error_paths_leave_state_unchanged():
 
 
 # ----------------------------------------------- large single problems
-# eigen-problems of order >= 96 run on the cooperative multi-workgroup solvers
+# eigen-problems of order 129-256 run on the panel-blocked tridiagonal solver,
+# CholeskyQR with k >= 129 on the cooperative multi-workgroup kernel
 @pytest.mark.parametrize("d,ell,n", [(300, 64, 1500), (160, 100, 900)])
 def test_exact_fp64_large_eigenproblem(d, ell, n):
     note(f"exact fp64 coop d={d} ell={ell} n={n}")
@@ -413,3 +414,132 @@ def test_bf16_projection_tracks_fp32_projection():
     sb.update(A)
     ga, gb = gram(sa.query()), gram(sb.query())
     assert rel_fro(gb, ga) < 2e-2
+
+
+# -------------------------------------- cooperative Jacobi (order >= 257)
+@pytest.mark.parametrize("d,ell,extra", [(300, 129, 129), (300, 200, 150), (520, 256, 200)])
+def test_exact_fp64_cooperative_jacobi_shrinks_and_query(d, ell, extra):
+    # 2 ell >= 258: every shrink's eigen-solve runs on the multi-workgroup
+    # block Jacobi solver; the query then shrinks r = ell - 1 + extra >= 257
+    # buffered rows (r = 257, 349, 455: orders that are not multiples of 32)
+    n = 2 * ell + (ell + 1) + extra
+    note(f"exact fp64 cooperative Jacobi d={d} ell={ell} n={n} query r={ell - 1 + extra}")
+    A = synth.lowrank_rows(n, d, 5 * np.arange(1, 301) ** -0.7, 0.05, seed=ell)
+    o = run_oracle(A, d, ell)
+    s = make(d, ell)
+    s.update(torch.from_numpy(A).cuda())
+    assert s.info()["shrinks"] == o.shrinks == 2
+    assert s.info()["fill"] == o.fill == ell - 1 + extra
+    assert rel_fro(gram(s.query()), gram(o.query())) <= 1e-9
+    s.close()
+
+
+def test_exact_fp64_cooperative_jacobi_batch_equals_alone():
+    # two order-258 / order-400 exact cores share one multi-task cooperative
+    # Jacobi launch; each result is bitwise its result alone
+    from paper_2601_02019_amd import sketch_update_batch
+    shapes = [(300, 129), (300, 200), (280, 129)]
+    rows = [torch.from_numpy(synth.lowrank_rows(2 * ell + ell + 1 + 60, d, 5 * np.arange(1, d + 1) ** -0.7,
+                                                 0.05, seed=90 + i)).cuda()
+            for i, (d, ell) in enumerate(shapes)]
+    alone, mixed = [], []
+    for i, (d, ell) in enumerate(shapes):
+        a = make(d, ell)
+        a.update(rows[i])
+        alone.append(a.query())
+        a.close()
+        mixed.append(make(d, ell))
+    note("batched cooperative Jacobi: 2 ell = 258, 400, 258")
+    sketch_update_batch(mixed, rows)
+    for i in range(len(shapes)):
+        assert torch.equal(mixed[i].query(), alone[i]), i
+        mixed[i].close()
+    d, ell = shapes[1]
+    o = run_oracle(rows[1].cpu().numpy(), d, ell)
+    assert rel_fro(gram(alone[1]), gram(o.query())) <= 1e-9
+
+
+def test_rand_fp64_cooperative_cholqr_rank_drop():
+    # k = ell = 136 >= 129 on a rank-40 stream: the cooperative CholeskyQR
+    # drops columns inside its 32 x 32 diagonal blocks; the sketch still
+    # matches the oracle and, the rank being below ell, carries no error
+    d, ell = 300, 136
+    A = synth.lowrank_rows(2 * ell + 2 * (ell + 1) + 30, d, np.geomspace(5, 0.5, 40), 0.0, seed=17)
+    note(f"rand fp64 cooperative CholeskyQR rank 40 d={d} ell={ell} n={A.shape[0]}")
+    o = run_oracle(A, d, ell, "rand", k=ell, q=1, seed=4, stream=8)
+    s = make(d, ell, shrink="rand", q=1, seed=4, stream_id=8)
+    s.update(torch.from_numpy(A).cuda())
+    assert s.info()["k"] == ell and s.info()["shrinks"] == o.shrinks == 3
+    Bg, Bo = gram(s.query()), gram(o.query())
+    assert rel_fro(Bg, Bo) <= 1e-9
+    assert rel_fro(Bg, A.T @ A) <= 1e-9
+    s.close()
+
+
+# --------------------------------- tight-error workload shape (d = 4096)
+def test_tight_error_shape_d4096_ell256():
+    # the tight-error stream's shape: d = 4096, ell = k = 256, q = 1; two
+    # shrinks (769 rows; the query is a copy of the 255 buffered rows).  The
+    # FP64 path matches the oracle to 1e-9; FP32 state with the bf16 MFMA
+    # projection stays within 1.05x the oracle's covariance error and the
+    # FD bound.  The oracle takes about 25 s per shrink on the host.
+    d, ell, n = 4096, 256, 512 + 257
+    A32 = synth.persistent_tight(n, seed=1)
+    A = A32.astype(np.float64)
+    note(f"tight-error shape d={d} ell={ell} n={n}: oracle (about a minute)")
+    o = run_oracle(A, d, ell, "rand", k=ell, q=1, seed=7, stream=1)
+    Bo = gram(o.query())
+    note("  fp64 GPU path")
+    s = make(d, ell, shrink="rand", q=1, seed=7, stream_id=1)
+    s.update(torch.from_numpy(A).cuda())
+    assert s.info()["shrinks"] == o.shrinks == 2
+    assert rel_fro(gram(s.query()), Bo) <= 1e-9
+    s.close()
+    note("  fp32 state, bf16 projection")
+    s = make(d, ell, shrink="rand", q=1, state_dtype="f32", proj_dtype="bf16", seed=7, stream_id=1)
+    s.update(torch.from_numpy(A32).cuda())
+    AtA = A.T @ A
+    eg, eo = cov_err_gram(AtA, gram(s.query())), cov_err_gram(AtA, Bo)
+    note(f"  cov-err gpu {eg:.5e} oracle {eo:.5e} bound {np.trace(AtA) / ell:.5e}")
+    assert eg <= 1.05 * eo
+    assert eg <= np.trace(AtA) / ell
+    s.close()
+
+
+# -------------------------------------------- CSR with duplicate indices
+def test_csr_duplicate_indices_summed_in_row_order():
+    # rows that repeat column indices (up to five times, interleaved): the
+    # duplicates are summed in row order in FP64, so the batch equals the
+    # single-sketch call bitwise and the sketch matches the oracle on rows
+    # densified by the same ordered sum
+    from paper_2601_02019_amd import sketch_update_csr_batch
+    d, ell, n = 96, 8, 150
+    rng = np.random.default_rng(31)
+    indptr, idx, val = [0], [], []
+    for i in range(n):
+        cols = rng.integers(0, d, size=rng.integers(0, 12))
+        reps = rng.integers(0, d, size=3)
+        cols = np.concatenate([cols, np.repeat(reps, rng.integers(1, 6, size=3))])
+        rng.shuffle(cols)
+        idx.extend(cols.tolist())
+        val.extend(rng.standard_normal(len(cols)).astype(np.float32).tolist())
+        indptr.append(len(idx))
+    ip = np.asarray(indptr, dtype=np.int64)
+    ix = np.asarray(idx, dtype=np.int32)
+    vv = np.asarray(val, dtype=np.float32)
+    dense = np.zeros((n, d))
+    for i in range(n):
+        for p in range(ip[i], ip[i + 1]):
+            dense[i, ix[p]] += float(vv[p])
+    assert any(len(set(ix[ip[i]:ip[i + 1]])) < ip[i + 1] - ip[i] for i in range(n))
+    dev = tuple(torch.from_numpy(a).cuda() for a in (ip, ix, vv))
+    a = make(d, ell)
+    a.update_csr(*dev)
+    b = make(d, ell)
+    other = make(128, 8)
+    sketch_update_csr_batch([b, other], [dev, dev])
+    assert torch.equal(a.query(), b.query())
+    o = run_oracle(dense, d, ell)
+    assert rel_fro(gram(a.query()), gram(o.query())) <= 1e-9
+    for h in (a, b, other):
+        h.close()

@@ -103,6 +103,23 @@ def test_window_rotating_subspace_stream():
     assert compare(o, g, o.levels) <= 1e-9
 
 
+def test_window_d512_ell32():
+    # a larger window: d = 512, ell = 32, three levels, randomized FD reduce,
+    # queried twice (the d x d restore runs on the cooperative eigen-solver)
+    d, ell, N, R = 512, 32, 600, 8.0
+    A = normed_rows(1200, d, R, seed=13, rank=12)
+    note(f"window rand d={d} ell={ell} N={N}")
+    o = oracle.Window(d, ell, N, R, q=1, seed=6, stream=2, fd="rand")
+    g = make(d, ell, N, R, "rand", seed=6, stream=2)
+    At = torch.from_numpy(A).cuda()
+    for t0 in (0, 600):
+        o.update(A[t0:t0 + 600])
+        g.update(At[t0:t0 + 600])
+        assert compare(o, g, o.levels) <= 1e-9
+    assert sum(o.stats(j)["dumps"] for j in range(o.levels)) > 100
+    g.close()
+
+
 def test_window_advance_backwards_is_rejected():
     from paper_2601_02019_amd import SketchError
     g = make(8, 4, 10, 2.0, "exact")
