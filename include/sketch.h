@@ -186,6 +186,21 @@ SK_EXPORT sk_status sketch_update_csr_batch(sketch_t* hs, const int64_t* const* 
                                             const int32_t* const* indices, const float* const* values,
                                             const int64_t* n, int32_t count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * sketch_update_batch (dense rows on the device, same results bit for bit),
+ * but the call allocates nothing.  The batch's task records (one per ingest
+ * segment and per shrink) go into a static device array of
+ * SK_NOALLOC_MAX_TASKS records (about 1.4 MiB, held by each GPU the library
+ * runs on until the process ends) instead of the library's growable task
+ * arena; the records are staged from host memory before the call returns.
+ * SK_EINVAL, with the state unchanged, when the batch needs more records than
+ * that.  All calls on one GPU share the array: calls that overlap on one GPU
+ * (different streams or threads) race; calls on one stream are ordered. */
+#define SK_NOALLOC_MAX_TASKS 16384
+SK_EXPORT sk_status sketch_update_batch_noalloc(sketch_t* hs, const void* const* rows, const int64_t* n,
+                                                int32_t count, int32_t dtype);
+
 /* ---- serving ---------------------------------------------------------------
  * A request loop over many resident stream sketches on one GPU: streams are
  * admitted while the device-memory budget allows (others wait, first come

@@ -184,7 +184,7 @@ def sketch_memory_in_use():
     return _lib.load().sketch_memory_in_use()
 
 
-def sketch_update_batch(sketches, rows_list, dtype=None):
+def sketch_update_batch(sketches, rows_list, dtype=None, _entry="sketch_update_batch"):
     """Batched update: rows_list[i] is a contiguous CUDA tensor (n_i x d_i)."""
     n = len(sketches)
     hs = _handles(sketches)
@@ -198,8 +198,13 @@ def sketch_update_batch(sketches, rows_list, dtype=None):
         dt = _TORCH_DT[r.dtype] if dt is None else dt
     if dtype is not None:
         dt = _dt(dtype)
-    _lib.check(_lib.load().sketch_update_batch(hs, ptrs, ns, n, SK_F32 if dt is None else dt),
-               "sketch_update_batch")
+    _lib.check(getattr(_lib.load(), _entry)(hs, ptrs, ns, n, SK_F32 if dt is None else dt), _entry)
+
+
+def sketch_update_batch_noalloc(sketches, rows_list, dtype=None):
+    """sketch_update_batch through the entry point that allocates nothing (task
+    records in the library's static device array)."""
+    sketch_update_batch(sketches, rows_list, dtype, _entry="sketch_update_batch_noalloc")
 
 
 def sketch_update_csr_batch(sketches, csr_list):

@@ -77,7 +77,8 @@ EXPORTS = [
     "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query",
     "window_advance", "sketch_merge", "sketch_merge_tree", "sketch_sync", "sketch_destroy",
     "sketch_last_error", "sketch_info", "sketch_set_memory_budget", "sketch_memory_in_use",
-    "sketch_update_batch", "sketch_update_csr_batch", "sketch_profile_enable", "sketch_profile_read", "window_stats",
+    "sketch_update_batch", "sketch_update_batch_noalloc", "sketch_update_csr_batch", "sketch_profile_enable",
+    "sketch_profile_read", "window_stats",
     "server_config_init", "server_create", "server_open", "server_submit", "server_tick", "server_poll",
     "server_drain", "server_query", "server_close", "server_stats", "server_now", "server_destroy",
     "sketch_debug_fail_solver", "server_debug_fail_solver",
@@ -113,6 +114,8 @@ def load():
     lib.sketch_memory_in_use.restype = i64
     lib.sketch_update_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64),
                                         i32, i32]
+    lib.sketch_update_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                                i32, i32]
     lib.sketch_update_csr_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                             ctypes.POINTER(vp), ctypes.POINTER(i64), i32]
     lib.window_stats.argtypes = [vp, i32, ctypes.POINTER(i64)]

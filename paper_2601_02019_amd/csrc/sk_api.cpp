@@ -759,10 +759,12 @@ int64_t sketch_memory_in_use(void) { return g_in_use.load(); }
 // Lock-step rounds: round r holds every sketch's r-th ingest segment, then the
 // shrinks those segments triggered, grouped by shrink flavour.  Dense rows
 // (rows[i], dtype) or CSR rows (indptr[i], indices[i], values[i]).
+static sk_status noalloc_tasks(sketch_t h, const std::vector<Task>& tasks, Task** out);
+
 static sk_status update_batch_impl(const char* what, sketch_t* hs, const void* const* rows,
                                    const int64_t* const* indptr, const int32_t* const* indices,
                                    const float* const* values, const int64_t* n, int32_t count,
-                                   int32_t dtype) {
+                                   int32_t dtype, bool noalloc = false) {
     const bool csr = indptr != nullptr;
     if (count < 0 || (count > 0 && (!hs || !n || (!csr && !rows) || (csr && (!indices || !values)))))
         return fail(SK_EINVAL, std::string(what) + ": bad arguments");
@@ -784,6 +786,25 @@ static sk_status update_batch_impl(const char* what, sketch_t* hs, const void* c
     }
     sketch_t h0 = hs[0];
     HIP_TRY(h0, hipSetDevice(h0->cfg.device));
+    if (noalloc) {
+        // the task list must fit the static scratch: count it before any
+        // sketch's state moves (one ingest segment per buffer fill, one
+        // shrink per fill that completes the buffer)
+        int64_t ntask = 0;
+        for (int i = 0; i < count; ++i) {
+            const sketch_t h = hs[i];
+            const int64_t free0 = h->n2 - h->fill;
+            if (n[i] == 0) continue;
+            const int64_t per = h->n2 - (h->ell - 1);  // rows per later fill
+            const int64_t fills = n[i] <= free0 ? 1 : 1 + (n[i] - free0 + per - 1) / per;
+            const int64_t shr = n[i] < free0 ? 0 : 1 + (n[i] - free0) / per;
+            ntask += fills + shr;
+        }
+        if (ntask > SK_NOALLOC_MAX_TASKS)
+            return fail(SK_EINVAL, std::string(what) + ": " + std::to_string(ntask) +
+                                       " tasks exceed the static scratch (" +
+                                       std::to_string(SK_NOALLOC_MAX_TASKS) + ")");
+    }
     std::vector<int64_t> cur((size_t)count, 0);
     std::vector<sketch_t> owners;
     std::vector<Task> tasks;
@@ -848,12 +869,21 @@ static sk_status update_batch_impl(const char* what, sketch_t* hs, const void* c
             tasks.push_back(p.second);
         }
     }
-    return execute_batched(h0, owners, tasks, csr ? DT_F32 : dtype, csr);
+    if (!noalloc) return execute_batched(h0, owners, tasks, csr ? DT_F32 : dtype, csr);
+    Task* dt = nullptr;
+    if ((rc = noalloc_tasks(h0, tasks, &dt))) return rc;
+    return execute_batched(h0, owners, tasks, dtype, false, dt);
 }
 
 sk_status sketch_update_batch(sketch_t* hs, const void* const* rows, const int64_t* n, int32_t count,
                               int32_t dtype) {
     return update_batch_impl("sketch_update_batch", hs, rows, nullptr, nullptr, nullptr, n, count, dtype);
+}
+
+sk_status sketch_update_batch_noalloc(sketch_t* hs, const void* const* rows, const int64_t* n, int32_t count,
+                                      int32_t dtype) {
+    return update_batch_impl("sketch_update_batch_noalloc", hs, rows, nullptr, nullptr, nullptr, n, count, dtype,
+                             true);
 }
 
 sk_status sketch_update_csr_batch(sketch_t* hs, const int64_t* const* indptr, const int32_t* const* indices,
@@ -873,10 +903,10 @@ sk_status sketch_destroy_idle(sketch_t h) {
 // Batched execution: like execute(), but a group also breaks where the shrink
 // flavour (q, dtypes) changes.
 sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
-                          int in_dtype, bool csr) {
+                          int in_dtype, bool csr, Task* uploaded) {
     if (tasks.empty()) return SK_OK;
-    Task* dt = nullptr;
-    HIP_TRY(h, h->arena.upload(tasks, h->stream, &dt));
+    Task* dt = uploaded;
+    if (!dt) HIP_TRY(h, h->arena.upload(tasks, h->stream, &dt));
     size_t i = 0;
     while (i < tasks.size()) {
         size_t j = i + 1;
@@ -897,7 +927,45 @@ sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector
         }
         i = j;
     }
-    HIP_TRY(h, h->arena.done(h->stream));
+    if (!uploaded) HIP_TRY(h, h->arena.done(h->stream));
+    return SK_OK;
+}
+
+// ------------------------------------------------- allocation-free variant
+// Task list of sketch_update_batch_noalloc: a static device array (each GPU
+// holds its own copy for the life of the process).  In host code `scratch`
+// names a host-side stand-in, never the device memory: its device address is
+// taken once per device with hipGetSymbolAddress and only that address is
+// used.  Calls that overlap on one GPU share the array and race.
+static __device__ __align__(256) Task scratch[SK_NOALLOC_MAX_TASKS];
+
+static std::mutex g_scratch_mu;
+static Task* g_scratch_ptr[64] = {};
+
+static sk_status noalloc_tasks(sketch_t h, const std::vector<Task>& tasks, Task** out) {
+    const int dev = h->cfg.device;
+    if (dev < 0 || dev >= 64) return fail(SK_EINVAL, "sketch_update_batch_noalloc: device ordinal >= 64");
+    Task* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // the device is current (set by the caller of this function)
+            hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(SK_EDEVICE, std::string("sketch_update_batch_noalloc: hipGetSymbolAddress: ") +
+                                            hipGetErrorString(e));
+            g_scratch_ptr[dev] = ptr;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    if (tasks.empty()) {
+        *out = ptr;
+        return SK_OK;
+    }
+    // stream-ordered behind earlier work that read the array; the host copy
+    // is pageable memory, which HIP stages before the call returns
+    HIP_TRY(h, hipMemcpyAsync(ptr, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice, h->stream));
+    *out = ptr;
     return SK_OK;
 }
 

@@ -236,8 +236,10 @@ struct sketch_s {
 void plan_rows(sketch_t h, int64_t n, const char* src, int64_t src_ld, int in_dtype,
                const int64_t* indptr, const int32_t* idx, const float* val,
                std::vector<sketch_t>& owners, std::vector<Task>& tasks);
+// uploaded != nullptr: the task list is already on the device there (the
+// allocation-free entry point); otherwise it goes through the task arena
 sk_status execute_batched(sketch_t h, std::vector<sketch_t>& owners, std::vector<Task>& tasks,
-                          int in_dtype, bool csr = false);
+                          int in_dtype, bool csr = false, Task* uploaded = nullptr);
 sk_status check_handle(sketch_t h, const char* what);
 bool eig_solver_jacobi();
 // Device bytes sketch_create would allocate for cfg (persistent sketches);
