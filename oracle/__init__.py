@@ -74,6 +74,18 @@ def _load():
     lib.o_aero_dump.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int64, ctypes.c_int64, _dp, _dp,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
+    lib.o_attp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                  ctypes.c_int]
+    lib.o_attp_create.restype = ctypes.c_void_p
+    lib.o_attp_destroy.argtypes = [ctypes.c_void_p]
+    lib.o_attp_update.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, ctypes.c_int64]
+    lib.o_attp_gram_at.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp]
+    lib.o_attp_query_at.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp]
+    lib.o_attp_stats.argtypes = [ctypes.c_void_p, _i64p]
+    lib.o_attp_theta.argtypes = [ctypes.c_void_p]
+    lib.o_attp_theta.restype = ctypes.c_double
+    lib.o_attp_snapshot.argtypes = [ctypes.c_void_p, ctypes.c_int64, _i64p, _dp, _dp]
+    lib.o_attp_buffer.argtypes = [ctypes.c_void_p, _dp]
     _lib = lib
     return lib
 
@@ -310,4 +322,61 @@ class Window:
         r = _lib.o_win_buffer(self._h, level, _p(C))
         if r < 0:
             raise RuntimeError("oracle win_buffer failed")
+        return C[:r].copy()
+
+
+class ATTP:
+    """ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch")."""
+
+    def __init__(self, d, ell, q=1, seed=0, stream=0, fd="exact"):
+        lib = _load()
+        self._h = lib.o_attp_create(d, ell, q, seed, stream, {"exact": 0, "rand": 1}[fd])
+        if not self._h:
+            raise ValueError("bad ATTP parameters")
+        self.d, self.ell = d, ell
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o_attp_destroy(self._h)
+            self._h = None
+
+    def update(self, rows):
+        rows = _f64(np.atleast_2d(rows))
+        if rows.shape[0] == 0:
+            return
+        _check(_lib.o_attp_update(self._h, _p(rows), rows.shape[0], rows.shape[1]), "attp_update")
+
+    def gram_at(self, t):
+        G = np.zeros((self.d, self.d))
+        _check(_lib.o_attp_gram_at(self._h, t, _p(G)), "attp_gram_at")
+        return G
+
+    def query_at(self, t):
+        out = np.zeros((self.ell, self.d))
+        _check(_lib.o_attp_query_at(self._h, t, _p(out)), "attp_query_at")
+        return out
+
+    def stats(self):
+        st = np.zeros(6, dtype=np.int64)
+        _check(_lib.o_attp_stats(self._h, st.ctypes.data_as(_i64p)), "attp_stats")
+        return dict(zip(["snapshots", "dirs", "fill", "shrinks", "simul_iters", "T"], st.tolist()))
+
+    @property
+    def theta(self):
+        return _lib.o_attp_theta(self._h)
+
+    def snapshots(self):
+        out = []
+        meta = np.zeros(3, dtype=np.int64)
+        for e in range(self.stats()["snapshots"]):
+            _check(_lib.o_attp_snapshot(self._h, e, meta.ctypes.data_as(_i64p), None, None), "attp_snapshot")
+            xi = int(meta[0])
+            Z, W = np.zeros((self.d, xi)), np.zeros((xi, self.d))
+            _check(_lib.o_attp_snapshot(self._h, e, meta.ctypes.data_as(_i64p), _p(Z), _p(W)), "attp_snapshot")
+            out.append({"xi": xi, "s": int(meta[1]), "t": int(meta[2]), "Z": Z, "W": W})
+        return out
+
+    def buffer(self):
+        C = np.zeros((2 * self.ell, self.d))
+        r = _lib.o_attp_buffer(self._h, _p(C))
         return C[:r].copy()

@@ -16,6 +16,8 @@
  *   - Query with the final shrink: Algorithm "AeroSketch: Query".
  *   - Sliding window: Algorithm "ML-AeroSketch".
  *   - Merge: Lemma "Decomposability" (appendix, proof of the P5 theorem).
+ *   - Persistent (at-the-time) sketch: Algorithm "ATTP Sketch using
+ *     AeroSketch" (Sec. 4.1).
  *
  * Conventions: every matrix is row-major FP64 with an explicit leading
  * dimension; every function returns 0 on success and a negative code on a
@@ -123,6 +125,29 @@ int o_win_buffer(const o_win* w, int level, double* C);
  * rows), and C becomes C - C Z Z^T. */
 int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
                 int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi);
+
+/* ---- ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch") --
+ * One AeroSketch whose dump threshold is theta_i = eps ||A_i||_F^2 (eps =
+ * 2 / ell) at row i; snapshots are kept for ever, so the sketch of any time
+ * t <= T can be queried.  fd_mode as for the window (level 0's key). */
+typedef struct o_attp o_attp;
+o_attp* o_attp_create(int d, int ell, int q, uint64_t seed, uint64_t stream, int fd_mode);
+void o_attp_destroy(o_attp* a);
+int o_attp_update(o_attp* a, const double* rows, int64_t n, int64_t ld);
+/* d x d restored matrix of time t: the restore of every snapshot with
+ * timestamp <= t, plus the residual's Gram when t is the current time T. */
+int o_attp_gram_at(const o_attp* a, int64_t t, double* G);
+/* ell x d sketch of A_t (the restored matrix shrunk by its ell-th eigenvalue). */
+int o_attp_query_at(const o_attp* a, int64_t t, double* out);
+/* [0] snapshots [1] dumped directions [2] residual rows [3] FD reduces
+ * [4] simul_iter calls [5] current time T. */
+int o_attp_stats(const o_attp* a, int64_t* st /* [6] */);
+/* Threshold used for the last row (eps ||A_T||_F^2). */
+double o_attp_theta(const o_attp* a);
+/* Snapshot e (oldest first): meta = {xi, s, t}; Z (d x xi), W (xi x d). */
+int o_attp_snapshot(const o_attp* a, int64_t e, int64_t* meta /* [3] */, double* Z, double* W);
+/* The residual rows (r x d) into C; returns r. */
+int o_attp_buffer(const o_attp* a, double* C);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,9 @@ a threshold compared against theta instead of theta / 2, strict instead of
 inclusive comparisons, an off-by-one count of dumped directions, a residual
 that is not downdated, a wrong Philox key for a level's FD reduce, a wrong
 level threshold, and in the persistent oracle a wrong shrink threshold index
-or a missing power step.
+or a missing power step; in the ATTP oracle a historical filter that
+drops the snapshot taken at time t, a wrong or stale threshold, the
+residual added to past times, a wrong Philox key and a wrong restore sign.
 """
 import os
 import shutil
@@ -22,6 +24,7 @@ ORACLE = os.path.join(ROOT, "oracle")
 # (file, original text, mutated text, pin files expected to catch it)
 WINDOW_PINS = ["tests/test_oracle_window_pins.py", "tests/test_oracle_window.py"]
 FD_PINS = ["tests/test_oracle_pins.py"]
+ATTP_PINS = ["tests/test_oracle_attp.py"]
 MUTANTS = {
     "pi_threshold_theta": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
                            "if (!(s1 >= theta)) return 0;", WINDOW_PINS),
@@ -50,6 +53,15 @@ MUTANTS = {
     "rand_omega_shrink_counter": ("fd.c", "o_omega(seed, stream, b, 0, d, k, Om);",
                                   "o_omega(seed, stream, 0, 0, d, k, Om);", FD_PINS),
     "fill_after_shrink": ("fd.c", "s->r = s->ell - 1;", "s->r = s->ell;", FD_PINS),
+    "attp_history_strict": ("attp.c", "if (s->t > t) continue;", "if (s->t >= t) continue;", ATTP_PINS),
+    "attp_theta_eps": ("attp.c", "a->theta = (2.0 / ell) * a->fro2;", "a->theta = (1.0 / ell) * a->fro2;",
+                       ATTP_PINS),
+    "attp_theta_stale": ("attp.c", "a->fro2 += nrm;\n    a->theta = (2.0 / ell) * a->fro2;",
+                         "a->theta = (2.0 / ell) * a->fro2;\n    a->fro2 += nrm;", ATTP_PINS),
+    "attp_residual_in_history": ("attp.c", "if (t == a->T)", "if (t >= 0)", ATTP_PINS),
+    "attp_reduce_key": ("attp.c", "a->stream * 64u + 1u", "a->stream * 64u", ATTP_PINS),
+    "attp_restore_sign": ("attp.c", "G[(int64_t)x * d + y] += acc - sub;", "G[(int64_t)x * d + y] += acc + sub;",
+                          ATTP_PINS),
     "power_iteration_step": ("fd.c", "for (int it = 0; it < steps; ++it) {", "for (int it = 1; it < steps; ++it) {",
                              FD_PINS + WINDOW_PINS),
 }
