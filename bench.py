@@ -16,6 +16,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -35,15 +36,15 @@ def parse():
     ap.add_argument("--d", type=int, default=4096)
     ap.add_argument("--ell", type=int, default=256)
     ap.add_argument("--q", type=int, default=1)
-    ap.add_argument("--exact-rows", type=int, default=20_000,
-                    help="prefix of the stream on which the exact-SVD FD path is timed")
+    ap.add_argument("--exact-rows", type=int, default=0,
+                    help="rows on which the exact-SVD FD path is timed and the errors compared (0: all)")
     ap.add_argument("--no-exact", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-err", action="store_true",
                     help="skip the covariance-error evaluation (torch eigvalsh) of the timed sketch")
     ap.add_argument("--cpu-shrinks", type=int, default=1,
                     help="shrinks of the CPU oracle sample")
-    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy"],
+    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy", "attp"],
                     default="persistent",
                     help="persistent: the tight-error single stream (default); small: the FP64 exact "
                          "small stream; window: the sliding-window stream; sites: 64 CSR sites with "
@@ -51,6 +52,7 @@ def parse():
                          "plain device copy of known size (HBM reference and counter calibration)")
     ap.add_argument("--window-rows", type=int, default=200_000, help="rows of the window stream")
     ap.add_argument("--site-rows", type=int, default=100_000, help="rows per site")
+    ap.add_argument("--attp-rows", type=int, default=10_000, help="rows of the ATTP stream")
     ap.add_argument("--sites", type=int, default=64)
     ap.add_argument("--streams", type=int, default=512)
     ap.add_argument("--bursts", type=int, default=2000, help="bursts per load point")
@@ -114,6 +116,55 @@ def measured_traffic(kernel, source):
     if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _site_oracle_job(job):
+    """CPU-baseline job: the FP64 oracle over the first m rows of one site."""
+    import oracle
+    import synth
+    site, m, d, ell = job
+    ip, ix, vv = synth.streams.sparse_sites(m, d=d, density=0.01, seed=4, site=site)
+    Xd = synth.streams.csr_to_dense(ip, ix, vv, d)
+    o = oracle.FD(d, ell, "rand", k=ell, q=1, seed=4, stream=site)
+    o.update(Xd)
+    return m
+
+
+def _serving_oracle_job(job):
+    """CPU-baseline job: the FP64 oracle over two shrinks' worth of rows of
+    one serving stream (its own low-rank-plus-noise model)."""
+    import numpy as np
+    import oracle
+    import synth
+    i, d, ell = job
+    r = min(2 * ell, d)
+    m = 2 * ell + ell + 1
+    A = synth.lowrank_rows(m, d, 1.0 - np.arange(r) / r, 0.1, seed=1000 + i)
+    o = oracle.FD(d, ell, "rand", k=ell, q=1, seed=5, stream=i)
+    o.update(A)
+    return m
+
+
+def oracle_pool(fn, jobs, procs):
+    """Runs fn over jobs on `procs` processes (fresh interpreters, so the GPU
+    state of this process is not shared); returns (seconds, rows)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        t = time.perf_counter()
+        rows = sum(pool.map(fn, jobs))
+        tc = time.perf_counter() - t
+    return tc, rows
 
 
 def tri_flops(n):
@@ -242,6 +293,18 @@ def serving_main(args):
     st = srv.stats()
     finite = all(bool(torch.isfinite(srv.query(ids[i], torch.float32)).all()) for i in range(0, len(ids), 37))
     srv.close()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on a pool of processes over the host cores, one stream
+        # each (the first streams of the set with ell <= 128, so that a sample
+        # stays within seconds), two shrinks' worth of rows per stream
+        procs = max(1, min(os.cpu_count() or 1, 16))
+        jobs = [(i, d, ell) for i, (d, ell) in enumerate(zip(ds, ells)) if ell <= 128][:procs]
+        tc, rows_c = oracle_pool(_serving_oracle_job, jobs, procs)
+        cpu = {"value": rows_c / tc, "unit": "rows/s", "cores": procs, "kind": "oracle",
+               "sample": f"{len(jobs)} serving streams with ell <= 128, 3 ell + 1 rows each, one process per "
+                         f"stream, randomized shrink k=ell q=1, FP64 plain C, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
     hi = points[-1] if points else None
     out = {
         "metric": "rows/sec sketch update at matched cov-err vs exact-SVD FD; batched p99 lat",
@@ -259,6 +322,7 @@ def serving_main(args):
         "p99_ms_at_highest_load": hi["p99_ms"] if hi else None,
         "server": {"ticks": st["ticks"], "batches": st["batches"], "state_MiB": st["bytes_in_use"] / 2**20},
         "sketches_finite": finite,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
@@ -319,7 +383,7 @@ def small_main(args):
         tc = time.perf_counter() - t
         cpu = {"value": n / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
                "sample": f"the whole stream ({n} rows, {o.shrinks} exact shrinks), FP64 plain C, one "
-                         f"thread, {tc:.1f}s"}
+                         f"thread, {tc:.1f}s", "cpu": cpu_model(), "nproc": os.cpu_count()}
     stages = {k: v for k, v in prof.items() if v[0] > 0}
     base_line(args, n / (ms / 1e3), "rows/s", ms,
               "persistent stream, exact FP64 shrink: n=10000, d=256, ell=32, rank-20 signal "
@@ -374,7 +438,7 @@ def window_main(args):
         o.update(A[:m].astype(np.float64))
         tc = time.perf_counter() - t
         cpu = {"value": m / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} rows of the window stream, FP64 plain C, one thread, {tc:.1f}s"}
+               "sample": f"first {m} rows of the window stream, FP64 plain C, one thread, {tc:.1f}s", "cpu": cpu_model(), "nproc": os.cpu_count()}
     base_line(args, n / upd, "rows/s", None,
               "sliding window: d=1024, ell=128, N=100000, FP32 rows, rank-64 spectrum 0.95^j rotating "
               "by a Givens sweep every 50000 rows; first %d rows, query every 10000" % n,
@@ -382,6 +446,57 @@ def window_main(args):
                "query_ms_median": 1e3 * float(np.median(qry)), "query_ms_max": 1e3 * float(np.max(qry)),
                "cov_err_rel_max": max(errs), "bound_rel_25_over_ell": 25.0 / ell,
                "level_stats": stats, "cpu_baseline": cpu})
+
+
+def attp_main(args):
+    """ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch"): the
+    shape of the paper's ATTP experiment, a Random Noisy stream (D_ii =
+    1 - (i-1)/d, noise 1/zeta, zeta = 10) with d = 500 and T = --attp-rows
+    rows; ell = 64 (eps = 1/32), randomized FD reduce, FP64.  After the
+    stream, the sketches of 20 past times t = T/20, 2T/20, ..., T are queried."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2601_02019_amd import Sketch
+    d, ell, n = 500, 64, args.attp_rows
+    A = synth.random_noisy(n, d, seed=5)
+    At = torch.from_numpy(A).cuda()
+    warm = Sketch(d, ell, kind="attp", shrink="rand", q=1, seed=3, stream_id=1)
+    warm.update(At[:500])
+    warm.query_at(250)
+    warm.close()
+    s = Sketch(d, ell, kind="attp", shrink="rand", q=1, seed=3, stream_id=0)
+    _, tu = timed(lambda: s.update(At))
+    times = [n * (i + 1) // 20 for i in range(20)]
+    qms, errs = [], []
+    for t in times:
+        B, tq = timed(lambda: s.query_at(t))
+        qms.append(1e3 * tq)
+        Ap = At[:t]
+        G = Ap.T @ Ap
+        D = G - B.T @ B
+        errs.append(float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / torch.trace(G)))
+    st = s.window_stats(0)
+    s.close()
+    print(f"[bench] attp: update {tu:.2f}s, queries {np.median(qms):.1f} ms, max err {max(errs):.3e}",
+          file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        m = 600
+        o = oracle.ATTP(d, ell, q=1, seed=3, stream=0, fd="rand")
+        tc0 = time.perf_counter()
+        o.update(A[:m])
+        tc = time.perf_counter() - tc0
+        cpu = {"value": m / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} rows of the ATTP stream, FP64 plain C, one thread, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
+    base_line(args, n / tu, "rows/s", None,
+              "ATTP persistent sketch: Random Noisy stream d=500, T=%d rows, ell=64 (eps=1/32), randomized "
+              "FD reduce, FP64; sketches of 20 past times queried" % n,
+              {"dtype": "f64", "rows": n, "update_s": tu, "query_ms_median": float(np.median(qms)),
+               "cov_err_rel_max_over_times": max(errs), "bound_rel_10_over_ell": 10.0 / ell,
+               "snapshots": st["dumps"], "dumped_directions": st["dirs"], "cpu_baseline": cpu})
 
 
 def sites_main(args):
@@ -464,18 +579,14 @@ def sites_main(args):
     err = float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / torch.trace(G))
     cpu = None
     if not args.no_cpu:
-        import oracle
-        import synth
+        # the oracle on a pool of processes over the host cores, one site each
         m = 2 * ell + 2 * (ell + 1)
-        ip, ix, vv = synth.streams.sparse_sites(m, d=d, density=0.01, seed=4, site=0)
-        Xd = synth.streams.csr_to_dense(ip, ix, vv, d)
-        o = oracle.FD(d, ell, "rand", k=ell, q=1, seed=4, stream=0)
-        t = time.perf_counter()
-        o.update(Xd)
-        tc = time.perf_counter() - t
-        cpu = {"value": m / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} rows of one site densified ({o.shrinks} randomized shrinks), FP64 "
-                         f"plain C, one thread, {tc:.1f}s"}
+        procs = max(1, min(S, os.cpu_count() or 1, 16))
+        tc, rows = oracle_pool(_site_oracle_job, [(site, m, d, ell) for site in range(procs)], procs)
+        cpu = {"value": rows / tc, "unit": "rows/s", "cores": procs, "kind": "oracle",
+               "sample": f"first {m} rows of each of {procs} sites densified ({procs} processes, one site "
+                         f"each, randomized shrinks k={ell}), FP64 plain C, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
     base_line(args, S * n / total, "rows/s", None,
               "distributed sites on one GPU: %d sites x %d CSR rows, d=2048, 1%% density, values N(0,1) "
               "j^-0.5, ell=128 per site, tree merge every 10000 rows per site" % (S, n),
@@ -515,7 +626,7 @@ def main():
         sys.exit(2)
     if args.workload != "persistent":
         return {"serving": serving_main, "small": small_main, "window": window_main,
-                "sites": sites_main, "copy": copy_main}[args.workload](args)
+                "sites": sites_main, "copy": copy_main, "attp": attp_main}[args.workload](args)
     import torch
     from paper_2601_02019_amd import Sketch
 
@@ -546,7 +657,7 @@ def main():
         print(f"[bench] step {k}: {times[-1]:.3f}s", file=sys.stderr, flush=True)
     prof = sk.profile_read()
     sk.close()
-    ms_per_step = 1e3 * sum(times) / len(times)
+    ms_per_step = 1e3 * float(sorted(times)[len(times) // 2])  # median step
     rows_per_s = n / (ms_per_step / 1e3)
 
     # dominant kernel: the stage with the largest event-timed total
@@ -584,19 +695,18 @@ def main():
     else:
         roofline = {"bound": "unknown", "kernel": dom, "avg_launch_ms": avg_ms}
 
-    # ---------------- matched-error check on a prefix, exact path timed there
+    # ---------------- exact-SVD FD on the same GPU and the matched-error check:
+    # both paths over the same rows (the whole stream unless --exact-rows)
     exact = None
-    pre = min(args.exact_rows, n)
+    pre = min(args.exact_rows, n) if args.exact_rows > 0 else n
     if not args.no_exact:
         Ap = A[:pre]
         ex = Sketch(d, ell, shrink="exact", state_dtype="f32", seed=7, stream_id=1)
         ra = Sketch(d, ell, shrink="rand", state_dtype="f32", proj_dtype="bf16", q=args.q, seed=7,
                     stream_id=1)
-        ex.update(Ap[: 2 * ell])
-        ex.sync()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        ex.update(Ap[2 * ell:])
+        ex.update(Ap)
         Be = ex.query()
         torch.cuda.synchronize()
         te = time.perf_counter() - t
@@ -605,9 +715,10 @@ def main():
         AtA = gram_f64(Ap)
         ee, er = cov_err(AtA, Be), cov_err(AtA, Br)
         fro2 = float(torch.trace(AtA))
-        exact = {"rows_per_s": (pre - 2 * ell) / te, "timed_rows": pre - 2 * ell,
+        exact = {"rows_per_s": pre / te, "timed_rows": pre,
                  "cov_err_rel_exact": ee / fro2, "cov_err_rel_rand": er / fro2,
-                 "rand_over_exact_err": er / ee, "bound_rel": 1.0 / ell}
+                 "rand_over_exact_err": er / ee, "matched": bool(er <= 1.05 * ee), "bound_rel": 1.0 / ell,
+                 "eig_solver": "tridiagonal (multi-workgroup reduction) for 2 ell <= 512"}
         print(f"[bench] exact path: {exact}", file=sys.stderr, flush=True)
         ex.close()
         ra.close()
@@ -633,7 +744,8 @@ def main():
         tc = time.perf_counter() - t
         cpu = {"value": rows_cpu / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
                "sample": f"first {rows_cpu} rows of the d={d} stream ({o.shrinks} randomized "
-                         f"shrinks, k={ell}, q={args.q}), FP64 plain C, one thread, {tc:.1f}s"}
+                         f"shrinks, k={ell}, q={args.q}), FP64 plain C, one thread, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
 
     out = {
         "metric": "rows/sec sketch update at matched cov-err vs exact-SVD FD; batched p99 lat",

@@ -15,6 +15,9 @@
  *   - persistent stream sketch (SK_PERSISTENT): cov-error of the whole stream;
  *   - sliding window (SK_WINDOW): Algorithm "ML-AeroSketch", window of the
  *     last window_N rows;
+ *   - at-the-time persistent sketch (SK_ATTP, Sec. 4.1): Algorithm "ATTP
+ *     Sketch using AeroSketch", the sketch of any earlier prefix of the
+ *     stream (sketch_query_at);
  *   - distributed streams: per-site sketches combined by sketch_merge
  *     (Lemma "Decomposability").
  *
@@ -66,7 +69,7 @@ typedef enum {
 } sk_status;
 
 typedef enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 } sk_dtype;
-typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1 } sk_kind;
+typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1, SK_ATTP = 2 } sk_kind;
 typedef enum { SK_SHRINK_EXACT = 0, SK_SHRINK_RAND = 1 } sk_shrink;
 
 typedef struct {
@@ -121,6 +124,19 @@ SK_EXPORT sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const i
  * Window: the query of Algorithm "ML-AeroSketch" for the window (T-N, T].
  * Non-destructive. */
 SK_EXPORT sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device);
+
+/* SK_ATTP only (Sec. 4.1, Algorithm "ATTP Sketch using AeroSketch";
+ * Theorem "ATTP"): writes the ell x d sketch of A_t, the first t rows of the
+ * stream, 0 <= t <= T (T = rows seen), to B_out (row-major, SK_F64 or
+ * SK_F32, host or device as on_device).  The sketch keeps one AeroSketch
+ * whose dump threshold is eps ||A_i||_F^2 (eps = 2 / ell) when row i
+ * arrives and every snapshot it ever dumped; B_out^T B_out is the restored
+ * matrix of the snapshots taken at times <= t (plus the residual's Gram
+ * when t = T) shrunk by its ell-th eigenvalue, with covariance error
+ * O(eps) ||A_t||_F^2 w.h.p.  Blocks until B_out is written.  SK_EINVAL for t
+ * outside [0, T] (state unchanged); SK_EUNSUPPORTED for other kinds.
+ * sketch_query on an SK_ATTP sketch is sketch_query_at(T). */
+SK_EXPORT sk_status sketch_query_at(sketch_t h, int64_t t, void* B_out, int32_t dtype, int32_t on_device);
 
 /* SK_WINDOW only: moves time to t_now >= current time without rows and
  * expires what left the window.  SK_EUNSUPPORTED on persistent sketches,

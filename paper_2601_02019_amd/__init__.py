@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import (  # noqa: F401
     SK_BF16, SK_EDEVICE, SK_EINVAL, SK_ENOMEM, SK_ESHAPE, SK_ESTATE, SK_EUNSUPPORTED, SK_F32,
-    SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
+    SK_ATTP, SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
     sk_completion, sk_server_config, sk_server_stats, sketch_config, sketch_info_t,
 )
 
@@ -121,6 +121,20 @@ def sketch_query(h, out):
         assert out.flags["C_CONTIGUOUS"]
         _lib.check(_lib.load().sketch_query(h, ctypes.c_void_p(out.ctypes.data), _NP_DT[out.dtype], 0),
                    "sketch_query")
+    return out
+
+
+def sketch_query_at(h, t, out):
+    """ATTP sketches: writes the ell x d sketch of the first t rows into
+    ``out`` (as sketch_query)."""
+    if isinstance(out, torch.Tensor):
+        assert out.is_contiguous()
+        _lib.check(_lib.load().sketch_query_at(h, int(t), ctypes.c_void_p(out.data_ptr()), _TORCH_DT[out.dtype],
+                                               int(out.is_cuda)), "sketch_query_at")
+    else:
+        assert out.flags["C_CONTIGUOUS"]
+        _lib.check(_lib.load().sketch_query_at(h, int(t), ctypes.c_void_p(out.ctypes.data), _NP_DT[out.dtype], 0),
+                   "sketch_query_at")
     return out
 
 
@@ -247,7 +261,7 @@ def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", pr
                 oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0):
     cfg = sketch_config_init()
     cfg.d, cfg.ell = d, ell
-    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW}[kind]
+    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP}[kind]
     cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
     cfg.state_dtype = _dt(state_dtype)
     cfg.proj_dtype = _dt(proj_dtype)
@@ -466,6 +480,13 @@ class Sketch:
         if out is None:
             out = torch.empty((self.ell, self.d), dtype=dtype, device=f"cuda:{self.device}")
         sketch_query(self.handle, out)
+        self._keep.clear()
+        return out
+
+    def query_at(self, t, dtype=torch.float64, out=None):
+        if out is None:
+            out = torch.empty((self.ell, self.d), dtype=dtype, device=f"cuda:{self.device}")
+        sketch_query_at(self.handle, t, out)
         self._keep.clear()
         return out
 

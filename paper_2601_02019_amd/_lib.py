@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsketch.so")
 
 SK_OK, SK_EINVAL, SK_ENOMEM, SK_EDEVICE, SK_ESHAPE, SK_EUNSUPPORTED, SK_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SK_F64, SK_F32, SK_BF16 = 0, 1, 2
-SK_PERSISTENT, SK_WINDOW = 0, 1
+SK_PERSISTENT, SK_WINDOW, SK_ATTP = 0, 1, 2
 SK_SHRINK_EXACT, SK_SHRINK_RAND = 0, 1
 
 STATUS_NAMES = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_ENOMEM", -3: "SK_EDEVICE", -4: "SK_ESHAPE",
@@ -74,7 +74,7 @@ SK_STAGE = {"ingest": 1 << 0, "omega": 1 << 1, "gram": 1 << 2, "project": 1 << 3
 SK_STAGE_ALL = 0x7FF
 
 EXPORTS = [
-    "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query",
+    "sketch_config_init", "sketch_create", "sketch_update", "sketch_update_csr", "sketch_query", "sketch_query_at",
     "window_advance", "sketch_merge", "sketch_merge_tree", "sketch_sync", "sketch_destroy",
     "sketch_last_error", "sketch_info", "sketch_set_memory_budget", "sketch_memory_in_use",
     "sketch_update_batch", "sketch_update_batch_noalloc", "sketch_update_csr_batch", "sketch_profile_enable",
@@ -101,6 +101,7 @@ def load():
     lib.sketch_update.argtypes = [vp, vp, i64, i64, i32, i32]
     lib.sketch_update_csr.argtypes = [vp, vp, vp, vp, i64, i32]
     lib.sketch_query.argtypes = [vp, vp, i32, i32]
+    lib.sketch_query_at.argtypes = [vp, i64, vp, i32, i32]
     lib.window_advance.argtypes = [vp, i64]
     lib.sketch_merge.argtypes = [vp, ctypes.POINTER(vp), i32]
     lib.sketch_merge_tree.argtypes = [vp, ctypes.POINTER(vp), i32]

@@ -28,40 +28,45 @@ __device__ __forceinline__ int dim_sel(const Task& t, int code) {
     return code == 0 ? t.m : (code == 1 ? t.s->k : eig_n(t));
 }
 
-template <bool TA, bool TB>
+// TS x TS output tile per workgroup of 256 threads, each thread a (TS/16)^2
+// register block; every output element accumulates over k in order, so the
+// result does not depend on TS (small products take TS = 32 for 4x the
+// workgroups).
+template <bool TA, bool TB, int TS>
 __global__ __launch_bounds__(256) void k_core_gemm(const Task* tasks, int sa, int sb, int sc,
                                                    int dims) {
+    constexpr int RB = TS / 16;  // register block edge
     const Task& t = tasks[blockIdx.z];
     if (t.kind == T_INGEST) return;
     const SkDev* s = t.s;
     const int M = dim_sel(t, dims & 3), N = dim_sel(t, (dims >> 2) & 3), K = dim_sel(t, (dims >> 4) & 3);
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int r0 = blockIdx.y * TS, c0 = blockIdx.x * TS;
     if (r0 >= M || c0 >= N) return;
     const double* A = s->slot[sa];
     const double* B = s->slot[sb];
     double* C = s->slot[sc];
     const int lda = s->sld[sa], ldb = s->sld[sb], ldc = s->sld[sc];
-    __shared__ double As[16][64 + 2];
-    __shared__ double Bs[16][64 + 2];
+    __shared__ double As[16][TS + 2];
+    __shared__ double Bs[16][TS + 2];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    double acc[4][4];
+    double acc[RB][RB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < RB; ++j) acc[i][j] = 0.0;
     for (int kk = 0; kk < K; kk += 16) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;  // 1024 elements of a 64 x 16 slice
+        for (int u = 0; u < RB; ++u) {
+            const int e = tid + 256 * u;  // 16 * TS elements of a TS x 16 slice
             if (!TA) {  // A row-major: consecutive threads walk k
                 const int r = e >> 4, k = e & 15;
                 As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(r0 + r) * lda + kk + k] : 0.0;
             } else {    // A^T: consecutive threads walk the row index of op(A)
-                const int r = e & 63, k = e >> 6;
+                const int r = e % TS, k = e / TS;
                 As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(kk + k) * lda + r0 + r] : 0.0;
             }
             if (!TB) {
-                const int c = e & 63, k = e >> 6;
+                const int c = e % TS, k = e / TS;
                 Bs[k][c] = (c0 + c < N && kk + k < K) ? B[(int64_t)(kk + k) * ldb + c0 + c] : 0.0;
             } else {
                 const int c = e >> 4, k = e & 15;
@@ -71,26 +76,26 @@ __global__ __launch_bounds__(256) void k_core_gemm(const Task* tasks, int sa, in
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            double a[4], b[4];
+            double a[RB], b[RB];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = As[k][ty * 4 + i];
-                b[i] = Bs[k][tx * 4 + i];
+            for (int i = 0; i < RB; ++i) {
+                a[i] = As[k][ty * RB + i];
+                b[i] = Bs[k][tx * RB + i];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < RB; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + ty * 4 + i;
+    for (int i = 0; i < RB; ++i) {
+        const int r = r0 + ty * RB + i;
         if (r >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = c0 + tx * 4 + j;
+        for (int j = 0; j < RB; ++j) {
+            const int c = c0 + tx * RB + j;
             if (c < N) C[(int64_t)r * ldc + c] = acc[i][j];
         }
     }
@@ -174,7 +179,7 @@ template <bool LDS>
 __global__ __launch_bounds__(1024) void k_cholinv(const Task* tasks, int sw, int sx, int lds_max) {
     extern __shared__ double lds[];
     const Task& t = tasks[blockIdx.z];
-    if (t.kind != T_SHRINK_RAND || (t.flags & TF_COOP_CHOL)) return;
+    if (t.kind != T_SHRINK_RAND || (t.flags & (TF_COOP_CHOL | TF_X_CHOL))) return;
     const SkDev* s = t.s;
     const int n = s->k;
     if (LDS != (n <= lds_max)) return;
@@ -293,13 +298,23 @@ int chol_lds_max() {
     return g_chol_lds;
 }
 
+template <int TS>
+static void core_gemm_ts(const Task* tasks, int count, int max_M, int max_N, bool ta, bool tb, int sa, int sb,
+                         int sc, int dims, hipStream_t st) {
+    const dim3 grid((unsigned)((max_N + TS - 1) / TS), (unsigned)((max_M + TS - 1) / TS), (unsigned)count);
+    if (!ta && !tb) hipLaunchKernelGGL((k_core_gemm<false, false, TS>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else if (ta && !tb) hipLaunchKernelGGL((k_core_gemm<true, false, TS>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else if (!ta && tb) hipLaunchKernelGGL((k_core_gemm<false, true, TS>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    else hipLaunchKernelGGL((k_core_gemm<true, true, TS>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+}
+
+// 64 x 64 tiles when they give the launch at least 256 workgroups, else
+// 32 x 32 tiles (the same values either way).
 hipError_t launch_core_gemm(const Task* tasks, int count, int max_M, int max_N, bool ta, bool tb,
                             int sa, int sb, int sc, int dims, hipStream_t st) {
-    const dim3 grid((unsigned)((max_N + 63) / 64), (unsigned)((max_M + 63) / 64), (unsigned)count);
-    if (!ta && !tb) hipLaunchKernelGGL((k_core_gemm<false, false>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
-    else if (ta && !tb) hipLaunchKernelGGL((k_core_gemm<true, false>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
-    else if (!ta && tb) hipLaunchKernelGGL((k_core_gemm<false, true>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
-    else hipLaunchKernelGGL((k_core_gemm<true, true>), grid, dim3(256), 0, st, tasks, sa, sb, sc, dims);
+    const int64_t t64 = (int64_t)((max_N + 63) / 64) * ((max_M + 63) / 64) * count;
+    if (t64 >= 256) core_gemm_ts<64>(tasks, count, max_M, max_N, ta, tb, sa, sb, sc, dims, st);
+    else core_gemm_ts<32>(tasks, count, max_M, max_N, ta, tb, sa, sb, sc, dims, st);
     return hipGetLastError();
 }
 

@@ -619,6 +619,68 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
     }
 }
 
+// Gershgorin bounds of T widened by the bisection tolerance, its norm and
+// the pivot floor (the same values in every kernel that calls this).
+struct TriBounds {
+    double gl, gu, tnorm, pivmin;
+};
+__device__ __forceinline__ TriBounds tri_bounds(const double* d, const double* e, int n) {
+    double emax2 = 0.0;
+    for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, e[i] * e[i]);
+    double gl = 1e308, gu = -1e308;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+        gl = fmin(gl, d[i] - r);
+        gu = fmax(gu, d[i] + r);
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double eps = 2.220446049250313e-16;
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
+    gu += 2.0 * eps * tnorm + 2.0 * pivmin;
+    return {gl, gu, tnorm, pivmin};
+}
+
+// Eigenvalues k0 .. k1-1 (k-th largest) of T (d, e2 = e^2) into lam[k] by
+// multisection: tpe threads (contiguous lanes) per eigenvalue count at the
+// tpe interior points that cut the interval into tpe + 1 parts; the first
+// point with more than m eigenvalues below it bounds the next interval.
+// Every thread of the workgroup must call it.
+#ifndef TRI_BISECT_LANES
+#define TRI_BISECT_LANES 768
+#endif
+__device__ __forceinline__ void tri_bisect(const double* d, const double* e2, int n, const TriBounds& tb, int k0,
+                                           int k1, double* lam) {
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int cnt = k1 - k0;
+    const double eps = 2.220446049250313e-16;
+    int tpe = 1;  // tpe * cnt <= lanes: one eigenvalue per group of lanes
+    const int lanes = cnt < n ? nth : min(nth, TRI_BISECT_LANES);
+    while (tpe < 32 && tpe * 2 * cnt <= lanes) tpe *= 2;
+    const int sub = lane % tpe, k = k0 + tid / tpe;
+    const unsigned long long gmask = (1ull << tpe) - 1ull;
+    const bool act = k < k1;
+    const int m = n - 1 - (act ? k : 0);  // k-th largest = ascending index n - 1 - k
+    double lo = tb.gl, hi = tb.gu;
+    for (int it = 0; it < 200; ++it) {
+        const double tol = fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), eps * tb.tnorm) + tb.pivmin;
+        const bool more = act && hi - lo > tol;
+        if (!__any(more)) break;  // wave-uniform: every ballot sees whole groups
+        const double h = (hi - lo) / (double)(tpe + 1);
+        bool gt = false;
+        if (more) gt = sturm_count(d, e2, n, lo + h * (double)(sub + 1), tb.pivmin) > m;
+        const unsigned long long bal = (__ballot(gt) >> (lane - sub)) & gmask;
+        if (more) {
+            const int sidx = bal ? __ffsll((long long)bal) - 1 : tpe;  // part holding eigenvalue m
+            const double nhi = (sidx < tpe) ? lo + h * (double)(sidx + 1) : hi;
+            const double nlo = (sidx > 0) ? lo + h * (double)sidx : lo;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (act && sub == 0) lam[k] = 0.5 * (lo + hi);
+}
+
 // Eigenpairs of the tridiagonal T left by the reduction (diagonal in row 0
 // of U, off-diagonal in row 1) into lam (descending) and U (eigenvectors of
 // T; the back-transformation applies Q).  On clusters it cannot separate,
@@ -626,7 +688,7 @@ __device__ __forceinline__ void tri_reduce_blk_body(const double* Ain, int ldin,
 // these; Dm[0] = 1 then tells the back-transformation to skip).
 // Dm: n x n global scratch.
 __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n, double* W, double* Dm, double* U,
-                                             int lu, double* lam, int* info) {
+                                             int lu, double* lam, int* info, int have_lam) {
     __shared__ TriShared S;
     const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
     for (int i = tid; i < n; i += nth) {
@@ -636,55 +698,13 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
     if (tid == 0) S.flag = 0;
     __syncthreads();
 
-    // ---- 2. eigenvalues by bisection
-    double emax2 = 0.0;
-    for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, S.e[i] * S.e[i]);
+    // ---- 2. eigenvalues by bisection (unless computed already)
     double* e2 = S.w;
     for (int i = tid; i + 1 < n; i += nth) e2[i] = S.e[i] * S.e[i];
-    double gl = 1e308, gu = -1e308;
-    for (int i = 0; i < n; ++i) {
-        const double r = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(S.e[i]) : 0.0);
-        gl = fmin(gl, S.d[i] - r);
-        gu = fmax(gu, S.d[i] + r);
-    }
-    const double tnorm = fmax(fabs(gl), fabs(gu));
-    const double eps = 2.220446049250313e-16;
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-    gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
-    gu += 2.0 * eps * tnorm + 2.0 * pivmin;
+    TriBounds tb = tri_bounds(S.d, S.e, n);
+    const double tnorm = tb.tnorm, pivmin = tb.pivmin;
     __syncthreads();
-    // multisection: tpe threads (contiguous lanes) per eigenvalue count at the
-    // tpe interior points that cut the interval into tpe + 1 parts; the first
-    // point with more than m eigenvalues below it bounds the next interval
-#ifndef TRI_BISECT_LANES
-#define TRI_BISECT_LANES 768
-#endif
-    int tpe = 1;  // tpe * n <= TRI_BISECT_LANES: one eigenvalue per group of lanes
-    while (tpe < 32 && tpe * 2 * n <= min(nth, TRI_BISECT_LANES)) tpe *= 2;
-    {
-        const int sub = lane % tpe, k = tid / tpe;
-        const unsigned long long gmask = (1ull << tpe) - 1ull;
-        const bool act = k < n;
-        const int m = n - 1 - (act ? k : 0);  // k-th largest = ascending index n - 1 - k
-        double lo = gl, hi = gu;
-        for (int it = 0; it < 200; ++it) {
-            const double tol = fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), eps * tnorm) + pivmin;
-            const bool more = act && hi - lo > tol;
-            if (!__any(more)) break;  // wave-uniform: every ballot sees whole groups
-            const double h = (hi - lo) / (double)(tpe + 1);
-            bool gt = false;
-            if (more) gt = sturm_count(S.d, e2, n, lo + h * (double)(sub + 1), pivmin) > m;
-            const unsigned long long bal = (__ballot(gt) >> (lane - sub)) & gmask;
-            if (more) {
-                const int sidx = bal ? __ffsll((long long)bal) - 1 : tpe;  // part holding eigenvalue m
-                const double nhi = (sidx < tpe) ? lo + h * (double)(sidx + 1) : hi;
-                const double nlo = (sidx > 0) ? lo + h * (double)sidx : lo;
-                lo = nlo;
-                hi = nhi;
-            }
-        }
-        if (act && sub == 0) lam[k] = 0.5 * (lo + hi);
-    }
+    if (!have_lam) tri_bisect(S.d, e2, n, tb, 0, n, lam);
     __syncthreads();
     // ---- 3. eigenvectors of T, one per thread: column k of U
     if (tnorm > 0.0) {
@@ -879,26 +899,50 @@ __device__ __forceinline__ void tri_back_body(const double* W, const double* Dm,
     const bool rnd = t.kind == T_SHRINK_RAND;                               \
     (void)rnd;
 
-__global__ __launch_bounds__(1024) void k_tri_reduce(const Task* tasks, int lds_doubles, int blk_ok) {
+// Tasks of order xmin..512 take the multi-workgroup reduction (k_trix.hip).
+__device__ __forceinline__ bool tri_by_x(int n, int xmin) { return n >= xmin && n <= TRI_NMAX; }
+
+__global__ __launch_bounds__(1024) void k_tri_reduce(const Task* tasks, int lds_doubles, int blk_ok, int xmin) {
     extern __shared__ double lds[];
     TRI_TASK_PROLOGUE
-    if (tri_blocked(n, blk_ok)) return;
+    if (tri_blocked(n, blk_ok) || tri_by_x(n, xmin)) return;
     tri_reduce_unblk_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U],
                           s->sld[S_U], lds, lds_doubles);
 }
 
-__global__ __launch_bounds__(1024) void k_tri_reduce_blk(const Task* tasks) {
+__global__ __launch_bounds__(1024) void k_tri_reduce_blk(const Task* tasks, int xmin) {
     extern __shared__ double lds[];
     TRI_TASK_PROLOGUE
-    if (!tri_blocked(n, 1)) return;
+    if (!tri_blocked(n, 1) || tri_by_x(n, xmin)) return;
     tri_reduce_blk_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U],
                         s->sld[S_U], lds);
 }
 
-__global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks) {
+// Eigenvalues of the tasks' T split over the workgroups of blockIdx.x
+// (n / gridDim.x each, so several compute units bisect one problem).
+__global__ __launch_bounds__(1024) void k_tri_eigval(const Task* tasks) {
+    __shared__ double d[TRI_NMAX], e[TRI_NMAX], e2[TRI_NMAX];
+    TRI_TASK_PROLOGUE
+    const int G = gridDim.x, per = (n + G - 1) / G, k0 = blockIdx.x * per, k1 = min(n, k0 + per);
+    if (k0 >= k1) return;
+    const double* U = s->slot[S_U];
+    const int lu = s->sld[S_U];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        d[i] = U[i];
+        if (i + 1 < n) {
+            e[i] = U[lu + i];
+            e2[i] = e[i] * e[i];
+        }
+    }
+    __syncthreads();
+    const TriBounds tb = tri_bounds(d, e, n);
+    tri_bisect(d, e2, n, tb, k0, k1, s->slot[S_LAM]);
+}
+
+__global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks, int have_lam) {
     TRI_TASK_PROLOGUE
     tri_eig_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_EV], s->slot[S_U],
-                 s->sld[S_U], s->slot[S_LAM], s->info);
+                 s->sld[S_U], s->slot[S_LAM], s->info, have_lam);
 }
 
 __global__ __launch_bounds__(64) void k_tri_back(const Task* tasks) {
@@ -925,7 +969,7 @@ __global__ __launch_bounds__(1024) void k_tri_reduce_blk_desc(DescArg<SmallDesc>
 __global__ __launch_bounds__(1024) void k_tri_eig_desc(DescArg<SmallDesc> ds) {
     const SmallDesc q = ds.get();
     if (q.n < 1) return;
-    tri_eig_body(q.A, q.lda, q.n, q.work, q.work2, q.X, q.ldx, q.lam, q.info);
+    tri_eig_body(q.A, q.lda, q.n, q.work, q.work2, q.X, q.ldx, q.lam, q.info, 0);
 }
 
 __global__ __launch_bounds__(64) void k_tri_back_desc(DescArg<SmallDesc> ds) {
@@ -982,24 +1026,49 @@ static int back_lds(int max_n) {
 hipError_t launch_tri_reduce(const Task* tasks, int count, int min_n, int max_n, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;
-    const bool any_blk = g_blk_ok && max_n > 128 && min_n <= 256;
-    const bool any_unblk = !g_blk_ok || min_n <= 128 || max_n > 256;
+    const int xmin = trix_min_n();
+    // sizes outside the multi-workgroup range
+    const bool below_x = min_n < xmin, above_x = max_n > TRI_NMAX;
+    const int lo_max = std::min(max_n, xmin - 1);  // largest size the one-workgroup kernels may see
+    const bool any_blk = g_blk_ok && below_x && lo_max > 128 && min_n <= 256;
+    const bool any_unblk = (below_x && (!g_blk_ok || min_n <= 128 || lo_max > 256)) || above_x;
+    const bool any_x = max_n >= xmin && min_n <= TRI_NMAX;
     hipError_t e = hipSuccess;
     if (any_unblk) {
         hipLaunchKernelGGL(k_tri_reduce, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st,
-                           tasks, dbl, g_blk_ok);
+                           tasks, dbl, g_blk_ok, xmin);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (any_blk) {
         hipLaunchKernelGGL(k_tri_reduce_blk, dim3(1, 1, (unsigned)count), dim3(1024),
-                           sizeof(double) * (size_t)tri_blk_lds(std::min(max_n, 256)), st, tasks);
-        e = hipGetLastError();
+                           sizeof(double) * (size_t)tri_blk_lds(std::min(lo_max, 256)), st, tasks, xmin);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    if (any_x) e = launch_tri_reduce_x(tasks, count, max_n, st);
     return e;
 }
 
-hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks);
+// Workgroups that bisect one problem's eigenvalues: n / 8 (8 eigenvalues,
+// 32 lanes each, per workgroup), at most 64; SK_TRI_EIGVAL_GROUPS overrides
+// (1 leaves the bisection inside the eigenpair kernel).
+static int eigval_groups(int max_n) {
+    static int v = -2;
+    if (v == -2) {
+        const char* e = getenv("SK_TRI_EIGVAL_GROUPS");
+        v = e ? std::max(1, std::min(64, atoi(e))) : -1;
+    }
+    if (v > 0) return v;
+    return std::max(1, std::min(64, max_n / 8));
+}
+
+hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
+    const int G = eigval_groups(max_n);
+    if (G > 1) {
+        hipLaunchKernelGGL(k_tri_eigval, dim3((unsigned)G, 1, (unsigned)count), dim3(1024), 0, st, tasks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks, G > 1 ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -1,0 +1,307 @@
+// k_trix.hip -- Householder tridiagonalisation of one symmetric eigen-problem
+// (the k x k Rayleigh-Ritz matrix of Algorithm "Simultaneous Iteration", or
+// the 2 ell x 2 ell buffer Gram of the exact FD shrink, Sec. 2.3) by a group
+// of P workgroups on one XCD.
+//
+// The rows of A are dealt out cyclically (row i to member i mod P, at most
+// XR rows each) and stay in LDS for the whole reduction.  Column j's
+// reflector needs row j of the current matrix, A22 v over every row, and the
+// scalar p.v; each member computes its rows' part of A22 v, and one exchange
+// per column (through L2) gives every member all of p, the partial dots and
+// the not-yet-updated row j + 1.  Every member then derives w, applies the
+// rank-2 update to its own rows and forms row j + 1 of the updated matrix
+// itself, so the next reflector starts without another exchange.  All
+// members run the same arithmetic on the same inputs, so they agree bit for
+// bit; every sum has a fixed order (results repeat exactly).
+//
+// Output as the one-workgroup reductions: W row j holds v_j beyond the
+// super-diagonal and W[j][j] = tau_j (H_j = I - tau_j v_j v_j^T, v_j[j+1] = 1),
+// U row 0 the diagonal of T and U row 1 its off-diagonal.
+//
+// Exchange words: each member publishes (epoch << 32 | step) in its flag
+// after its step data; the epoch grows with every launch, so flags left by
+// earlier launches never satisfy a wait.  A wait gives up after a bounded
+// number of polls and counts the failure in info[3] (the solve then reports
+// SK_EDEVICE); no wait can hang.
+#include <atomic>
+
+#include "sk_device.h"
+#include "sk_kernels.h"
+#include "sk_xwg.h"
+
+namespace sk {
+
+constexpr int XR = 16;          // rows per member
+constexpr int XTHREADS = 256;   // 16 rows x 16 lanes
+constexpr int XNMAX = 512;
+constexpr int XSLOT = 2 * XNMAX + 32;  // p, row, partial dots
+
+__device__ __forceinline__ double x_sum16(double x) {
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    x += __shfl_xor(x, 4, 64);
+    x += __shfl_xor(x, 8, 64);
+    return x;
+}
+
+__device__ __forceinline__ double x_wave_sum(double x) {
+    x = x_sum16(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
+// The member group of workgroup b.  Workgroups are dealt to the 8 XCDs round
+// robin, so with `local` the P members of a problem share one XCD (b = xcd +
+// 8 (P g + m), m < P); otherwise they are consecutive (b = P problem + m) and
+// spread over the XCDs.
+struct XMap {
+    int problem, member;
+};
+__device__ __forceinline__ XMap x_map(int P, int local) {
+    const int b = blockIdx.x;
+    if (!local) return {b / P, b % P};
+    const int xcd = b & 7, slot = b >> 3;
+    return {(slot / P) * 8 + xcd, slot % P};
+}
+
+__host__ __device__ __forceinline__ int x_members(int n) { return (n + XR - 1) / XR; }
+
+__device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, double* __restrict__ Wr,
+                          double* __restrict__ U, int lu, double* xch, uint64_t* flags, int* info, uint64_t epoch,
+                          int member) {
+    extern __shared__ double lds[];
+    const int P = x_members(n);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid >> 4, part = tid & 15;  // row slot and lane within it
+    double* Al = lds;                          // [XR][n] this member's rows
+    double* v = lds + XR * n;                  // reflector (global column index)
+    double* pb = v + n;                        // p of every row, on arrival
+    double* rb = pb + n;                       // shipped row j + 1, on arrival
+    double* xrow = rb + n;                     // row j of the current matrix
+    __shared__ double red[4], pl[XR], pvw[4], pvs_s;
+    __shared__ int bad;
+    const int my_i = member + P * r;           // this thread's row
+    const bool has_row = my_i < n;
+    for (int e = tid; e < XR * n; e += XTHREADS) {
+        const int rr = e / n, c = e - rr * n, i = member + P * rr;
+        Al[e] = i < n ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
+    }
+    double s2 = 0.0;
+    for (int c = tid; c < n; c += XTHREADS) {
+        const double x = 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]);
+        xrow[c] = x;
+        if (c >= 2) s2 = fma(x, x, s2);
+    }
+    s2 = x_wave_sum(s2);
+    if (lane == 0) red[wave] = s2;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j + 2 < n; ++j) {
+        // (a) reflector of column j from row j (identical in every member);
+        // red holds |row j beyond j + 1|^2
+        const double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
+        const double alpha = xrow[j + 1];
+        double beta = alpha, tau = 0.0, scal = 0.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        for (int c = j + 1 + tid; c < n; c += XTHREADS) v[c] = (c == j + 1) ? 1.0 : xrow[c] * scal;
+        if (member == 0) {
+            if (tid == 0) {
+                U[j] = xrow[j];
+                U[lu + j] = beta;
+                Wr[(int64_t)j * n + j] = tau;
+            }
+            for (int c = j + 2 + tid; c < n; c += XTHREADS) Wr[(int64_t)j * n + c] = xrow[c] * scal;
+        }
+        __syncthreads();
+        // (b) p_i = tau (A22 v)_i for this member's rows i > j
+        const bool live = has_row && my_i > j;
+        double acc = 0.0;
+        if (live) {
+            const double* ar = Al + r * n;
+            for (int c = j + 1 + part; c < n; c += 16) acc = fma(ar[c], v[c], acc);
+        }
+        acc = x_sum16(acc);
+        const double pi = tau * acc;
+        if (part == 0) pl[r] = live ? pi : 0.0;
+        double pv = (live && part == 0) ? pi * v[my_i] : 0.0;
+        pv = x_wave_sum(pv);
+        if (lane == 0) pvw[wave] = pv;
+        __syncthreads();
+        // (c) exchange through L2, wave 0 only: this member's p and partial
+        // dot (and row j + 1 as it stands if it owns it), one release, the
+        // flag; then every member's data after one acquire
+        if (wave == 0) {
+            double* slot = xch + (j & 1) * XSLOT;
+            if (lane < XR) {
+                const int i = member + P * lane;
+                if (i > j && i < n) slot[i] = pl[lane];
+            }
+            if (lane == 0) slot[2 * XNMAX + member] = (pvw[0] + pvw[1]) + (pvw[2] + pvw[3]);
+            if (member == (j + 1) % P) {
+                const double* ar = Al + ((j + 1) / P) * n;
+                for (int c = j + 1 + lane; c < n; c += 64) slot[XNMAX + c] = ar[c];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint64_t target = (epoch << 32) | (uint64_t)(j + 1);
+            if (lane == 0) __hip_atomic_store(flags + member, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned polls = 0;
+            while (true) {
+                const uint64_t f =
+                    lane < P ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : target;
+                if (__all(f >= target)) break;
+                if (++polls > (1u << 22)) {
+                    if (lane == 0) bad = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // every load issued before any is used
+            double pvv = lane < P ? slot[2 * XNMAX + lane] : 0.0;
+            constexpr int LPL = XNMAX / 64;
+            double pr[LPL], rr_[LPL];
+#pragma unroll
+            for (int u = 0; u < LPL; ++u) {
+                const int c = j + 1 + lane + 64 * u;
+                pr[u] = c < n ? slot[c] : 0.0;
+                rr_[u] = c < n ? slot[XNMAX + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < LPL; ++u) {
+                const int c = j + 1 + lane + 64 * u;
+                if (c < n) {
+                    pb[c] = pr[u];
+                    rb[c] = rr_[u];
+                }
+            }
+            // partial dots in member order (the same sum in every member)
+            double sum = 0.0;
+            for (int m = 0; m < P; ++m) sum += __shfl(pvv, m, 64);
+            if (lane == 0) pvs_s = sum;
+        }
+        __syncthreads();
+        if (bad) break;
+        // (d) w = p - K v on the fly; rank-2 update of this member's rows and
+        // of the shipped row j + 1 (the next pivot row, with its norm)
+        const double K = 0.5 * tau * pvs_s;
+        const double w1 = fma(-K, v[j + 1], pb[j + 1]);
+        if (live) {
+            double* ar = Al + r * n;
+            const double vi = v[my_i], wi = fma(-K, vi, pb[my_i]);
+            for (int c = j + 1 + part; c < n; c += 16) {
+                const double wc = fma(-K, v[c], pb[c]);
+                ar[c] = fma(-vi, wc, fma(-wi, v[c], ar[c]));
+            }
+        }
+        s2 = 0.0;
+        for (int c = j + 1 + tid; c < n; c += XTHREADS) {
+            const double wc = fma(-K, v[c], pb[c]);
+            const double x = fma(-1.0, wc, fma(-w1, v[c], rb[c]));
+            xrow[c] = x;
+            if (c >= j + 3) s2 = fma(x, x, s2);
+        }
+        s2 = x_wave_sum(s2);
+        if (lane == 0) red[wave] = s2;
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0 && member == 0) atomicAdd(&info[3], 1);
+        return;
+    }
+    // last two rows: T's trailing 2 x 2 block
+    if (n >= 2) {
+        if (member == 0 && tid == 0) {
+            U[n - 2] = xrow[n - 2];
+            U[lu + n - 2] = xrow[n - 1];
+            Wr[(int64_t)(n - 2) * n + n - 2] = 0.0;
+            Wr[(int64_t)(n - 1) * n + n - 1] = 0.0;
+        }
+        // A[n-1][n-1] after every update: its owner holds it
+        if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * n + n - 1];
+    } else if (member == 0 && tid == 0) {
+        U[0] = Ain[0];
+        Wr[0] = 0.0;
+    }
+}
+
+// Task form: eigen-problems of shrink / query tasks that the tridiagonal
+// solver takes and whose size is in [xmin, XNMAX].
+__global__ __launch_bounds__(XTHREADS) void k_tri_reduce_x(const Task* tasks, int count, int P, int xmin,
+                                                            uint64_t epoch, int local) {
+    const XMap mp = x_map(P, local);
+    if (mp.problem >= count) return;
+    const Task& t = tasks[mp.problem];
+    if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
+    const int n = eig_n(t);
+    if (n < xmin || n > XNMAX || mp.member >= x_members(n)) return;
+    const SkDev* s = t.s;
+    const bool rnd = t.kind == T_SHRINK_RAND;
+    trix_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U], s->sld[S_U],
+              s->slot[S_EV], s->xflags, s->info, epoch, mp.member);
+}
+
+static std::atomic<uint64_t> g_xwg_epoch{0};
+uint64_t xwg_next_epoch() { return ++g_xwg_epoch; }
+
+// Members of a problem on one XCD (SK_TRIX_LOCAL=1) or spread (0).
+static int trix_local() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_TRIX_LOCAL");
+        v = e ? atoi(e) : 0;
+    }
+    return v;
+}
+
+int trix_min_n() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_TRIX_MIN_N");
+        v = e ? atoi(e) : 160;
+        if (v < 8) v = 8;
+    }
+    return v;
+}
+
+// Every task with xmin <= n <= XNMAX (that the tridiagonal solver takes) by
+// cooperative launches of 8 P ceil(count / 8) workgroups, P = members of the
+// largest problem (smaller problems leave their surplus members idle); as
+// many tasks per launch as can be resident at once.
+hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st) {
+    const int nmax = std::min(max_n, XNMAX);
+    int P = x_members(nmax);
+    const size_t lds = sizeof(double) * (size_t)(XR + 4) * (size_t)nmax;
+    static int per_cu = -1, cus = 0;
+    if (per_cu < 0) {
+        int dev = 0;
+        if (hipFuncSetAttribute((const void*)k_tri_reduce_x, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * (XR + 4) * XNMAX)) != hipSuccess ||
+            hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, XTHREADS,
+                                                         sizeof(double) * (XR + 4) * XNMAX) != hipSuccess ||
+            per_cu < 1)
+            return hipErrorInvalidConfiguration;
+    }
+    // resident workgroups at the largest LDS size; 8 P per group of 8 tasks
+    const int chunk = std::max(8, ((per_cu * cus) / (8 * P)) * 8);
+    int xmin = trix_min_n(), local = trix_local();
+    for (int off = 0; off < count; off += chunk) {
+        const Task* tl = tasks + off;
+        int cnt = std::min(chunk, count - off);
+        const int groups = (cnt + 7) / 8;
+        uint64_t epoch = xwg_next_epoch();
+        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&P, (void*)&xmin, (void*)&epoch, (void*)&local};
+        const unsigned grid = local ? (unsigned)(8 * P * groups) : (unsigned)(P * cnt);
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_tri_reduce_x, dim3(grid), dim3(XTHREADS), args,
+                                                  (unsigned)lds, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace sk

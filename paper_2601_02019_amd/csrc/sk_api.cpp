@@ -26,10 +26,11 @@ std::atomic<int64_t> g_in_use{0};
 std::atomic<int64_t> g_budget{0};
 
 // Problem sizes from which one task alone runs the cooperative solvers:
-// CholeskyQR from k = 129 (SK_COOP_MIN_N), the eigen-solve from n = 257
-// (SK_COOP_EIG_MIN_N; below it the one-workgroup tridiagonal solver is as
-// fast and leaves the other compute units to the rest of the batch; with
-// SK_EIG_SOLVER=jacobi the one-workgroup Jacobi solver stops at 128).
+// CholeskyQR from k = 129 (SK_COOP_MIN_N), the eigen-solve from n = 513
+// (SK_COOP_EIG_MIN_N; up to 512 the tridiagonal solver, whose reduction
+// runs on several workgroups from n = 160, is faster than the block Jacobi
+// method: 2.7 vs 9.4 ms per 512 x 512 solve; with SK_EIG_SOLVER=jacobi the
+// one-workgroup Jacobi solver stops at 128).
 static int coop_min_n() {
     static int v = -1;
     if (v < 0) {
@@ -41,11 +42,22 @@ static int coop_min_n() {
 
 bool eig_solver_jacobi();
 
+// CholeskyQR of k >= SK_CHOLX_MIN_K runs on ceil(k / 16) workgroups with one
+// exchange per 16 columns (k_cholx.hip); off unless the variable is set.
+static int cholx_min_k() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_CHOLX_MIN_K");
+        v = e ? atoi(e) : (1 << 30);
+    }
+    return v;
+}
+
 static int coop_eig_min_n() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_COOP_EIG_MIN_N");
-        v = e ? atoi(e) : (eig_solver_jacobi() ? 129 : 257);
+        v = e ? atoi(e) : (eig_solver_jacobi() ? 129 : 513);
     }
     return v;
 }
@@ -69,7 +81,8 @@ static void mark_coop(Task& t, const sketch_s* h) {
     const int n = (t.kind == T_SHRINK_RAND) ? h->k : t.m;
     t.flags = 0;
     if (n >= coop_eig_min_n()) t.flags |= TF_COOP_EIG;
-    if (t.kind == T_SHRINK_RAND && h->k >= coop_min_n()) t.flags |= TF_COOP_CHOL;
+    if (t.kind == T_SHRINK_RAND && h->k >= cholx_min_k() && h->k <= 512) t.flags |= TF_X_CHOL;
+    else if (t.kind == T_SHRINK_RAND && h->k >= coop_min_n()) t.flags |= TF_COOP_CHOL;
 }
 
 // Split-K plan: about 512 workgroups in total for a launch.
@@ -143,6 +156,12 @@ static sk_status build_device_state(sketch_t h) {
     HIP_TRY(h, h->dalloc(&info, 64));
     HIP_TRY(h, h->dzero(info, 64));
     s.info = (int32_t*)info;
+    {
+        void* p = nullptr;
+        HIP_TRY(h, h->dalloc(&p, 64 * sizeof(uint64_t)));
+        HIP_TRY(h, h->dzero(p, 64 * sizeof(uint64_t)));
+        s.xflags = (uint64_t*)p;
+    }
     HIP_TRY(h, h->dalloc((void**)&h->dev, sizeof(SkDev)));
     if (!h->dry) HIP_TRY(h, hipMemcpy(h->dev, &s, sizeof(SkDev), hipMemcpyHostToDevice));
     return SK_OK;
@@ -163,6 +182,7 @@ struct Group {
     int kind = 0;
     // tasks (offsets in the group) whose eigen-solve / CholeskyQR is cooperative
     std::vector<int> coop_eig, coop_chol;
+    int x_chol_k = 0;             // largest k of the tasks on the multi-workgroup CholeskyQR
     std::vector<sketch_t> own;
     std::vector<int> ns;          // eigen-problem size of each task
     bool any_plain_eig = false, any_plain_chol = false;
@@ -199,7 +219,8 @@ Group describe(const std::vector<sketch_t>& owners, const std::vector<Task>& tas
         g.ns.push_back(n);
         if (t.flags & TF_COOP_EIG) g.coop_eig.push_back((int)(i - first));
         else g.any_plain_eig = true;
-        if (t.flags & TF_COOP_CHOL) g.coop_chol.push_back((int)(i - first));
+        if (t.flags & TF_X_CHOL) g.x_chol_k = std::max(g.x_chol_k, h->k);
+        else if (t.flags & TF_COOP_CHOL) g.coop_chol.push_back((int)(i - first));
         else if (t.kind == T_SHRINK_RAND) g.any_plain_chol = true;
     }
     return g;
@@ -234,6 +255,10 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
         if ((e = launch_cholqr_coop_tasks(t, g.coop_chol.data(), (int)g.coop_chol.size(), m, k, sy, sq, passes, st)))
             return e;
     }
+    if (g.x_chol_k > 0) {
+        g_stage = "cholqr_x";
+        if ((e = launch_cholqr_x(t, g.count, g.x_chol_k, sy, sq, passes, st))) return e;
+    }
     return hipSuccess;
 }
 
@@ -253,7 +278,7 @@ hipError_t eig(const Task* t, const Group& g, hipStream_t st) {
             if (e == hipSuccess) {
                 StageScope sc(g.prof, ST_EIG, st);
                 g_stage = "tridiagonal eig";
-                e = launch_tri_eig(t, g.count, st);
+                e = launch_tri_eig(t, g.count, g.max_n, st);
             }
             if (e == hipSuccess) {
                 StageScope sc(g.prof, ST_EIG_BACK, st);
@@ -398,7 +423,7 @@ static sk_status validate_config(const sketch_config* cfg) {
         return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
     if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
         return fail(SK_EINVAL, "sketch_create: bad shrink");
-    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW)
+    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW && cfg->kind != SK_ATTP)
         return fail(SK_EINVAL, "sketch_create: bad kind");
     if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
         return fail(SK_EINVAL, "sketch_create: bad q or oversample");
@@ -499,7 +524,7 @@ sk_status sketch_create(const sketch_config* cfg, sketch_t* out) {
         h->own_stream = true;
     }
     sk_status rc;
-    if (cfg->kind == SK_WINDOW) rc = window_create(h);
+    if (cfg->kind == SK_WINDOW || cfg->kind == SK_ATTP) rc = window_create(h);
     else rc = build_device_state(h);
     const int64_t budget = g_budget.load();
     if (rc == SK_OK && budget > 0 && g_in_use.load() + h->bytes > budget) {
@@ -610,10 +635,11 @@ static sk_status query_to_qout(sketch_t h) {
 }
 
 static sk_status check_info(sketch_t h) {
-    int32_t info[2] = {0, 0};
+    int32_t info[4] = {0, 0, 0, 0};
     const int32_t* dinfo = h->win ? window_info_ptr(h) : h->host.info;
     HIP_TRY(h, hipMemcpy(info, dinfo, sizeof(info), hipMemcpyDeviceToHost));
     if (info[0] != 0) return h->device_fail("eigen-solver did not converge");
+    if (info[3] != 0) return h->device_fail("multi-workgroup reduction: exchange wait timed out");
     if (h->coop_ctrl) {
         unsigned bar[2] = {0, 0};
         HIP_TRY(h, hipMemcpy(bar, h->coop_ctrl + 8, sizeof(bar), hipMemcpyDeviceToHost));
@@ -621,6 +647,10 @@ static sk_status check_info(sketch_t h) {
     }
     return SK_OK;
 }
+
+// Copies the FP64 ell x ld result src to B_out (dtype, host or device) and
+// waits for it.
+static sk_status query_out(sketch_t h, const double* src, void* B_out, int32_t dtype, int32_t on_device);
 
 sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device) {
     sk_status rc = check_handle(h, "sketch_query");
@@ -636,6 +666,22 @@ sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device
         src = h->host.slot[S_QOUT];
     }
     if (rc) return rc;
+    return query_out(h, src, B_out, dtype, on_device);
+}
+
+sk_status sketch_query_at(sketch_t h, int64_t t, void* B_out, int32_t dtype, int32_t on_device) {
+    sk_status rc = check_handle(h, "sketch_query_at");
+    if (rc) return rc;
+    if (!B_out) return fail(SK_EINVAL, "sketch_query_at: B_out is NULL");
+    if (dtype != SK_F64 && dtype != SK_F32) return fail(SK_EINVAL, "sketch_query_at: dtype must be F64 or F32");
+    if (!h->win || h->cfg.kind != SK_ATTP) return fail(SK_EUNSUPPORTED, "sketch_query_at: not an ATTP sketch");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const double* src = nullptr;
+    if ((rc = window_query_at(h, t, &src))) return rc;
+    return query_out(h, src, B_out, dtype, on_device);
+}
+
+static sk_status query_out(sketch_t h, const double* src, void* B_out, int32_t dtype, int32_t on_device) {
     const size_t es = (size_t)dtype_size(dtype);
     const size_t nb = es * (size_t)h->ell * (size_t)h->d;
     if (on_device) {
@@ -652,7 +698,7 @@ sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device
 sk_status window_advance(sketch_t h, int64_t t_now) {
     sk_status rc = check_handle(h, "window_advance");
     if (rc) return rc;
-    if (!h->win) return fail(SK_EUNSUPPORTED, "window_advance: not a window sketch");
+    if (!h->win || h->cfg.kind != SK_WINDOW) return fail(SK_EUNSUPPORTED, "window_advance: not a window sketch");
     return window_advance_impl(h, t_now);
 }
 

@@ -50,6 +50,7 @@ struct SkDev {
     uint64_t seed, stream;
     double* coop;              // cooperative-solver scratch (COOP_* layout)
     int32_t* coop_ctrl;        // [0..1] rotation counters, [8..9] grid barrier
+    uint64_t* xflags;          // 64 exchange flags of the multi-workgroup reduction
 };
 
 // Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
@@ -59,7 +60,7 @@ constexpr int64_t COOP_UBUF = 0, COOP_PART = 16 * 1024, COOP_LINV = COOP_PART + 
                   COOP_DOUBLES = COOP_STATS + 16;
 
 
-enum TaskFlags : int32_t { TF_COOP_EIG = 1, TF_COOP_CHOL = 2 };
+enum TaskFlags : int32_t { TF_COOP_EIG = 1, TF_COOP_CHOL = 2, TF_X_CHOL = 4 };
 
 enum TaskKind : int32_t { T_INGEST = 0, T_SHRINK_EXACT = 1, T_SHRINK_RAND = 2, T_QUERY = 3 };
 
@@ -71,7 +72,7 @@ struct Task {
     int32_t row0;              // ingest: first destination row
     int32_t nrows;             // ingest: rows to copy
     int32_t src_dtype;         // ingest: dtype of src
-    int32_t flags;             // TF_COOP_EIG / TF_COOP_CHOL: solved by the cooperative kernels
+    int32_t flags;             // TF_*: stages solved by the cooperative / multi-workgroup kernels
     int32_t pad0;
     int64_t shrink_idx;        // Philox counter word of this shrink
     int64_t src_ld;            // ingest: leading dimension of src

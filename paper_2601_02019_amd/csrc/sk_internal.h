@@ -218,6 +218,17 @@ struct sketch_s {
         return e;
     }
     hipError_t dzero(void* p, size_t n) { return dry ? hipSuccess : hipMemset(p, 0, n); }
+    // A grown allocation takes the place of `old` (which is freed); the
+    // sketch's byte count grows by `extra`.
+    void replace_alloc(void* old, void* now, size_t extra) {
+        for (void*& p : allocs)
+            if (p == old) {
+                (void)hipFree(old);
+                p = now;
+            }
+        bytes += (int64_t)extra;
+        if (counted) g_in_use += (int64_t)extra;
+    }
     hipError_t ensure_stage(size_t n) {
         if (n <= stage_bytes) return hipSuccess;
         hipError_t e = hipStreamSynchronize(stream);

@@ -58,10 +58,16 @@ hipError_t launch_shrink_rows(const double* V, int ldv, const double* lam, int n
 // The tridiagonal solver in three launches: the reduction (tasks' sizes in
 // [min_n, max_n]), the eigenpairs of T, the back-transformation.
 hipError_t launch_tri_reduce(const Task* tasks, int count, int min_n, int max_n, hipStream_t st);
-hipError_t launch_tri_eig(const Task* tasks, int count, hipStream_t st);
+hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st);
 hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t st);
 hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st);
 int tri_lds_doubles();
+// Multi-workgroup reduction (one group of workgroups on one XCD per problem)
+// of the tasks of order trix_min_n() .. 512.
+hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st);
+int trix_min_n();
+// Multi-workgroup CholeskyQR (passes 1 or 2) of the tasks flagged TF_X_CHOL.
+hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int sy, int sq, int passes, hipStream_t st);
 // Multi-task cooperative solvers: tasks[idx[i]] for i < count, each by its
 // own group of workgroups (several launches when residency requires).
 hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st);

@@ -56,6 +56,11 @@ struct WinLevel {
 }  // namespace
 
 struct WindowState {
+    // ATTP (Algorithm "ATTP Sketch using AeroSketch"): one level whose
+    // threshold follows the stream (theta_i = eps ||A_i||_F^2), no expiry, no
+    // raw rows, snapshots kept for ever in a growing store
+    bool attp = false;
+    double fro2 = 0.0;
     int L = 0, d = 0, ell = 0, q = 1, kmax = 0, steps = 0;
     int64_t N = 0, T = 0, ld = 0;
     uint64_t seed = 0, stream = 0;
@@ -252,6 +257,24 @@ static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
     const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
     const int ldc = (int)l.sub->ld;
     double* C = (double*)level_C(l);
+    if (w->attp && l.ptail + xi > l.pcap) {
+        // append-only store: double it (the old vectors are copied over)
+        int64_t ncap = std::max<int64_t>(2 * l.pcap, l.ptail + xi);
+        double *nZ = nullptr, *nW = nullptr;
+        W_TRY(hipStreamSynchronize(h->stream));
+        W_TRY(hipMalloc((void**)&nZ, sizeof(double) * (size_t)ncap * w->ld));
+        W_TRY(hipMalloc((void**)&nW, sizeof(double) * (size_t)ncap * w->ld));
+        W_TRY(hipMemcpyAsync(nZ, l.Zp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
+                             h->stream));
+        W_TRY(hipMemcpyAsync(nW, l.Wp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
+                             h->stream));
+        W_TRY(hipStreamSynchronize(h->stream));
+        h->replace_alloc(l.Zp, nZ, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
+        h->replace_alloc(l.Wp, nW, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
+        l.Zp = nZ;
+        l.Wp = nW;
+        l.pcap = ncap;
+    }
     if (l.ptail + xi > l.pcap) l.ptail = 0;
     const int64_t slot = l.ptail;
     for (const WinEntry& e : l.q)
@@ -327,14 +350,16 @@ sk_status window_create(sketch_t h) {
     w->stream = cfg.stream_id;
     w->kmax = std::min(cfg.ell, cfg.d);
     w->steps = (int)std::ceil(std::log2((double)cfg.d)) + 1;
-    int L = (int)std::ceil(std::log2(cfg.R));
+    w->attp = cfg.kind == SK_ATTP;
+    int L = w->attp ? 1 : (int)std::ceil(std::log2(cfg.R));
     w->L = L < 1 ? 1 : L;
+    if (w->attp) w->N = INT64_MAX;
     const double eps = 2.0 / cfg.ell;
     const int d = w->d, ell = w->ell, lk = w->kmax, n2 = 2 * ell;
     w->lv.resize((size_t)w->L);
     for (int j = 0; j < w->L; ++j) {
         WinLevel& l = w->lv[(size_t)j];
-        l.theta = std::ldexp(1.0, j) * eps * (double)w->N;
+        l.theta = w->attp ? 0.0 : std::ldexp(1.0, j) * eps * (double)w->N;
         sketch_config sc = cfg;
         sc.kind = SK_PERSISTENT;
         sc.state_dtype = SK_F64;
@@ -345,7 +370,8 @@ sk_status window_create(sketch_t h) {
         sc.use_given_stream = 1;
         sk_status rc = sketch_create(&sc, &l.sub);
         if (rc) return rc;
-        l.pcap = (4 * (int64_t)ell + 4) * lk;
+        // ATTP's store starts small and doubles as snapshots accumulate
+        l.pcap = w->attp ? 4 * (int64_t)lk : (4 * (int64_t)ell + 4) * lk;
         l.rcap = 4 * (int64_t)ell + 2;
         W_TRY(h->dalloc((void**)&l.Zp, sizeof(double) * (size_t)l.pcap * w->ld));
         W_TRY(h->dalloc((void**)&l.Wp, sizeof(double) * (size_t)l.pcap * w->ld));
@@ -442,10 +468,15 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
         tasks.clear();
         pis.clear();
         pj.clear();
+        if (w->attp) {
+            // theta_i = eps ||A_i||_F^2 before the row's update
+            w->fro2 += w->h_norms[e];
+            w->lv[0].theta = (2.0 / w->ell) * w->fro2;
+        }
         for (int j = 0; j < w->L; ++j) {
             WinLevel& l = w->lv[(size_t)j];
-            expire(w, l, i);
-            if (w->h_norms[e] >= l.theta) {
+            if (!w->attp) expire(w, l, i);
+            if (!w->attp && w->h_norms[e] >= l.theta) {
                 const int64_t slot = l.rtail;
                 l.rtail = (l.rtail + 1) % l.rcap;
                 W_TRY(launch_rows_to_f64(row, ld, dtype, l.Rp + slot * w->ld, w->ld, 1, d, h->stream));
@@ -545,26 +576,49 @@ static sk_status eig_d(sketch_t h) {
     return SK_OK;
 }
 
+// The query of Algorithm "AeroSketch: Query" over entries with lb < t <= ub:
+// the window (T - N, T] on the valid level, or for ATTP (0, ub] on its one
+// level, where the residual's Gram enters only at the current time (past
+// residuals are not kept).
+static sk_status query_range(sketch_t h, int64_t lb, int64_t ub, const double** out);
+
 sk_status window_query(sketch_t h, const double** out) {
     WindowState* w = h->win;
+    if (w->attp) return query_range(h, 0, w->T, out);
+    return query_range(h, w->T - w->N, w->T, out);
+}
+
+sk_status window_query_at(sketch_t h, int64_t t, const double** out) {
+    WindowState* w = h->win;
+    if (!w->attp) return fail(SK_EUNSUPPORTED, "sketch_query_at: not an ATTP sketch");
+    if (t < 0 || t > w->T) return fail(SK_EINVAL, "sketch_query_at: t outside [0, current time]");
+    return query_range(h, 0, t, out);
+}
+
+static sk_status query_range(sketch_t h, int64_t lb, int64_t ub, const double** out) {
+    WindowState* w = h->win;
     const int d = w->d, ell = w->ell;
-    const int64_t T = w->T, N = w->N, ld = w->ld;
+    const int64_t T = w->T, ld = w->ld;
     int j = w->L - 1;
     for (int c = 0; c < w->L; ++c)
-        if (w->lv[(size_t)c].dropped_t <= T - N) {
+        if (w->lv[(size_t)c].dropped_t <= lb) {
             j = c;
             break;
         }
     WinLevel& l = w->lv[(size_t)j];
     const double* C = level_C(l);
-    const int r = (int)l.sub->fill;
+    const int r = (ub == T) ? (int)l.sub->fill : 0;
     sk_status rc;
     W_TRY(sync_reset(h));
-    // B = C^T C + sum over in-window snapshots of Z W + W^T Z^T - Z (W Z) Z^T
-    if ((rc = gemm1(h, gd(C, (int)l.sub->ld, true, C, (int)l.sub->ld, false, w->Bq, d, d, d, r)))) return rc;
+    // B = C^T C + sum over the snapshots in (lb, ub] of Z W + W^T Z^T - Z (W Z) Z^T
+    if (r > 0) {
+        if ((rc = gemm1(h, gd(C, (int)l.sub->ld, true, C, (int)l.sub->ld, false, w->Bq, d, d, d, r)))) return rc;
+    } else {
+        W_TRY(hipMemsetAsync(w->Bq, 0, sizeof(double) * (size_t)d * d, h->stream));
+    }
     std::vector<const WinEntry*> snaps, raws;
     for (const WinEntry& e : l.q) {
-        if (!(T - N < e.t && e.t <= T)) continue;
+        if (!(lb < e.t && e.t <= ub)) continue;
         (e.kind == 0 ? snaps : raws).push_back(&e);
     }
     size_t si = 0;

@@ -10,6 +10,8 @@ struct WindowState;
 sk_status window_create(sketch_t h);
 sk_status window_update(sketch_t h, const char* rows_dev, int64_t n, int64_t ld, int dtype);
 sk_status window_query(sketch_t h, const double** out_f64);
+// ATTP sketches: the sketch of the first t rows.
+sk_status window_query_at(sketch_t h, int64_t t, const double** out_f64);
 sk_status window_advance_impl(sketch_t h, int64_t t_now);
 void window_destroy(sketch_t h);
 const int32_t* window_info_ptr(sketch_t h);

@@ -416,14 +416,15 @@ def test_bf16_projection_tracks_fp32_projection():
     assert rel_fro(gb, ga) < 2e-2
 
 
-# -------------------------------------- cooperative Jacobi (order >= 257)
+# ------------------------------------------ eigen-problems of order 257-512
 @pytest.mark.parametrize("d,ell,extra", [(300, 129, 129), (300, 200, 150), (520, 256, 200)])
-def test_exact_fp64_cooperative_jacobi_shrinks_and_query(d, ell, extra):
-    # 2 ell >= 258: every shrink's eigen-solve runs on the multi-workgroup
-    # block Jacobi solver; the query then shrinks r = ell - 1 + extra >= 257
-    # buffered rows (r = 257, 349, 455: orders that are not multiples of 32)
+def test_exact_fp64_large_orders_shrinks_and_query(d, ell, extra):
+    # 2 ell >= 258: every shrink's eigen-solve runs the tridiagonal solver
+    # with the multi-workgroup reduction; the query then shrinks
+    # r = ell - 1 + extra >= 257 buffered rows (r = 257, 349, 455: orders that
+    # are not multiples of the 16 rows a workgroup holds)
     n = 2 * ell + (ell + 1) + extra
-    note(f"exact fp64 cooperative Jacobi d={d} ell={ell} n={n} query r={ell - 1 + extra}")
+    note(f"exact fp64 large orders d={d} ell={ell} n={n} query r={ell - 1 + extra}")
     A = synth.lowrank_rows(n, d, 5 * np.arange(1, 301) ** -0.7, 0.05, seed=ell)
     o = run_oracle(A, d, ell)
     s = make(d, ell)
@@ -434,9 +435,9 @@ def test_exact_fp64_cooperative_jacobi_shrinks_and_query(d, ell, extra):
     s.close()
 
 
-def test_exact_fp64_cooperative_jacobi_batch_equals_alone():
-    # two order-258 / order-400 exact cores share one multi-task cooperative
-    # Jacobi launch; each result is bitwise its result alone
+def test_exact_fp64_large_orders_batch_equals_alone():
+    # order-258 and order-400 exact cores share one multi-workgroup reduction
+    # launch; each result is bitwise its result alone
     from paper_2601_02019_amd import sketch_update_batch
     shapes = [(300, 129), (300, 200), (280, 129)]
     rows = [torch.from_numpy(synth.lowrank_rows(2 * ell + ell + 1 + 60, d, 5 * np.arange(1, d + 1) ** -0.7,
@@ -449,7 +450,7 @@ def test_exact_fp64_cooperative_jacobi_batch_equals_alone():
         alone.append(a.query())
         a.close()
         mixed.append(make(d, ell))
-    note("batched cooperative Jacobi: 2 ell = 258, 400, 258")
+    note("batched large orders: 2 ell = 258, 400, 258")
     sketch_update_batch(mixed, rows)
     for i in range(len(shapes)):
         assert torch.equal(mixed[i].query(), alone[i]), i
