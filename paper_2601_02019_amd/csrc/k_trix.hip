@@ -36,19 +36,31 @@ constexpr int XTHREADS = 256;   // 16 rows x 16 lanes
 constexpr int XNMAX = 512;
 constexpr int XSLOT = 2 * XNMAX + 32;  // p, row, partial dots
 
+// Sums within each 16-lane row of a wavefront by DPP exchanges (every lane
+// of the row gets the row's sum): lane ^ 1, lane ^ 2 by quad permutes, then
+// the half-row and row mirrors pair the (by then uniform) quads.
+template <int CTRL>
+__device__ __forceinline__ double x_dpp(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double x_sum16(double x) {
-    x += __shfl_xor(x, 1, 64);
-    x += __shfl_xor(x, 2, 64);
-    x += __shfl_xor(x, 4, 64);
-    x += __shfl_xor(x, 8, 64);
+    x += x_dpp<0xB1>(x);
+    x += x_dpp<0x4E>(x);
+    x += x_dpp<0x141>(x);
+    x += x_dpp<0x140>(x);
     return x;
 }
-
+__device__ __forceinline__ double x_lane(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+// wave sum (every lane gets it), rows summed in order
 __device__ __forceinline__ double x_wave_sum(double x) {
     x = x_sum16(x);
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-    return x;
+    return (x_lane(x, 0) + x_lane(x, 16)) + (x_lane(x, 32) + x_lane(x, 48));
 }
 
 // The member group of workgroup b.  Workgroups are dealt to the 8 XCDs round
@@ -67,6 +79,75 @@ __device__ __forceinline__ XMap x_map(int P, int local) {
 
 __host__ __device__ __forceinline__ int x_members(int n) { return (n + XR - 1) / XR; }
 
+// Householder vector of row j (xrow) into v[j+1 ..] with tau; member 0 also
+// writes the reflector (W row j), the diagonal entry and beta.  red holds
+// the four wave partials of |xrow beyond j + 1|^2.  Identical in every member.
+__device__ __forceinline__ double trix_reflector(int j, int n, const double* xrow, const double* red, double* v,
+                                                 double* Wr, double* U, int lu, int member) {
+    const int tid = threadIdx.x;
+    const double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
+    const double alpha = xrow[j + 1];
+    double beta = alpha, tau = 0.0, scal = 0.0;
+    if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+    }
+    for (int c = j + 1 + tid; c < n; c += XTHREADS) v[c] = (c == j + 1) ? 1.0 : xrow[c] * scal;
+    if (member == 0) {
+        if (tid == 0) {
+            U[j] = xrow[j];
+            U[lu + j] = beta;
+            Wr[(int64_t)j * n + j] = tau;
+        }
+        for (int c = j + 2 + tid; c < n; c += XTHREADS) Wr[(int64_t)j * n + c] = xrow[c] * scal;
+    }
+    return tau;
+}
+
+// Exchange of step j, wave 0 only: this member's p (pl) and partial dot (the
+// sum of pvw), row j + 1 as it stands if this member owns it; then every
+// member's data into pb, rb and *pvs.  Returns false on a timed-out wait.
+__device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, const double* Al, const double* pl,
+                                              const double* pvw, double* xch, uint64_t* flags, uint64_t epoch,
+                                              double* pb, double* rb, double* pvs) {
+    const int lane = threadIdx.x & 63;
+    double* slot = xch + (j & 1) * XSLOT;
+    if (lane < XR) {
+        const int i = member + P * lane;
+        if (i > j && i < n) slot[i] = pl[lane];
+    }
+    if (lane == 0) slot[2 * XNMAX + member] = (pvw[0] + pvw[1]) + (pvw[2] + pvw[3]);
+    if (member == (j + 1) % P) {
+        const double* ar = Al + ((j + 1) / P) * n;
+        for (int c = j + 1 + lane; c < n; c += 64) slot[XNMAX + c] = ar[c];
+    }
+    const uint64_t target = xwg_flag(epoch, (unsigned)(j + 1));
+    xwg_publish(flags + member, target);
+    const bool ok = xwg_wait(flags, P, target);
+    double pvv = lane < P ? slot[2 * XNMAX + lane] : 0.0;
+    constexpr int LPL = XNMAX / 64;
+    double pr[LPL], rr_[LPL];
+#pragma unroll
+    for (int u = 0; u < LPL; ++u) {
+        const int c = j + 1 + lane + 64 * u;
+        pr[u] = c < n ? slot[c] : 0.0;
+        rr_[u] = c < n ? slot[XNMAX + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < LPL; ++u) {
+        const int c = j + 1 + lane + 64 * u;
+        if (c < n) {
+            pb[c] = pr[u];
+            rb[c] = rr_[u];
+        }
+    }
+    double sum = 0.0;  // partial dots in member order (the same sum in every member)
+    for (int m = 0; m < P; ++m) sum += x_lane(pvv, m);
+    if (lane == 0) *pvs = sum;
+    return ok;
+}
+
 __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, double* __restrict__ Wr,
                           double* __restrict__ U, int lu, double* xch, uint64_t* flags, int* info, uint64_t epoch,
                           int member) {
@@ -75,8 +156,9 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid >> 4, part = tid & 15;  // row slot and lane within it
     double* Al = lds;                          // [XR][n] this member's rows
-    double* v = lds + XR * n;                  // reflector (global column index)
-    double* pb = v + n;                        // p of every row, on arrival
+    double* va = lds + XR * n;                 // reflector of the current column
+    double* vb = va + n;                       // reflector of the next column
+    double* pb = vb + n;                       // p of every row, on arrival
     double* rb = pb + n;                       // shipped row j + 1, on arrival
     double* xrow = rb + n;                     // row j of the current matrix
     __shared__ double red[4], pl[XR], pvw[4], pvs_s;
@@ -97,135 +179,97 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
     if (lane == 0) red[wave] = s2;
     if (tid == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j + 2 < n; ++j) {
-        // (a) reflector of column j from row j (identical in every member);
-        // red holds |row j beyond j + 1|^2
-        const double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
-        const double alpha = xrow[j + 1];
-        double beta = alpha, tau = 0.0, scal = 0.0;
-        if (xn2 > 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        for (int c = j + 1 + tid; c < n; c += XTHREADS) v[c] = (c == j + 1) ? 1.0 : xrow[c] * scal;
-        if (member == 0) {
-            if (tid == 0) {
-                U[j] = xrow[j];
-                U[lu + j] = beta;
-                Wr[(int64_t)j * n + j] = tau;
-            }
-            for (int c = j + 2 + tid; c < n; c += XTHREADS) Wr[(int64_t)j * n + c] = xrow[c] * scal;
-        }
-        __syncthreads();
-        // (b) p_i = tau (A22 v)_i for this member's rows i > j
-        const bool live = has_row && my_i > j;
+    // (n >= 3 here: the launcher takes orders from trix_min_n() >= 8)
+    // column 0: reflector, p for this member's rows, exchange
+    double tau = trix_reflector(0, n, xrow, red, va, Wr, U, lu, member);
+    __syncthreads();
+    {
+        const bool live = has_row && my_i > 0;
         double acc = 0.0;
         if (live) {
             const double* ar = Al + r * n;
-            for (int c = j + 1 + part; c < n; c += 16) acc = fma(ar[c], v[c], acc);
+            for (int c = 1 + part; c < n; c += 16) acc = fma(ar[c], va[c], acc);
         }
         acc = x_sum16(acc);
         const double pi = tau * acc;
         if (part == 0) pl[r] = live ? pi : 0.0;
-        double pv = (live && part == 0) ? pi * v[my_i] : 0.0;
-        pv = x_wave_sum(pv);
-        if (lane == 0) pvw[wave] = pv;
-        __syncthreads();
-        // (c) exchange through L2, wave 0 only: this member's p and partial
-        // dot (and row j + 1 as it stands if it owns it), one release, the
-        // flag; then every member's data after one acquire
-        if (wave == 0) {
-            double* slot = xch + (j & 1) * XSLOT;
-            if (lane < XR) {
-                const int i = member + P * lane;
-                if (i > j && i < n) slot[i] = pl[lane];
-            }
-            if (lane == 0) slot[2 * XNMAX + member] = (pvw[0] + pvw[1]) + (pvw[2] + pvw[3]);
-            if (member == (j + 1) % P) {
-                const double* ar = Al + ((j + 1) / P) * n;
-                for (int c = j + 1 + lane; c < n; c += 64) slot[XNMAX + c] = ar[c];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const uint64_t target = (epoch << 32) | (uint64_t)(j + 1);
-            if (lane == 0) __hip_atomic_store(flags + member, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned polls = 0;
-            while (true) {
-                const uint64_t f =
-                    lane < P ? __hip_atomic_load(flags + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : target;
-                if (__all(f >= target)) break;
-                if (++polls > (1u << 22)) {
-                    if (lane == 0) bad = 1;
-                    break;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            // every load issued before any is used
-            double pvv = lane < P ? slot[2 * XNMAX + lane] : 0.0;
-            constexpr int LPL = XNMAX / 64;
-            double pr[LPL], rr_[LPL];
-#pragma unroll
-            for (int u = 0; u < LPL; ++u) {
-                const int c = j + 1 + lane + 64 * u;
-                pr[u] = c < n ? slot[c] : 0.0;
-                rr_[u] = c < n ? slot[XNMAX + c] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < LPL; ++u) {
-                const int c = j + 1 + lane + 64 * u;
-                if (c < n) {
-                    pb[c] = pr[u];
-                    rb[c] = rr_[u];
-                }
-            }
-            // partial dots in member order (the same sum in every member)
-            double sum = 0.0;
-            for (int m = 0; m < P; ++m) sum += __shfl(pvv, m, 64);
-            if (lane == 0) pvs_s = sum;
-        }
-        __syncthreads();
-        if (bad) break;
-        // (d) w = p - K v on the fly; rank-2 update of this member's rows and
-        // of the shipped row j + 1 (the next pivot row, with its norm)
+        const double pv = (live && part == 0) ? pi * va[my_i] : 0.0;
+        const double wsum = (x_lane(pv, 0) + x_lane(pv, 16)) + (x_lane(pv, 32) + x_lane(pv, 48));
+        if (lane == 0) pvw[wave] = wsum;
+    }
+    __syncthreads();
+    if (wave == 0 && !trix_exchange(0, n, P, member, Al, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) && lane == 0)
+        bad = 1;
+    __syncthreads();
+    for (int j = 0; j + 2 < n && !bad; ++j) {
+        // (1) w = p - K v (on the fly) and row j + 1 after this column's
+        // update, with the squared norm of its part beyond j + 2
         const double K = 0.5 * tau * pvs_s;
-        const double w1 = fma(-K, v[j + 1], pb[j + 1]);
-        if (live) {
-            double* ar = Al + r * n;
-            const double vi = v[my_i], wi = fma(-K, vi, pb[my_i]);
-            for (int c = j + 1 + part; c < n; c += 16) {
-                const double wc = fma(-K, v[c], pb[c]);
-                ar[c] = fma(-vi, wc, fma(-wi, v[c], ar[c]));
-            }
-        }
+        const double w1 = fma(-K, va[j + 1], pb[j + 1]);
         s2 = 0.0;
         for (int c = j + 1 + tid; c < n; c += XTHREADS) {
-            const double wc = fma(-K, v[c], pb[c]);
-            const double x = fma(-1.0, wc, fma(-w1, v[c], rb[c]));
+            const double wc = fma(-K, va[c], pb[c]);
+            const double x = fma(-1.0, wc, fma(-w1, va[c], rb[c]));
             xrow[c] = x;
             if (c >= j + 3) s2 = fma(x, x, s2);
         }
         s2 = x_wave_sum(s2);
         if (lane == 0) red[wave] = s2;
         __syncthreads();
-    }
-    if (bad) {
-        if (tid == 0 && member == 0) atomicAdd(&info[3], 1);
-        return;
-    }
-    // last two rows: T's trailing 2 x 2 block
-    if (n >= 2) {
-        if (member == 0 && tid == 0) {
+        // (2) the next column's reflector (its v into vb)
+        const bool next = j + 3 < n;
+        double tau2 = 0.0;
+        if (next) {
+            tau2 = trix_reflector(j + 1, n, xrow, red, vb, Wr, U, lu, member);
+        } else if (member == 0 && tid == 0) {
             U[n - 2] = xrow[n - 2];
             U[lu + n - 2] = xrow[n - 1];
             Wr[(int64_t)(n - 2) * n + n - 2] = 0.0;
             Wr[(int64_t)(n - 1) * n + n - 1] = 0.0;
         }
-        // A[n-1][n-1] after every update: its owner holds it
-        if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * n + n - 1];
-    } else if (member == 0 && tid == 0) {
-        U[0] = Ain[0];
-        Wr[0] = 0.0;
+        __syncthreads();
+        // (3) one pass over this member's rows: the update of column j and
+        // the products with the next reflector
+        {
+            const bool live = has_row && my_i > j, live2 = has_row && my_i > j + 1;
+            double acc = 0.0;
+            if (live) {
+                double* ar = Al + r * n;
+                const double vi = va[my_i], wi = fma(-K, vi, pb[my_i]);
+                for (int c = j + 1 + part; c < n; c += 16) {
+                    const double wc = fma(-K, va[c], pb[c]);
+                    const double a = fma(-vi, wc, fma(-wi, va[c], ar[c]));
+                    ar[c] = a;
+                    if (c >= j + 2) acc = fma(a, vb[c], acc);
+                }
+            }
+            if (next) {
+                acc = x_sum16(acc);
+                const double pi = tau2 * acc;
+                if (part == 0) pl[r] = live2 ? pi : 0.0;
+                const double pv = (live2 && part == 0) ? pi * vb[my_i] : 0.0;
+                const double wsum = (x_lane(pv, 0) + x_lane(pv, 16)) + (x_lane(pv, 32) + x_lane(pv, 48));
+                if (lane == 0) pvw[wave] = wsum;
+            }
+        }
+        __syncthreads();
+        if (!next) break;
+        // (4) exchange of column j + 1
+        if (wave == 0 && !trix_exchange(j + 1, n, P, member, Al, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) &&
+            lane == 0)
+            bad = 1;
+        __syncthreads();
+        double* t = va;
+        va = vb;
+        vb = t;
+        tau = tau2;
     }
+    if (bad) {
+        if (tid == 0 && member == 0) atomicAdd(&info[3], 1);
+        return;
+    }
+    // A[n-1][n-1] after every update: its owner holds it
+    if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * n + n - 1];
 }
 
 // Task form: eigen-problems of shrink / query tasks that the tridiagonal
@@ -274,16 +318,16 @@ int trix_min_n() {
 hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int nmax = std::min(max_n, XNMAX);
     int P = x_members(nmax);
-    const size_t lds = sizeof(double) * (size_t)(XR + 4) * (size_t)nmax;
+    const size_t lds = sizeof(double) * (size_t)(XR + 5) * (size_t)nmax;
     static int per_cu = -1, cus = 0;
     if (per_cu < 0) {
         int dev = 0;
         if (hipFuncSetAttribute((const void*)k_tri_reduce_x, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * (XR + 4) * XNMAX)) != hipSuccess ||
+                                (int)(sizeof(double) * (XR + 5) * XNMAX)) != hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, XTHREADS,
-                                                         sizeof(double) * (XR + 4) * XNMAX) != hipSuccess ||
+                                                         sizeof(double) * (XR + 5) * XNMAX) != hipSuccess ||
             per_cu < 1)
             return hipErrorInvalidConfiguration;
     }
