@@ -799,27 +799,28 @@ __device__ __forceinline__ void tri_eig_body(const double* Ain, int ldin, int n,
 
 // U = Q U for the reflectors in W (row j: v_j beyond the super-diagonal,
 // W[j][j] = tau_j), skipped when the Jacobi fallback produced U.  One
-// wavefront per 4-column strip of U, held in LDS; the sixteen lanes of a row
-// of the wavefront take one column and split its rows (the product with v_j
-// ends in a DPP row sum), so the reflectors follow one another without a
-// barrier.  The reflectors arrive in
-// blocks of TRI_RB(n) rows of W through LDS; the next block's loads are issued
-// before the current block is applied, so their latency is hidden.
+// wavefront per 4-column strip of U; the sixteen lanes of a row of the
+// wavefront take one column, lane p holding rows p, p + 16, ... of it in
+// registers, so the product with v_j is 16 (or 32) independent LDS loads and
+// FMAs and a DPP row sum, and the update reuses the loaded v.  The reflectors
+// arrive in blocks of tri_rb(n) rows of W through LDS, the next block's loads
+// issued before the current block is applied.
 constexpr int TRI_SC = 4;
 __host__ __device__ constexpr int tri_rb(int n) { return n <= 256 ? 8 : 4; }
-__host__ __device__ constexpr int tri_back_lds(int n) { return (TRI_SC + tri_rb(n)) * n; }
+__host__ __device__ constexpr int tri_back_lds(int n) { return tri_rb(n) * n; }
 
-__device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n,
-                                              double* lds) {
-    if (Dm[0] != 0.0) return;
+template <int NS>
+__device__ __forceinline__ void tri_back_strip(const double* W, double* U, int lu, int n, double* vb) {
     const int lane = threadIdx.x, c = lane >> 4, p = lane & 15;  // a row of 16 lanes per column
     const int c0 = blockIdx.x * TRI_SC;
-    if (c0 >= n) return;
     const bool act = c0 + c < n;
     const int RB = tri_rb(n);
-    double* Z = lds;                // [n][TRI_SC]
-    double* vb = lds + n * TRI_SC;  // RB rows of W
-    for (int i = p; i < n; i += 16) Z[i * TRI_SC + c] = act ? U[(int64_t)i * lu + c0 + c] : 0.0;
+    double z[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int r = p + 16 * u;
+        z[u] = (act && r < n) ? U[(int64_t)r * lu + c0 + c] : 0.0;
+    }
     double pf[32];  // RB * n <= 2048 = 32 per lane
     int jhi = n - 2;
     if (jhi >= 0) {
@@ -852,40 +853,43 @@ __device__ __forceinline__ void tri_back_body(const double* W, const double* Dm,
             const double* row = vb + (j - jlo) * n;
             const double tau = row[j];
             if (tau == 0.0) continue;
-            const int L = n - j - 1;
-            const double* v = row + j + 1;  // v[0] = 1 implied
-            double* z = Z + (j + 1) * TRI_SC + c;
-            // eight independent partial sums and eight rows per step, so a
-            // lane keeps eight LDS loads in flight
-            double acc[8];
+            // v over rows r > j: 1 at r = j + 1, W[j][r] beyond
+            double v[NS];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-            int i = p;
-            for (; i + 112 < L; i += 128) {
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int r = i + 16 * u;
-                    acc[u] = fma(r == 0 ? 1.0 : v[r], z[r * TRI_SC], acc[u]);
-                }
+            for (int u = 0; u < NS; ++u) {
+                const int r = p + 16 * u;
+                v[u] = (r > j + 1 && r < n) ? row[r] : (r == j + 1 ? 1.0 : 0.0);
             }
-            for (; i < L; i += 16) acc[0] = fma(i == 0 ? 1.0 : v[i], z[i * TRI_SC], acc[0]);
-            double y = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-            y = tri_row_sum(y);
-            y *= tau;
-            for (i = p; i + 112 < L; i += 128) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int r = i + 16 * u;
-                    z[r * TRI_SC] = fma(-(r == 0 ? 1.0 : v[r]), y, z[r * TRI_SC]);
-                }
+            for (int u = 0; u < NS; u += 4) {
+                a0 = fma(v[u], z[u], a0);
+                a1 = fma(v[u + 1], z[u + 1], a1);
+                a2 = fma(v[u + 2], z[u + 2], a2);
+                a3 = fma(v[u + 3], z[u + 3], a3);
             }
-            for (; i < L; i += 16) z[i * TRI_SC] = fma(-(i == 0 ? 1.0 : v[i]), y, z[i * TRI_SC]);
+            const double y = tau * tri_row_sum((a0 + a1) + (a2 + a3));
+#pragma unroll
+            for (int u = 0; u < NS; ++u) z[u] = fma(-v[u], y, z[u]);
         }
         jhi = jlo - 1;
         __syncthreads();
     }
-    if (act)
-        for (int i = p; i < n; i += 16) U[(int64_t)i * lu + c0 + c] = Z[i * TRI_SC + c];
+    if (act) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int r = p + 16 * u;
+            if (r < n) U[(int64_t)r * lu + c0 + c] = z[u];
+        }
+    }
+}
+
+__device__ __forceinline__ void tri_back_body(const double* W, const double* Dm, double* U, int lu, int n,
+                                              double* lds) {
+    if (Dm[0] != 0.0) return;
+    if (blockIdx.x * TRI_SC >= n) return;
+    if (n <= 256) tri_back_strip<16>(W, U, lu, n, lds);
+    else tri_back_strip<32>(W, U, lu, n, lds);
 }
 
 // Task form: the eigen-problem of a shrink / query task (not the

@@ -26,16 +26,18 @@ std::atomic<int64_t> g_in_use{0};
 std::atomic<int64_t> g_budget{0};
 
 // Problem sizes from which one task alone runs the cooperative solvers:
-// CholeskyQR from k = 129 (SK_COOP_MIN_N), the eigen-solve from n = 513
+// CholeskyQR from k = 64 (SK_COOP_MIN_N; 4 % more rows/s than the
+// one-workgroup kernel on the 64 CSR sites at k = 128), the eigen-solve from n = 513
 // (SK_COOP_EIG_MIN_N; up to 512 the tridiagonal solver, whose reduction
 // runs on several workgroups from n = 160, is faster than the block Jacobi
-// method: 2.7 vs 9.4 ms per 512 x 512 solve; with SK_EIG_SOLVER=jacobi the
-// one-workgroup Jacobi solver stops at 128).
+// method: the exact shrink with a 512 x 512 core took 6.9 ms against 25 ms
+// at d = 4096; with SK_EIG_SOLVER=jacobi the one-workgroup Jacobi solver
+// stops at 128).
 static int coop_min_n() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_COOP_MIN_N");
-        v = e ? atoi(e) : 129;
+        v = e ? atoi(e) : 64;
     }
     return v;
 }
@@ -231,15 +233,22 @@ inline int dims(int M, int N, int K) { return M | (N << 2) | (K << 4); }  // 0 m
 hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hipStream_t st) {
     hipError_t e;
     StageScope sc(g.prof, ST_CHOLQR, st);
-    if (g.any_plain_chol) {
-        // batched CholeskyQR; k_cholinv skips the cooperative tasks, whose
-        // outputs are then rewritten below from the unchanged input sy
+    if (g.any_plain_chol || g.x_chol_k > 0) {
+        // batched CholeskyQR passes: the Gram of every task, then the
+        // one-workgroup Cholesky-inverse and Q = Y X^T (which skip or are
+        // overwritten for the other tasks), then the multi-workgroup pass of
+        // the tasks flagged for it; cooperative tasks are rewritten below from
+        // the unchanged input sy
         int src = sy;
         for (int pass = 0; pass < passes; ++pass) {
             const int dst = (pass == passes - 1) ? sq : S_Q1;
             if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, src, src, S_W, dims(1, 1, 0), st))) return e;
-            if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
-            if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
+            if (g.any_plain_chol) {
+                if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
+                if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
+            }
+            if (g.x_chol_k > 0 && (g_stage = "cholqr_x", e = launch_cholqr_x(t, g.count, g.x_chol_k, src, dst, pass, st)))
+                return e;
             src = dst;
         }
     }
@@ -254,10 +263,6 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
         g_stage = "cholqr_coop";
         if ((e = launch_cholqr_coop_tasks(t, g.coop_chol.data(), (int)g.coop_chol.size(), m, k, sy, sq, passes, st)))
             return e;
-    }
-    if (g.x_chol_k > 0) {
-        g_stage = "cholqr_x";
-        if ((e = launch_cholqr_x(t, g.count, g.x_chol_k, sy, sq, passes, st))) return e;
     }
     return hipSuccess;
 }
