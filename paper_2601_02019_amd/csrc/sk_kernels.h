@@ -66,8 +66,10 @@ int tri_lds_doubles();
 // of the tasks of order trix_min_n() .. 512.
 hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st);
 int trix_min_n();
-// Multi-workgroup CholeskyQR (passes 1 or 2) of the tasks flagged TF_X_CHOL.
-hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int sy, int sq, int passes, hipStream_t st);
+// One pass of the multi-workgroup CholeskyQR (the Gram of src already in
+// slot S_W) of the tasks flagged TF_X_CHOL: src -> dst.
+hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int src_slot, int dst_slot, int pass,
+                           hipStream_t st);
 // Multi-task cooperative solvers: tasks[idx[i]] for i < count, each by its
 // own group of workgroups (several launches when residency requires).
 hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st);
