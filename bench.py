@@ -646,11 +646,12 @@ def main():
         print(f"[bench] warmup step {w} done", file=sys.stderr, flush=True)
     sk.profile("all")
     torch.cuda.synchronize()
-    times = []
+    times, fills = [], []
     for k in range(args.steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
         sk.update(A)
+        fills.append(sk.info()["fill"])  # host-planned: no device round trip
         B = sk.query()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
@@ -667,31 +668,26 @@ def main():
     avg_ms = dom_ms / dom_calls
     roofline = None
     if dom == "eig_reduce":
-        # Householder reduction of the k x k Rayleigh-Ritz matrix (k = ell) on
-        # one workgroup: blocked, with the matrix in L2, for 128 < n <= 256
-        kern = "k_tri_reduce_blk" if 128 < ell <= 256 else "k_tri_reduce"
-        flops = tri_flops(ell)
+        # Householder reduction of the k x k Rayleigh-Ritz matrix of every
+        # shrink (k = ell) and of the query's r x r buffer Gram (r = the fill
+        # at the query, when r >= ell): orders from 160 up run on ceil(n / 16)
+        # workgroups with one exchange per column
+        orders = [ell] * (dom_calls - len([f for f in fills if f >= ell])) + [f for f in fills if f >= ell]
+        flops = sum(tri_flops(n_) for n_ in orders) / dom_calls
         achieved = flops / (avg_ms / 1e3) / 1e12
-        roofline = {"bound": "alu", "kernel": "%s (FP64 Householder tridiagonalisation, one workgroup, n=%d)"
-                    % (kern, ell),
+        multi = ell >= 160
+        kern = "k_tri_reduce_x" if multi else ("k_tri_reduce_blk" if ell > 128 else "k_tri_reduce")
+        src = "paper_2601_02019_amd/csrc/k_trix.hip" if multi else "paper_2601_02019_amd/csrc/k_tri.hip"
+        roofline = {"bound": "alu",
+                    "kernel": "%s (FP64 Householder tridiagonalisation, n=%d, %s)"
+                    % (kern, ell, "%d workgroups, one exchange per column" % ((ell + 15) // 16) if multi
+                       else "one workgroup"),
                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_FP64_TFLOPS,
-                    "traffic": measured_traffic(kern, "paper_2601_02019_amd/csrc/k_tri.hip"),
-                    "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops,
-                    "l2_product_bytes_per_launch": tri_product_bytes(ell),
-                    "l2_product_gbps": tri_product_bytes(ell) / (avg_ms / 1e3) / 1e9,
+                    "traffic": measured_traffic(kern, src),
+                    "avg_launch_ms": avg_ms, "launches": dom_calls, "algorithmic_flops_per_launch": flops,
+                    "us_per_column": 1e3 * avg_ms / max(1.0, sum(n_ - 2 for n_ in orders) / dom_calls),
                     "fallbacks_to_jacobi": prof.get("eig_fallbacks", (0, 0.0))[1]}
-    elif dom == "eig" and (ell > 256 or os.environ.get("SK_EIG_SOLVER") == "jacobi"):
-        solves = prof.get("eig_solves", (0, 0.0))[1]
-        sweeps = prof.get("eig_sweeps", (0, 0.0))[1] / max(solves, 1)
-        flops = jacobi_flops(ell, sweeps)
-        achieved = flops / (avg_ms / 1e3) / 1e12
-        roofline = {"bound": "alu", "kernel": "k_jacobi_coop (FP64 block Jacobi, n=%d)" % ell,
-                    "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP64_TFLOPS,
-                    "traffic": measured_traffic("k_jacobi_coop", "paper_2601_02019_amd/csrc/k_coop.hip"),
-                    "avg_launch_ms": avg_ms, "sweeps_per_solve": sweeps,
-                    "algorithmic_flops_per_launch": flops}
     else:
         roofline = {"bound": "unknown", "kernel": dom, "avg_launch_ms": avg_ms}
 
@@ -747,6 +743,14 @@ def main():
                          f"shrinks, k={ell}, q={args.q}), FP64 plain C, one thread, {tc:.1f}s",
                "cpu": cpu_model(), "nproc": os.cpu_count()}
 
+    # row ingest: FP32 rows read once, written once into the FP32 buffer
+    ingest = None
+    if "ingest" in stages:
+        ing_bytes = float(n) * d * (4 + 4) * args.steps
+        ing_s = stages["ingest"][1] / 1e3
+        ingest = {"gbs": ing_bytes / ing_s / 1e9, "frac_of_hbm_peak": ing_bytes / ing_s / 1e9 / PEAK_HBM_GBS,
+                  "launches": stages["ingest"][0], "bytes_per_step": ing_bytes / args.steps}
+
     out = {
         "metric": "rows/sec sketch update at matched cov-err vs exact-SVD FD; batched p99 lat",
         "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
@@ -762,6 +766,7 @@ def main():
         "exact_fd_same_gpu": exact,
         "cov_err_rel_full_stream": err_full,
         "stage_ms_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+        "ingest": ingest,
     }
     print(json.dumps(out))
 

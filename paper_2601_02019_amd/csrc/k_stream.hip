@@ -14,6 +14,7 @@
 //   k_convert_rows FP64 staging -> caller dtype
 #include "sk_device.h"
 #include "sk_kernels.h"
+#include "sk_philox.h"
 
 namespace sk {
 
@@ -34,47 +35,6 @@ template <> __device__ __forceinline__ uint16_t from_f64<uint16_t>(double v) {
     uint32_t lsb = (u >> 16) & 1u;
     u += 0x7fffu + lsb;
     return (uint16_t)(u >> 16);
-}
-
-// ---------------------------------------------------------------- Philox
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        const uint64_t y0 = hi1 ^ c[1] ^ k0;
-        const uint64_t y2 = hi0 ^ c[3] ^ k1;
-        c[0] = y0;
-        c[1] = lo1;
-        c[2] = y2;
-        c[3] = lo0;
-    }
-}
-
-// Four N(0,1) draws for counter (c0, c1, c2, c3) and key (seed, stream):
-// Box-Muller on (w0, w1) and (w2, w3); u1 in (0, 1], u2 in [0, 1) from the
-// top 53 bits of each word.
-__device__ __forceinline__ void gauss4(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1,
-                                       uint64_t c2, uint64_t c3, double out[4]) {
-    uint64_t c[4] = {c0, c1, c2, c3};
-    philox4x64_10(c, seed, stream);
-    const double two_pi = 6.283185307179586476925286766559;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const double u1 = (double)((c[2 * h] >> 11) + 1) * 0x1p-53;
-        const double u2 = (double)(c[2 * h + 1] >> 11) * 0x1p-53;
-        const double rad = sqrt(-2.0 * log(u1));
-        double sn, cs;
-        sincos(two_pi * u2, &sn, &cs);
-        out[2 * h] = rad * cs;
-        out[2 * h + 1] = rad * sn;
-    }
 }
 
 // ---------------------------------------------------------------- ingest

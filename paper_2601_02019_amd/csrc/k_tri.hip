@@ -1,21 +1,25 @@
 // k_tri.hip -- symmetric eigen-decomposition of the shrink's core (the eigen
 // step of Algorithm "Simultaneous Iteration" on the k x k Rayleigh-Ritz
 // matrix; the exact FD shrink's eigen-decomposition of the 2 ell x 2 ell
-// buffer Gram, Sec. 2.3) by one workgroup per problem, in three kernels:
+// buffer Gram, Sec. 2.3), in four kernels:
 //
-//   1. k_tri_reduce: Householder tridiagonalisation A = Q T Q^T (A in LDS
-//      when it fits; else in the global work matrix, which stays in L2, and
-//      for n <= 256 blocked by panels so that each column reads the matrix
-//      once and the panel updates it once);
-//   2. k_tri_eig: eigenvalues of T by multisection on Sturm counts to
-//      absolute accuracy eps ||T||, then eigenvectors of T by a twisted
-//      factorisation at each eigenvalue (the forward and backward pivots of
-//      T - lambda I meet at the index where the twist is smallest; the vector
-//      follows from one pass each way), one eigenvector per thread;
-//   3. k_tri_back: U = Q Z, four wavefronts per 64-column strip of Z
-//      applying the reflectors from the last to the first.
+//   1. k_tri_reduce / k_tri_reduce_blk: Householder tridiagonalisation
+//      A = Q T Q^T on one workgroup per problem (A in LDS when it fits; else
+//      in the global work matrix, which stays in L2, blocked by 32-column
+//      panels for n <= 256).  Orders from trix_min_n() up run instead on
+//      ceil(n / 16) workgroups (k_tri_reduce_x in k_trix.hip);
+//   2. k_tri_eigval: eigenvalues of T by multisection on Sturm counts to
+//      absolute accuracy eps ||T||, the spectrum split by index over up to
+//      64 workgroups per problem;
+//   3. k_tri_eig: eigenvectors of T by a twisted factorisation at each
+//      eigenvalue (the forward and backward pivots of T - lambda I meet at
+//      the index where the twist is smallest; the vector follows from one
+//      pass each way), one eigenvector per thread;
+//   4. k_tri_back: U = Q Z, one wavefront per strip of NS columns of Z with
+//      each column's rows held in registers, applying the reflectors from
+//      the last to the first.
 //
-// Eigenvectors from step 2 are accurate to eps ||T|| / gap.  Within clusters
+// Eigenvectors from step 3 are accurate to eps ||T|| / gap.  Within clusters
 // of close eigenvalues the vectors are made orthogonal by Gram-Schmidt, with
 // other twist indices where they coincide; more than 8 equal eigenvalues, or
 // a vector that is not finite, send the problem to the Jacobi method.  Every
@@ -641,6 +645,30 @@ __device__ __forceinline__ TriBounds tri_bounds(const double* d, const double* e
     return {gl, gu, tnorm, pivmin};
 }
 
+// The same bounds from the lanes of one wavefront (min and max are exact, so
+// the values equal tri_bounds' bit for bit).
+__device__ __forceinline__ TriBounds tri_bounds_wave(const double* d, const double* e, int n) {
+    const int lane = threadIdx.x & 63;
+    double emax2 = 0.0, gl = 1e308, gu = -1e308;
+    for (int i = lane; i < n; i += 64) {
+        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+        gl = fmin(gl, d[i] - r);
+        gu = fmax(gu, d[i] + r);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+        gl = fmin(gl, __shfl_xor(gl, o, 64));
+        gu = fmax(gu, __shfl_xor(gu, o, 64));
+    }
+    const double tnorm = fmax(fabs(gl), fabs(gu));
+    const double eps = 2.220446049250313e-16;
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    gl -= 2.0 * eps * tnorm + 2.0 * pivmin;
+    gu += 2.0 * eps * tnorm + 2.0 * pivmin;
+    return {gl, gu, tnorm, pivmin};
+}
+
 // Eigenvalues k0 .. k1-1 (k-th largest) of T (d, e2 = e^2) into lam[k] by
 // multisection: tpe threads (contiguous lanes) per eigenvalue count at the
 // tpe interior points that cut the interval into tpe + 1 parts; the first
@@ -938,8 +966,18 @@ __global__ __launch_bounds__(1024) void k_tri_eigval(const Task* tasks) {
             e2[i] = e[i] * e[i];
         }
     }
+    // workgroup 0 leaves T (d at Dm[1..n], e at Dm[n+1..2n-1]) for the vector
+    // kernel, which overwrites U, and clears the fallback flag Dm[0]
+    if (blockIdx.x == 0) {
+        double* Dm = s->slot[S_EV];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            Dm[1 + i] = d[i];
+            if (i + 1 < n) Dm[1 + n + i] = e[i];
+        }
+        if (threadIdx.x == 0) Dm[0] = 0.0;
+    }
     __syncthreads();
-    const TriBounds tb = tri_bounds(d, e, n);
+    const TriBounds tb = tri_bounds_wave(d, e, n);
     tri_bisect(d, e2, n, tb, k0, k1, s->slot[S_LAM]);
 }
 
@@ -947,6 +985,215 @@ __global__ __launch_bounds__(1024) void k_tri_eig(const Task* tasks, int have_la
     TRI_TASK_PROLOGUE
     tri_eig_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_EV], s->slot[S_U],
                  s->sld[S_U], s->slot[S_LAM], s->info, have_lam);
+}
+
+// Eigenvectors of T for the eigenvalues in lam, split over workgroups of one
+// wavefront.  Neighbours closer than 1e-6 |lambda| (and not below 1e-10 ||T||)
+// form clusters, as in tri_eig_body; workgroup b takes the clusters that
+// start in [b TRI_VPER, (b + 1) TRI_VPER), so a cluster's re-orthogonalisation
+// stays in one workgroup.  Two lanes per eigenvalue run the forward and the
+// backward pivot recurrences of the twisted factorisation side by side (one
+// instruction stream, the direction chosen by the lane), with the pivots in
+// LDS; the twist index is the largest index of the smallest |gamma_i| (the
+// one tri_eig_body picks); then the two lanes build the vector upwards and
+// downwards from the twist.  A cluster of more than 8 or a vector that is not
+// finite sets the flag Dm[0], and k_tri_fix solves the problem again by the
+// Jacobi method.  The arithmetic of a vector does not depend on the split.
+constexpr int TRI_VPER = 8;
+constexpr int TRI_VMAX = TRI_VPER + 7;  // a range ends inside a cluster of at most 8
+__host__ __device__ constexpr int tri_vec_lds(int n) { return 2 * TRI_VMAX * (n + 1); }
+
+__device__ __forceinline__ bool tri_close(const double* lam, int k, double tnorm) {
+    const double mag = fmax(fabs(lam[k - 1]), fabs(lam[k]));
+    return lam[k - 1] - lam[k] <= 1e-6 * mag && mag >= 1e-10 * tnorm;
+}
+
+__global__ __launch_bounds__(64) void k_tri_vec(const Task* tasks) {
+    extern __shared__ double lds[];
+    __shared__ double d[TRI_NMAX], e[TRI_NMAX], e2[TRI_NMAX], lam[TRI_NMAX];
+    __shared__ unsigned char start[TRI_NMAX + 1];
+    __shared__ int rng[2], bad;
+    TRI_TASK_PROLOGUE
+    const int lane = threadIdx.x;
+    const int b0 = blockIdx.x * TRI_VPER;
+    if (b0 >= n) return;
+    double* Dm = s->slot[S_EV];
+    double* U = s->slot[S_U];
+    const int lu = s->sld[S_U];
+    const double* glam = s->slot[S_LAM];
+    for (int i = lane; i < n; i += 64) {
+        d[i] = Dm[1 + i];
+        if (i + 1 < n) {
+            e[i] = Dm[1 + n + i];
+            e2[i] = e[i] * e[i];
+        }
+        lam[i] = glam[i];
+    }
+    __syncthreads();
+    const TriBounds tb = tri_bounds_wave(d, e, n);
+    const double tnorm = tb.tnorm, pivmin = tb.pivmin;
+    for (int k = lane; k <= n; k += 64) start[k] = (k == 0 || k == n || !tri_close(lam, k, tnorm)) ? 1 : 0;
+    __syncthreads();
+    if (lane == 0) {
+        int lo = b0, hi = min(n, b0 + TRI_VPER);
+        while (!start[lo]) ++lo;
+        while (!start[hi]) ++hi;
+        int flag = 0;
+        for (int k = lo, run = 0; k < hi; ++k) {  // cluster lengths inside the range
+            run = start[k] ? 1 : run + 1;
+            if (run > 8) flag = 1;
+        }
+        rng[0] = lo;
+        rng[1] = hi;
+        bad = flag || hi - lo > TRI_VMAX;
+    }
+    __syncthreads();
+    const int lo = rng[0], hi = rng[1], V = hi - lo;
+    if (bad) {
+        if (lane == 0) Dm[0] = 1.0;
+        return;
+    }
+    if (V <= 0) return;
+    if (!(tnorm > 0.0)) {  // the zero matrix: unit vectors
+        for (int x = lane; x < V * n; x += 64) {
+            const int i = x / V, c = lo + (x - (x / V) * V);
+            U[(int64_t)i * lu + c] = (i == c) ? 1.0 : 0.0;
+        }
+        return;
+    }
+    const int ns = n + 1;  // odd row stride: the lanes' rows fall in different banks
+    const int v = lane >> 1, half = lane & 1;
+    const bool act = v < V;
+    double* Pp = lds + (int64_t)min(v, V - 1) * ns;           // forward pivots, later the vector
+    double* Pm = lds + (int64_t)(TRI_VMAX + min(v, V - 1)) * ns;  // backward pivots
+    const double x = lam[lo + min(v, V - 1)];
+    // forward (half 0: i = 0 .. n-1) and backward (half 1: i = n-1 .. 0) pivots
+    {
+        double* P = half ? Pm : Pp;
+        int i = half ? n - 1 : 0;
+        double q = d[i] - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (act) P[i] = q;
+        for (int st = 1; st < n; ++st) {
+            i = half ? n - 1 - st : st;
+            q = (d[i] - x) - tri_div(e2[half ? i : i - 1], q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            if (act) P[i] = q;
+        }
+    }
+    __syncthreads();
+    // twist: half 0 scans [0, n/2), half 1 [n/2, n), each keeping the largest
+    // index of its smallest |gamma|; the upper half wins ties
+    int r;
+    {
+        const int h = n >> 1, i0 = half ? h : 0, i1 = half ? n : h;
+        double gb = 1e308;
+        int rb = -1;
+        for (int i = i0; i < i1; ++i) {
+            const double g = fabs(Pp[i] + Pm[i] - (d[i] - x));
+            if (rb < 0 || g <= gb) {
+                gb = g;
+                rb = i;
+            }
+        }
+        const double go = __shfl_xor(gb, 1, 64);
+        const int ro = __shfl_xor(rb, 1, 64);
+        if (half) r = (rb >= 0 && (ro < 0 || gb <= go)) ? rb : ro;
+        else r = (ro >= 0 && (rb < 0 || go <= gb)) ? ro : rb;
+        if (r < 0) r = n - 1;  // no comparable |gamma| (not finite): flagged below
+    }
+    __syncthreads();
+    // z_r = 1; half 0 upwards with the forward pivots, half 1 downwards with
+    // the backward ones (vector stored over the forward pivots)
+    double nrm = half ? 0.0 : 1.0;
+    {
+        const int len = half ? n - 1 - r : r;
+        double z = 1.0;
+        for (int st = 0; st < len; ++st) {
+            const int i = half ? r + 1 + st : r - 1 - st;
+            z = -tri_div(half ? e[i - 1] : e[i], half ? Pm[i] : Pp[i]) * z;
+            if (act) Pp[i] = z;
+            nrm = fma(z, z, nrm);
+        }
+        if (act && !half) Pp[r] = 1.0;
+    }
+    const double nrm2 = nrm + __shfl_xor(nrm, 1, 64);
+    __syncthreads();
+    if (act && !(nrm2 < 1e300)) bad = 1;
+    {
+        const double inv = 1.0 / sqrt(nrm2);
+        const int a = half ? r + 1 : 0, bnd = half ? n : r + 1;
+        if (act)
+            for (int i = a; i < bnd; ++i) Pp[i] *= inv;
+    }
+    __syncthreads();
+    if (bad) {
+        if (lane == 0) Dm[0] = 1.0;
+        return;
+    }
+    // clusters: every member after the first made orthogonal to the earlier
+    // ones (two Gram-Schmidt passes), recomputed with a twist of higher
+    // |gamma| rank when too little is left
+    for (int k0 = lo; k0 < hi;) {
+        int k1 = k0 + 1;
+        while (k1 < hi && !start[k1]) ++k1;
+        for (int m = k0 + 1; m < k1; ++m) {
+            double* zm = lds + (int64_t)(m - lo) * ns;
+            double* pm = lds + (int64_t)(TRI_VMAX + m - lo) * ns;
+            bool ok = false;
+            for (int rank = 0; rank < 8 && !ok; ++rank) {
+                if (rank > 0) {
+                    int fin = 1;
+                    if (lane == 0)
+                        fin = twisted_vec(d, e, e2, n, lam[m], pivmin, zm, 1, pm, 1, (m - k0) + rank - 1, zm, 1);
+                    __syncthreads();
+                    if (!__shfl(fin, 0, 64)) break;
+                }
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int q = k0; q < m; ++q) {
+                        const double* zq = lds + (int64_t)(q - lo) * ns;
+                        double dot = 0.0;
+                        for (int i = lane; i < n; i += 64) dot = fma(zq[i], zm[i], dot);
+                        dot = tri_wave_sum(dot);
+                        for (int i = lane; i < n; i += 64) zm[i] = fma(-dot, zq[i], zm[i]);
+                        __syncthreads();
+                    }
+                double nr = 0.0;
+                for (int i = lane; i < n; i += 64) nr = fma(zm[i], zm[i], nr);
+                nr = tri_wave_sum(nr);
+                if (nr > 0.25) {
+                    const double inv = 1.0 / sqrt(nr);
+                    for (int i = lane; i < n; i += 64) zm[i] *= inv;
+                    ok = true;
+                }
+                __syncthreads();
+            }
+            if (!ok) {
+                if (lane == 0) Dm[0] = 1.0;
+                return;
+            }
+        }
+        k0 = k1;
+    }
+    // columns lo .. hi-1 of U, row by row
+    for (int xx = lane; xx < V * n; xx += 64) {
+        const int i = xx / V, c = xx - i * V;
+        U[(int64_t)i * lu + lo + c] = lds[(int64_t)c * ns + i];
+    }
+}
+
+// The Jacobi method for a problem whose vector kernel set the flag Dm[0]
+// (info[2] counts these; Dm[0] = 1 then tells the back-transformation to
+// skip).
+__global__ __launch_bounds__(1024) void k_tri_fix(const Task* tasks) {
+    TRI_TASK_PROLOGUE
+    double* Dm = s->slot[S_EV];
+    if (Dm[0] == 0.0) return;
+    if (threadIdx.x == 0) atomicAdd(&s->info[2], 1);
+    jacobi_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], Dm, s->slot[S_U], s->sld[S_U],
+                s->slot[S_LAM], s->info, nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0) Dm[0] = 1.0;
 }
 
 __global__ __launch_bounds__(64) void k_tri_back(const Task* tasks) {
@@ -1065,12 +1312,28 @@ static int eigval_groups(int max_n) {
     return std::max(1, std::min(64, max_n / 8));
 }
 
+static int g_vec_ok = -1;
+
 hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int G = eigval_groups(max_n);
+    if (g_vec_ok < 0) {  // SK_TRI_VEC=0 keeps the eigenvectors in the one-workgroup kernel
+        const char* env = getenv("SK_TRI_VEC");
+        g_vec_ok = (!env || atoi(env) != 0) &&
+                   set_dyn_lds((const void*)k_tri_vec, tri_vec_lds(TRI_NMAX)) >= tri_vec_lds(TRI_NMAX);
+        (void)hipGetLastError();
+    }
     if (G > 1) {
         hipLaunchKernelGGL(k_tri_eigval, dim3((unsigned)G, 1, (unsigned)count), dim3(1024), 0, st, tasks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (g_vec_ok && max_n <= TRI_NMAX) {
+            hipLaunchKernelGGL(k_tri_vec, dim3((unsigned)((max_n + TRI_VPER - 1) / TRI_VPER), 1, (unsigned)count),
+                               dim3(64), sizeof(double) * (size_t)tri_vec_lds(max_n), st, tasks);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_tri_fix, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks);
+            return hipGetLastError();
+        }
     }
     hipLaunchKernelGGL(k_tri_eig, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks, G > 1 ? 1 : 0);
     return hipGetLastError();

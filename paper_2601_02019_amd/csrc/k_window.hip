@@ -17,42 +17,9 @@
 //                 final shrink)
 #include "sk_device.h"
 #include "sk_kernels.h"
+#include "sk_philox.h"
 
 namespace sk {
-
-__device__ __forceinline__ void w_philox(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        const uint64_t y0 = hi1 ^ c[1] ^ k0;
-        const uint64_t y2 = hi0 ^ c[3] ^ k1;
-        c[0] = y0;
-        c[1] = lo1;
-        c[2] = y2;
-        c[3] = lo0;
-    }
-}
-
-// Normal number `which` (0..3) of the block at counter (c0, c1, c2, c3).
-__device__ __forceinline__ double w_gauss(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1,
-                                          uint64_t c2, uint64_t c3, int which) {
-    uint64_t c[4] = {c0, c1, c2, c3};
-    w_philox(c, seed, stream);
-    const int h = which >> 1;
-    const double u1 = (double)((c[2 * h] >> 11) + 1) * 0x1p-53;
-    const double u2 = (double)(c[2 * h + 1] >> 11) * 0x1p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincos(6.283185307179586476925286766559 * u2, &sn, &cs);
-    return (which & 1) ? rad * sn : rad * cs;
-}
 
 template <typename T> __device__ __forceinline__ double wf64(T v);
 template <> __device__ __forceinline__ double wf64<double>(double v) { return v; }
@@ -85,7 +52,7 @@ __global__ __launch_bounds__(256) void k_philox_mat(DescArg<MatGenDesc> ds) {
     const int t = blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
     if (t >= q.rows || c >= q.cols) return;
-    q.M[(int64_t)t * q.ld + c] = w_gauss(q.seed, q.stream, (uint64_t)t, (uint64_t)(c >> 2), q.c2, q.c3, c & 3);
+    q.M[(int64_t)t * q.ld + c] = gauss_pick(q.seed, q.stream, (uint64_t)t, (uint64_t)(c >> 2), q.c2, q.c3, c & 3);
 }
 
 
@@ -152,7 +119,7 @@ __global__ __launch_bounds__(256) void k_win_pi_coop(const PiDesc* ds, int G, in
         return tot;
     };
 
-    for (int c = tid; c < nc; c += 256) xs[c] = w_gauss(q.seed, q.stream, (uint64_t)(c0 + c), 0ull, q.c2, q.c3, 0);
+    for (int c = tid; c < nc; c += 256) xs[c] = gauss_pick(q.seed, q.stream, (uint64_t)(c0 + c), 0ull, q.c2, q.c3, 0);
     __syncthreads();
     const int lane = tid & 63, grp = tid >> 6;
     bool zero = false;

@@ -44,13 +44,13 @@ static int coop_min_n() {
 
 bool eig_solver_jacobi();
 
-// CholeskyQR of k >= SK_CHOLX_MIN_K runs on ceil(k / 16) workgroups with one
-// exchange per 16 columns (k_cholx.hip); off unless the variable is set.
+// CholeskyQR of 64 <= k <= 512 (SK_CHOLX_MIN_K moves the lower end) runs on
+// ceil(k / 16) workgroups with one exchange per 16 columns (k_cholx.hip).
 static int cholx_min_k() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_CHOLX_MIN_K");
-        v = e ? atoi(e) : (1 << 30);
+        v = e ? atoi(e) : 64;
     }
     return v;
 }
