@@ -1,6 +1,6 @@
 // k_mfma.hip -- the random projection C Omega on the bfloat16 matrix cores of
 // gfx950 (v_mfma_f32_32x32x16_bf16), FP32 accumulation within a K chunk,
-// FP64 across chunks (the split-K partials go through k_reduce).
+// FP64 across chunks (the FP32 split-K partials go through k_reduce<2>).
 //
 // Operands come straight from global memory into registers: for the
 // 32x32x16 instruction lane l holds row (l mod 32) of the A tile and column
@@ -37,10 +37,12 @@ __global__ __launch_bounds__(256) void k_proj_bf16(const Task* tasks) {
     const SkDev* s = t.s;
     const int M = t.m, N = s->k;
     const int splits = s->sp, kc = s->kcp;
-    if ((int)blockIdx.y >= splits) return;
     const int ntn = (N + 63) >> 6, ntm = (M + 63) >> 6;
-    if ((int)blockIdx.x >= ntm * ntn) return;
-    const int ti = blockIdx.x / ntn, tj = blockIdx.x % ntn;
+    const int L = blockIdx.x + blockIdx.y * gridDim.x;
+    if (L >= ntm * ntn * splits) return;
+    int tile, split;
+    xcd_tile_split(L, ntm * ntn, splits, &tile, &split);
+    const int ti = tile / ntn, tj = tile % ntn;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wr = ti * 64 + (wave >> 1) * 32;   // first row of this wave's tile
     const int wc = tj * 64 + (wave & 1) * 32;    // first column
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(256) void k_proj_bf16(const Task* tasks) {
     const float* A = (const float*)s->buf[t.par];
     const uint16_t* B = (const uint16_t*)s->omegaT;
     const int kend = (s->d + 15) & ~15;
-    const int k0 = blockIdx.y * kc;
+    const int k0 = split * kc;
     const int k1 = min(k0 + kc, kend);
     const int ar = wr + (lane & 31), bc = wc + (lane & 31);
     const int koff = (lane >> 5) * 8;
@@ -74,13 +76,15 @@ __global__ __launch_bounds__(256) void k_proj_bf16(const Task* tasks) {
         else b.q = make_uint4(0u, 0u, 0u, 0u);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b.v, acc, 0, 0, 0);
     }
+    // FP32 partials (what the matrix cores accumulated; summed in FP64 by
+    // k_reduce<2>)
     const int ldp = s->sld[S_PPART];
-    double* part = s->slot[S_PPART] + (int64_t)blockIdx.y * (int64_t)s->n2 * ldp;
+    float* part = (float*)s->slot[S_PPART] + (int64_t)split * (int64_t)s->n2 * ldp;
     const int col = wc + (lane & 31);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int row = wr + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-        if (row < M && col < N) part[(int64_t)row * ldp + col] = (double)acc[i];
+        if (row < M && col < N) part[(int64_t)row * ldp + col] = acc[i];
     }
 }
 
@@ -91,7 +95,7 @@ hipError_t launch_project_bf16(const Task* tasks, int count, int max_m, int max_
                        dim3(256), 0, st, tasks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_reduce_proj(tasks, count, max_m, max_k, st);
+    return launch_reduce_proj_f32(tasks, count, max_m, max_k, st);
 }
 
 }  // namespace sk

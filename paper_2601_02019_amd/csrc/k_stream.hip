@@ -129,12 +129,15 @@ __global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
     const int N = MODE == 0 ? t.m : s->k;
     const int splits = MODE == 0 ? s->sg : s->sp;
     const int kc = MODE == 0 ? s->kcg : s->kcp;
-    if ((int)blockIdx.y >= splits) return;
     const int ntm = (M + 63) >> 6, ntn = (N + 63) >> 6;
+    const int tiles = MODE == 0 ? ntm * (ntm + 1) / 2 : ntm * ntn;
+    const int L = blockIdx.x + blockIdx.y * gridDim.x;
+    if (L >= tiles * splits) return;
+    int tile, split;
+    xcd_tile_split(L, tiles, splits, &tile, &split);
     int ti, tj;
     if (MODE == 0) {
-        int idx = blockIdx.x;
-        if (idx >= ntm * (ntm + 1) / 2) return;
+        int idx = tile;
         ti = 0;
         while (idx >= ntm - ti) {
             idx -= ntm - ti;
@@ -142,15 +145,14 @@ __global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
         }
         tj = ti + idx;
     } else {
-        if ((int)blockIdx.x >= ntm * ntn) return;
-        ti = blockIdx.x / ntn;
-        tj = blockIdx.x % ntn;
+        ti = tile / ntn;
+        tj = tile % ntn;
     }
     const TA* A = (const TA*)s->buf[t.par];
     const TB* B = MODE == 0 ? (const TB*)s->buf[t.par] : (const TB*)s->omegaT;
     const int64_t ld = s->ld;
     const int kend = (s->d + 15) & ~15;
-    const int k0 = blockIdx.y * kc;
+    const int k0 = split * kc;
     const int k1 = min(k0 + kc, kend);
 
     __shared__ double As[16][64 + 2];
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
     }
     const int ldp = s->sld[MODE == 0 ? S_GPART : S_PPART];
     const int64_t pstride = (int64_t)s->n2 * ldp;
-    double* part = s->slot[MODE == 0 ? S_GPART : S_PPART] + (int64_t)blockIdx.y * pstride;
+    double* part = s->slot[MODE == 0 ? S_GPART : S_PPART] + (int64_t)split * pstride;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = ti * 64 + ty * 4 + i;
@@ -201,30 +203,79 @@ __global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
     }
 }
 
+// P = sum of the split-K partials of C Omega in split order (MODE 1: FP64
+// partials; MODE 2: the FP32 partials of the bfloat16 matrix-core product,
+// summed in FP64).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce(const Task* tasks) {
     const Task& t = tasks[blockIdx.z];
-    if (t.kind == T_INGEST) return;
-    if (MODE == 1 && t.kind != T_SHRINK_RAND) return;
+    if (t.kind != T_SHRINK_RAND) return;
     const SkDev* s = t.s;
     const int M = t.m;
-    const int N = MODE == 0 ? t.m : s->k;
+    const int N = s->k;
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= M * N) return;
-    int i = idx / N, j = idx % N;
-    if (MODE == 0 && (i >> 6) > (j >> 6)) {  // lower tiles read the transposed partials
-        const int tmp = i;
-        i = j;
-        j = tmp;
-    }
-    const int splits = MODE == 0 ? s->sg : s->sp;
-    const int ldp = s->sld[MODE == 0 ? S_GPART : S_PPART];
+    const int i = idx / N, j = idx % N;
+    const int splits = s->sp;
+    const int ldp = s->sld[S_PPART];
     const int64_t pstride = (int64_t)s->n2 * ldp;
-    const double* part = s->slot[MODE == 0 ? S_GPART : S_PPART];
     double acc = 0.0;
-    for (int q = 0; q < splits; ++q) acc += part[q * pstride + (int64_t)i * ldp + j];
-    const int so = MODE == 0 ? S_G : S_P;
-    s->slot[so][(int64_t)(idx / N) * s->sld[so] + (idx % N)] = acc;
+    if (MODE == 2) {
+        const float* part = (const float*)s->slot[S_PPART];
+        for (int q = 0; q < splits; ++q) acc += (double)part[q * pstride + (int64_t)i * ldp + j];
+    } else {
+        const double* part = s->slot[S_PPART];
+        for (int q = 0; q < splits; ++q) acc += part[q * pstride + (int64_t)i * ldp + j];
+    }
+    s->slot[S_P][(int64_t)i * s->sld[S_P] + j] = acc;
+}
+
+// G = sum of the split-K partials of C C^T in split order, for the upper
+// 64 x 64 tiles the partial kernel computed; one workgroup per 16-row band
+// of an upper tile writes the band and, through LDS, its mirror below the
+// diagonal, both row-contiguous.
+__global__ __launch_bounds__(256) void k_reduce_gram(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind == T_INGEST) return;
+    const SkDev* s = t.s;
+    const int M = t.m;
+    const int ntm = (M + 63) >> 6;
+    const int band = blockIdx.x & 3;
+    int idx = blockIdx.x >> 2;
+    if (idx >= ntm * (ntm + 1) / 2) return;
+    int ti = 0;
+    while (idx >= ntm - ti) {
+        idx -= ntm - ti;
+        ++ti;
+    }
+    const int tj = ti + idx;
+    const int splits = s->sg;
+    const int ldp = s->sld[S_GPART];
+    const int64_t pstride = (int64_t)s->n2 * ldp;
+    const double* part = s->slot[S_GPART];
+    double* G = s->slot[S_G];
+    const int ldg = s->sld[S_G];
+    __shared__ double tile[16][64 + 1];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u, r = e >> 6, c = e & 63;
+        const int gi = ti * 64 + band * 16 + r, gj = tj * 64 + c;
+        double acc = 0.0;
+        if (gi < M && gj < M) {
+            for (int q = 0; q < splits; ++q) acc += part[q * pstride + (int64_t)gi * ldp + gj];
+            G[(int64_t)gi * ldg + gj] = acc;
+        }
+        tile[r][c] = acc;
+    }
+    if (ti == tj) return;  // the diagonal tile holds both triangles
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = tid + 256 * u, r = e >> 4, c = e & 15;  // 64 rows x 16 columns of the mirror
+        const int gi = tj * 64 + r, gj = ti * 64 + band * 16 + c;
+        if (gi < M && gj < M) G[(int64_t)gi * ldg + gj] = tile[c][r];
+    }
 }
 
 // ---------------------------------------------------------------- rebuild
@@ -239,8 +290,14 @@ __global__ __launch_bounds__(256) void k_rebuild(const Task* tasks) {
     const int rows_out = QUERY ? s->ell : s->ell - 1;
     const int K = t.m;
     const int N = s->d;
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    if (r0 >= rows_out || c0 >= N) return;
+    // the row tiles of one column slab of C run on one XCD (xcd_tile_split
+    // with the column tiles in the role of the splits): the slab is fetched once
+    const int R = (rows_out + 63) >> 6, Cn = (N + 63) >> 6;
+    const int L = blockIdx.x + blockIdx.y * gridDim.x;
+    if (L >= R * Cn) return;
+    int rt, ct;
+    xcd_tile_split(L, R, Cn, &rt, &ct);
+    const int r0 = rt * 64, c0 = ct * 64;
     const double* T = s->slot[S_T];
     const int ldt = s->sld[S_T];
     const Tst* X = (const Tst*)s->buf[t.par];
@@ -365,8 +422,8 @@ hipError_t launch_gram(const Task* tasks, int count, int max_m, int max_splits, 
     else hipLaunchKernelGGL((k_nt_partial<float, float, 0>), grid, dim3(256), 0, st, tasks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 g2 = g3((max_m * max_m + 255) / 256, 1, count);
-    hipLaunchKernelGGL((k_reduce<0>), g2, dim3(256), 0, st, tasks);
+    const dim3 g2 = g3(4 * (nt * (nt + 1) / 2), 1, count);
+    hipLaunchKernelGGL(k_reduce_gram, g2, dim3(256), 0, st, tasks);
     return hipGetLastError();
 }
 
@@ -390,9 +447,9 @@ hipError_t launch_project(const Task* tasks, int count, int max_m, int max_k, in
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_proj(const Task* tasks, int count, int max_m, int max_k, hipStream_t st) {
+hipError_t launch_reduce_proj_f32(const Task* tasks, int count, int max_m, int max_k, hipStream_t st) {
     const dim3 g2 = g3((max_m * max_k + 255) / 256, 1, count);
-    hipLaunchKernelGGL((k_reduce<1>), g2, dim3(256), 0, st, tasks);
+    hipLaunchKernelGGL((k_reduce<2>), g2, dim3(256), 0, st, tasks);
     return hipGetLastError();
 }
 

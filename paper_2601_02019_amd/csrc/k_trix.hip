@@ -79,28 +79,46 @@ __device__ __forceinline__ XMap x_map(int P, int local) {
 
 __host__ __device__ __forceinline__ int x_members(int n) { return (n + XR - 1) / XR; }
 
-// Householder vector of row j (xrow) into v[j+1 ..] with tau; member 0 also
-// writes the reflector (W row j), the diagonal entry and beta.  red holds
-// the four wave partials of |xrow beyond j + 1|^2.  Identical in every member.
-__device__ __forceinline__ double trix_reflector(int j, int n, const double* xrow, const double* red, double* v,
-                                                 double* Wr, double* U, int lu, int member) {
-    const int tid = threadIdx.x;
-    const double xn2 = (red[0] + red[1]) + (red[2] + red[3]);
-    const double alpha = xrow[j + 1];
+// LDS row stride of the member's rows: 16 doubles past a multiple of 32, so
+// the four rows a wavefront touches at once fall in two bank halves.
+__host__ __device__ __forceinline__ int x_ald(int n) { return (n + 31) / 32 * 32 + 16; }
+// LDS (doubles) of a problem of order n: the rows, four waves' private
+// reflector pairs, and the arrivals p and row j + 1.
+__host__ __device__ __forceinline__ int x_lds_doubles(int n) { return XR * x_ald(n) + 10 * n; }
+
+// Row jj + 1 of the reflector pair, in every wavefront of every member (no
+// barrier): lane l holds xr[t] = x[c] for c = jj + lane + 64 t of the row x
+// that column jj reduces (x[jj + 1] = alpha).  Writes v[jj + 1 ..] into this
+// wave's v (v[jj + 1] = 1) and returns tau; member 0's wave 0 also writes
+// the reflector (W row jj), the diagonal entry and beta.  Identical
+// arithmetic in every wavefront and member.
+template <int LPL>
+__device__ __forceinline__ double trix_reflector_w(int jj, int n, const double (&xr)[LPL], double xn2, double* v,
+                                                   double* Wr, double* U, int lu, bool writer) {
+    const int lane = threadIdx.x & 63;
+    const double alpha = x_lane(xr[0], 1);  // x[jj + 1]
     double beta = alpha, tau = 0.0, scal = 0.0;
     if (xn2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
         tau = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
     }
-    for (int c = j + 1 + tid; c < n; c += XTHREADS) v[c] = (c == j + 1) ? 1.0 : xrow[c] * scal;
-    if (member == 0) {
-        if (tid == 0) {
-            U[j] = xrow[j];
-            U[lu + j] = beta;
-            Wr[(int64_t)j * n + j] = tau;
+#pragma unroll
+    for (int t = 0; t < LPL; ++t) {
+        const int c = jj + lane + 64 * t;
+        if (c > jj && c < n) v[c] = (c == jj + 1) ? 1.0 : xr[t] * scal;
+    }
+    if (writer) {
+        if (lane == 0) {
+            U[jj] = xr[0];
+            U[lu + jj] = beta;
+            Wr[(int64_t)jj * n + jj] = tau;
         }
-        for (int c = j + 2 + tid; c < n; c += XTHREADS) Wr[(int64_t)j * n + c] = xrow[c] * scal;
+#pragma unroll
+        for (int t = 0; t < LPL; ++t) {
+            const int c = jj + lane + 64 * t;
+            if (c > jj + 1 && c < n) Wr[(int64_t)jj * n + c] = xr[t] * scal;
+        }
     }
     return tau;
 }
@@ -108,9 +126,9 @@ __device__ __forceinline__ double trix_reflector(int j, int n, const double* xro
 // Exchange of step j, wave 0 only: this member's p (pl) and partial dot (the
 // sum of pvw), row j + 1 as it stands if this member owns it; then every
 // member's data into pb, rb and *pvs.  Returns false on a timed-out wait.
-__device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, const double* Al, const double* pl,
-                                              const double* pvw, double* xch, uint64_t* flags, uint64_t epoch,
-                                              double* pb, double* rb, double* pvs) {
+__device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, const double* Al, int ald,
+                                              const double* pl, const double* pvw, double* xch, uint64_t* flags,
+                                              uint64_t epoch, double* pb, double* rb, double* pvs) {
     const int lane = threadIdx.x & 63;
     double* slot = xch + (j & 1) * XSLOT;
     if (lane < XR) {
@@ -119,7 +137,7 @@ __device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, c
     }
     if (lane == 0) slot[2 * XNMAX + member] = (pvw[0] + pvw[1]) + (pvw[2] + pvw[3]);
     if (member == (j + 1) % P) {
-        const double* ar = Al + ((j + 1) / P) * n;
+        const double* ar = Al + ((j + 1) / P) * ald;
         for (int c = j + 1 + lane; c < n; c += 64) slot[XNMAX + c] = ar[c];
     }
     const uint64_t target = xwg_flag(epoch, (unsigned)(j + 1));
@@ -148,48 +166,84 @@ __device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, c
     return ok;
 }
 
+// One pass over this thread's part of its row: the rank-2 update of column
+// j (skipped for j < 0, the first column) and the dot with the reflector vb
+// over columns from jv; the loads of four columns are issued together.
+__device__ __forceinline__ double trix_row_pass(double* ar, int c0, int n, int jv, const double* va, const double* pb,
+                                                const double* vb, double K, double vi, double wi, bool update) {
+    double acc = 0.0;
+    for (int cb = c0; cb < n; cb += 64) {
+        double av[4], vv[4], pv[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = min(cb + 16 * u, n - 1);
+            av[u] = ar[c];
+            bv[u] = vb[c];
+            if (update) {
+                vv[u] = va[c];
+                pv[u] = pb[c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = cb + 16 * u;
+            if (c < n) {
+                double a = av[u];
+                if (update) {
+                    const double wc = fma(-K, vv[u], pv[u]);
+                    a = fma(-vi, wc, fma(-wi, vv[u], a));
+                    ar[c] = a;
+                }
+                if (c >= jv) acc = fma(a, bv[u], acc);
+            }
+        }
+    }
+    return acc;
+}
+
 __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, double* __restrict__ Wr,
                           double* __restrict__ U, int lu, double* xch, uint64_t* flags, int* info, uint64_t epoch,
                           int member) {
     extern __shared__ double lds[];
+    constexpr int LPL = XNMAX / 64;
     const int P = x_members(n);
+    const int ald = x_ald(n);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid >> 4, part = tid & 15;  // row slot and lane within it
-    double* Al = lds;                          // [XR][n] this member's rows
-    double* va = lds + XR * n;                 // reflector of the current column
-    double* vb = va + n;                       // reflector of the next column
-    double* pb = vb + n;                       // p of every row, on arrival
+    double* Al = lds;                          // [XR][ald] this member's rows
+    double* va = lds + XR * ald + wave * 2 * n;  // this wave's reflector of the current column
+    double* vb = va + n;                       // ... and of the next column
+    double* pb = lds + XR * ald + 8 * n;       // p of every row, on arrival
     double* rb = pb + n;                       // shipped row j + 1, on arrival
-    double* xrow = rb + n;                     // row j of the current matrix
-    __shared__ double red[4], pl[XR], pvw[4], pvs_s;
+    __shared__ double pl[XR], pvw[4], pvs_s;
     __shared__ int bad;
     const int my_i = member + P * r;           // this thread's row
     const bool has_row = my_i < n;
+    const bool writer = member == 0 && wave == 0;
     for (int e = tid; e < XR * n; e += XTHREADS) {
         const int rr = e / n, c = e - rr * n, i = member + P * rr;
-        Al[e] = i < n ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
+        Al[rr * ald + c] = i < n ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
     }
-    double s2 = 0.0;
-    for (int c = tid; c < n; c += XTHREADS) {
-        const double x = 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]);
-        xrow[c] = x;
-        if (c >= 2) s2 = fma(x, x, s2);
-    }
-    s2 = x_wave_sum(s2);
-    if (lane == 0) red[wave] = s2;
     if (tid == 0) bad = 0;
-    __syncthreads();
     // (n >= 3 here: the launcher takes orders from trix_min_n() >= 8)
-    // column 0: reflector, p for this member's rows, exchange
-    double tau = trix_reflector(0, n, xrow, red, va, Wr, U, lu, member);
-    __syncthreads();
+    // column 0 in every wave: row 0 of A, its reflector into va
+    double tau;
+    {
+        double xr[LPL], s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < LPL; ++t) {
+            const int c = lane + 64 * t;
+            xr[t] = c < n ? 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]) : 0.0;
+            if (c >= 2 && c < n) s2 = fma(xr[t], xr[t], s2);
+        }
+        s2 = x_wave_sum(s2);
+        tau = trix_reflector_w<LPL>(0, n, xr, s2, va, Wr, U, lu, writer);
+    }
+    __syncthreads();  // rows in LDS; every wave's va
     {
         const bool live = has_row && my_i > 0;
         double acc = 0.0;
-        if (live) {
-            const double* ar = Al + r * n;
-            for (int c = 1 + part; c < n; c += 16) acc = fma(ar[c], va[c], acc);
-        }
+        if (live) acc = trix_row_pass(Al + r * ald, 1 + part, n, 1, va, pb, va, 0.0, 0.0, 0.0, false);
         acc = x_sum16(acc);
         const double pi = tau * acc;
         if (part == 0) pl[r] = live ? pi : 0.0;
@@ -198,50 +252,52 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         if (lane == 0) pvw[wave] = wsum;
     }
     __syncthreads();
-    if (wave == 0 && !trix_exchange(0, n, P, member, Al, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) && lane == 0)
+    if (wave == 0 && !trix_exchange(0, n, P, member, Al, ald, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) &&
+        lane == 0)
         bad = 1;
     __syncthreads();
     for (int j = 0; j + 2 < n && !bad; ++j) {
-        // (1) w = p - K v (on the fly) and row j + 1 after this column's
-        // update, with the squared norm of its part beyond j + 2
+        // (1) in every wave: w = p - K v (on the fly) and row j + 1 after this
+        // column's update (lane l: columns j + 1 + l + 64 t), with the squared
+        // norm of its part beyond j + 2
         const double K = 0.5 * tau * pvs_s;
         const double w1 = fma(-K, va[j + 1], pb[j + 1]);
-        s2 = 0.0;
-        for (int c = j + 1 + tid; c < n; c += XTHREADS) {
-            const double wc = fma(-K, va[c], pb[c]);
-            const double x = fma(-1.0, wc, fma(-w1, va[c], rb[c]));
-            xrow[c] = x;
-            if (c >= j + 3) s2 = fma(x, x, s2);
-        }
-        s2 = x_wave_sum(s2);
-        if (lane == 0) red[wave] = s2;
-        __syncthreads();
-        // (2) the next column's reflector (its v into vb)
         const bool next = j + 3 < n;
+        double xr[LPL], s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < LPL; ++t) {
+            const int c = j + 1 + lane + 64 * t;
+            double x = 0.0;
+            if (c < n) {
+                const double wc = fma(-K, va[c], pb[c]);
+                x = fma(-1.0, wc, fma(-w1, va[c], rb[c]));
+                if (c >= j + 3) s2 = fma(x, x, s2);
+            }
+            xr[t] = x;
+        }
+        // (2) the next column's reflector, in every wave (its v into vb)
         double tau2 = 0.0;
         if (next) {
-            tau2 = trix_reflector(j + 1, n, xrow, red, vb, Wr, U, lu, member);
-        } else if (member == 0 && tid == 0) {
-            U[n - 2] = xrow[n - 2];
-            U[lu + n - 2] = xrow[n - 1];
-            Wr[(int64_t)(n - 2) * n + n - 2] = 0.0;
-            Wr[(int64_t)(n - 1) * n + n - 1] = 0.0;
+            s2 = x_wave_sum(s2);
+            tau2 = trix_reflector_w<LPL>(j + 1, n, xr, s2, vb, Wr, U, lu, writer);
+        } else {  // j = n - 3: the last 2 x 2 block of T
+            const double last = x_lane(xr[0], 1);  // row n - 2, column n - 1
+            if (writer && lane == 0) {
+                U[n - 2] = xr[0];
+                U[lu + n - 2] = last;
+                Wr[(int64_t)(n - 2) * n + n - 2] = 0.0;
+                Wr[(int64_t)(n - 1) * n + n - 1] = 0.0;
+            }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();  // the wave's vb before its reads
         // (3) one pass over this member's rows: the update of column j and
         // the products with the next reflector
         {
             const bool live = has_row && my_i > j, live2 = has_row && my_i > j + 1;
             double acc = 0.0;
             if (live) {
-                double* ar = Al + r * n;
                 const double vi = va[my_i], wi = fma(-K, vi, pb[my_i]);
-                for (int c = j + 1 + part; c < n; c += 16) {
-                    const double wc = fma(-K, va[c], pb[c]);
-                    const double a = fma(-vi, wc, fma(-wi, va[c], ar[c]));
-                    ar[c] = a;
-                    if (c >= j + 2) acc = fma(a, vb[c], acc);
-                }
+                acc = trix_row_pass(Al + r * ald, j + 1 + part, n, j + 2, va, pb, vb, K, vi, wi, true);
             }
             if (next) {
                 acc = x_sum16(acc);
@@ -255,8 +311,8 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         __syncthreads();
         if (!next) break;
         // (4) exchange of column j + 1
-        if (wave == 0 && !trix_exchange(j + 1, n, P, member, Al, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) &&
-            lane == 0)
+        if (wave == 0 &&
+            !trix_exchange(j + 1, n, P, member, Al, ald, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) && lane == 0)
             bad = 1;
         __syncthreads();
         double* t = va;
@@ -269,7 +325,7 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         return;
     }
     // A[n-1][n-1] after every update: its owner holds it
-    if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * n + n - 1];
+    if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * ald + n - 1];
 }
 
 // Task form: eigen-problems of shrink / query tasks that the tridiagonal
@@ -318,16 +374,16 @@ int trix_min_n() {
 hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int nmax = std::min(max_n, XNMAX);
     int P = x_members(nmax);
-    const size_t lds = sizeof(double) * (size_t)(XR + 5) * (size_t)nmax;
+    const size_t lds = sizeof(double) * (size_t)x_lds_doubles(nmax);
     static int per_cu = -1, cus = 0;
     if (per_cu < 0) {
         int dev = 0;
         if (hipFuncSetAttribute((const void*)k_tri_reduce_x, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * (XR + 5) * XNMAX)) != hipSuccess ||
+                                (int)(sizeof(double) * x_lds_doubles(XNMAX))) != hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, XTHREADS,
-                                                         sizeof(double) * (XR + 5) * XNMAX) != hipSuccess ||
+                                                         sizeof(double) * x_lds_doubles(XNMAX)) != hipSuccess ||
             per_cu < 1)
             return hipErrorInvalidConfiguration;
     }

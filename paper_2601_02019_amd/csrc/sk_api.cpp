@@ -87,9 +87,12 @@ static void mark_coop(Task& t, const sketch_s* h) {
     else if (t.kind == T_SHRINK_RAND && h->k >= coop_min_n()) t.flags |= TF_COOP_CHOL;
 }
 
-// Split-K plan: about 512 workgroups in total for a launch.
+// Split-K plan: about 512 workgroups in total for a launch, the split count
+// rounded up to a multiple of 8 so that each K chunk stays on one XCD
+// (xcd_tile_split), and chunks of at least 128 columns.
 static void splitk_plan(int tiles, int d, int* splits, int* chunk) {
     int s = std::max(1, (512 + tiles - 1) / tiles);
+    if (s > 1) s = (s + 7) / 8 * 8;
     s = std::min(s, std::max(1, (d + 127) / 128));
     int kc = (int)round_up((d + s - 1) / s, 16);
     s = (d + kc - 1) / kc;

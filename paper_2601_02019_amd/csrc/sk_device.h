@@ -199,4 +199,22 @@ __host__ __device__ inline int eig_n(const Task& t) {
     return t.kind == T_SHRINK_RAND ? t.s->k : t.m;
 }
 
+// Workgroups are handed to the eight XCDs (each with its own L2) round-robin
+// in linear launch order.  xcd_tile_split maps a workgroup's linear index L
+// in [0, tiles * splits) of one task to (tile, split) so that, when splits is
+// a multiple of 8, every tile of one split (one K chunk of the operands) runs
+// on the same XCD: the chunk is fetched from HBM once and re-read from that
+// L2.  Any other split count gets the plain row-major map.  Results do not
+// depend on the map (each (tile, split) product is the same arithmetic).
+__device__ __forceinline__ void xcd_tile_split(int L, int tiles, int splits, int* tile, int* split) {
+    if ((splits & 7) == 0) {
+        const int j = L >> 3;
+        *split = (L & 7) + 8 * (j / tiles);
+        *tile = j % tiles;
+    } else {
+        *tile = L % tiles;
+        *split = L / tiles;
+    }
+}
+
 }  // namespace sk

@@ -19,7 +19,7 @@ hipError_t launch_project(const Task* tasks, int count, int max_m, int max_k, in
                           int st_dtype, int pj_dtype, hipStream_t st);
 hipError_t launch_project_bf16(const Task* tasks, int count, int max_m, int max_k, int max_splits,
                                hipStream_t st);
-hipError_t launch_reduce_proj(const Task* tasks, int count, int max_m, int max_k, hipStream_t st);
+hipError_t launch_reduce_proj_f32(const Task* tasks, int count, int max_m, int max_k, hipStream_t st);
 hipError_t launch_rebuild(const Task* tasks, int count, int max_ell, int max_d, int st_dtype,
                           bool query, hipStream_t st);
 hipError_t launch_convert_rows(const double* src, int64_t lds, void* dst, int64_t ldd, int rows,
