@@ -1,28 +1,36 @@
 // k_trix.hip -- Householder tridiagonalisation of one symmetric eigen-problem
 // (the k x k Rayleigh-Ritz matrix of Algorithm "Simultaneous Iteration", or
-// the 2 ell x 2 ell buffer Gram of the exact FD shrink, Sec. 2.3) by a group
-// of P workgroups on one XCD.
+// the 2 ell x 2 ell buffer Gram of the exact FD shrink, Sec. 2.3) by P
+// one-wavefront workgroups ("members").
 //
-// The rows of A are dealt out cyclically (row i to member i mod P, at most
-// XR rows each) and stay in LDS for the whole reduction.  Column j's
-// reflector needs row j of the current matrix, A22 v over every row, and the
-// scalar p.v; each member computes its rows' part of A22 v, and one exchange
-// per column (through L2) gives every member all of p, the partial dots and
-// the not-yet-updated row j + 1.  Every member then derives w, applies the
-// rank-2 update to its own rows and forms row j + 1 of the updated matrix
-// itself, so the next reflector starts without another exchange.  All
-// members run the same arithmetic on the same inputs, so they agree bit for
-// bit; every sum has a fixed order (results repeat exactly).
+// Member m holds rows i = m + P q (q < XR) of A in registers, lane l the
+// columns c = l + 64 t; every vector of the reduction (the current and the
+// next reflector, p = tau A v, the shipped row) is kept the same way, so a
+// lane only ever touches its own columns and no LDS or barrier is needed.
+// Column j's reflector needs row j of the current matrix, A v over every row
+// and the scalar p.v; each member computes its rows' part of A v, and one
+// exchange per column gives every member all of p, the members' partial dots
+// and the not-yet-updated row j + 1.  Every member then derives w, applies
+// the rank-2 update to its own rows and forms row j + 1 of the updated
+// matrix itself, so the next reflector starts without another exchange.
+// All members run the same arithmetic on the same inputs, so they agree bit
+// for bit; every sum has a fixed order (results repeat exactly).
+//
+// The exchange goes through self-tagged 64-bit words: a double travels as two
+// words, each carrying 32 bits of it and the 32-bit tag of the step
+// ((launch epoch << 10) | step, the epoch growing with every launch).  Words
+// are written and read with relaxed agent-scope atomics, which are
+// single-copy atomic, so a reader that sees the step's tag in a word has that
+// word's payload, whatever the order in which the words arrive: no flag, no
+// fence.  Two buffers alternate by step parity; a member writes step s + 2
+// only after it has read every member's step s + 1, which every member
+// publishes only after reading step s, so no word is overwritten before it
+// is read.  Polls are bounded: a wait that gives up counts the failure in
+// info[3] (the solve then reports SK_EDEVICE); no wait can hang.
 //
 // Output as the one-workgroup reductions: W row j holds v_j beyond the
 // super-diagonal and W[j][j] = tau_j (H_j = I - tau_j v_j v_j^T, v_j[j+1] = 1),
 // U row 0 the diagonal of T and U row 1 its off-diagonal.
-//
-// Exchange words: each member publishes (epoch << 32 | step) in its flag
-// after its step data; the epoch grows with every launch, so flags left by
-// earlier launches never satisfy a wait.  A wait gives up after a bounded
-// number of polls and counts the failure in info[3] (the solve then reports
-// SK_EDEVICE); no wait can hang.
 #include <atomic>
 
 #include "sk_device.h"
@@ -31,10 +39,16 @@
 
 namespace sk {
 
-constexpr int XR = 16;          // rows per member
-constexpr int XTHREADS = 256;   // 16 rows x 16 lanes
+constexpr int XR = 4;             // rows per member
 constexpr int XNMAX = 512;
-constexpr int XSLOT = 2 * XNMAX + 32;  // p, row, partial dots
+constexpr int XT = XNMAX / 64;    // columns per lane
+// A step buffer of a problem of order n holds p (2 words per row, from word
+// 0), the shipped row (2 per column, from 2 n) and the members' partial dots
+// (2 per member, from 4 n): 4 n + 2 P words; the two buffers take at most
+// 9 n + 4 words, inside the n x n scratch slot for every n >= 10.
+__host__ __device__ __forceinline__ int x_slot_words(int n) { return 4 * n + 2 * ((n + 3) / 4); }
+
+__host__ __device__ __forceinline__ int x_members(int n) { return (n + XR - 1) / XR; }
 
 // Sums within each 16-lane row of a wavefront by DPP exchanges (every lane
 // of the row gets the row's sum): lane ^ 1, lane ^ 2 by quad permutes, then
@@ -62,41 +76,46 @@ __device__ __forceinline__ double x_wave_sum(double x) {
     x = x_sum16(x);
     return (x_lane(x, 0) + x_lane(x, 16)) + (x_lane(x, 32) + x_lane(x, 48));
 }
+// Element k of a register array (k uniform).  The entries arrive as values,
+// not as a reference to the array: a select among loads of the array could
+// be folded into one load at a computed address, which would move the array
+// out of registers.
+__device__ __forceinline__ double x_pick4(int k, double v0, double v1, double v2, double v3) {
+    return k == 0 ? v0 : k == 1 ? v1 : k == 2 ? v2 : v3;
+}
+__device__ __forceinline__ double x_pick8(int k, double v0, double v1, double v2, double v3, double v4, double v5,
+                                          double v6, double v7) {
+    return k < 4 ? x_pick4(k, v0, v1, v2, v3) : x_pick4(k - 4, v4, v5, v6, v7);
+}
+static_assert(XT == 8 && XR == 4, "x_at and x_row pick from 8 columns per lane and 4 rows per member");
+// entry c of a lane-distributed vector (c uniform)
+#define x_at(v, c) x_lane(x_pick8((c) >> 6, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]), (c) & 63)
+// column slot t of row slot q (q uniform) of the member's rows
+#define x_row(a, q, t) x_pick4(q, a[0][t], a[1][t], a[2][t], a[3][t])
 
-// The member group of workgroup b.  Workgroups are dealt to the 8 XCDs round
-// robin, so with `local` the P members of a problem share one XCD (b = xcd +
-// 8 (P g + m), m < P); otherwise they are consecutive (b = P problem + m) and
-// spread over the XCDs.
-struct XMap {
-    int problem, member;
-};
-__device__ __forceinline__ XMap x_map(int P, int local) {
-    const int b = blockIdx.x;
-    if (!local) return {b / P, b % P};
-    const int xcd = b & 7, slot = b >> 3;
-    return {(slot / P) * 8 + xcd, slot % P};
+__device__ __forceinline__ uint32_t x_tag(uint64_t epoch, int step) {
+    return (uint32_t)((epoch << 10) | (uint64_t)step);
+}
+__device__ __forceinline__ void x_put(uint64_t* w, int half, uint32_t tag, double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint64_t p = half ? (b >> 32) : (b & 0xffffffffull);
+    __hip_atomic_store(w + half, ((uint64_t)tag << 32) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t x_get(const uint64_t* w) {
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double x_join(uint64_t lo, uint64_t hi) {
+    return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
 }
 
-__host__ __device__ __forceinline__ int x_members(int n) { return (n + XR - 1) / XR; }
-
-// LDS row stride of the member's rows: 16 doubles past a multiple of 32, so
-// the four rows a wavefront touches at once fall in two bank halves.
-__host__ __device__ __forceinline__ int x_ald(int n) { return (n + 31) / 32 * 32 + 16; }
-// LDS (doubles) of a problem of order n: the rows, four waves' private
-// reflector pairs, and the arrivals p and row j + 1.
-__host__ __device__ __forceinline__ int x_lds_doubles(int n) { return XR * x_ald(n) + 10 * n; }
-
-// Row jj + 1 of the reflector pair, in every wavefront of every member (no
-// barrier): lane l holds xr[t] = x[c] for c = jj + lane + 64 t of the row x
-// that column jj reduces (x[jj + 1] = alpha).  Writes v[jj + 1 ..] into this
-// wave's v (v[jj + 1] = 1) and returns tau; member 0's wave 0 also writes
-// the reflector (W row jj), the diagonal entry and beta.  Identical
-// arithmetic in every wavefront and member.
-template <int LPL>
-__device__ __forceinline__ double trix_reflector_w(int jj, int n, const double (&xr)[LPL], double xn2, double* v,
-                                                   double* Wr, double* U, int lu, bool writer) {
+// Reflector of column jj from the row x that it reduces (x[jj + 1] = alpha),
+// in every member (no exchange): v[jj + 1 ..] into v (v[jj + 1] = 1, zero
+// before), returns tau; member 0 also writes the reflector (W row jj), the
+// diagonal entry and beta.  xn2 = |x beyond jj + 1|^2.
+__device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[XT], double xn2, double (&v)[XT],
+                                              double* Wr, double* U, int lu, bool writer) {
     const int lane = threadIdx.x & 63;
-    const double alpha = x_lane(xr[0], 1);  // x[jj + 1]
+    const double alpha = x_at(x, jj + 1);
     double beta = alpha, tau = 0.0, scal = 0.0;
     if (xn2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -104,301 +123,282 @@ __device__ __forceinline__ double trix_reflector_w(int jj, int n, const double (
         scal = 1.0 / (alpha - beta);
     }
 #pragma unroll
-    for (int t = 0; t < LPL; ++t) {
-        const int c = jj + lane + 64 * t;
-        if (c > jj && c < n) v[c] = (c == jj + 1) ? 1.0 : xr[t] * scal;
+    for (int t = 0; t < XT; ++t) {
+        const int c = lane + 64 * t;
+        v[t] = (c <= jj || c >= n) ? 0.0 : (c == jj + 1) ? 1.0 : x[t] * scal;
     }
     if (writer) {
+        const double xjj = x_at(x, jj);
         if (lane == 0) {
-            U[jj] = xr[0];
+            U[jj] = xjj;
             U[lu + jj] = beta;
             Wr[(int64_t)jj * n + jj] = tau;
         }
 #pragma unroll
-        for (int t = 0; t < LPL; ++t) {
-            const int c = jj + lane + 64 * t;
-            if (c > jj + 1 && c < n) Wr[(int64_t)jj * n + c] = xr[t] * scal;
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            if (c > jj + 1 && c < n) Wr[(int64_t)jj * n + c] = v[t];
         }
     }
     return tau;
 }
 
-// Exchange of step j, wave 0 only: this member's p (pl) and partial dot (the
-// sum of pvw), row j + 1 as it stands if this member owns it; then every
-// member's data into pb, rb and *pvs.  Returns false on a timed-out wait.
-__device__ __forceinline__ bool trix_exchange(int j, int n, int P, int member, const double* Al, int ald,
-                                              const double* pl, const double* pvw, double* xch, uint64_t* flags,
-                                              uint64_t epoch, double* pb, double* rb, double* pvs) {
+// Publishes step s (column jj = s - 1): p of this member's rows beyond jj,
+// its partial dot, and row jj + 1 (columns from jj + 1) if this member holds
+// it; then reads every member's step s into p, row and the dot sum.
+// Returns false on a timed-out wait.
+__device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, const double (&a)[XR][XT],
+                                           const double (&pl)[XR], double dot, uint64_t* xw, uint64_t epoch,
+                                           double (&p)[XT], double (&row)[XT], double* dsum) {
     const int lane = threadIdx.x & 63;
-    double* slot = xch + (j & 1) * XSLOT;
-    if (lane < XR) {
-        const int i = member + P * lane;
-        if (i > j && i < n) slot[i] = pl[lane];
+    const int jj = s - 1;
+    const uint32_t tag = x_tag(epoch, s);
+    uint64_t* buf = xw + (s & 1) * x_slot_words(n);
+    const int XW_P = 0, XW_ROW = 2 * n, XW_DOT = 4 * n;
+    if (lane < 2 * XR) {
+        const int q = lane >> 1, i = member + P * q;
+        const double v = x_pick4(q, pl[0], pl[1], pl[2], pl[3]);
+        if (i > jj && i < n) x_put(buf + XW_P + 2 * i, lane & 1, tag, v);
+    } else if (lane < 2 * XR + 2) {
+        x_put(buf + XW_DOT + 2 * member, lane & 1, tag, dot);
     }
-    if (lane == 0) slot[2 * XNMAX + member] = (pvw[0] + pvw[1]) + (pvw[2] + pvw[3]);
-    if (member == (j + 1) % P) {
-        const double* ar = Al + ((j + 1) / P) * ald;
-        for (int c = j + 1 + lane; c < n; c += 64) slot[XNMAX + c] = ar[c];
-    }
-    const uint64_t target = xwg_flag(epoch, (unsigned)(j + 1));
-    xwg_publish(flags + member, target);
-    const bool ok = xwg_wait(flags, P, target);
-    double pvv = lane < P ? slot[2 * XNMAX + lane] : 0.0;
-    constexpr int LPL = XNMAX / 64;
-    double pr[LPL], rr_[LPL];
+    if (member == (jj + 1) % P) {
+        const int q = (jj + 1) / P;
 #pragma unroll
-    for (int u = 0; u < LPL; ++u) {
-        const int c = j + 1 + lane + 64 * u;
-        pr[u] = c < n ? slot[c] : 0.0;
-        rr_[u] = c < n ? slot[XNMAX + c] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < LPL; ++u) {
-        const int c = j + 1 + lane + 64 * u;
-        if (c < n) {
-            pb[c] = pr[u];
-            rb[c] = rr_[u];
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            if (c > jj && c < n) {
+                const double v = x_row(a, q, t);
+                x_put(buf + XW_ROW + 2 * c, 0, tag, v);
+                x_put(buf + XW_ROW + 2 * c, 1, tag, v);
+            }
         }
     }
-    double sum = 0.0;  // partial dots in member order (the same sum in every member)
-    for (int m = 0; m < P; ++m) sum += x_lane(pvv, m);
-    if (lane == 0) *pvs = sum;
+    // every word of the step this lane needs, until all carry the tag
+    uint64_t wp[XT][2], wr[XT][2], wd[2][2];
+    bool ok = false;
+    for (unsigned polls = 0; polls <= XWG_POLLS; ++polls) {
+        bool mine = true;
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            if (c > jj && c < n) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    wp[t][h] = x_get(buf + XW_P + 2 * c + h);
+                    wr[t][h] = x_get(buf + XW_ROW + 2 * c + h);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int m = lane + 64 * k;
+            if (m < P)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) wd[k][h] = x_get(buf + XW_DOT + 2 * m + h);
+        }
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            if (c > jj && c < n)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) mine &= (uint32_t)(wp[t][h] >> 32) == tag && (uint32_t)(wr[t][h] >> 32) == tag;
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (lane + 64 * k < P)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) mine &= (uint32_t)(wd[k][h] >> 32) == tag;
+        if (__all(mine)) {
+            ok = true;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+#pragma unroll
+    for (int t = 0; t < XT; ++t) {
+        const int c = lane + 64 * t;
+        const bool live = c > jj && c < n;
+        p[t] = live ? x_join(wp[t][0], wp[t][1]) : 0.0;
+        row[t] = live ? x_join(wr[t][0], wr[t][1]) : 0.0;
+    }
+    // partial dots in member order through a fixed tree (the same sum in every member)
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (lane + 64 * k < P) d += x_join(wd[k][0], wd[k][1]);
+    *dsum = x_wave_sum(d);
     return ok;
 }
 
-// One pass over this thread's part of its row: the rank-2 update of column
-// j (skipped for j < 0, the first column) and the dot with the reflector vb
-// over columns from jv; the loads of four columns are issued together.
-__device__ __forceinline__ double trix_row_pass(double* ar, int c0, int n, int jv, const double* va, const double* pb,
-                                                const double* vb, double K, double vi, double wi, bool update) {
-    double acc = 0.0;
-    for (int cb = c0; cb < n; cb += 64) {
-        double av[4], vv[4], pv[4], bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = min(cb + 16 * u, n - 1);
-            av[u] = ar[c];
-            bv[u] = vb[c];
-            if (update) {
-                vv[u] = va[c];
-                pv[u] = pb[c];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = cb + 16 * u;
-            if (c < n) {
-                double a = av[u];
-                if (update) {
-                    const double wc = fma(-K, vv[u], pv[u]);
-                    a = fma(-vi, wc, fma(-wi, vv[u], a));
-                    ar[c] = a;
-                }
-                if (c >= jv) acc = fma(a, bv[u], acc);
-            }
-        }
-    }
-    return acc;
-}
-
 __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, double* __restrict__ Wr,
-                          double* __restrict__ U, int lu, double* xch, uint64_t* flags, int* info, uint64_t epoch,
-                          int member) {
-    extern __shared__ double lds[];
-    constexpr int LPL = XNMAX / 64;
+                          double* __restrict__ U, int lu, uint64_t* xw, int* info, uint64_t epoch, int member) {
     const int P = x_members(n);
-    const int ald = x_ald(n);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = tid >> 4, part = tid & 15;  // row slot and lane within it
-    double* Al = lds;                          // [XR][ald] this member's rows
-    double* va = lds + XR * ald + wave * 2 * n;  // this wave's reflector of the current column
-    double* vb = va + n;                       // ... and of the next column
-    double* pb = lds + XR * ald + 8 * n;       // p of every row, on arrival
-    double* rb = pb + n;                       // shipped row j + 1, on arrival
-    __shared__ double pl[XR], pvw[4], pvs_s;
-    __shared__ int bad;
-    const int my_i = member + P * r;           // this thread's row
-    const bool has_row = my_i < n;
-    const bool writer = member == 0 && wave == 0;
-    for (int e = tid; e < XR * n; e += XTHREADS) {
-        const int rr = e / n, c = e - rr * n, i = member + P * rr;
-        Al[rr * ald + c] = i < n ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
-    }
-    if (tid == 0) bad = 0;
-    // (n >= 3 here: the launcher takes orders from trix_min_n() >= 8)
-    // column 0 in every wave: row 0 of A, its reflector into va
-    double tau;
-    {
-        double xr[LPL], s2 = 0.0;
+    const int lane = threadIdx.x & 63;
+    const bool writer = member == 0;
+    double a[XR][XT];  // rows member + P q, columns lane + 64 t
 #pragma unroll
-        for (int t = 0; t < LPL; ++t) {
+    for (int q = 0; q < XR; ++q) {
+        const int i = member + P * q;
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
             const int c = lane + 64 * t;
-            xr[t] = c < n ? 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]) : 0.0;
-            if (c >= 2 && c < n) s2 = fma(xr[t], xr[t], s2);
+            a[q][t] = (i < n && c < n) ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
+        }
+    }
+    // (n >= 16 here: the launcher takes orders from trix_min_n() >= 16)
+    // column 0: row 0 of A, its reflector, p of this member's rows
+    double va[XT], vb[XT], p[XT], row[XT], x[XT];
+    double tau, dsum;
+    {
+        double s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            x[t] = c < n ? 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]) : 0.0;
+            if (c >= 2 && c < n) s2 = fma(x[t], x[t], s2);
         }
         s2 = x_wave_sum(s2);
-        tau = trix_reflector_w<LPL>(0, n, xr, s2, va, Wr, U, lu, writer);
+        tau = x_reflector(0, n, x, s2, va, Wr, U, lu, writer);
     }
-    __syncthreads();  // rows in LDS; every wave's va
-    {
-        const bool live = has_row && my_i > 0;
-        double acc = 0.0;
-        if (live) acc = trix_row_pass(Al + r * ald, 1 + part, n, 1, va, pb, va, 0.0, 0.0, 0.0, false);
-        acc = x_sum16(acc);
-        const double pi = tau * acc;
-        if (part == 0) pl[r] = live ? pi : 0.0;
-        const double pv = (live && part == 0) ? pi * va[my_i] : 0.0;
-        const double wsum = (x_lane(pv, 0) + x_lane(pv, 16)) + (x_lane(pv, 32) + x_lane(pv, 48));
-        if (lane == 0) pvw[wave] = wsum;
-    }
-    __syncthreads();
-    if (wave == 0 && !trix_exchange(0, n, P, member, Al, ald, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) &&
-        lane == 0)
-        bad = 1;
-    __syncthreads();
-    for (int j = 0; j + 2 < n && !bad; ++j) {
-        // (1) in every wave: w = p - K v (on the fly) and row j + 1 after this
-        // column's update (lane l: columns j + 1 + l + 64 t), with the squared
-        // norm of its part beyond j + 2
-        const double K = 0.5 * tau * pvs_s;
-        const double w1 = fma(-K, va[j + 1], pb[j + 1]);
-        const bool next = j + 3 < n;
-        double xr[LPL], s2 = 0.0;
+    double pl[XR], dot = 0.0;
 #pragma unroll
-        for (int t = 0; t < LPL; ++t) {
-            const int c = j + 1 + lane + 64 * t;
-            double x = 0.0;
-            if (c < n) {
-                const double wc = fma(-K, va[c], pb[c]);
-                x = fma(-1.0, wc, fma(-w1, va[c], rb[c]));
-                if (c >= j + 3) s2 = fma(x, x, s2);
-            }
-            xr[t] = x;
+    for (int q = 0; q < XR; ++q) {
+        const int i = member + P * q;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < XT; ++t) acc = fma(a[q][t], va[t], acc);  // va is zero up to column 0
+        acc = x_wave_sum(acc);
+        pl[q] = (i > 0 && i < n) ? tau * acc : 0.0;
+        if (i > 0 && i < n) dot = fma(pl[q], x_at(va, i), dot);
+    }
+    bool bad = !x_exchange(1, n, P, member, a, pl, dot, xw, epoch, p, row, &dsum);
+    for (int j = 0; j + 2 < n && !bad; ++j) {
+        // row j + 1 after this column's update, w = p - K v on the fly, with
+        // the squared norm of its part beyond j + 2
+        const double K = 0.5 * tau * dsum;
+        const double w1 = fma(-K, x_at(va, j + 1), x_at(p, j + 1));
+        const bool next = j + 3 < n;
+        double wv[XT], s2 = 0.0;
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+            const int c = lane + 64 * t;
+            wv[t] = fma(-K, va[t], p[t]);
+            x[t] = (c > j && c < n) ? fma(-1.0, wv[t], fma(-w1, va[t], row[t])) : 0.0;
+            if (c >= j + 3 && c < n) s2 = fma(x[t], x[t], s2);
         }
-        // (2) the next column's reflector, in every wave (its v into vb)
         double tau2 = 0.0;
         if (next) {
             s2 = x_wave_sum(s2);
-            tau2 = trix_reflector_w<LPL>(j + 1, n, xr, s2, vb, Wr, U, lu, writer);
+            tau2 = x_reflector(j + 1, n, x, s2, vb, Wr, U, lu, writer);
         } else {  // j = n - 3: the last 2 x 2 block of T
-            const double last = x_lane(xr[0], 1);  // row n - 2, column n - 1
+            const double d0 = x_at(x, n - 2), e0 = x_at(x, n - 1);
             if (writer && lane == 0) {
-                U[n - 2] = xr[0];
-                U[lu + n - 2] = last;
+                U[n - 2] = d0;
+                U[lu + n - 2] = e0;
                 Wr[(int64_t)(n - 2) * n + n - 2] = 0.0;
                 Wr[(int64_t)(n - 1) * n + n - 1] = 0.0;
             }
         }
-        __builtin_amdgcn_wave_barrier();  // the wave's vb before its reads
-        // (3) one pass over this member's rows: the update of column j and
-        // the products with the next reflector
-        {
-            const bool live = has_row && my_i > j, live2 = has_row && my_i > j + 1;
-            double acc = 0.0;
-            if (live) {
-                const double vi = va[my_i], wi = fma(-K, vi, pb[my_i]);
-                acc = trix_row_pass(Al + r * ald, j + 1 + part, n, j + 2, va, pb, vb, K, vi, wi, true);
-            }
-            if (next) {
-                acc = x_sum16(acc);
-                const double pi = tau2 * acc;
-                if (part == 0) pl[r] = live2 ? pi : 0.0;
-                const double pv = (live2 && part == 0) ? pi * vb[my_i] : 0.0;
-                const double wsum = (x_lane(pv, 0) + x_lane(pv, 16)) + (x_lane(pv, 32) + x_lane(pv, 48));
-                if (lane == 0) pvw[wave] = wsum;
+        // the update of column j on this member's rows and their products
+        // with the next reflector
+        dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const int i = member + P * q;
+            if (i > j && i < n) {  // uniform
+                const double vi = x_at(va, i), wi = fma(-K, vi, x_at(p, i));
+                double acc = 0.0;
+#pragma unroll
+                for (int t = 0; t < XT; ++t) {
+                    const int c = lane + 64 * t;
+                    if (c > j && c < n) a[q][t] = fma(-vi, wv[t], fma(-wi, va[t], a[q][t]));
+                    acc = fma(a[q][t], vb[t], acc);  // vb is zero up to column j + 1
+                }
+                if (next && i > j + 1) {
+                    acc = x_wave_sum(acc);
+                    pl[q] = tau2 * acc;
+                    dot = fma(pl[q], x_at(vb, i), dot);
+                }
             }
         }
-        __syncthreads();
         if (!next) break;
-        // (4) exchange of column j + 1
-        if (wave == 0 &&
-            !trix_exchange(j + 1, n, P, member, Al, ald, pl, pvw, xch, flags, epoch, pb, rb, &pvs_s) && lane == 0)
-            bad = 1;
-        __syncthreads();
-        double* t = va;
-        va = vb;
-        vb = t;
+        bad = !x_exchange(j + 2, n, P, member, a, pl, dot, xw, epoch, p, row, &dsum);
+#pragma unroll
+        for (int t = 0; t < XT; ++t) va[t] = vb[t];
         tau = tau2;
     }
     if (bad) {
-        if (tid == 0 && member == 0) atomicAdd(&info[3], 1);
+        if (lane == 0) atomicAdd(&info[3], 1);
         return;
     }
-    // A[n-1][n-1] after every update: its owner holds it
-    if (member == (n - 1) % P && tid == 0) U[n - 1] = Al[((n - 1) / P) * ald + n - 1];
+    // A[n-1][n-1] after every update: its holder writes it
+    if (member == (n - 1) % P) {
+        const int q = (n - 1) / P, t = (n - 1) >> 6;
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < XT; ++u)
+            if (u == t) v = x_row(a, q, u);
+        v = x_lane(v, (n - 1) & 63);
+        if (lane == 0) U[n - 1] = v;
+    }
 }
 
 // Task form: eigen-problems of shrink / query tasks that the tridiagonal
-// solver takes and whose size is in [xmin, XNMAX].
-__global__ __launch_bounds__(XTHREADS) void k_tri_reduce_x(const Task* tasks, int count, int P, int xmin,
-                                                            uint64_t epoch, int local) {
-    const XMap mp = x_map(P, local);
-    if (mp.problem >= count) return;
-    const Task& t = tasks[mp.problem];
+// solver takes and whose size is in [xmin, XNMAX]; workgroup b is member
+// b mod P of problem b / P.
+__global__ __launch_bounds__(64) void k_tri_reduce_x(const Task* tasks, int count, int P, int xmin, uint64_t epoch) {
+    const int problem = blockIdx.x / P, member = blockIdx.x % P;
+    if (problem >= count) return;
+    const Task& t = tasks[problem];
     if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
     const int n = eig_n(t);
-    if (n < xmin || n > XNMAX || mp.member >= x_members(n)) return;
+    if (n < xmin || n > XNMAX || member >= x_members(n)) return;
     const SkDev* s = t.s;
     const bool rnd = t.kind == T_SHRINK_RAND;
     trix_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U], s->sld[S_U],
-              s->slot[S_EV], s->xflags, s->info, epoch, mp.member);
+              (uint64_t*)s->slot[S_EV], s->info, epoch, member);
 }
 
 static std::atomic<uint64_t> g_xwg_epoch{0};
 uint64_t xwg_next_epoch() { return ++g_xwg_epoch; }
-
-// Members of a problem on one XCD (SK_TRIX_LOCAL=1) or spread (0).
-static int trix_local() {
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("SK_TRIX_LOCAL");
-        v = e ? atoi(e) : 0;
-    }
-    return v;
-}
 
 int trix_min_n() {
     static int v = -1;
     if (v < 0) {
         const char* e = getenv("SK_TRIX_MIN_N");
         v = e ? atoi(e) : 160;
-        if (v < 8) v = 8;
+        if (v < 16) v = 16;  // the step buffers fit the n x n scratch slot
     }
     return v;
 }
 
 // Every task with xmin <= n <= XNMAX (that the tridiagonal solver takes) by
-// cooperative launches of 8 P ceil(count / 8) workgroups, P = members of the
-// largest problem (smaller problems leave their surplus members idle); as
-// many tasks per launch as can be resident at once.
+// cooperative launches of P workgroups per task, P = members of the largest
+// problem (smaller problems leave their surplus members idle); as many tasks
+// per launch as can be resident at once.  The step buffers live in the
+// eigen-solver's scratch slot (at least n x n doubles).
 hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int nmax = std::min(max_n, XNMAX);
     int P = x_members(nmax);
-    const size_t lds = sizeof(double) * (size_t)x_lds_doubles(nmax);
     static int per_cu = -1, cus = 0;
     if (per_cu < 0) {
         int dev = 0;
-        if (hipFuncSetAttribute((const void*)k_tri_reduce_x, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * x_lds_doubles(XNMAX))) != hipSuccess ||
-            hipGetDevice(&dev) != hipSuccess ||
+        if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, XTHREADS,
-                                                         sizeof(double) * x_lds_doubles(XNMAX)) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, 64, 0) != hipSuccess ||
             per_cu < 1)
             return hipErrorInvalidConfiguration;
     }
-    // resident workgroups at the largest LDS size; 8 P per group of 8 tasks
-    const int chunk = std::max(8, ((per_cu * cus) / (8 * P)) * 8);
-    int xmin = trix_min_n(), local = trix_local();
+    const int chunk = std::max(1, (per_cu * cus) / P);
+    int xmin = trix_min_n();
     for (int off = 0; off < count; off += chunk) {
         const Task* tl = tasks + off;
         int cnt = std::min(chunk, count - off);
-        const int groups = (cnt + 7) / 8;
         uint64_t epoch = xwg_next_epoch();
-        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&P, (void*)&xmin, (void*)&epoch, (void*)&local};
-        const unsigned grid = local ? (unsigned)(8 * P * groups) : (unsigned)(P * cnt);
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_tri_reduce_x, dim3(grid), dim3(XTHREADS), args,
-                                                  (unsigned)lds, st);
+        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&P, (void*)&xmin, (void*)&epoch};
+        hipError_t e = hipLaunchCooperativeKernel((const void*)k_tri_reduce_x, dim3((unsigned)(P * cnt)), dim3(64),
+                                                  args, 0, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

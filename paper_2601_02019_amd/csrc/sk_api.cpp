@@ -90,14 +90,24 @@ static void mark_coop(Task& t, const sketch_s* h) {
 // Split-K plan: about 512 workgroups in total for a launch, the split count
 // rounded up to a multiple of 8 so that each K chunk stays on one XCD
 // (xcd_tile_split), and chunks of at least 128 columns.
-static void splitk_plan(int tiles, int d, int* splits, int* chunk) {
-    int s = std::max(1, (512 + tiles - 1) / tiles);
+static void splitk_plan(int tiles, int d, int* splits, int* chunk, int target = 512) {
+    int s = std::max(1, (target + tiles - 1) / tiles);
     if (s > 1) s = (s + 7) / 8 * 8;
     s = std::min(s, std::max(1, (d + 127) / 128));
     int kc = (int)round_up((d + s - 1) / s, 16);
     s = (d + kc - 1) / kc;
     *splits = std::max(1, s);
     *chunk = kc;
+}
+
+// Workgroups the Gram's split-K plan aims at (SK_GRAM_SPLITK_TARGET).
+static int gram_splitk_target() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("SK_GRAM_SPLITK_TARGET");
+        v = e ? std::max(1, atoi(e)) : 512;
+    }
+    return v;
 }
 
 static sk_status build_device_state(sketch_t h) {
@@ -117,7 +127,7 @@ static sk_status build_device_state(sketch_t h) {
     s.seed = h->cfg.seed;
     s.stream = h->cfg.stream_id;
     const int ntg = (n2 + 63) / 64;
-    splitk_plan(ntg * (ntg + 1) / 2, d, &s.sg, &s.kcg);
+    splitk_plan(ntg * (ntg + 1) / 2, d, &s.sg, &s.kcg, gram_splitk_target());
     splitk_plan(ntg * ((kk + 63) / 64), d, &s.sp, &s.kcp);
     const size_t es = (size_t)dtype_size(h->st);
     for (int b = 0; b < 2; ++b) {

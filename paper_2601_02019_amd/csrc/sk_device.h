@@ -50,7 +50,7 @@ struct SkDev {
     uint64_t seed, stream;
     double* coop;              // cooperative-solver scratch (COOP_* layout)
     int32_t* coop_ctrl;        // [0..1] rotation counters, [8..9] grid barrier
-    uint64_t* xflags;          // 64 exchange flags of the multi-workgroup reduction
+    uint64_t* xflags;          // 64 exchange flags of the multi-workgroup CholeskyQR
 };
 
 // Cooperative scratch layout (doubles): 16 pair-block rotations of 32 x 32,
