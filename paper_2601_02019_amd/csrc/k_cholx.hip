@@ -42,19 +42,118 @@ __device__ __forceinline__ double cx_bcast(double x, int lane) {
 // L^T is published in flags[p]
 __device__ __forceinline__ unsigned cx_stage(int pass) { return (unsigned)(pass + 1); }
 
-// rows of Y per block of the Q step (the block and one column block of L^T
-// share the LDS; chosen from the launch's largest K, so that every task of
-// the launch fits the LDS sized for it)
-__host__ __device__ __forceinline__ int cx_qrows(int K) { return K <= 256 ? 32 : 16; }
-__host__ __device__ __forceinline__ size_t cx_lds_doubles(int K) {
-    const size_t a = (size_t)CB * K, b = (size_t)cx_qrows(K) * K + (size_t)K * CB;
-    return a > b ? a : b;
+// dynamic LDS: this member's rows of W
+__host__ __device__ __forceinline__ size_t cx_lds_doubles(int K) { return (size_t)CB * K; }
+
+// Barrier over LDS only: waits for this wave's LDS accesses, not for its
+// global loads (a plain __syncthreads also drains the global loads in
+// flight, which would serialise the prefetch of L^T below).
+__device__ __forceinline__ void cx_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Q = src L^{-T} for the row blocks of QR rows from QR member, stride QR P,
+// right-looking by column blocks of 16.  Thread t keeps an 8-row x 4-column
+// tile of the block in registers (row group t mod RG, RG = QR / 8; column
+// group t / RG).  For block p the owners of its 16 columns hand them to LDS,
+// QR threads solve q L_pp^T = z row by row, and every thread with later
+// columns subtracts q L[its columns, block p]^T (its 4 x 16 entries of L^T,
+// loaded while the solve runs; 8 x 16 q values from LDS per 512 FMAs).  Two
+// LDS buffers alternate by block, so one LDS-only barrier on each side of
+// the solve suffices.
+template <int QR>
+__device__ __forceinline__ void cholqr_x_qstep(const double* src, double* dst, const double* Lt, int m, int k, int K,
+                                               int ldk, int member, int P) {
+    constexpr int RG = QR / 8;  // row groups of 8 (K = 64 * 4 * (CTH / RG / 64) columns)
+    __shared__ double Zs[2][QR][CB + 1], Lp[2][CB][CB + 1], dinv[2][CB];
+    const int tid = threadIdx.x;
+    const int rg = tid % RG, c0 = 4 * (tid / RG);  // rows 8 rg .. 8 rg + 7, columns c0 .. c0 + 3
+    for (int r0 = QR * member; r0 < m; r0 += QR * P) {
+        double y[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int row = r0 + 8 * rg + i;
+#pragma unroll
+            for (int jc = 0; jc < 4; ++jc) {
+                const int c = c0 + jc;
+                y[i][jc] = (row < m && c < k) ? src[(int64_t)row * ldk + c] : 0.0;
+            }
+        }
+        for (int p = 0; p < K / CB; ++p) {
+            const int cp = CB * p, bf = p & 1;
+            // block p's columns to LDS; its diagonal block of L and the
+            // reciprocals of its pivots (a dropped column has pivot 0: 0)
+            if (c0 >= cp && c0 < cp + CB)
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int jc = 0; jc < 4; ++jc) Zs[bf][8 * rg + i][c0 - cp + jc] = y[i][jc];
+            {
+                const int i = tid >> 4, j = tid & 15;  // L_pp[i][j] = L^T[cp + j][cp + i]
+                const double l = Lt[(int64_t)(cp + j) * K + cp + i];
+                Lp[bf][i][j] = j <= i ? l : 0.0;
+                if (i == j) dinv[bf][i] = l != 0.0 ? 1.0 / l : 0.0;
+            }
+            // L[c, block p] for this thread's later columns, in flight during the solve
+            const bool later = c0 >= cp + CB && c0 < K;
+            double lc[CB][4];
+#pragma unroll
+            for (int i = 0; i < CB; ++i)
+#pragma unroll
+                for (int jc = 0; jc < 4; ++jc) lc[i][jc] = later ? Lt[(int64_t)(cp + i) * K + c0 + jc] : 0.0;
+            cx_lds_barrier();
+            if (tid < QR) {
+                double q[CB];
+#pragma unroll
+                for (int i = 0; i < CB; ++i) {
+                    double v = Zs[bf][tid][i];
+#pragma unroll
+                    for (int j = 0; j < i; ++j) v = fma(-Lp[bf][i][j], q[j], v);
+                    q[i] = v * dinv[bf][i];
+                }
+#pragma unroll
+                for (int i = 0; i < CB; ++i) Zs[bf][tid][i] = q[i];
+            }
+            cx_lds_barrier();
+            if (c0 >= cp && c0 < cp + CB) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int jc = 0; jc < 4; ++jc) y[i][jc] = Zs[bf][8 * rg + i][c0 - cp + jc];
+            } else if (later) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    double qv[CB];
+#pragma unroll
+                    for (int l = 0; l < CB; ++l) qv[l] = Zs[bf][8 * rg + i][l];
+#pragma unroll
+                    for (int jc = 0; jc < 4; ++jc) {
+                        double acc = y[i][jc];
+#pragma unroll
+                        for (int l = 0; l < CB; ++l) acc = fma(-qv[l], lc[l][jc], acc);
+                        y[i][jc] = acc;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int row = r0 + 8 * rg + i;
+#pragma unroll
+            for (int jc = 0; jc < 4; ++jc) {
+                const int c = c0 + jc;
+                if (row < m && c < k) dst[(int64_t)row * ldk + c] = y[i][jc];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // One CholeskyQR pass: W (k x k, slot S_W, the Gram of src computed before
 // the launch) -> L; dst = src L^{-T}.
-__device__ void cholqr_x_body(const Task& t, int src_slot, int dst_slot, int member, uint64_t epoch, int QR,
-                              int pass) {
+__device__ void cholqr_x_body(const Task& t, int src_slot, int dst_slot, int member, uint64_t epoch, int pass) {
     extern __shared__ double lds[];
     const SkDev* s = t.s;
     const int m = t.m, k = s->k, K = cx_members(k) * CB, P = K / CB;
@@ -64,8 +163,6 @@ __device__ void cholqr_x_body(const Task& t, int src_slot, int dst_slot, int mem
     double* dst = s->slot[dst_slot];
     const double* Wg = s->slot[S_W];
     double* Wb = lds;                 // [CB][K] this member's rows of W
-    double* Qs = lds;                 // [QR][K] rows of Q (Q step, after the factor)
-    double* Lc = lds + QR * K;        // [K][CB] one column block of L^T (Q step)
     double* Lt = s->slot[S_EA];       // K x K: L^T, block row p from member p
     uint64_t* flags = s->xflags;
     __shared__ double Ld[CB][CB + 1], rd[CB], d0[CB], coef[CB * CB];
@@ -199,93 +296,21 @@ __device__ void cholqr_x_body(const Task& t, int src_slot, int dst_slot, int mem
         return;
     }
     // ---- 5. Q = src L^{-T} for row blocks member, member + P, ...
-    for (int r0 = QR * member; r0 < m; r0 += QR * P) {
-        {
-            const int c0 = tid, c1 = tid + CTH;
-            for (int rr0 = 0; rr0 < QR; rr0 += 16) {
-                double y0[16], y1[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int row = r0 + rr0 + u;
-                    y0[u] = (row < m && c0 < k) ? src[(int64_t)row * ldk + c0] : 0.0;
-                    y1[u] = (row < m && c1 < k) ? src[(int64_t)row * ldk + c1] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    if (c0 < K) Qs[(rr0 + u) * K + c0] = y0[u];
-                    if (c1 < K) Qs[(rr0 + u) * K + c1] = y1[u];
-                }
-            }
-        }
-        for (int p = 0; p < P; ++p) {
-            const int cp = CB * p;
-            __syncthreads();
-            // column block p of L^T, rows 0 .. cp + 15
-            for (int base = 0, ne = (cp + CB) * CB; base < ne; base += 16 * CTH) {
-                double lv[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int e = base + tid + CTH * u;
-                    lv[u] = e < ne ? Lt[(int64_t)(e >> 4) * K + cp + (e & 15)] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int e = base + tid + CTH * u;
-                    if (e < ne) Lc[e] = lv[u];
-                }
-            }
-            __syncthreads();
-            // z = y[:, block p] - q[:, blocks < p] L[block p, blocks < p]^T
-            for (int e = tid; e < QR * CB; e += CTH) {
-                const int rr = e >> 4, c = e & 15;
-                double z0 = Qs[rr * K + cp + c], z1 = 0.0;
-                for (int j = 0; j < cp; j += 2) {
-                    z0 = fma(-Qs[rr * K + j], Lc[j * CB + c], z0);
-                    z1 = fma(-Qs[rr * K + j + 1], Lc[(j + 1) * CB + c], z1);
-                }
-                Qs[rr * K + cp + c] = z0 + z1;
-            }
-            __syncthreads();
-            // q[:, block p] L_pp^T = z, one row per thread (a zero pivot --
-            // a dropped column -- gives a zero column)
-            if (tid < QR) {
-                double q[CB];
-#pragma unroll
-                for (int i = 0; i < CB; ++i) {
-                    double v = Qs[tid * K + cp + i];
-#pragma unroll
-                    for (int j = 0; j < i; ++j) v = fma(-Lc[(cp + j) * CB + i], q[j], v);
-                    const double lii = Lc[(cp + i) * CB + i];
-                    q[i] = lii != 0.0 ? v / lii : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < CB; ++i) Qs[tid * K + cp + i] = q[i];
-            }
-        }
-        __syncthreads();
-        {
-            const int c0 = tid, c1 = tid + CTH;
-#pragma unroll 4
-            for (int rr = 0; rr < QR; ++rr) {
-                const int row = r0 + rr;
-                if (row < m && c0 < k) dst[(int64_t)row * ldk + c0] = Qs[rr * K + c0];
-                if (row < m && c1 < k) dst[(int64_t)row * ldk + c1] = Qs[rr * K + c1];
-            }
-        }
-        __syncthreads();
-    }
+    // 256 threads x 4 columns cover K <= 256 with 32-row blocks, K <= 512 with 16
+    if (K <= 256) cholqr_x_qstep<32>(src, dst, Lt, m, k, K, ldk, member, P);
+    else cholqr_x_qstep<16>(src, dst, Lt, m, k, K, ldk, member, P);
 }
 
 // Members b of task i are workgroups P i + b (consecutive: spread over the
 // XCDs); tasks with fewer members leave the surplus idle.
 __global__ __launch_bounds__(CTH) void k_cholqr_x(const Task* tasks, int count, int Pmax, int src_slot,
-                                                  int dst_slot, uint64_t epoch, int qrows, int pass) {
+                                                  int dst_slot, uint64_t epoch, int pass) {
     const int task = blockIdx.x / Pmax, member = blockIdx.x % Pmax;
     if (task >= count) return;
     const Task& t = tasks[task];
     if (t.kind != T_SHRINK_RAND || !(t.flags & TF_X_CHOL)) return;
     if (member >= cx_members(t.s->k)) return;
-    cholqr_x_body(t, src_slot, dst_slot, member, epoch, qrows, pass);
+    cholqr_x_body(t, src_slot, dst_slot, member, epoch, pass);
 }
 
 // One CholeskyQR pass (W in slot S_W already) of every task flagged
@@ -313,9 +338,8 @@ hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int src_slot
         const Task* tl = tasks + off;
         int cnt = std::min(chunk, count - off);
         uint64_t epoch = xwg_next_epoch();
-        int pm = Pmax, a = src_slot, b = dst_slot, qr = cx_qrows(K), ps = pass;
-        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&pm, (void*)&a, (void*)&b, (void*)&epoch, (void*)&qr,
-                        (void*)&ps};
+        int pm = Pmax, a = src_slot, b = dst_slot, ps = pass;
+        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&pm, (void*)&a, (void*)&b, (void*)&epoch, (void*)&ps};
         hipError_t e = hipLaunchCooperativeKernel((const void*)k_cholqr_x, dim3((unsigned)(Pmax * cnt)), dim3(CTH),
                                                   args, (unsigned)lds, st);
         if (e != hipSuccess) return e;

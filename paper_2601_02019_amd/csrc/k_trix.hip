@@ -41,7 +41,7 @@ namespace sk {
 
 constexpr int XR = 4;             // rows per member
 constexpr int XNMAX = 512;
-constexpr int XT = XNMAX / 64;    // columns per lane
+// columns per lane: NT = 4 for orders up to 256, 8 up to 512 (templates)
 // A step buffer of a problem of order n holds p (2 words per row, from word
 // 0), the shipped row (2 per column, from 2 n) and the members' partial dots
 // (2 per member, from 4 n): 4 n + 2 P words; the two buffers take at most
@@ -87,22 +87,32 @@ __device__ __forceinline__ double x_pick8(int k, double v0, double v1, double v2
                                           double v6, double v7) {
     return k < 4 ? x_pick4(k, v0, v1, v2, v3) : x_pick4(k - 4, v4, v5, v6, v7);
 }
-static_assert(XT == 8 && XR == 4, "x_at and x_row pick from 8 columns per lane and 4 rows per member");
+template <int NT> __device__ __forceinline__ double x_pickv(int k, const double (&v)[NT]);
+template <> __device__ __forceinline__ double x_pickv<8>(int k, const double (&v)[8]) {
+    return x_pick8(k, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+}
+template <> __device__ __forceinline__ double x_pickv<4>(int k, const double (&v)[4]) {
+    return x_pick4(k, v[0], v[1], v[2], v[3]);
+}
+static_assert(XR == 4, "x_row picks from 4 rows per member");
 // entry c of a lane-distributed vector (c uniform)
-#define x_at(v, c) x_lane(x_pick8((c) >> 6, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]), (c) & 63)
+#define x_at(v, c) x_lane(x_pickv<NT>((c) >> 6, v), (c) & 63)
 // column slot t of row slot q (q uniform) of the member's rows
 #define x_row(a, q, t) x_pick4(q, a[0][t], a[1][t], a[2][t], a[3][t])
 
 __device__ __forceinline__ uint32_t x_tag(uint64_t epoch, int step) {
     return (uint32_t)((epoch << 10) | (uint64_t)step);
 }
+// global (not flat) accesses: the compiler then waits for just the loads a
+// check needs, not for every load in flight
+typedef __attribute__((address_space(1))) uint64_t xg_u64;
 __device__ __forceinline__ void x_put(uint64_t* w, int half, uint32_t tag, double x) {
     const uint64_t b = (uint64_t)__double_as_longlong(x);
     const uint64_t p = half ? (b >> 32) : (b & 0xffffffffull);
-    __hip_atomic_store(w + half, ((uint64_t)tag << 32) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((xg_u64*)(w + half), ((uint64_t)tag << 32) | p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t x_get(const uint64_t* w) {
-    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const xg_u64*)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double x_join(uint64_t lo, uint64_t hi) {
     return __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
@@ -112,7 +122,8 @@ __device__ __forceinline__ double x_join(uint64_t lo, uint64_t hi) {
 // in every member (no exchange): v[jj + 1 ..] into v (v[jj + 1] = 1, zero
 // before), returns tau; member 0 also writes the reflector (W row jj), the
 // diagonal entry and beta.  xn2 = |x beyond jj + 1|^2.
-__device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[XT], double xn2, double (&v)[XT],
+template <int NT>
+__device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[NT], double xn2, double (&v)[NT],
                                               double* Wr, double* U, int lu, bool writer) {
     const int lane = threadIdx.x & 63;
     const double alpha = x_at(x, jj + 1);
@@ -123,7 +134,7 @@ __device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[X
         scal = 1.0 / (alpha - beta);
     }
 #pragma unroll
-    for (int t = 0; t < XT; ++t) {
+    for (int t = 0; t < NT; ++t) {
         const int c = lane + 64 * t;
         v[t] = (c <= jj || c >= n) ? 0.0 : (c == jj + 1) ? 1.0 : x[t] * scal;
     }
@@ -135,7 +146,7 @@ __device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[X
             Wr[(int64_t)jj * n + jj] = tau;
         }
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int c = lane + 64 * t;
             if (c > jj + 1 && c < n) Wr[(int64_t)jj * n + c] = v[t];
         }
@@ -143,13 +154,59 @@ __device__ __forceinline__ double x_reflector(int jj, int n, const double (&x)[X
     return tau;
 }
 
+// The words of one step a lane reads: p and the shipped row at its columns
+// beyond jj, the partial dots of members lane and lane + 64.
+template <int NT>
+struct XWords {
+    uint64_t p[NT][2], r[NT][2], d[2][2];
+    __device__ __forceinline__ void load(const uint64_t* buf, int op, int orow, int odot, int lane, int jj, int n,
+                                         int P) {
+        // straight-line loads from clamped (always valid) addresses; the
+        // words a lane does not need are ignored by tagged()
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = min(lane + 64 * t, n - 1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                p[t][h] = x_get(buf + op + 2 * c + h);
+                r[t][h] = x_get(buf + orow + 2 * c + h);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int m = min(lane + 64 * k, P - 1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) d[k][h] = x_get(buf + odot + 2 * m + h);
+        }
+    }
+    __device__ __forceinline__ bool tagged(uint32_t tag, int lane, int jj, int n, int P) const {
+        bool ok = true;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = lane + 64 * t;
+            const bool need = c > jj && c < n;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                ok &= !need || ((uint32_t)(p[t][h] >> 32) == tag && (uint32_t)(r[t][h] >> 32) == tag);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const bool need = lane + 64 * k < P;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) ok &= !need || (uint32_t)(d[k][h] >> 32) == tag;
+        }
+        return ok;
+    }
+};
+
 // Publishes step s (column jj = s - 1): p of this member's rows beyond jj,
 // its partial dot, and row jj + 1 (columns from jj + 1) if this member holds
 // it; then reads every member's step s into p, row and the dot sum.
 // Returns false on a timed-out wait.
-__device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, const double (&a)[XR][XT],
+template <int NT>
+__device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, const double (&a)[XR][NT],
                                            const double (&pl)[XR], double dot, uint64_t* xw, uint64_t epoch,
-                                           double (&p)[XT], double (&row)[XT], double* dsum) {
+                                           double (&p)[NT], double (&row)[NT], double* dsum) {
     const int lane = threadIdx.x & 63;
     const int jj = s - 1;
     const uint32_t tag = x_tag(epoch, s);
@@ -165,7 +222,7 @@ __device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, cons
     if (member == (jj + 1) % P) {
         const int q = (jj + 1) / P;
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int c = lane + 64 * t;
             if (c > jj && c < n) {
                 const double v = x_row(a, q, t);
@@ -175,48 +232,30 @@ __device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, cons
         }
     }
     // every word of the step this lane needs, until all carry the tag
-    uint64_t wp[XT][2], wr[XT][2], wd[2][2];
+    XWords<NT> A;
     bool ok = false;
     for (unsigned polls = 0; polls <= XWG_POLLS; ++polls) {
-        bool mine = true;
-#pragma unroll
-        for (int t = 0; t < XT; ++t) {
-            const int c = lane + 64 * t;
-            if (c > jj && c < n) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    wp[t][h] = x_get(buf + XW_P + 2 * c + h);
-                    wr[t][h] = x_get(buf + XW_ROW + 2 * c + h);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int m = lane + 64 * k;
-            if (m < P)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) wd[k][h] = x_get(buf + XW_DOT + 2 * m + h);
-        }
-#pragma unroll
-        for (int t = 0; t < XT; ++t) {
-            const int c = lane + 64 * t;
-            if (c > jj && c < n)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) mine &= (uint32_t)(wp[t][h] >> 32) == tag && (uint32_t)(wr[t][h] >> 32) == tag;
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (lane + 64 * k < P)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) mine &= (uint32_t)(wd[k][h] >> 32) == tag;
-        if (__all(mine)) {
+        A.load(buf, XW_P, XW_ROW, XW_DOT, lane, jj, n, P);
+        if (__all(A.tagged(tag, lane, jj, n, P))) {
             ok = true;
             break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    uint64_t wp[NT][2], wr[NT][2], wd[2][2];
 #pragma unroll
-    for (int t = 0; t < XT; ++t) {
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            wp[t][h] = A.p[t][h];
+            wr[t][h] = A.r[t][h];
+        }
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) wd[k2][h] = A.d[k2][h];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
         const int c = lane + 64 * t;
         const bool live = c > jj && c < n;
         p[t] = live ? x_join(wp[t][0], wp[t][1]) : 0.0;
@@ -231,29 +270,30 @@ __device__ __forceinline__ bool x_exchange(int s, int n, int P, int member, cons
     return ok;
 }
 
+template <int NT>
 __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, double* __restrict__ Wr,
                           double* __restrict__ U, int lu, uint64_t* xw, int* info, uint64_t epoch, int member) {
     const int P = x_members(n);
     const int lane = threadIdx.x & 63;
     const bool writer = member == 0;
-    double a[XR][XT];  // rows member + P q, columns lane + 64 t
+    double a[XR][NT];  // rows member + P q, columns lane + 64 t
 #pragma unroll
     for (int q = 0; q < XR; ++q) {
         const int i = member + P * q;
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int c = lane + 64 * t;
             a[q][t] = (i < n && c < n) ? 0.5 * (Ain[(int64_t)i * ldin + c] + Ain[(int64_t)c * ldin + i]) : 0.0;
         }
     }
     // (n >= 16 here: the launcher takes orders from trix_min_n() >= 16)
     // column 0: row 0 of A, its reflector, p of this member's rows
-    double va[XT], vb[XT], p[XT], row[XT], x[XT];
+    double va[NT], vb[NT], p[NT], row[NT], x[NT];
     double tau, dsum;
     {
         double s2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int c = lane + 64 * t;
             x[t] = c < n ? 0.5 * (Ain[c] + Ain[(int64_t)c * ldin]) : 0.0;
             if (c >= 2 && c < n) s2 = fma(x[t], x[t], s2);
@@ -267,7 +307,7 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         const int i = member + P * q;
         double acc = 0.0;
 #pragma unroll
-        for (int t = 0; t < XT; ++t) acc = fma(a[q][t], va[t], acc);  // va is zero up to column 0
+        for (int t = 0; t < NT; ++t) acc = fma(a[q][t], va[t], acc);  // va is zero up to column 0
         acc = x_wave_sum(acc);
         pl[q] = (i > 0 && i < n) ? tau * acc : 0.0;
         if (i > 0 && i < n) dot = fma(pl[q], x_at(va, i), dot);
@@ -279,9 +319,9 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         const double K = 0.5 * tau * dsum;
         const double w1 = fma(-K, x_at(va, j + 1), x_at(p, j + 1));
         const bool next = j + 3 < n;
-        double wv[XT], s2 = 0.0;
+        double wv[NT], s2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < XT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const int c = lane + 64 * t;
             wv[t] = fma(-K, va[t], p[t]);
             x[t] = (c > j && c < n) ? fma(-1.0, wv[t], fma(-w1, va[t], row[t])) : 0.0;
@@ -310,7 +350,7 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
                 const double vi = x_at(va, i), wi = fma(-K, vi, x_at(p, i));
                 double acc = 0.0;
 #pragma unroll
-                for (int t = 0; t < XT; ++t) {
+                for (int t = 0; t < NT; ++t) {
                     const int c = lane + 64 * t;
                     if (c > j && c < n) a[q][t] = fma(-vi, wv[t], fma(-wi, va[t], a[q][t]));
                     acc = fma(a[q][t], vb[t], acc);  // vb is zero up to column j + 1
@@ -325,7 +365,7 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         if (!next) break;
         bad = !x_exchange(j + 2, n, P, member, a, pl, dot, xw, epoch, p, row, &dsum);
 #pragma unroll
-        for (int t = 0; t < XT; ++t) va[t] = vb[t];
+        for (int t = 0; t < NT; ++t) va[t] = vb[t];
         tau = tau2;
     }
     if (bad) {
@@ -337,7 +377,7 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
         const int q = (n - 1) / P, t = (n - 1) >> 6;
         double v = 0.0;
 #pragma unroll
-        for (int u = 0; u < XT; ++u)
+        for (int u = 0; u < NT; ++u)
             if (u == t) v = x_row(a, q, u);
         v = x_lane(v, (n - 1) & 63);
         if (lane == 0) U[n - 1] = v;
@@ -347,16 +387,17 @@ __device__ void trix_body(const double* __restrict__ Ain, int ldin, int n, doubl
 // Task form: eigen-problems of shrink / query tasks that the tridiagonal
 // solver takes and whose size is in [xmin, XNMAX]; workgroup b is member
 // b mod P of problem b / P.
+template <int NT>
 __global__ __launch_bounds__(64) void k_tri_reduce_x(const Task* tasks, int count, int P, int xmin, uint64_t epoch) {
     const int problem = blockIdx.x / P, member = blockIdx.x % P;
     if (problem >= count) return;
     const Task& t = tasks[problem];
     if (t.kind == T_INGEST || (t.flags & TF_COOP_EIG)) return;
     const int n = eig_n(t);
-    if (n < xmin || n > XNMAX || member >= x_members(n)) return;
+    if (n < xmin || n > 64 * NT || member >= x_members(n)) return;
     const SkDev* s = t.s;
     const bool rnd = t.kind == T_SHRINK_RAND;
-    trix_body(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U], s->sld[S_U],
+    trix_body<NT>(s->slot[rnd ? S_M : S_G], s->sld[rnd ? S_M : S_G], n, s->slot[S_EA], s->slot[S_U], s->sld[S_U],
               (uint64_t*)s->slot[S_EV], s->info, epoch, member);
 }
 
@@ -380,25 +421,28 @@ int trix_min_n() {
 // eigen-solver's scratch slot (at least n x n doubles).
 hipError_t launch_tri_reduce_x(const Task* tasks, int count, int max_n, hipStream_t st) {
     const int nmax = std::min(max_n, XNMAX);
+    const bool small = nmax <= 256;
+    const void* kern = small ? (const void*)k_tri_reduce_x<4> : (const void*)k_tri_reduce_x<8>;
     int P = x_members(nmax);
-    static int per_cu = -1, cus = 0;
-    if (per_cu < 0) {
+    static int per_cu[2] = {-1, -1}, cus = 0;
+    int& pc = per_cu[small ? 0 : 1];
+    if (pc < 0) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_tri_reduce_x, 64, 0) != hipSuccess ||
-            per_cu < 1)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, 64, 0) != hipSuccess || pc < 1) {
+            pc = -1;
             return hipErrorInvalidConfiguration;
+        }
     }
-    const int chunk = std::max(1, (per_cu * cus) / P);
+    const int chunk = std::max(1, (pc * cus) / P);
     int xmin = trix_min_n();
     for (int off = 0; off < count; off += chunk) {
         const Task* tl = tasks + off;
         int cnt = std::min(chunk, count - off);
         uint64_t epoch = xwg_next_epoch();
         void* args[] = {(void*)&tl, (void*)&cnt, (void*)&P, (void*)&xmin, (void*)&epoch};
-        hipError_t e = hipLaunchCooperativeKernel((const void*)k_tri_reduce_x, dim3((unsigned)(P * cnt)), dim3(64),
-                                                  args, 0, st);
+        hipError_t e = hipLaunchCooperativeKernel(kern, dim3((unsigned)(P * cnt)), dim3(64), args, 0, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
