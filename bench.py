@@ -251,6 +251,8 @@ def serve(srv, ids, pools, sched):
             rows += c["rows"]
             last_done = max(last_done, c["done"])
             outstanding -= 1
+            if len(lat) % 20000 == 0:
+                print(f"[bench] {len(lat)} of {len(sched)} bursts done", file=sys.stderr, flush=True)
     return np.asarray(lat), rows, last_done - t0
 
 

@@ -916,7 +916,9 @@ __device__ __forceinline__ void tri_back_body(const double* W, const double* Dm,
                                               double* lds) {
     if (Dm[0] != 0.0) return;
     if (blockIdx.x * TRI_SC >= n) return;
-    if (n <= 256) tri_back_strip<16>(W, U, lu, n, lds);
+    if (n <= 64) tri_back_strip<4>(W, U, lu, n, lds);
+    else if (n <= 128) tri_back_strip<8>(W, U, lu, n, lds);
+    else if (n <= 256) tri_back_strip<16>(W, U, lu, n, lds);
     else tri_back_strip<32>(W, U, lu, n, lds);
 }
 
