@@ -301,14 +301,56 @@ __device__ void cholqr_x_body(const Task& t, int src_slot, int dst_slot, int mem
     else cholqr_x_qstep<16>(src, dst, Lt, m, k, K, ldk, member, P);
 }
 
+// The second CholeskyQR pass when the first left Q1 nearly orthonormal: with
+// W = Q1^T Q1 = I + E and max |E_ij| <= CX_POLAR_TOL, Q2 = Q1 (3I - W) / 2 (one
+// Newton-Schulz step towards the polar factor) has Q2^T Q2 = I - 3E^2/4 + O(E^3)
+// and the span of Q1, so it serves as the orthonormal basis as well as the
+// Cholesky pass does, with one product instead of a chain of block steps.
+// This kernel writes X = (3I - W) / 2 into S_X (the product is the
+// X-multiply launch of the one-workgroup path) and the decision into info[8];
+// the multi-workgroup pass then skips the task.  Rank-deficient iterates
+// (a dropped column gives W_jj = 0) always take the Cholesky pass.
+constexpr double CX_POLAR_TOL = 1e-8;
+
+__global__ __launch_bounds__(1024) void k_cholx_polar(const Task* tasks) {
+    const Task& t = tasks[blockIdx.z];
+    if (t.kind != T_SHRINK_RAND || !(t.flags & TF_X_CHOL)) return;
+    const SkDev* s = t.s;
+    const int k = s->k, ldw = s->sld[S_W], ldx = s->sld[S_X];
+    const double* W = s->slot[S_W];
+    double* X = s->slot[S_X];
+    double dev = 0.0;
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+        const int i = e / k, j = e - i * k;
+        const double w = W[(int64_t)i * ldw + j], id = i == j ? 1.0 : 0.0;
+        X[(int64_t)i * ldx + j] = 1.5 * id - 0.5 * w;
+        dev = fmax(dev, fabs(w - id));
+    }
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        s->info[8] = m <= CX_POLAR_TOL ? 1 : 0;  // a NaN deviation keeps the Cholesky pass
+    }
+}
+
+hipError_t launch_cholx_polar(const Task* tasks, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_cholx_polar, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, tasks);
+    return hipGetLastError();
+}
+
 // Members b of task i are workgroups P i + b (consecutive: spread over the
 // XCDs); tasks with fewer members leave the surplus idle.
 __global__ __launch_bounds__(CTH) void k_cholqr_x(const Task* tasks, int count, int Pmax, int src_slot,
-                                                  int dst_slot, uint64_t epoch, int pass) {
+                                                  int dst_slot, uint64_t epoch, int pass, int polar) {
     const int task = blockIdx.x / Pmax, member = blockIdx.x % Pmax;
     if (task >= count) return;
     const Task& t = tasks[task];
     if (t.kind != T_SHRINK_RAND || !(t.flags & TF_X_CHOL)) return;
+    if (polar && t.s->info[8]) return;  // the polar step has written dst
     if (member >= cx_members(t.s->k)) return;
     cholqr_x_body(t, src_slot, dst_slot, member, epoch, pass);
 }
@@ -317,7 +359,7 @@ __global__ __launch_bounds__(CTH) void k_cholqr_x(const Task* tasks, int count, 
 // TF_X_CHOL, P = members of the largest k, as many tasks per cooperative
 // launch as are resident.
 hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int src_slot, int dst_slot, int pass,
-                           hipStream_t st) {
+                           int polar, hipStream_t st) {
     if (max_k > CKMAX) return hipErrorInvalidConfiguration;
     const int Pmax = cx_members(max_k), K = Pmax * CB;
     const size_t lds = sizeof(double) * cx_lds_doubles(K);
@@ -338,8 +380,9 @@ hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int src_slot
         const Task* tl = tasks + off;
         int cnt = std::min(chunk, count - off);
         uint64_t epoch = xwg_next_epoch();
-        int pm = Pmax, a = src_slot, b = dst_slot, ps = pass;
-        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&pm, (void*)&a, (void*)&b, (void*)&epoch, (void*)&ps};
+        int pm = Pmax, a = src_slot, b = dst_slot, ps = pass, pl = polar;
+        void* args[] = {(void*)&tl, (void*)&cnt, (void*)&pm, (void*)&a, (void*)&b, (void*)&epoch, (void*)&ps,
+                        (void*)&pl};
         hipError_t e = hipLaunchCooperativeKernel((const void*)k_cholqr_x, dim3((unsigned)(Pmax * cnt)), dim3(CTH),
                                                   args, (unsigned)lds, st);
         if (e != hipSuccess) return e;

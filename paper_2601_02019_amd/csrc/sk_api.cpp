@@ -252,15 +252,23 @@ hipError_t cholqr(const Task* t, const Group& g, int sy, int sq, int passes, hip
         // overwritten for the other tasks), then the multi-workgroup pass of
         // the tasks flagged for it; cooperative tasks are rewritten below from
         // the unchanged input sy
+        // The second pass of the multi-workgroup tasks may be the polar step
+        // (k_cholx.hip): X = (3I - W) / 2 goes to S_X, the same X-multiply
+        // launch as the one-workgroup tasks' applies it, and the Cholesky pass
+        // skips the tasks it served.
         int src = sy;
         for (int pass = 0; pass < passes; ++pass) {
             const int dst = (pass == passes - 1) ? sq : S_Q1;
+            const bool polar = g.x_chol_k > 0 && pass == 1;
             if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_k, g.max_k, true, false, src, src, S_W, dims(1, 1, 0), st))) return e;
-            if (g.any_plain_chol) {
-                if ((g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st))) return e;
-                if ((g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st))) return e;
-            }
-            if (g.x_chol_k > 0 && (g_stage = "cholqr_x", e = launch_cholqr_x(t, g.count, g.x_chol_k, src, dst, pass, st)))
+            if (g.any_plain_chol && (g_stage = "cholinv", e = launch_cholinv(t, g.count, g.max_k, g.small_k, g.large_k, S_W, S_X, st)))
+                return e;
+            if (polar && (g_stage = "cholx_polar", e = launch_cholx_polar(t, g.count, st))) return e;
+            if ((g.any_plain_chol || polar) &&
+                (g_stage = "core_gemm", e = launch_core_gemm(t, g.count, g.max_m, g.max_k, false, true, src, S_X, dst, dims(0, 1, 1), st)))
+                return e;
+            if (g.x_chol_k > 0 &&
+                (g_stage = "cholqr_x", e = launch_cholqr_x(t, g.count, g.x_chol_k, src, dst, pass, polar ? 1 : 0, st)))
                 return e;
             src = dst;
         }

@@ -46,7 +46,8 @@ struct SkDev {
     void* omegaT;              // k x ld, projection dtype
     double* slot[NSLOT];
     int32_t sld[NSLOT];        // leading dimension of each slot
-    int32_t* info;             // [0]: non-converged eigen-solves, [1]: max sweeps
+    int32_t* info;             // [0]: non-converged eigen-solves, [1]: max sweeps, [2]: eigen fall-backs,
+                               // [3]: exchange timeouts, [8]: second CholeskyQR pass taken by the polar step
     uint64_t seed, stream;
     double* coop;              // cooperative-solver scratch (COOP_* layout)
     int32_t* coop_ctrl;        // [0..1] rotation counters, [8..9] grid barrier

@@ -69,7 +69,10 @@ int trix_min_n();
 // One pass of the multi-workgroup CholeskyQR (the Gram of src already in
 // slot S_W) of the tasks flagged TF_X_CHOL: src -> dst.
 hipError_t launch_cholqr_x(const Task* tasks, int count, int max_k, int src_slot, int dst_slot, int pass,
-                           hipStream_t st);
+                           int polar, hipStream_t st);
+// X = (3I - W) / 2 and the polar decision (info[8]) for the second CholeskyQR
+// pass of the multi-workgroup tasks.
+hipError_t launch_cholx_polar(const Task* tasks, int count, hipStream_t st);
 // Multi-task cooperative solvers: tasks[idx[i]] for i < count, each by its
 // own group of workgroups (several launches when residency requires).
 hipError_t launch_jacobi_coop_tasks(const Task* tasks, const int* idx, int count, int max_n, hipStream_t st);
