@@ -54,26 +54,41 @@ __global__ __launch_bounds__(256) void k_core_gemm(const Task* tasks, int sa, in
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < RB; ++j) acc[i][j] = 0.0;
-    for (int kk = 0; kk < K; kk += 16) {
+    // the next 16-deep slices of A and B are loaded into registers while the
+    // current ones are multiplied out of LDS
+    double pa[RB], pb[RB];
+    auto fetch = [&](int kk) {
 #pragma unroll
         for (int u = 0; u < RB; ++u) {
             const int e = tid + 256 * u;  // 16 * TS elements of a TS x 16 slice
             if (!TA) {  // A row-major: consecutive threads walk k
                 const int r = e >> 4, k = e & 15;
-                As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(r0 + r) * lda + kk + k] : 0.0;
+                pa[u] = (r0 + r < M && kk + k < K) ? A[(int64_t)(r0 + r) * lda + kk + k] : 0.0;
             } else {    // A^T: consecutive threads walk the row index of op(A)
                 const int r = e % TS, k = e / TS;
-                As[k][r] = (r0 + r < M && kk + k < K) ? A[(int64_t)(kk + k) * lda + r0 + r] : 0.0;
+                pa[u] = (r0 + r < M && kk + k < K) ? A[(int64_t)(kk + k) * lda + r0 + r] : 0.0;
             }
             if (!TB) {
                 const int c = e % TS, k = e / TS;
-                Bs[k][c] = (c0 + c < N && kk + k < K) ? B[(int64_t)(kk + k) * ldb + c0 + c] : 0.0;
+                pb[u] = (c0 + c < N && kk + k < K) ? B[(int64_t)(kk + k) * ldb + c0 + c] : 0.0;
             } else {
                 const int c = e >> 4, k = e & 15;
-                Bs[k][c] = (c0 + c < N && kk + k < K) ? B[(int64_t)(c0 + c) * ldb + kk + k] : 0.0;
+                pb[u] = (c0 + c < N && kk + k < K) ? B[(int64_t)(c0 + c) * ldb + kk + k] : 0.0;
             }
         }
+    };
+    if (K > 0) fetch(0);
+    for (int kk = 0; kk < K; kk += 16) {
+#pragma unroll
+        for (int u = 0; u < RB; ++u) {
+            const int e = tid + 256 * u;
+            if (!TA) As[e & 15][e >> 4] = pa[u];
+            else As[e / TS][e % TS] = pa[u];
+            if (!TB) Bs[e / TS][e % TS] = pb[u];
+            else Bs[e & 15][e >> 4] = pb[u];
+        }
         __syncthreads();
+        if (kk + 16 < K) fetch(kk + 16);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             double a[RB], b[RB];

@@ -166,13 +166,25 @@ __global__ __launch_bounds__(256) void k_nt_partial(const Task* tasks) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
 
+    // the next 16-deep slices are loaded into registers while the current
+    // ones are multiplied out of LDS
+    double pa[4], pb[4];
+    auto fetch = [&](int kk) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pa[u] = (ga < M) ? to_f64(A[(int64_t)ga * ld + kk + lk + u]) : 0.0;
+            pb[u] = (gb < N) ? to_f64(B[(int64_t)gb * ld + kk + lk + u]) : 0.0;
+        }
+    };
+    if (k0 < k1) fetch(k0);
     for (int kk = k0; kk < k1; kk += 16) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            As[lk + u][lr] = (ga < M) ? to_f64(A[(int64_t)ga * ld + kk + lk + u]) : 0.0;
-            Bs[lk + u][lr] = (gb < N) ? to_f64(B[(int64_t)gb * ld + kk + lk + u]) : 0.0;
+            As[lk + u][lr] = pa[u];
+            Bs[lk + u][lr] = pb[u];
         }
         __syncthreads();
+        if (kk + 16 < k1) fetch(kk + 16);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             double a[4], b[4];
@@ -311,24 +323,28 @@ __global__ __launch_bounds__(256) void k_rebuild(const Task* tasks) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int kk = 0; kk < K; kk += 16) {
-        {   // T tile: 64 rows x 16 k
-            const int lr = tid >> 2, lk = (tid & 3) * 4;
+    // T tile (64 rows x 16 k) and C tile (16 k rows x 64 columns; columns < ld
+    // are always allocated), the next pair loaded into registers while the
+    // current one is multiplied out of LDS
+    const int lr = tid >> 2, lk = (tid & 3) * 4, kr = tid >> 4, lc = (tid & 15) * 4;
+    double pa[4], pb[4];
+    auto fetch = [&](int kk) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int r = r0 + lr, k = kk + lk + u;
-                As[lk + u][lr] = (r < rows_out && k < K) ? T[(int64_t)r * ldt + k] : 0.0;
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + lr, k = kk + lk + u;
+            pa[u] = (r < rows_out && k < K) ? T[(int64_t)r * ldt + k] : 0.0;
+            pb[u] = (kk + kr < K) ? to_f64(X[(int64_t)(kk + kr) * ld + c0 + lc + u]) : 0.0;
         }
-        {   // C tile: 16 k rows x 64 columns (columns < ld are always allocated)
-            const int kr = tid >> 4, lc = (tid & 15) * 4;
+    };
+    if (K > 0) fetch(0);
+    for (int kk = 0; kk < K; kk += 16) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = kk + kr;
-                Bs[kr][lc + u] = (k < K) ? to_f64(X[(int64_t)k * ld + c0 + lc + u]) : 0.0;
-            }
+        for (int u = 0; u < 4; ++u) {
+            As[lk + u][lr] = pa[u];
+            Bs[kr][lc + u] = pb[u];
         }
         __syncthreads();
+        if (kk + 16 < K) fetch(kk + 16);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             double a[4], b[4];
