@@ -74,6 +74,9 @@ def _load():
     lib.o_aero_dump.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int64, ctypes.c_int64, _dp, _dp,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _dp]
+    lib.o_aero_dump_amp.argtypes = lib.o_aero_dump.argtypes + [ctypes.c_int, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]
+    lib.o_win_set_amplify.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.o_attp_set_amplify.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     lib.o_attp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                   ctypes.c_int]
     lib.o_attp_create.restype = ctypes.c_void_p
@@ -174,21 +177,29 @@ def shrink_rand(X, ell, k, q, seed, stream, b):
     return X
 
 
-def aero_dump(C, theta, ell, q=1, seed=0, stream=0, level=0, i=1):
+def aero_dump(C, theta, ell, q=1, seed=0, stream=0, level=0, i=1, amplify=(1, 0)):
     """The window's dump step on the buffer C (r x d).  Returns a dict with
     the power-iteration estimate ``pi``, the simul_iter call count ``nsi``,
     ``xi``, the snapshot ``Z`` (d x xi) and ``W`` (xi x d) and the residual
-    buffer ``C`` (C - C Z Z^T)."""
+    buffer ``C`` (C - C Z Z^T).  ``amplify = (r, s)`` runs Algorithm
+    "Probability Amplification" in place of each simul_iter call; then
+    ``amp_c`` holds the r candidates' squared residual estimates of the last
+    amplified step and ``amp_h`` the candidate kept."""
     lib = _load()
     C = _f64(np.atleast_2d(C)).copy()
     r, d = C.shape
     Z = np.zeros((d, ell))
     W = np.zeros((ell, d))
     xi, nsi, pi = ctypes.c_int(0), ctypes.c_int(0), np.zeros(1)
-    _check(lib.o_aero_dump(d, ell, q, seed, stream, level, float(theta), _p(C), r, i, _p(Z), _p(W),
-                           ctypes.byref(xi), ctypes.byref(nsi), _p(pi)), "aero_dump")
+    ar, as_ = amplify
+    amp_c = np.full(16, np.nan)
+    amp_h = ctypes.c_int(-1)
+    _check(lib.o_aero_dump_amp(d, ell, q, seed, stream, level, float(theta), _p(C), r, i, _p(Z), _p(W),
+                               ctypes.byref(xi), ctypes.byref(nsi), _p(pi), int(ar), int(as_), _p(amp_c),
+                               ctypes.byref(amp_h)), "aero_dump")
     x = xi.value
-    return {"pi": float(pi[0]), "nsi": nsi.value, "xi": x, "Z": Z[:, :x].copy(), "W": W[:x].copy(), "C": C}
+    return {"pi": float(pi[0]), "nsi": nsi.value, "xi": x, "Z": Z[:, :x].copy(), "W": W[:x].copy(), "C": C,
+            "amp_c": amp_c[:ar].copy(), "amp_h": amp_h.value}
 
 
 def power_iteration(C, x0, steps):
@@ -249,11 +260,13 @@ class FD:
 class Window:
     """ML-AeroSketch over a sliding window of N rows."""
 
-    def __init__(self, d, ell, N, R, q=1, seed=0, stream=0, fd="exact"):
+    def __init__(self, d, ell, N, R, q=1, seed=0, stream=0, fd="exact", amplify=(1, 0)):
         lib = _load()
         self._h = lib.o_win_create2(d, ell, N, float(R), q, seed, stream, {"exact": 0, "rand": 1}[fd])
         if not self._h:
             raise ValueError("bad window parameters")
+        if lib.o_win_set_amplify(self._h, int(amplify[0]), int(amplify[1])) != 0:
+            raise ValueError("bad amplification parameters")
         self.d, self.ell, self.N = d, ell, N
 
     def __del__(self):
@@ -328,11 +341,13 @@ class Window:
 class ATTP:
     """ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch")."""
 
-    def __init__(self, d, ell, q=1, seed=0, stream=0, fd="exact"):
+    def __init__(self, d, ell, q=1, seed=0, stream=0, fd="exact", amplify=(1, 0)):
         lib = _load()
         self._h = lib.o_attp_create(d, ell, q, seed, stream, {"exact": 0, "rand": 1}[fd])
         if not self._h:
             raise ValueError("bad ATTP parameters")
+        if lib.o_attp_set_amplify(self._h, int(amplify[0]), int(amplify[1])) != 0:
+            raise ValueError("bad amplification parameters")
         self.d, self.ell = d, ell
 
     def __del__(self):

@@ -47,6 +47,7 @@ struct o_attp {
     double* C; /* 2 ell x d */
     int64_t r, T, shrinks, ndirs, nsi, last_t;
     double fro2, theta;
+    int amp_r, amp_s; /* probability amplification of the dump step (1, 0: off) */
     asnap* sn;
     int64_t nsn, cap;
 };
@@ -58,7 +59,16 @@ o_attp* o_attp_create(int d, int ell, int q, uint64_t seed, uint64_t stream, int
     o_attp* a = (o_attp*)calloc(1, sizeof(o_attp));
     a->d = d; a->ell = ell; a->q = q; a->fd_mode = fd_mode; a->seed = seed; a->stream = stream;
     a->C = aalloc((int64_t)2 * ell * d);
+    a->amp_r = 1;
+    a->amp_s = 0;
     return a;
+}
+
+int o_attp_set_amplify(o_attp* a, int r, int s) {
+    if (!a || r < 1 || r > 16 || s < 0 || s > 16) return -1;
+    a->amp_r = r;
+    a->amp_s = s;
+    return 0;
 }
 
 void o_attp_destroy(o_attp* a) {
@@ -98,7 +108,8 @@ static int attp_row(o_attp* a, const double* row) {
     double* W = aalloc((int64_t)ell * d);
     int xi = 0, nsi = 0;
     double pi = 0.0;
-    int rc = o_aero_dump(d, ell, a->q, a->seed, a->stream, 0, a->theta, a->C, a->r, i, Z, W, &xi, &nsi, &pi);
+    int rc = o_aero_dump_amp(d, ell, a->q, a->seed, a->stream, 0, a->theta, a->C, a->r, i, Z, W, &xi, &nsi, &pi,
+                             a->amp_r, a->amp_s, NULL, NULL);
     a->nsi += nsi;
     if (rc == 0 && xi > 0) {
         if (a->nsn == a->cap) {

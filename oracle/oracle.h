@@ -125,6 +125,15 @@ int o_win_buffer(const o_win* w, int level, double* C);
  * rows), and C becomes C - C Z Z^T. */
 int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
                 int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi);
+/* The same with Algorithm "Probability Amplification" in place of each
+ * simul_iter call: amp_r candidates (1..16), amp_s power iterations on each
+ * candidate's residual (0..16); amp_r = 1, amp_s = 0 is o_aero_dump.  amp_c
+ * (amp_r doubles, optional) receives the candidates' squared estimates c_h^2
+ * of the last amplified step, amp_h (optional) the candidate kept there. */
+int o_aero_dump_amp(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
+                    int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi, int amp_r, int amp_s,
+                    double* amp_c, int* amp_h);
+int o_win_set_amplify(o_win* w, int r, int s);
 
 /* ---- ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch") --
  * One AeroSketch whose dump threshold is theta_i = eps ||A_i||_F^2 (eps =
@@ -132,6 +141,7 @@ int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level
  * t <= T can be queried.  fd_mode as for the window (level 0's key). */
 typedef struct o_attp o_attp;
 o_attp* o_attp_create(int d, int ell, int q, uint64_t seed, uint64_t stream, int fd_mode);
+int o_attp_set_amplify(o_attp* a, int r, int s);
 void o_attp_destroy(o_attp* a);
 int o_attp_update(o_attp* a, const double* rows, int64_t n, int64_t ld);
 /* d x d restored matrix of time t: the restore of every snapshot with

@@ -62,6 +62,7 @@ typedef struct {
 
 struct o_win {
     int d, ell, L, q, fd_mode;
+    int amp_r, amp_s; /* probability amplification of the dump step (1, 0: off) */
     int64_t N, T;
     uint64_t seed, stream;
     wlevel* lv;
@@ -85,6 +86,8 @@ o_win* o_win_create2(int d, int ell, int64_t N, double R, int q, uint64_t seed, 
     o_win* w = (o_win*)calloc(1, sizeof(o_win));
     w->d = d; w->ell = ell; w->N = N; w->q = q; w->seed = seed; w->stream = stream;
     w->fd_mode = fd_mode;
+    w->amp_r = 1;
+    w->amp_s = 0;
     int L = (int)ceil(log2(R));
     if (L < 1) L = 1;
     w->L = L;
@@ -98,6 +101,13 @@ o_win* o_win_create2(int d, int ell, int64_t N, double R, int q, uint64_t seed, 
         l->q = (wentry*)calloc((size_t)l->capq, sizeof(wentry));
     }
     return w;
+}
+
+int o_win_set_amplify(o_win* w, int r, int s) {
+    if (!w || r < 1 || r > 16 || s < 0 || s > 16) return -1;
+    w->amp_r = r;
+    w->amp_s = s;
+    return 0;
 }
 
 void o_win_destroy(o_win* w) {
@@ -136,10 +146,14 @@ static void expire(o_win* w, wlevel* l, int64_t i) {
     }
 }
 
-/* Parameters of one level's dump step. */
+/* Parameters of one level's dump step; amp_r > 1 or amp_s > 0 turns on the
+ * probability amplification of Algorithm "Probability Amplification". */
 typedef struct {
     int d, ell, q;
     uint64_t seed, stream;
+    int amp_r, amp_s;
+    double* amp_c; /* optional: the r candidate estimates of the last amplified step */
+    int* amp_h;    /* optional: the candidate kept there */
 } dump_par;
 
 /* simul_iter on A = C'^T (reading: Omega on the d side), returns Z' (d x k)
@@ -205,6 +219,63 @@ out:
     return rc;
 }
 
+/* Algorithm "Probability Amplification" in place of the simul_iter call of
+ * doubling step s (k columns): r independent simul_iters, candidate h with
+ * Omega counter (row, column/4, i, 0x200 + 32 j + s + 0x1000 h) (h = 0 is the
+ * plain call); for each, xi_h = the count of leading estimates >= theta,
+ * Z_h = its first xi_h columns, and the residual R_h = C - C Z_h Z_h^T; then
+ * s power iterations on R_h (start vectors from counter (coordinate, 0, i,
+ * 0x100000 + 0x10000 g + 0x1000 h + 32 j + s), ceil(log2 d) + 1 steps each),
+ * c_h^2 = the largest of their estimates; the candidate with the smallest
+ * c_h (the first on ties) becomes [Z', estimates].
+ * Readings: the squared estimates are compared (same order as c_h); xi_h
+ * counts leading estimates as the dump itself does. */
+static int simul_iter_amplified(const dump_par* w, int j, int s, const double* C, int64_t r, int k,
+                                double theta, uint64_t i, double* Zp, double* est) {
+    const int d = w->d;
+    const int steps = (int)ceil(log2((double)d)) + 1;
+    double* Zh = walloc((int64_t)d * k);
+    double* eh = walloc(k);
+    double* R = walloc(r * d);
+    double* x0 = walloc(d);
+    double best = 0.0;
+    int besth = -1, rc = 0;
+    for (int h = 0; h < w->amp_r; ++h) {
+        rc = simul_iter_window(w, C, r, k, i, 0x200u + 32u * (uint64_t)j + (uint64_t)s + 0x1000u * (uint64_t)h,
+                               Zh, eh);
+        if (rc) break;
+        int xi = 0;
+        while (xi < k && eh[xi] >= theta) ++xi;
+        /* R_h = C - C Z_h Z_h^T */
+        for (int64_t rr = 0; rr < r; ++rr) {
+            for (int t = 0; t < d; ++t) R[rr * d + t] = C[rr * d + t];
+            for (int c = 0; c < xi; ++c) {
+                double cz = 0.0;
+                for (int t = 0; t < d; ++t) cz += C[rr * d + t] * Zh[(int64_t)t * k + c];
+                for (int t = 0; t < d; ++t) R[rr * d + t] -= cz * Zh[(int64_t)t * k + c];
+            }
+        }
+        double ch = 0.0;
+        for (int g = 0; g < w->amp_s; ++g) {
+            o_omega(w->seed, w->stream, i,
+                    0x100000u + 0x10000u * (uint64_t)g + 0x1000u * (uint64_t)h + 32u * (uint64_t)j + (uint64_t)s, d,
+                    1, x0);
+            const double e = o_power_iteration(R, (int)r, d, d, x0, steps, NULL);
+            if (e > ch) ch = e;
+        }
+        if (w->amp_c && h < 16) w->amp_c[h] = ch;
+        if (besth < 0 || ch < best) {
+            best = ch;
+            besth = h;
+            memcpy(Zp, Zh, sizeof(double) * (size_t)d * k);
+            memcpy(est, eh, sizeof(double) * (size_t)k);
+        }
+    }
+    if (w->amp_h) *w->amp_h = besth;
+    free(Zh); free(eh); free(R); free(x0);
+    return rc;
+}
+
 /* The dump step of Algorithm "AeroSketch: Update" on the level buffer C
  * (r x d, after the FD reduce) for the row with timestamp i at level j:
  * power iteration on C^T C with ceil(log2 d) + 1 steps (start vector from
@@ -237,8 +308,10 @@ static int aero_dump(const dump_par* w, int j, double theta, double* C, int64_t 
         if (k > kmax) k = kmax;
         double* Zp = walloc((int64_t)d * k);
         double* est = walloc(k);
-        int rc = simul_iter_window(w, C, r, k, (uint64_t)i, 0x200u + 32u * (uint64_t)j + (uint64_t)s, Zp, est);
-        *nsi += 1;
+        const int amplified = w->amp_r > 1 || w->amp_s > 0;
+        int rc = amplified ? simul_iter_amplified(w, j, s, C, r, k, theta, (uint64_t)i, Zp, est)
+                           : simul_iter_window(w, C, r, k, (uint64_t)i, 0x200u + 32u * (uint64_t)j + (uint64_t)s, Zp, est);
+        *nsi += amplified ? w->amp_r : 1;
         if (rc) { free(Zp); free(est); return rc; }
         if (est[k - 1] < theta || k == kmax) {
             int xi = 0;
@@ -280,8 +353,15 @@ static int aero_dump(const dump_par* w, int j, double theta, double* C, int64_t 
 
 int o_aero_dump(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
                 int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi) {
+    return o_aero_dump_amp(d, ell, q, seed, stream, level, theta, C, r, i, Z, W, xi, nsi, pi, 1, 0, NULL, NULL);
+}
+
+int o_aero_dump_amp(int d, int ell, int q, uint64_t seed, uint64_t stream, int level, double theta, double* C,
+                    int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi, int amp_r, int amp_s,
+                    double* amp_c, int* amp_h) {
     if (d < 1 || ell < 2 || q < 0 || r < 0 || !C || !Z || !W || !xi || !nsi || !pi) return -1;
-    dump_par par = {d, ell, q, seed, stream};
+    if (amp_r < 1 || amp_r > 16 || amp_s < 0 || amp_s > 16) return -1;
+    dump_par par = {d, ell, q, seed, stream, amp_r, amp_s, amp_c, amp_h};
     return aero_dump(&par, level, theta, C, r, i, Z, W, xi, nsi, pi);
 }
 
@@ -309,7 +389,7 @@ static int level_update(o_win* w, int j, const double* a, int64_t i) {
     double* W = walloc((int64_t)ell * d);
     int xi = 0, nsi = 0;
     double pi = 0.0;
-    dump_par par = {d, ell, w->q, w->seed, w->stream};
+    dump_par par = {d, ell, w->q, w->seed, w->stream, w->amp_r, w->amp_s, NULL, NULL};
     int rc = aero_dump(&par, j, l->theta, l->C, l->r, i, Z, W, &xi, &nsi, &pi);
     l->nsi += nsi;
     if (rc == 0 && xi > 0) {

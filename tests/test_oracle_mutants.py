@@ -9,7 +9,10 @@ that is not downdated, a wrong Philox key for a level's FD reduce, a wrong
 level threshold, and in the persistent oracle a wrong shrink threshold index
 or a missing power step; in the ATTP oracle a historical filter that
 drops the snapshot taken at time t, a wrong or stale threshold, the
-residual added to past times, a wrong Philox key and a wrong restore sign.
+residual added to past times, a wrong Philox key and a wrong restore sign;
+in the probability amplification the candidate with the largest estimate
+kept, the smallest of the power iterations taken, the residual not formed,
+and a wrong start-vector counter.
 """
 import os
 import shutil
@@ -25,6 +28,7 @@ ORACLE = os.path.join(ROOT, "oracle")
 WINDOW_PINS = ["tests/test_oracle_window_pins.py", "tests/test_oracle_window.py"]
 FD_PINS = ["tests/test_oracle_pins.py"]
 ATTP_PINS = ["tests/test_oracle_attp.py"]
+AMP_PINS = ["tests/test_oracle_amplify.py"]
 MUTANTS = {
     "pi_threshold_theta": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
                            "if (!(s1 >= theta)) return 0;", WINDOW_PINS),
@@ -62,6 +66,12 @@ MUTANTS = {
     "attp_reduce_key": ("attp.c", "a->stream * 64u + 1u", "a->stream * 64u", ATTP_PINS),
     "attp_restore_sign": ("attp.c", "G[(int64_t)x * d + y] += acc - sub;", "G[(int64_t)x * d + y] += acc + sub;",
                           ATTP_PINS),
+    "amp_keeps_largest": ("window.c", "if (besth < 0 || ch < best) {", "if (besth < 0 || ch > best) {", AMP_PINS),
+    "amp_min_over_power_iterations": ("window.c", "if (e > ch) ch = e;", "if (g == 0 || e < ch) ch = e;", AMP_PINS),
+    "amp_no_residual": ("window.c", "R[rr * d + t] -= cz * Zh[(int64_t)t * k + c];",
+                        "R[rr * d + t] -= 0.0 * cz * Zh[(int64_t)t * k + c];", AMP_PINS),
+    "amp_power_counter": ("window.c", "0x100000u + 0x10000u * (uint64_t)g", "0x100000u + 0x10000u * (uint64_t)(g + 1)",
+                          AMP_PINS),
     "power_iteration_step": ("fd.c", "for (int it = 0; it < steps; ++it) {", "for (int it = 1; it < steps; ++it) {",
                              FD_PINS + WINDOW_PINS),
 }
