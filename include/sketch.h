@@ -90,6 +90,21 @@ typedef struct {
                                  (the default stream); 0: NULL means a stream
                                  owned by the library                           */
     void* hip_stream;     /* hipStream_t to order work on                        */
+    /* SK_WINDOW and SK_ATTP: probability amplification of the dump step
+     * (Algorithm "Probability Amplification", analysed in the appendix on the
+     * amplified estimation).  Every doubling step of a dump runs amplify_r
+     * simul_iter candidates (candidate h draws its test matrix from counter
+     * word 3 = 0x200 + 32 j + s + 0x1000 h at level j, step s; h = 0 is the
+     * plain call); each candidate keeps its leading directions whose estimate
+     * reaches theta, and amplify_s power iterations on its residual
+     * C' - C' Z_h Z_h^T (start vectors from counter word 3 = 0x100000 +
+     * 0x10000 g + 0x1000 h + 32 j + s, ceil(log2 d) + 1 steps) estimate its
+     * top squared singular value; the candidate with the smallest estimate
+     * (the first on ties) decides the step.  1 <= amplify_r <= 16,
+     * 0 <= amplify_s <= 16; (1, 0) (the value sketch_config_init sets) is
+     * the plain dump step.  Other kinds require (1, 0).                    */
+    int32_t amplify_r;
+    int32_t amplify_s;
 } sketch_config;
 
 /* Fills *cfg with defaults: exact FP64 persistent sketch, q = 1, no

@@ -258,7 +258,7 @@ def sketch_profile_read(h):
 
 
 def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", proj_dtype="f64", q=1,
-                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0):
+                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0, amplify=(1, 0)):
     cfg = sketch_config_init()
     cfg.d, cfg.ell = d, ell
     cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP}[kind]
@@ -268,6 +268,7 @@ def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", pr
     cfg.q, cfg.oversample = q, oversample
     cfg.window_N, cfg.R = int(window_N), float(R)
     cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
+    cfg.amplify_r, cfg.amplify_s = int(amplify[0]), int(amplify[1])
     return cfg
 
 
@@ -446,9 +447,9 @@ class Sketch:
 
     def __init__(self, d, ell, kind="persistent", shrink="exact", state_dtype="f64",
                  proj_dtype="f64", q=1, oversample=0, window_N=0, R=1.0, seed=0, stream_id=0,
-                 device=0, stream=None):
+                 device=0, stream=None, amplify=(1, 0)):
         cfg = make_config(d, ell, kind, shrink, state_dtype, proj_dtype, q, oversample, window_N, R,
-                          seed, stream_id, device)
+                          seed, stream_id, device, amplify)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         if stream is not False:

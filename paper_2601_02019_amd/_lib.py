@@ -30,6 +30,7 @@ class sketch_config(ctypes.Structure):
         ("q", ctypes.c_int32), ("oversample", ctypes.c_int32), ("window_N", ctypes.c_int64),
         ("R", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64),
         ("device", ctypes.c_int32), ("use_given_stream", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+        ("amplify_r", ctypes.c_int32), ("amplify_s", ctypes.c_int32),
     ]
 
 

@@ -456,6 +456,10 @@ static sk_status validate_config(const sketch_config* cfg) {
     if (cfg->kind == SK_WINDOW && (cfg->window_N < 1 || !(cfg->R >= 1.0)))
         return fail(SK_EINVAL, "sketch_create: window needs window_N >= 1 and R >= 1");
     if (cfg->d > (1 << 20)) return fail(SK_EINVAL, "sketch_create: d too large");
+    if (cfg->amplify_r < 1 || cfg->amplify_r > 16 || cfg->amplify_s < 0 || cfg->amplify_s > 16)
+        return fail(SK_EINVAL, "sketch_create: need 1 <= amplify_r <= 16 and 0 <= amplify_s <= 16");
+    if (cfg->kind == SK_PERSISTENT && (cfg->amplify_r != 1 || cfg->amplify_s != 0))
+        return fail(SK_EINVAL, "sketch_create: amplification applies to window and ATTP sketches only");
     return SK_OK;
 }
 
@@ -524,6 +528,8 @@ sk_status sketch_config_init(sketch_config* cfg) {
     cfg->proj_dtype = SK_F64;
     cfg->q = 1;
     cfg->R = 1.0;
+    cfg->amplify_r = 1;
+    cfg->amplify_s = 0;
     return SK_OK;
 }
 

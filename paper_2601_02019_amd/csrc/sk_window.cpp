@@ -95,7 +95,20 @@ struct WindowState {
     // split-K partials of the skinny products (long K, few output tiles)
     double* gpart = nullptr;
     int64_t gpart_cap = 0;
+    // probability amplification of the dump step (amp_r candidates, amp_s
+    // power iterations on each residual; 1, 0: the plain step)
+    int amp_r = 1, amp_s = 0;
+    double* Zc = nullptr;        // candidate directions: amp_r x (d x kmax)
+    double* Rc = nullptr;        // candidate residuals: amp_r x (2 ell x ld)
+    double* amp_out = nullptr;   // amp_r x amp_s power-iteration estimates
+    double* h_amp = nullptr;     // pinned mirror
+    double* amp_part = nullptr;  // slab partials of one power-iteration launch
+    unsigned* amp_bars = nullptr;
+    std::vector<double> cand_est;  // amp_r x kmax estimates
 };
+
+// power iterations per cooperative launch of the amplified step
+static const int kAmpPiBatch = 16;
 
 static const int kWinDmax = 4096;  // largest d of a window sketch
 
@@ -300,6 +313,90 @@ static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
     return SK_OK;
 }
 
+// Algorithm "Probability Amplification" in place of the simul_iter call of
+// doubling step s (k columns) at level j: amp_r simul_iters (candidate h
+// draws its test matrix from counter word 3 = 0x200 + 32 j + s + 0x1000 h;
+// h = 0 is the plain call), each leaving xi_h directions (the leading
+// estimates that reach theta) and the residual R_h = C' - C' Z_h Z_h^T; then
+// amp_s power iterations on every R_h (start vectors from counter word 3 =
+// 0x100000 + 0x10000 g + 0x1000 h + 32 j + s), c_h = the largest of its
+// estimates, and the candidate with the smallest c_h (the first on ties)
+// goes on in Zd / h_est as if it were the plain call's result.  The squared
+// estimates are compared; their order is that of c_h.
+static sk_status simul_iter_amplified(sketch_t h, int j, int s, int k, int64_t ts) {
+    WindowState* w = h->win;
+    WinLevel& l = w->lv[(size_t)j];
+    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill, R = w->amp_r, S = w->amp_s;
+    const int ldc = (int)l.sub->ld;
+    const double* C = level_C(l);
+    const size_t zsz = (size_t)d * lk, rsz = (size_t)(2 * w->ell) * w->ld;
+    sk_status rc;
+    for (int hc = 0; hc < R; ++hc) {
+        if ((rc = simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s + 0x1000u * (uint64_t)hc)))
+            return rc;
+        std::copy(w->h_est, w->h_est + k, w->cand_est.begin() + (size_t)hc * lk);
+        if (R > 1)
+            W_TRY(hipMemcpyAsync(w->Zc + hc * zsz, w->Zd, sizeof(double) * zsz, hipMemcpyDeviceToDevice, h->stream));
+        if (S == 0) continue;
+        int xi = 0;
+        while (xi < k && w->h_est[xi] >= l.theta) ++xi;
+        double* Rh = w->Rc + hc * rsz;
+        W_TRY(hipMemcpy2DAsync(Rh, sizeof(double) * (size_t)w->ld, C, sizeof(double) * (size_t)ldc,
+                               sizeof(double) * (size_t)d, (size_t)r, hipMemcpyDeviceToDevice, h->stream));
+        if (xi > 0) {
+            if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
+            if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, Rh, (int)w->ld, r, d, xi, -1.0, 1.0))))
+                return rc;
+        }
+    }
+    int best = 0;
+    if (S > 0) {
+        std::vector<PiDesc> pis;
+        const int cnt = R * S;
+        for (int b = 0; b < cnt; b += kAmpPiBatch) {
+            pis.clear();
+            for (int u = b; u < std::min(cnt, b + kAmpPiBatch); ++u) {
+                const int hc = u / S, g = u % S;
+                PiDesc p{};
+                p.C = w->Rc + hc * rsz;
+                p.out = w->amp_out + u;
+                p.ldc = w->ld;
+                p.r = r;
+                p.d = d;
+                p.steps = w->steps;
+                p.seed = w->seed;
+                p.stream = w->stream;
+                p.c2 = (uint64_t)ts;
+                p.c3 = 0x100000u + 0x10000u * (uint64_t)g + 0x1000u * (uint64_t)hc + 32u * (uint64_t)j + (uint64_t)s;
+                pis.push_back(p);
+            }
+            const PiDesc* dp = nullptr;
+            W_TRY(put_desc(h, pis, &dp));
+            W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, w->amp_part, w->amp_bars, h->stream));
+        }
+        W_TRY(hipMemcpyAsync(w->h_amp, w->amp_out, sizeof(double) * (size_t)cnt, hipMemcpyDeviceToHost, h->stream));
+        W_TRY(sync_reset(h));
+        double cbest = 0.0;
+        for (int hc = 0; hc < R; ++hc) {
+            double ch = 0.0;
+            for (int g = 0; g < S; ++g) {
+                const double e = w->h_amp[hc * S + g];
+                if (std::isnan(e))
+                    return h->device_fail("window: amplified power iteration failed (barrier timeout or non-finite rows)");
+                if (e > ch) ch = e;
+            }
+            if (hc == 0 || ch < cbest) {
+                cbest = ch;
+                best = hc;
+            }
+        }
+    }
+    if (R > 1 && best != R - 1)
+        W_TRY(hipMemcpyAsync(w->Zd, w->Zc + best * zsz, sizeof(double) * zsz, hipMemcpyDeviceToDevice, h->stream));
+    std::copy(w->cand_est.begin() + (size_t)best * lk, w->cand_est.begin() + (size_t)best * lk + k, w->h_est);
+    return SK_OK;
+}
+
 // Doubling loop of Algorithm "AeroSketch: Update" (k = 2, 4, ...) for level j.
 static sk_status doubling(sketch_t h, int j, int64_t ts) {
     WindowState* w = h->win;
@@ -309,10 +406,12 @@ static sk_status doubling(sketch_t h, int j, int64_t ts) {
     if (kmax < 1) return SK_OK;
     int nsteps = (int)std::ceil(std::log2((double)kmax));
     if (nsteps < 1) nsteps = 1;
+    const bool amplified = w->amp_r > 1 || w->amp_s > 0;
     for (int s = 1; s <= nsteps; ++s) {
         int k = 1 << s;
         if (k > kmax) k = kmax;
-        sk_status rc = simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s);
+        sk_status rc = amplified ? simul_iter_amplified(h, j, s, k, ts)
+                                 : simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s);
         if (rc) return rc;
         if (w->h_est[k - 1] < l.theta || k == kmax) {
             int xi = 0;
@@ -362,6 +461,8 @@ sk_status window_create(sketch_t h) {
         l.theta = w->attp ? 0.0 : std::ldexp(1.0, j) * eps * (double)w->N;
         sketch_config sc = cfg;
         sc.kind = SK_PERSISTENT;
+        sc.amplify_r = 1;
+        sc.amplify_s = 0;
         sc.state_dtype = SK_F64;
         sc.proj_dtype = SK_F64;
         sc.oversample = 0;
@@ -424,6 +525,20 @@ sk_status window_create(sketch_t h) {
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_est, sizeof(double) * (size_t)lk, hipHostMallocDefault));
+    w->amp_r = cfg.amplify_r;
+    w->amp_s = cfg.amplify_s;
+    if (w->amp_r > 1 || w->amp_s > 0) {
+        const int R = w->amp_r, S = w->amp_s;
+        w->cand_est.assign((size_t)R * lk, 0.0);
+        if (R > 1) W_TRY(A(&w->Zc, (size_t)R * d * lk));
+        if (S > 0) {
+            W_TRY(A(&w->Rc, (size_t)R * n2 * w->ld));
+            W_TRY(A(&w->amp_out, (size_t)R * S));
+            W_TRY(A(&w->amp_part, (size_t)kAmpPiBatch * 2 * win_pi_groups(d) * (n2 + 1)));
+            W_TRY(h->dalloc((void**)&w->amp_bars, sizeof(unsigned) * 2 * (size_t)kAmpPiBatch));
+            W_TRY(hipHostMalloc((void**)&w->h_amp, sizeof(double) * (size_t)R * S, hipHostMallocDefault));
+        }
+    }
     return SK_OK;
 }
 
@@ -435,6 +550,7 @@ void window_destroy(sketch_t h) {
     if (w->harena) (void)hipHostFree(w->harena);
     if (w->h_pi) (void)hipHostFree(w->h_pi);
     if (w->h_est) (void)hipHostFree(w->h_est);
+    if (w->h_amp) (void)hipHostFree(w->h_amp);
     if (w->h_norms) (void)hipHostFree(w->h_norms);
     delete w;
     h->win = nullptr;

@@ -49,3 +49,21 @@ def test_library_loads_and_rejects_bad_config_without_gpu():
     assert b"d >= 1" in lib.sketch_last_error()
     assert lib.sketch_update(None, None, 1, 1, 0, 1) == _lib.SK_EINVAL
     assert lib.sketch_destroy(None) == _lib.SK_OK
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsketch.so not built")
+def test_amplification_parameters_are_validated_without_gpu():
+    from paper_2601_02019_amd import _lib
+    lib = _lib.load()
+    cfg = _lib.sketch_config()
+    assert lib.sketch_config_init(ctypes.byref(cfg)) == 0
+    assert (cfg.amplify_r, cfg.amplify_s) == (1, 0)
+    cfg.d, cfg.ell, cfg.kind, cfg.window_N, cfg.R = 8, 4, _lib.SK_WINDOW, 10, 2.0
+    h = ctypes.c_void_p()
+    for r, s in [(0, 1), (17, 0), (2, -1), (2, 17)]:
+        cfg.amplify_r, cfg.amplify_s = r, s
+        assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+        assert b"amplify_r" in lib.sketch_last_error()
+    cfg.kind, cfg.amplify_r, cfg.amplify_s = _lib.SK_PERSISTENT, 2, 1
+    assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+    assert b"amplification" in lib.sketch_last_error()
