@@ -89,6 +89,19 @@ def _load():
     lib.o_attp_theta.restype = ctypes.c_double
     lib.o_attp_snapshot.argtypes = [ctypes.c_void_p, ctypes.c_int64, _i64p, _dp, _dp]
     lib.o_attp_buffer.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_p5_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                ctypes.c_uint64, ctypes.c_int]
+    lib.o_p5_create.restype = ctypes.c_void_p
+    lib.o_p5_set_amplify.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.o_p5_destroy.argtypes = [ctypes.c_void_p]
+    lib.o_p5_update.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), _dp, ctypes.c_int64,
+                                ctypes.c_int64]
+    lib.o_p5_gram.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_p5_query.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_p5_stats.argtypes = [ctypes.c_void_p, _i64p]
+    lib.o_p5_fhat.argtypes = [ctypes.c_void_p]
+    lib.o_p5_fhat.restype = ctypes.c_double
+    lib.o_p5_site.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _i64p, _dp]
     _lib = lib
     return lib
 
@@ -395,3 +408,63 @@ class ATTP:
         C = np.zeros((2 * self.ell, self.d))
         r = _lib.o_attp_buffer(self._h, _p(C))
         return C[:r].copy()
+
+
+class P5:
+    """Continuous distributed tracking (Algorithm "P5"): m sites and a
+    coordinator, messages delivered at once."""
+
+    STATS = ["fmsgs", "broadcasts", "snapshots", "dirs", "raw", "words", "shrinks", "T"]
+    SITE = ["T", "fill", "shrinks", "snapshots", "dirs", "raw", "simul_iters"]
+
+    def __init__(self, d, ell, m, q=1, seed=0, stream=0, fd="exact", amplify=(1, 0)):
+        lib = _load()
+        self._h = lib.o_p5_create(d, ell, m, q, seed, stream, {"exact": 0, "rand": 1}[fd])
+        if not self._h:
+            raise ValueError("bad P5 parameters")
+        if lib.o_p5_set_amplify(self._h, int(amplify[0]), int(amplify[1])) != 0:
+            raise ValueError("bad amplification parameters")
+        self.d, self.ell, self.m = d, ell, m
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o_p5_destroy(self._h)
+            self._h = None
+
+    def update(self, rows, sites):
+        rows = _f64(np.atleast_2d(rows))
+        sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int32).reshape(-1))
+        if rows.shape[0] != sites.shape[0]:
+            raise ValueError("one site per row")
+        if rows.shape[0] == 0:
+            return
+        _check(_lib.o_p5_update(self._h, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _p(rows),
+                                rows.shape[0], rows.shape[1]), "p5_update")
+
+    def gram(self):
+        G = np.zeros((self.d, self.d))
+        _check(_lib.o_p5_gram(self._h, _p(G)), "p5_gram")
+        return G
+
+    def query(self):
+        out = np.zeros((self.ell, self.d))
+        _check(_lib.o_p5_query(self._h, _p(out)), "p5_query")
+        return out
+
+    def stats(self):
+        st = np.zeros(8, dtype=np.int64)
+        _check(_lib.o_p5_stats(self._h, st.ctypes.data_as(_i64p)), "p5_stats")
+        return dict(zip(self.STATS, st.tolist()))
+
+    @property
+    def fhat(self):
+        return _lib.o_p5_fhat(self._h)
+
+    def site(self, j):
+        f3 = np.zeros(3)
+        st = np.zeros(7, dtype=np.int64)
+        C = np.zeros((2 * self.ell, self.d))
+        _check(_lib.o_p5_site(self._h, j, _p(f3), st.ctypes.data_as(_i64p), _p(C)), "p5_site")
+        out = dict(zip(self.SITE, st.tolist()))
+        out.update(F=float(f3[0]), Fhat=float(f3[1]), theta=float(f3[2]), C=C[:out["fill"]].copy())
+        return out

@@ -159,6 +159,30 @@ int o_attp_snapshot(const o_attp* a, int64_t e, int64_t* meta /* [3] */, double*
 /* The residual rows (r x d) into C; returns r. */
 int o_attp_buffer(const o_attp* a, double* C);
 
+/* ---- P5: continuous distributed tracking (Algorithm "P5") --------------
+ * m sites (1..4096), each with a counter F_j and an AeroSketch at threshold
+ * (eps / m) Fhat_j (eps = 2 / ell); a coordinator with Fhat, broadcasts every m
+ * counter messages, and B += the restore of every snapshot a site dumps.
+ * site[e] names the site of row e; rows are taken in order. */
+typedef struct o_p5 o_p5;
+o_p5* o_p5_create(int d, int ell, int m, int q, uint64_t seed, uint64_t stream, int fd_mode);
+int o_p5_set_amplify(o_p5* p, int r, int s);
+void o_p5_destroy(o_p5* p);
+int o_p5_update(o_p5* p, const int32_t* site, const double* rows, int64_t n, int64_t ld);
+/* The coordinator's B (d x d). */
+int o_p5_gram(const o_p5* p, double* G);
+/* ell x d: B shrunk by its ell-th eigenvalue. */
+int o_p5_query(const o_p5* p, double* out);
+/* [0] counter messages [1] broadcasts [2] snapshot messages [3] dumped
+ * directions [4] rows sent as they are [5] words sent [6] FD reduces
+ * [7] rows seen. */
+int o_p5_stats(const o_p5* p, int64_t* st /* [8] */);
+double o_p5_fhat(const o_p5* p);
+/* Site j: f3 = {F_j, Fhat_j, theta_j}; st = {rows, buffer rows, FD reduces,
+ * snapshots, directions, rows sent as they are, simul_iter calls}; C: the
+ * buffer rows.  Any output may be NULL. */
+int o_p5_site(const o_p5* p, int j, double* f3, int64_t* st /* [7] */, double* C);
+
 #ifdef __cplusplus
 }
 #endif

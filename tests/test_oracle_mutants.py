@@ -12,7 +12,10 @@ drops the snapshot taken at time t, a wrong or stale threshold, the
 residual added to past times, a wrong Philox key and a wrong restore sign;
 in the probability amplification the candidate with the largest estimate
 kept, the smallest of the power iterations taken, the residual not formed,
-and a wrong start-vector counter.
+and a wrong start-vector counter; in P5 the listing's unscaled site
+threshold, a counter not reset after its message, a broadcast at every
+message or to all sites but one, a wrong restore sign and a wrong key of a
+site's FD reduce.
 """
 import os
 import shutil
@@ -29,6 +32,7 @@ WINDOW_PINS = ["tests/test_oracle_window_pins.py", "tests/test_oracle_window.py"
 FD_PINS = ["tests/test_oracle_pins.py"]
 ATTP_PINS = ["tests/test_oracle_attp.py"]
 AMP_PINS = ["tests/test_oracle_amplify.py"]
+P5_PINS = ["tests/test_oracle_p5.py"]
 MUTANTS = {
     "pi_threshold_theta": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
                            "if (!(s1 >= theta)) return 0;", WINDOW_PINS),
@@ -72,6 +76,15 @@ MUTANTS = {
                         "R[rr * d + t] -= 0.0 * cz * Zh[(int64_t)t * k + c];", AMP_PINS),
     "amp_power_counter": ("window.c", "0x100000u + 0x10000u * (uint64_t)g", "0x100000u + 0x10000u * (uint64_t)(g + 1)",
                           AMP_PINS),
+    "p5_site_threshold_unscaled": ("p5.c", "const double theta = (eps / m) * s->Fhat;",
+                                   "const double theta = eps * s->Fhat;", P5_PINS),
+    "p5_counter_not_reset": ("p5.c", "p->Fhat += s->F;\n        s->F = 0.0;", "p->Fhat += s->F;", P5_PINS),
+    "p5_broadcast_every_message": ("p5.c", "if (p->nmsg >= m) {", "if (p->nmsg >= 1) {", P5_PINS),
+    "p5_broadcast_skips_a_site": ("p5.c", "for (int k = 0; k < m; ++k) p->s[k].Fhat = p->Fhat;",
+                                  "for (int k = 1; k < m; ++k) p->s[k].Fhat = p->Fhat;", P5_PINS),
+    "p5_restore_sign": ("p5.c", "p->B[(int64_t)x * d + y] += acc - sub;", "p->B[(int64_t)x * d + y] += acc + sub;",
+                        P5_PINS),
+    "p5_site_reduce_key": ("p5.c", "sid * 64u + 1u", "sid * 64u", P5_PINS),
     "power_iteration_step": ("fd.c", "for (int it = 0; it < steps; ++it) {", "for (int it = 1; it < steps; ++it) {",
                              FD_PINS + WINDOW_PINS),
 }
