@@ -19,7 +19,9 @@
  *     Sketch using AeroSketch", the sketch of any earlier prefix of the
  *     stream (sketch_query_at);
  *   - distributed streams: per-site sketches combined by sketch_merge
- *     (Lemma "Decomposability").
+ *     (Lemma "Decomposability"), or tracked continuously by the protocol
+ *     of Algorithm "P5" (SK_P5, Sec. 4.3): m simulated sites and their
+ *     coordinator on one GPU (p5_update).
  *
  * Conventions (all entry points):
  *   - Matrices are row-major.  A row block is n_rows x d with leading
@@ -69,7 +71,7 @@ typedef enum {
 } sk_status;
 
 typedef enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 } sk_dtype;
-typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1, SK_ATTP = 2 } sk_kind;
+typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1, SK_ATTP = 2, SK_P5 = 3 } sk_kind;
 typedef enum { SK_SHRINK_EXACT = 0, SK_SHRINK_RAND = 1 } sk_shrink;
 
 typedef struct {
@@ -90,7 +92,7 @@ typedef struct {
                                  (the default stream); 0: NULL means a stream
                                  owned by the library                           */
     void* hip_stream;     /* hipStream_t to order work on                        */
-    /* SK_WINDOW and SK_ATTP: probability amplification of the dump step
+    /* SK_WINDOW, SK_ATTP and SK_P5: probability amplification of the dump step
      * (Algorithm "Probability Amplification", analysed in the appendix on the
      * amplified estimation).  Every doubling step of a dump runs amplify_r
      * simul_iter candidates (candidate h draws its test matrix from counter
@@ -102,9 +104,11 @@ typedef struct {
      * top squared singular value; the candidate with the smallest estimate
      * (the first on ties) decides the step.  1 <= amplify_r <= 16,
      * 0 <= amplify_s <= 16; (1, 0) (the value sketch_config_init sets) is
-     * the plain dump step.  Other kinds require (1, 0).                    */
+     * the plain dump step.  SK_P5 applies it at every site; persistent
+     * sketches require (1, 0).                                             */
     int32_t amplify_r;
     int32_t amplify_s;
+    int32_t sites;        /* SK_P5: number of sites m, 1..4096                  */
 } sketch_config;
 
 /* Fills *cfg with defaults: exact FP64 persistent sketch, q = 1, no
@@ -190,10 +194,43 @@ typedef struct {
 
 SK_EXPORT sk_status sketch_info(sketch_t h, sketch_info_t* info);
 
-/* SK_WINDOW only: counters of one level: [0] snapshots dumped, [1] raw rows
- * stored, [2] directions dumped, [3] rows in the level's FD buffer, [4] queue
- * length, [5] FD reduces. */
+/* SK_WINDOW and SK_ATTP: counters of one level: [0] snapshots dumped,
+ * [1] raw rows stored, [2] directions dumped, [3] rows in the level's FD
+ * buffer, [4] queue length, [5] FD reduces.  SK_P5: level j is site j, and
+ * [1] counts the rows it sent as they are, [4] is 0. */
 SK_EXPORT sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6);
+
+/* SK_P5 only (Sec. 4.3, Algorithm "P5"; Theorem "dist"): n_rows rows (rows,
+ * n_rows x d, leading dimension ld, dtype SK_F64 / SK_F32 / SK_BF16, host or
+ * device as on_device) arrive in order, row e at site sites[e] (host array
+ * of n_rows ints in [0, m)).  Per row at site j: the site adds |a|^2 to its
+ * counter F_j and sends it when F_j >= (eps / m) Fhat_j (eps = 2 / ell);
+ * the coordinator adds it to Fhat and broadcasts Fhat at every m-th such
+ * message, received by every site before the row's next step.  Then the
+ * site's AeroSketch (2 ell x d FD buffer, dump threshold (eps / m) Fhat_j,
+ * the theorem's per-site threshold) takes the row, and every snapshot it
+ * dumps, (Z, Z^T C'^T C'), goes to the coordinator, which adds
+ * Z W + W^T Z^T - Z (W Z) Z^T to its d x d matrix B.  While Fhat_j = 0 a
+ * row goes to the coordinator as it is (B += a^T a).  Site j's random
+ * draws are those of an SK_ATTP sketch with stream_id 4096 stream_id + j.
+ * The sites' steps run together on the GPU; the result equals processing
+ * the rows one by one.  Blocks until done.  SK_EINVAL (state unchanged) for
+ * a site outside [0, m); SK_EUNSUPPORTED for other kinds (sketch_update on
+ * an SK_P5 sketch is SK_EUNSUPPORTED too).  sketch_query returns B's
+ * eigen-decomposition shrunk by its ell-th eigenvalue. */
+SK_EXPORT sk_status p5_update(sketch_t h, const int32_t* sites, const void* rows, int64_t n_rows, int64_t ld,
+                              int32_t dtype, int32_t on_device);
+
+/* SK_P5 only: [0] counter messages, [1] broadcasts, [2] snapshot messages,
+ * [3] dumped directions, [4] rows sent as they are, [5] words sent (1 per
+ * counter message, m per broadcast, d per row sent as it is, 2 d per
+ * direction), [6] FD reduces over all sites, [7] rows seen. */
+SK_EXPORT sk_status p5_stats(sketch_t h, int64_t* stats8);
+
+/* SK_P5 only: the coordinator's Fhat (host double, may be NULL) and B
+ * (d x d FP64 row-major, host or device as on_device, may be NULL).
+ * Blocks until written. */
+SK_EXPORT sk_status p5_coordinator(sketch_t h, double* fhat, void* gram, int32_t on_device);
 
 /* Library-wide cap (bytes) on device memory held by live sketches; 0 = no
  * cap.  sketch_create returns SK_ENOMEM instead of exceeding it.  Used for

@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import (  # noqa: F401
     SK_BF16, SK_EDEVICE, SK_EINVAL, SK_ENOMEM, SK_ESHAPE, SK_ESTATE, SK_EUNSUPPORTED, SK_F32,
-    SK_ATTP, SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
+    SK_ATTP, SK_P5, SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
     sk_completion, sk_server_config, sk_server_stats, sketch_config, sketch_info_t,
 )
 
@@ -142,6 +142,34 @@ def window_advance(h, t_now):
     _lib.check(_lib.load().window_advance(h, int(t_now)), "window_advance")
 
 
+def p5_update(h, rows, sites):
+    """Rows arrive in order, row e at site sites[e] (Algorithm "P5")."""
+    ptr, n, ld, dt, dev, keep = _rows_arg(rows)
+    st = np.ascontiguousarray(np.asarray(sites, dtype=np.int32).reshape(-1))
+    if st.shape[0] != n:
+        raise ValueError("p5_update: one site per row")
+    _lib.check(_lib.load().p5_update(h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(ptr),
+                                     n, ld, dt, dev), "p5_update")
+    return keep
+
+
+def p5_stats(h):
+    st = (ctypes.c_int64 * 8)()
+    _lib.check(_lib.load().p5_stats(h, st), "p5_stats")
+    keys = ["fmsgs", "broadcasts", "snapshots", "dirs", "raw", "words", "shrinks", "T"]
+    return dict(zip(keys, list(st)))
+
+
+def p5_coordinator(h, gram=None):
+    """(Fhat, B): B into ``gram`` (a d x d FP64 CUDA tensor) when given."""
+    f = ctypes.c_double()
+    ptr = ctypes.c_void_p(gram.data_ptr()) if gram is not None else None
+    if gram is not None:
+        assert gram.is_cuda and gram.dtype == torch.float64 and gram.is_contiguous()
+    _lib.check(_lib.load().p5_coordinator(h, ctypes.byref(f), ptr, 1), "p5_coordinator")
+    return f.value, gram
+
+
 def window_stats(h, level):
     st = (ctypes.c_int64 * 6)()
     _lib.check(_lib.load().window_stats(h, level, st), "window_stats")
@@ -258,10 +286,10 @@ def sketch_profile_read(h):
 
 
 def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", proj_dtype="f64", q=1,
-                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0, amplify=(1, 0)):
+                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0, amplify=(1, 0), sites=0):
     cfg = sketch_config_init()
     cfg.d, cfg.ell = d, ell
-    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP}[kind]
+    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP, "p5": SK_P5}[kind]
     cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
     cfg.state_dtype = _dt(state_dtype)
     cfg.proj_dtype = _dt(proj_dtype)
@@ -269,6 +297,7 @@ def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", pr
     cfg.window_N, cfg.R = int(window_N), float(R)
     cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
     cfg.amplify_r, cfg.amplify_s = int(amplify[0]), int(amplify[1])
+    cfg.sites = int(sites)
     return cfg
 
 
@@ -447,9 +476,9 @@ class Sketch:
 
     def __init__(self, d, ell, kind="persistent", shrink="exact", state_dtype="f64",
                  proj_dtype="f64", q=1, oversample=0, window_N=0, R=1.0, seed=0, stream_id=0,
-                 device=0, stream=None, amplify=(1, 0)):
+                 device=0, stream=None, amplify=(1, 0), sites=0):
         cfg = make_config(d, ell, kind, shrink, state_dtype, proj_dtype, q, oversample, window_N, R,
-                          seed, stream_id, device, amplify)
+                          seed, stream_id, device, amplify, sites)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         if stream is not False:
@@ -496,6 +525,18 @@ class Sketch:
 
     def window_stats(self, level):
         return window_stats(self.handle, level)
+
+    def p5_update(self, rows, sites):
+        p5_update(self.handle, rows, sites)  # returns once the rows are processed
+        return self
+
+    def p5_stats(self):
+        return p5_stats(self.handle)
+
+    def p5_coordinator(self):
+        g = torch.empty((self.d, self.d), dtype=torch.float64, device=f"cuda:{self.device}")
+        f, _ = p5_coordinator(self.handle, g)
+        return f, g
 
     def merge(self, srcs):
         sketch_merge(self.handle, srcs)

@@ -449,8 +449,10 @@ static sk_status validate_config(const sketch_config* cfg) {
         return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
     if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
         return fail(SK_EINVAL, "sketch_create: bad shrink");
-    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW && cfg->kind != SK_ATTP)
+    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW && cfg->kind != SK_ATTP && cfg->kind != SK_P5)
         return fail(SK_EINVAL, "sketch_create: bad kind");
+    if (cfg->kind == SK_P5 && (cfg->sites < 1 || cfg->sites > 4096))
+        return fail(SK_EINVAL, "sketch_create: P5 needs 1 <= sites <= 4096");
     if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
         return fail(SK_EINVAL, "sketch_create: bad q or oversample");
     if (cfg->kind == SK_WINDOW && (cfg->window_N < 1 || !(cfg->R >= 1.0)))
@@ -556,7 +558,7 @@ sk_status sketch_create(const sketch_config* cfg, sketch_t* out) {
         h->own_stream = true;
     }
     sk_status rc;
-    if (cfg->kind == SK_WINDOW || cfg->kind == SK_ATTP) rc = window_create(h);
+    if (cfg->kind == SK_WINDOW || cfg->kind == SK_ATTP || cfg->kind == SK_P5) rc = window_create(h);
     else rc = build_device_state(h);
     const int64_t budget = g_budget.load();
     if (rc == SK_OK && budget > 0 && g_in_use.load() + h->bytes > budget) {
@@ -594,7 +596,8 @@ sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld
         src = (const char*)h->stage;
     }
     if (h->win) {
-        rc = window_update(h, src, n_rows, ld, dtype);
+        rc = h->cfg.kind == SK_P5 ? fail(SK_EUNSUPPORTED, "sketch_update: P5 sketches take rows by p5_update")
+                                  : window_update(h, src, n_rows, ld, dtype);
     } else {
         std::vector<sketch_t> owners;
         std::vector<Task> tasks;
@@ -816,6 +819,46 @@ sk_status sketch_info(sketch_t h, sketch_info_t* info) {
     info->k = h->k;
     info->levels = h->win ? window_levels(h) : 1;
     return SK_OK;
+}
+
+sk_status p5_update(sketch_t h, const int32_t* sites, const void* rows, int64_t n_rows, int64_t ld, int32_t dtype,
+                    int32_t on_device) {
+    sk_status rc = check_handle(h, "p5_update");
+    if (rc) return rc;
+    if (!h->win || h->cfg.kind != SK_P5) return fail(SK_EUNSUPPORTED, "p5_update: not a P5 sketch");
+    if (n_rows < 0) return fail(SK_EINVAL, "p5_update: n_rows < 0");
+    if (n_rows == 0) return SK_OK;
+    if (!rows || !sites) return fail(SK_EINVAL, "p5_update: NULL rows or sites");
+    if (ld < h->d) return fail(SK_EINVAL, "p5_update: ld < d");
+    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, "p5_update: bad dtype");
+    for (int64_t e = 0; e < n_rows; ++e)
+        if (sites[e] < 0 || sites[e] >= h->cfg.sites) return fail(SK_EINVAL, "p5_update: site outside [0, m)");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const char* src = (const char*)rows;
+    if (!on_device) {
+        const size_t nb = (size_t)dtype_size(dtype) * (size_t)((n_rows - 1) * ld + h->d);
+        HIP_TRY(h, h->ensure_stage(nb));
+        HIP_TRY(h, hipMemcpyAsync(h->stage, rows, nb, hipMemcpyHostToDevice, h->stream));
+        src = (const char*)h->stage;
+    }
+    return p5_update_impl(h, sites, src, n_rows, ld, dtype);
+}
+
+sk_status p5_stats(sketch_t h, int64_t* stats8) {
+    sk_status rc = check_handle(h, "p5_stats");
+    if (rc) return rc;
+    if (!h->win || h->cfg.kind != SK_P5) return fail(SK_EUNSUPPORTED, "p5_stats: not a P5 sketch");
+    if (!stats8) return fail(SK_EINVAL, "p5_stats: NULL output");
+    p5_counters(h, stats8);
+    return SK_OK;
+}
+
+sk_status p5_coordinator(sketch_t h, double* fhat, void* gram, int32_t on_device) {
+    sk_status rc = check_handle(h, "p5_coordinator");
+    if (rc) return rc;
+    if (!h->win || h->cfg.kind != SK_P5) return fail(SK_EUNSUPPORTED, "p5_coordinator: not a P5 sketch");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    return p5_coordinator_impl(h, fhat, gram, on_device);
 }
 
 sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6) {

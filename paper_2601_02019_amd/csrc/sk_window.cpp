@@ -51,6 +51,21 @@ struct WinLevel {
     double* Rp = nullptr;  // raw-row ring (rcap x ld)
     int64_t rcap = 0, rtail = 0;
     int64_t ndumps = 0, nraw = 0, ndirs = 0, nsi = 0;
+    // Philox stream word and level index of the level's power iteration,
+    // simul_iter and amplification draws (a P5 site: its own stream, level 0)
+    uint64_t rstream = 0;
+    int rlevel = 0;
+    // P5 site: row clock and unsent counter F_j
+    int64_t clock = 0;
+    double F = 0.0;
+};
+
+// one row of a P5 update call: its index in the block, the site's timestamp,
+// the site's threshold when it arrives, and whether it goes out as it is
+struct P5Row {
+    int64_t e, i;
+    double theta;
+    bool raw;
 };
 
 }  // namespace
@@ -102,13 +117,27 @@ struct WindowState {
     double* Rc = nullptr;        // candidate residuals: amp_r x (2 ell x ld)
     double* amp_out = nullptr;   // amp_r x amp_s power-iteration estimates
     double* h_amp = nullptr;     // pinned mirror
-    double* amp_part = nullptr;  // slab partials of one power-iteration launch
-    unsigned* amp_bars = nullptr;
     std::vector<double> cand_est;  // amp_r x kmax estimates
+    // P5 (Algorithm "P5"): the levels are the m sites; the coordinator's
+    // Fhat, the value of the last broadcast (every site holds it), the
+    // messages since that broadcast and the coordinator's d x d B.  Snapshot
+    // messages wait in Zs / Ws (directions as rows, ent = message index) and
+    // rows sent as they are in Rs until they are added to B.
+    bool p5 = false;
+    int m = 0;
+    double Fhat = 0.0, Fb = 0.0;
+    int64_t nmsg = 0;
+    int64_t fmsgs = 0, bcasts = 0, smsgs = 0, sdirs = 0, raws = 0, words = 0;
+    double* Bc = nullptr;
+    int qD = 0, qmsgs = 0, rawn = 0;
+    std::vector<int32_t> qent;
+    std::vector<std::vector<P5Row>> p5rows;
 };
 
-// power iterations per cooperative launch of the amplified step
-static const int kAmpPiBatch = 16;
+// power-iteration descriptors per cooperative launch (pi_part holds the slab
+// partials of one launch)
+static const int kPiBatch = 32;
+
 
 static const int kWinDmax = 4096;  // largest d of a window sketch
 
@@ -138,6 +167,20 @@ static hipError_t sync_reset(sketch_t h) {
     hipError_t e = hipStreamSynchronize(h->stream);
     h->win->aoff = 0;
     return e;
+}
+
+// Algorithm "Power Iteration" for every descriptor, kPiBatch per cooperative
+// launch (the launches share one partial buffer, in stream order).
+static sk_status launch_pis(sketch_t h, const std::vector<PiDesc>& pis) {
+    WindowState* w = h->win;
+    for (size_t b = 0; b < pis.size(); b += kPiBatch) {
+        const size_t cnt = std::min(pis.size() - b, (size_t)kPiBatch);
+        std::vector<PiDesc> part(pis.begin() + (ptrdiff_t)b, pis.begin() + (ptrdiff_t)(b + cnt));
+        const PiDesc* dp = nullptr;
+        W_TRY(put_desc(h, part, &dp));
+        W_TRY(launch_win_pi(dp, (int)cnt, w->d, 2 * w->ell, w->pi_part, w->pi_bars, h->stream));
+    }
+    return SK_OK;
 }
 
 static GemmDesc gd(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
@@ -232,7 +275,7 @@ static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) 
     m.cols = k;
     m.ld = lk;
     m.seed = w->seed;
-    m.stream = w->stream;
+    m.stream = l.rstream;
     m.c2 = (uint64_t)ts;
     m.c3 = tag;
     W_TRY(launch_philox_mat1(m, h->stream));
@@ -262,14 +305,65 @@ static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) 
     return SK_OK;
 }
 
+// P5 coordinator (Receive_Update of Algorithm "P5"): adds the waiting
+// messages to B -- B += R^T R for the rows sent as they are, and for the
+// snapshots (directions as rows of Zs, Ws; ent = message of each direction)
+// B += Z^T W + W^T Z - Z^T M Z with M = W Z^T masked to the blocks of one
+// message, i.e. Z W + W^T Z^T - Z (W Z) Z^T per message.
+static sk_status p5_flush(sketch_t h) {
+    WindowState* w = h->win;
+    const int d = w->d, li = (int)w->ld;
+    sk_status rc;
+    if (w->rawn > 0) {
+        if ((rc = gemm1(h, gd(w->Rs, li, true, w->Rs, li, false, w->Bc, d, d, d, w->rawn, 1.0, 1.0)))) return rc;
+        w->rawn = 0;
+    }
+    if (w->qD > 0) {
+        const int D = w->qD;
+        W_TRY(hipMemcpyAsync(w->ent, w->qent.data(), sizeof(int32_t) * (size_t)D, hipMemcpyHostToDevice, h->stream));
+        if ((rc = gemm1(h, gd(w->Zs, li, true, w->Ws, li, false, w->Bc, d, d, d, D, 1.0, 1.0)))) return rc;
+        if ((rc = gemm1(h, gd(w->Ws, li, true, w->Zs, li, false, w->Bc, d, d, d, D, 1.0, 1.0)))) return rc;
+        if ((rc = gemm1(h, gd(w->Ws, li, false, w->Zs, li, true, w->S, w->chunk, D, D, d)))) return rc;
+        W_TRY(launch_blockmask(w->S, w->chunk, D, w->ent, h->stream));
+        if ((rc = gemm1(h, gd(w->Zs, li, true, w->S, w->chunk, false, w->T2, w->chunk, d, D, D)))) return rc;
+        if ((rc = gemm1(h, gd(w->T2, w->chunk, false, w->Zs, li, false, w->Bc, d, d, d, D, -1.0, 1.0)))) return rc;
+        W_TRY(sync_reset(h));  // the host entry list is reused
+        w->qD = 0;
+        w->qmsgs = 0;
+        w->qent.clear();
+    }
+    return SK_OK;
+}
+
 // Snapshot (Z, Z^T C'^T C') of the first xi columns of Zd, then the residual
-// C <- C' - C' Z Z^T (the dump of Algorithm "AeroSketch: Update").
+// C <- C' - C' Z Z^T (the dump of Algorithm "AeroSketch: Update").  A P5
+// site sends the snapshot to the coordinator's message queue instead of
+// keeping it.
 static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
     WindowState* w = h->win;
     WinLevel& l = w->lv[(size_t)j];
     const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
     const int ldc = (int)l.sub->ld;
     double* C = (double*)level_C(l);
+    if (w->p5) {
+        sk_status rc;
+        if (w->qD + xi > w->chunk && (rc = p5_flush(h))) return rc;
+        const int64_t off = w->qD;
+        if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
+        if ((rc = gemm1(h, gd(w->CZ, lk, true, C, ldc, false, w->Ws + off * w->ld, (int)w->ld, xi, d, r))))
+            return rc;
+        W_TRY(launch_transpose(w->Zd, lk, w->Zs + off * w->ld, w->ld, d, xi, h->stream));
+        if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, C, ldc, r, d, xi, -1.0, 1.0)))) return rc;
+        for (int c = 0; c < xi; ++c) w->qent.push_back(w->qmsgs);
+        w->qD += xi;
+        w->qmsgs += 1;
+        l.ndumps += 1;
+        l.ndirs += xi;
+        w->smsgs += 1;
+        w->sdirs += xi;
+        w->words += 2 * (int64_t)d * xi;
+        return SK_OK;
+    }
     if (w->attp && l.ptail + xi > l.pcap) {
         // append-only store: double it (the old vectors are copied over)
         int64_t ncap = std::max<int64_t>(2 * l.pcap, l.ptail + xi);
@@ -332,7 +426,8 @@ static sk_status simul_iter_amplified(sketch_t h, int j, int s, int k, int64_t t
     const size_t zsz = (size_t)d * lk, rsz = (size_t)(2 * w->ell) * w->ld;
     sk_status rc;
     for (int hc = 0; hc < R; ++hc) {
-        if ((rc = simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s + 0x1000u * (uint64_t)hc)))
+        if ((rc = simul_iter(h, j, k, ts,
+                             0x200u + 32u * (uint64_t)l.rlevel + (uint64_t)s + 0x1000u * (uint64_t)hc)))
             return rc;
         std::copy(w->h_est, w->h_est + k, w->cand_est.begin() + (size_t)hc * lk);
         if (R > 1)
@@ -353,9 +448,8 @@ static sk_status simul_iter_amplified(sketch_t h, int j, int s, int k, int64_t t
     if (S > 0) {
         std::vector<PiDesc> pis;
         const int cnt = R * S;
-        for (int b = 0; b < cnt; b += kAmpPiBatch) {
-            pis.clear();
-            for (int u = b; u < std::min(cnt, b + kAmpPiBatch); ++u) {
+        {
+            for (int u = 0; u < cnt; ++u) {
                 const int hc = u / S, g = u % S;
                 PiDesc p{};
                 p.C = w->Rc + hc * rsz;
@@ -365,14 +459,14 @@ static sk_status simul_iter_amplified(sketch_t h, int j, int s, int k, int64_t t
                 p.d = d;
                 p.steps = w->steps;
                 p.seed = w->seed;
-                p.stream = w->stream;
+                p.stream = l.rstream;
                 p.c2 = (uint64_t)ts;
-                p.c3 = 0x100000u + 0x10000u * (uint64_t)g + 0x1000u * (uint64_t)hc + 32u * (uint64_t)j + (uint64_t)s;
+                p.c3 = 0x100000u + 0x10000u * (uint64_t)g + 0x1000u * (uint64_t)hc + 32u * (uint64_t)l.rlevel +
+                       (uint64_t)s;
                 pis.push_back(p);
             }
-            const PiDesc* dp = nullptr;
-            W_TRY(put_desc(h, pis, &dp));
-            W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, w->amp_part, w->amp_bars, h->stream));
+            sk_status prc = launch_pis(h, pis);
+            if (prc) return prc;
         }
         W_TRY(hipMemcpyAsync(w->h_amp, w->amp_out, sizeof(double) * (size_t)cnt, hipMemcpyDeviceToHost, h->stream));
         W_TRY(sync_reset(h));
@@ -411,7 +505,7 @@ static sk_status doubling(sketch_t h, int j, int64_t ts) {
         int k = 1 << s;
         if (k > kmax) k = kmax;
         sk_status rc = amplified ? simul_iter_amplified(h, j, s, k, ts)
-                                 : simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)j + (uint64_t)s);
+                                 : simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)l.rlevel + (uint64_t)s);
         if (rc) return rc;
         if (w->h_est[k - 1] < l.theta || k == kmax) {
             int xi = 0;
@@ -450,15 +544,20 @@ sk_status window_create(sketch_t h) {
     w->kmax = std::min(cfg.ell, cfg.d);
     w->steps = (int)std::ceil(std::log2((double)cfg.d)) + 1;
     w->attp = cfg.kind == SK_ATTP;
-    int L = w->attp ? 1 : (int)std::ceil(std::log2(cfg.R));
+    w->p5 = cfg.kind == SK_P5;
+    w->m = w->p5 ? cfg.sites : 0;
+    int L = w->p5 ? cfg.sites : w->attp ? 1 : (int)std::ceil(std::log2(cfg.R));
     w->L = L < 1 ? 1 : L;
-    if (w->attp) w->N = INT64_MAX;
+    if (w->attp || w->p5) w->N = INT64_MAX;
     const double eps = 2.0 / cfg.ell;
     const int d = w->d, ell = w->ell, lk = w->kmax, n2 = 2 * ell;
     w->lv.resize((size_t)w->L);
     for (int j = 0; j < w->L; ++j) {
         WinLevel& l = w->lv[(size_t)j];
-        l.theta = w->attp ? 0.0 : std::ldexp(1.0, j) * eps * (double)w->N;
+        l.theta = (w->attp || w->p5) ? 0.0 : std::ldexp(1.0, j) * eps * (double)w->N;
+        // P5 site j draws as an ATTP sketch with stream word 4096 stream + j
+        l.rstream = w->p5 ? cfg.stream_id * 4096u + (uint64_t)j : cfg.stream_id;
+        l.rlevel = w->p5 ? 0 : j;
         sketch_config sc = cfg;
         sc.kind = SK_PERSISTENT;
         sc.amplify_r = 1;
@@ -466,11 +565,13 @@ sk_status window_create(sketch_t h) {
         sc.state_dtype = SK_F64;
         sc.proj_dtype = SK_F64;
         sc.oversample = 0;
-        sc.stream_id = cfg.stream_id * 64u + (uint64_t)j + 1u;
+        sc.sites = 0;
+        sc.stream_id = w->p5 ? l.rstream * 64u + 1u : cfg.stream_id * 64u + (uint64_t)j + 1u;
         sc.hip_stream = h->stream;
         sc.use_given_stream = 1;
         sk_status rc = sketch_create(&sc, &l.sub);
         if (rc) return rc;
+        if (w->p5) continue;  // a site's snapshots go to the coordinator
         // ATTP's store starts small and doubles as snapshots accumulate
         l.pcap = w->attp ? 4 * (int64_t)lk : (4 * (int64_t)ell + 4) * lk;
         l.rcap = 4 * (int64_t)ell + 2;
@@ -516,8 +617,8 @@ sk_status window_create(sketch_t h) {
     W_TRY(A(&w->part, 256));
     W_TRY(A(&w->stats, 16));
     W_TRY(h->dalloc((void**)&w->ctrl, 64 * sizeof(int32_t)));
-    W_TRY(A(&w->pi_part, (size_t)w->L * 2 * win_pi_groups(d) * (n2 + 1)));
-    W_TRY(h->dalloc((void**)&w->pi_bars, sizeof(unsigned) * 2 * (size_t)w->L));
+    W_TRY(A(&w->pi_part, (size_t)kPiBatch * 2 * win_pi_groups(d) * (n2 + 1)));
+    W_TRY(h->dalloc((void**)&w->pi_bars, sizeof(unsigned) * 2 * (size_t)kPiBatch));
     w->gpart_cap = (int64_t)1 << 21;
     W_TRY(A(&w->gpart, (size_t)w->gpart_cap));
     w->acap = 1 << 20;
@@ -525,6 +626,12 @@ sk_status window_create(sketch_t h) {
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_est, sizeof(double) * (size_t)lk, hipHostMallocDefault));
+    if (w->p5) {
+        W_TRY(A(&w->Bc, (size_t)d * d));
+        W_TRY(hipMemset(w->Bc, 0, sizeof(double) * (size_t)d * d));
+        w->p5rows.resize((size_t)w->m);
+        w->qent.reserve((size_t)w->chunk);
+    }
     w->amp_r = cfg.amplify_r;
     w->amp_s = cfg.amplify_s;
     if (w->amp_r > 1 || w->amp_s > 0) {
@@ -534,8 +641,6 @@ sk_status window_create(sketch_t h) {
         if (S > 0) {
             W_TRY(A(&w->Rc, (size_t)R * n2 * w->ld));
             W_TRY(A(&w->amp_out, (size_t)R * S));
-            W_TRY(A(&w->amp_part, (size_t)kAmpPiBatch * 2 * win_pi_groups(d) * (n2 + 1)));
-            W_TRY(h->dalloc((void**)&w->amp_bars, sizeof(unsigned) * 2 * (size_t)kAmpPiBatch));
             W_TRY(hipHostMalloc((void**)&w->h_amp, sizeof(double) * (size_t)R * S, hipHostMallocDefault));
         }
     }
@@ -624,14 +729,12 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
             p.d = d;
             p.steps = w->steps;
             p.seed = w->seed;
-            p.stream = w->stream;
+            p.stream = l.rstream;
             p.c2 = (uint64_t)i;
-            p.c3 = 0x100u + (uint64_t)j;
+            p.c3 = 0x100u + (uint64_t)l.rlevel;
             pis.push_back(p);
         }
-        const PiDesc* dp = nullptr;
-        W_TRY(put_desc(h, pis, &dp));
-        W_TRY(launch_win_pi(dp, (int)pis.size(), d, 2 * w->ell, w->pi_part, w->pi_bars, h->stream));
+        if (sk_status prc = launch_pis(h, pis)) return prc;
         W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
         W_TRY(sync_reset(h));
         for (int j : pj)
@@ -698,8 +801,11 @@ static sk_status eig_d(sketch_t h) {
 // residuals are not kept).
 static sk_status query_range(sketch_t h, int64_t lb, int64_t ub, const double** out);
 
+static sk_status p5_query(sketch_t h, const double** out);
+
 sk_status window_query(sketch_t h, const double** out) {
     WindowState* w = h->win;
+    if (w->p5) return p5_query(h, out);
     if (w->attp) return query_range(h, 0, w->T, out);
     return query_range(h, w->T - w->N, w->T, out);
 }
@@ -802,5 +908,186 @@ sk_status window_level_stats(sketch_t h, int32_t level, int64_t* st) {
     st[3] = l.sub->fill;
     st[4] = (int64_t)l.q.size();
     st[5] = l.sub->shrinks;
+    return SK_OK;
+}
+
+// ---------------------------------------------------------------- P5
+// Algorithm "P5" with m simulated sites on one GPU.  The counter protocol
+// depends on the rows' squared norms alone, so one pass on the host over
+// the block's norms fixes, for every row, its site's timestamp and the
+// site's threshold (eps / m) Fhat_j when the row arrives (every site holds
+// the last broadcast value).  Given those thresholds the sites are
+// independent, so their rows go through in lockstep: step t takes the t-th
+// row of every site in the block -- one batched FD ingest (with the reduces
+// that fall due), one launch of all the sites' power iterations, one
+// transfer of the estimates -- and the rare doubling steps and dumps run
+// site by site.  This yields what processing the rows one at a time does.
+sk_status p5_update_impl(sketch_t h, const int32_t* site, const char* rows, int64_t n, int64_t ld, int dtype) {
+    WindowState* w = h->win;
+    const int d = w->d, m = w->m;
+    if (n > w->norms_cap) {
+        W_TRY(hipStreamSynchronize(h->stream));
+        int64_t cap = std::max<int64_t>(n, 4096);
+        if (w->h_norms) (void)hipHostFree(w->h_norms);
+        w->h_norms = nullptr;
+        W_TRY(h->dalloc((void**)&w->norms, sizeof(double) * (size_t)cap));
+        W_TRY(hipHostMalloc((void**)&w->h_norms, sizeof(double) * (size_t)cap, hipHostMallocDefault));
+        w->norms_cap = cap;
+    }
+    W_TRY(launch_rownorm(rows, ld, dtype, n, d, w->norms, h->stream));
+    W_TRY(hipMemcpyAsync(w->h_norms, w->norms, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+    W_TRY(sync_reset(h));
+    // the counter protocol (Update lines on F_j; the coordinator's
+    // Receive_Update on F_j and its broadcast)
+    const double eps = 2.0 / w->ell;
+    for (auto& v : w->p5rows) v.clear();
+    std::vector<int> act;
+    for (int64_t e = 0; e < n; ++e) {
+        const int j = site[e];
+        WinLevel& l = w->lv[(size_t)j];
+        const double nrm = w->h_norms[e];
+        l.clock += 1;
+        l.F += nrm;
+        if (l.F >= (eps / m) * w->Fb) {
+            w->Fhat += l.F;
+            l.F = 0.0;
+            w->fmsgs += 1;
+            w->words += 1;
+            if (++w->nmsg >= m) {
+                w->nmsg = 0;
+                w->bcasts += 1;
+                w->words += m;
+                w->Fb = w->Fhat;
+            }
+        }
+        const double theta = (eps / m) * w->Fb;
+        if (theta == 0.0 && !(nrm > 0.0)) continue;  // a zero row before the first broadcast sends nothing
+        auto& v = w->p5rows[(size_t)j];
+        if (v.empty()) act.push_back(j);
+        v.push_back(P5Row{e, l.clock, theta, theta == 0.0});
+    }
+    w->T += n;
+    std::sort(act.begin(), act.end());
+    const int64_t es = dtype_size(dtype);
+    std::vector<sketch_t> owners;
+    std::vector<Task> tasks;
+    std::vector<PiDesc> pis;
+    std::vector<int> pj;
+    std::vector<const P5Row*> pr;
+    sk_status rc;
+    for (size_t t = 0; !act.empty(); ++t) {
+        owners.clear();
+        tasks.clear();
+        pis.clear();
+        pj.clear();
+        pr.clear();
+        size_t keep = 0;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int j = act[a];
+            const auto& v = w->p5rows[(size_t)j];
+            if (t >= v.size()) continue;
+            act[keep++] = j;
+            const P5Row& r = v[t];
+            WinLevel& l = w->lv[(size_t)j];
+            const char* row = rows + r.e * ld * es;
+            if (r.raw) {
+                // the row goes to the coordinator as it is
+                if (w->rawn == 4 * w->ell + 2 && (rc = p5_flush(h))) return rc;
+                W_TRY(launch_rows_to_f64(row, ld, dtype, w->Rs + (int64_t)w->rawn * w->ld, w->ld, 1, d, h->stream));
+                w->rawn += 1;
+                l.nraw += 1;
+                w->raws += 1;
+                w->words += d;
+                continue;
+            }
+            plan_rows(l.sub, 1, row, ld, dtype, nullptr, nullptr, nullptr, owners, tasks);
+            pj.push_back(j);
+            pr.push_back(&r);
+        }
+        act.resize(keep);
+        if (!tasks.empty() && (rc = execute_batched(h, owners, tasks, dtype))) return rc;
+        if (pj.empty()) continue;
+        for (size_t u = 0; u < pj.size(); ++u) {
+            const WinLevel& l = w->lv[(size_t)pj[u]];
+            PiDesc p{};
+            p.C = level_C(l);
+            p.out = w->pi_out + pj[u];
+            p.ldc = l.sub->ld;
+            p.r = (int)l.sub->fill;
+            p.d = d;
+            p.steps = w->steps;
+            p.seed = w->seed;
+            p.stream = l.rstream;
+            p.c2 = (uint64_t)pr[u]->i;
+            p.c3 = 0x100u + (uint64_t)l.rlevel;
+            pis.push_back(p);
+        }
+        if ((rc = launch_pis(h, pis))) return rc;
+        W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
+        W_TRY(sync_reset(h));
+        for (int j : pj)
+            if (std::isnan(w->h_pi[j]))
+                return h->device_fail("P5: power iteration failed (barrier timeout or non-finite rows)");
+        for (size_t u = 0; u < pj.size(); ++u) {
+            const int j = pj[u];
+            WinLevel& l = w->lv[(size_t)j];
+            l.theta = pr[u]->theta;
+            if (w->h_pi[j] >= l.theta / 2.0 && (rc = doubling(h, j, pr[u]->i))) return rc;
+        }
+    }
+    if ((rc = p5_flush(h))) return rc;
+    W_TRY(sync_reset(h));
+    return SK_OK;
+}
+
+void p5_counters(sketch_t h, int64_t* st) {
+    const WindowState* w = h->win;
+    int64_t red = 0;
+    for (const WinLevel& l : w->lv) red += l.sub->shrinks;
+    st[0] = w->fmsgs;
+    st[1] = w->bcasts;
+    st[2] = w->smsgs;
+    st[3] = w->sdirs;
+    st[4] = w->raws;
+    st[5] = w->words;
+    st[6] = red;
+    st[7] = w->T;
+}
+
+static sk_status p5_check_sites(sketch_t h) {
+    for (const WinLevel& lv : h->win->lv) {
+        int32_t inf[2] = {0, 0};
+        W_TRY(hipMemcpy(inf, lv.sub->host.info, sizeof(inf), hipMemcpyDeviceToHost));
+        if (inf[0] != 0) return h->device_fail("P5: FD reduce eigen-solver did not converge");
+    }
+    return SK_OK;
+}
+
+sk_status p5_coordinator_impl(sketch_t h, double* fhat, void* gram, int on_device) {
+    WindowState* w = h->win;
+    sk_status rc;
+    if ((rc = p5_flush(h))) return rc;
+    if (fhat) *fhat = w->Fhat;
+    if (gram) {
+        const size_t nb = sizeof(double) * (size_t)w->d * w->d;
+        W_TRY(hipMemcpyAsync(gram, w->Bc, nb, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+    }
+    W_TRY(sync_reset(h));
+    return p5_check_sites(h);
+}
+
+// The coordinator's Query: B's eigen-decomposition, shrunk by its ell-th
+// eigenvalue.
+static sk_status p5_query(sketch_t h, const double** out) {
+    WindowState* w = h->win;
+    const int d = w->d;
+    sk_status rc;
+    if ((rc = p5_flush(h))) return rc;
+    W_TRY(hipMemcpyAsync(w->Bq, w->Bc, sizeof(double) * (size_t)d * d, hipMemcpyDeviceToDevice, h->stream));
+    if ((rc = eig_d(h))) return rc;
+    W_TRY(launch_shrink_rows(w->Uq, d, w->lamq, d, w->ell, w->Xq, w->ld, d, h->stream));
+    W_TRY(sync_reset(h));
+    if ((rc = p5_check_sites(h))) return rc;
+    *out = w->Xq;
     return SK_OK;
 }

@@ -18,3 +18,7 @@ const int32_t* window_info_ptr(sketch_t h);
 int64_t window_time(sketch_t h);
 int32_t window_levels(sketch_t h);
 sk_status window_level_stats(sketch_t h, int32_t level, int64_t* st);
+// P5 sketches (Algorithm "P5"): sites[e] in [0, m) checked by the caller.
+sk_status p5_update_impl(sketch_t h, const int32_t* sites, const char* rows_dev, int64_t n, int64_t ld, int dtype);
+void p5_counters(sketch_t h, int64_t* st8);
+sk_status p5_coordinator_impl(sketch_t h, double* fhat, void* gram, int on_device);

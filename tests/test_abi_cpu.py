@@ -67,3 +67,21 @@ def test_amplification_parameters_are_validated_without_gpu():
     cfg.kind, cfg.amplify_r, cfg.amplify_s = _lib.SK_PERSISTENT, 2, 1
     assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
     assert b"amplification" in lib.sketch_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsketch.so not built")
+def test_p5_configuration_is_validated_without_gpu():
+    from paper_2601_02019_amd import _lib
+    lib = _lib.load()
+    cfg = _lib.sketch_config()
+    assert lib.sketch_config_init(ctypes.byref(cfg)) == 0
+    assert cfg.sites == 0
+    cfg.d, cfg.ell, cfg.kind = 8, 4, _lib.SK_P5
+    h = ctypes.c_void_p()
+    for m in (0, 4097):
+        cfg.sites = m
+        assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+        assert b"sites" in lib.sketch_last_error()
+    st = (ctypes.c_int64 * 8)()
+    assert lib.p5_stats(None, st) == _lib.SK_EINVAL
+    assert lib.p5_update(None, None, None, 1, 8, 0, 1) == _lib.SK_EINVAL
