@@ -44,16 +44,19 @@ def parse():
                     help="skip the covariance-error evaluation (torch eigvalsh) of the timed sketch")
     ap.add_argument("--cpu-shrinks", type=int, default=1,
                     help="shrinks of the CPU oracle sample")
-    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy", "attp"],
+    ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy", "attp",
+                                           "p5"],
                     default="persistent",
                     help="persistent: the tight-error single stream (default); small: the FP64 exact "
                          "small stream; window: the sliding-window stream; sites: 64 CSR sites with "
                          "tree merges; serving: many concurrent streams with Poisson bursts; copy: a "
-                         "plain device copy of known size (HBM reference and counter calibration)")
+                         "plain device copy of known size (HBM reference and counter calibration); attp: "
+                         "the ATTP stream; p5: continuous distributed tracking over the sites' rows")
     ap.add_argument("--window-rows", type=int, default=200_000, help="rows of the window stream")
     ap.add_argument("--site-rows", type=int, default=100_000, help="rows per site")
     ap.add_argument("--attp-rows", type=int, default=10_000, help="rows of the ATTP stream")
     ap.add_argument("--sites", type=int, default=64)
+    ap.add_argument("--p5-rows", type=int, default=2000, help="rows per site (on average) of the p5 workload")
     ap.add_argument("--streams", type=int, default=512)
     ap.add_argument("--bursts", type=int, default=2000, help="bursts per load point")
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9",
@@ -597,6 +600,76 @@ def sites_main(args):
                "cpu_baseline": cpu})
 
 
+def p5_main(args):
+    """Continuous distributed tracking (Algorithm "P5") on the distributed
+    workload's shape: --sites sites (64), d = 2048, ell = 128, rows with 1 %
+    density and values N(0,1) j^-0.5 (stored dense, FP32 on the device), each
+    row at a site drawn uniformly; --p5-rows rows per site on average.  The
+    rows go in blocks of 16,384; the coordinator is queried at the end."""
+    import numpy as np
+    import torch
+    from paper_2601_02019_amd import Sketch
+    d, ell, S = 2048, 128, args.sites
+    n = S * args.p5_rows
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    w = torch.arange(1, d + 1, device=dev, dtype=torch.float32) ** -0.5
+    A = torch.empty(n, d, device=dev, dtype=torch.float32)
+    for r0 in range(0, n, 16_384):
+        m = min(16_384, n - r0)
+        mask = torch.rand(m, d, device=dev, generator=gen) < 0.01
+        A[r0:r0 + m] = torch.randn(m, d, device=dev, generator=gen) * w * mask
+    site = np.random.default_rng(5).integers(0, S, size=n).astype(np.int32)
+    torch.cuda.synchronize()
+    warm = Sketch(d, ell, kind="p5", shrink="rand", q=1, seed=5, stream_id=1, sites=S)
+    warm.p5_update(A[:4096], site[:4096])
+    warm.query()
+    warm.close()
+    s = Sketch(d, ell, kind="p5", shrink="rand", q=1, seed=5, stream_id=0, sites=S)
+    upd = 0.0
+    for r0 in range(0, n, 16_384):
+        m = min(16_384, n - r0)
+        _, t = timed(lambda: s.p5_update(A[r0:r0 + m], site[r0:r0 + m]))
+        upd += t
+        print(f"[bench] p5 rows {r0 + m}: {t:.2f}s", file=sys.stderr, flush=True)
+    B, tq = timed(lambda: s.query(torch.float64))
+    st = s.p5_stats()
+    fhat, Bc = s.p5_coordinator()
+    s.close()
+    G = gram_f64(A)
+    tot = float(torch.trace(G))
+    D = G - B.T @ B
+    err = float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / tot)
+    D = G - Bc
+    err_c = float(torch.linalg.eigvalsh((D + D.T) / 2).abs().max() / tot)
+    print(f"[bench] p5: update {upd:.2f}s, query {1e3 * tq:.0f} ms, err {err:.3e} (coordinator {err_c:.3e}), "
+          f"{st}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        Ah = A.double().cpu().numpy()
+        o = oracle.P5(d, ell, S, q=1, seed=5, stream=0, fd="rand")
+        done, tc = 0, 0.0
+        while done < n and tc < 20.0:
+            m = min(256, n - done)
+            t = time.perf_counter()
+            o.update(Ah[done:done + m], site[done:done + m])
+            tc += time.perf_counter() - t
+            done += m
+        cpu = {"value": done / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} rows of the P5 stream (about 20 s), FP64 plain C, one thread, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
+    base_line(args, n / upd, "rows/s", None,
+              "P5 continuous distributed tracking: %d sites, %d rows (d=2048, 1%% density, values N(0,1) "
+              "j^-0.5, dense FP32 on the device), each at a uniformly drawn site; ell=128, randomized FD "
+              "reduce at the sites" % (S, n),
+              {"dtype": "f32 rows, f64 state", "rows": n, "update_s": upd, "query_ms": 1e3 * tq,
+               "cov_err_rel": err, "cov_err_rel_coordinator": err_c, "bound_rel_eps": 2.0 / ell,
+               "fhat_over_fro2": fhat / tot, "messages": st,
+               "words_over_raw_rows": st["words"] / float(n * d), "cpu_baseline": cpu})
+
+
 def copy_main(args):
     """A plain device-to-device copy of 1 GiB, args.steps times: the measured
     HBM rate, and a kernel of known traffic for calibrating the FETCH_SIZE /
@@ -628,7 +701,7 @@ def main():
         sys.exit(2)
     if args.workload != "persistent":
         return {"serving": serving_main, "small": small_main, "window": window_main,
-                "sites": sites_main, "copy": copy_main, "attp": attp_main}[args.workload](args)
+                "sites": sites_main, "copy": copy_main, "attp": attp_main, "p5": p5_main}[args.workload](args)
     import torch
     from paper_2601_02019_amd import Sketch
 

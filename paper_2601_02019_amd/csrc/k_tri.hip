@@ -1349,6 +1349,30 @@ hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t 
     return hipGetLastError();
 }
 
+// The same for `count` descriptors in device memory, one workgroup (group of
+// workgroups for the back-transformation) per descriptor.
+hipError_t launch_tri_eig_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st) {
+    const int dbl = tri_lds_doubles();
+    if (dbl < 64 * 65 || !g_back_ok || max_n > TRI_NMAX) return hipErrorInvalidConfiguration;
+    DescArg<SmallDesc> a{ds, {}};
+    hipLaunchKernelGGL(k_tri_reduce_desc, dim3(1, 1, (unsigned)count), dim3(1024), sizeof(double) * (size_t)dbl, st,
+                       a, dbl, g_blk_ok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g_blk_ok && max_n > 128) {
+        hipLaunchKernelGGL(k_tri_reduce_blk_desc, dim3(1, 1, (unsigned)count), dim3(1024),
+                           sizeof(double) * (size_t)tri_blk_lds(256), st, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tri_eig_desc, dim3(1, 1, (unsigned)count), dim3(1024), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tri_back_desc, dim3((unsigned)((max_n + TRI_SC - 1) / TRI_SC), 1, (unsigned)count), dim3(64),
+                       sizeof(double) * (size_t)back_lds(max_n), st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st) {
     const int dbl = tri_lds_doubles();
     if (dbl < 64 * 65) return hipErrorInvalidConfiguration;

@@ -61,6 +61,7 @@ hipError_t launch_tri_reduce(const Task* tasks, int count, int min_n, int max_n,
 hipError_t launch_tri_eig(const Task* tasks, int count, int max_n, hipStream_t st);
 hipError_t launch_tri_back(const Task* tasks, int count, int max_n, hipStream_t st);
 hipError_t launch_tri_eig1(const SmallDesc& q, hipStream_t st);
+hipError_t launch_tri_eig_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
 int tri_lds_doubles();
 // Multi-workgroup reduction (one group of workgroups on one XCD per problem)
 // of the tasks of order trix_min_n() .. 512.

@@ -86,12 +86,17 @@ struct WindowState {
     double* h_norms = nullptr;   // pinned
     double* pi_out = nullptr;
     double* h_pi = nullptr;      // pinned
-    double *Kd = nullptr, *Q1d = nullptr, *Qd = nullptr, *Zd = nullptr;  // d x kmax
-    double *Y = nullptr, *CQ = nullptr, *CZ = nullptr;                   // 2 ell x kmax
-    double *Wk = nullptr, *Xk = nullptr, *Mk = nullptr, *Uk = nullptr, *lamk = nullptr;
-    double *w1 = nullptr, *w2 = nullptr;
-    double* h_est = nullptr;     // pinned
-    int32_t* info = nullptr;
+    int32_t* info = nullptr;     // eigen-solver counters (all simul_iter slots, the query)
+    // simul_iter job slots: every stage of a batch of simul_iter calls is one
+    // launch over the slots it uses
+    int nslots = 0;
+    double *sK = nullptr, *sQ1 = nullptr, *sZ = nullptr;   // nslots x (d x kmax)
+    double *sY = nullptr, *sCQ = nullptr, *sCZ = nullptr;  // nslots x (2 ell x kmax)
+    double *sW = nullptr, *sX = nullptr, *sM = nullptr, *sU = nullptr, *sw1 = nullptr, *sw2 = nullptr;  // kmax^2
+    double* slam = nullptr;      // nslots x kmax estimates
+    double* h_slam = nullptr;    // pinned mirror
+    double* sR = nullptr;        // nslots x (2 ell x ld): residuals of amplification candidates
+    std::vector<double*> sQcur;  // per slot: the buffer holding Q after its simul_iter
     // descriptor arena (device + pinned mirror), reset after every sync
     char* darena = nullptr;
     char* harena = nullptr;
@@ -113,11 +118,8 @@ struct WindowState {
     // probability amplification of the dump step (amp_r candidates, amp_s
     // power iterations on each residual; 1, 0: the plain step)
     int amp_r = 1, amp_s = 0;
-    double* Zc = nullptr;        // candidate directions: amp_r x (d x kmax)
-    double* Rc = nullptr;        // candidate residuals: amp_r x (2 ell x ld)
-    double* amp_out = nullptr;   // amp_r x amp_s power-iteration estimates
+    double* amp_out = nullptr;   // nslots x amp_s power-iteration estimates
     double* h_amp = nullptr;     // pinned mirror
-    std::vector<double> cand_est;  // amp_r x kmax estimates
     // P5 (Algorithm "P5"): the levels are the m sites; the coordinator's
     // Fhat, the value of the last broadcast (every site holds it), the
     // messages since that broadcast and the coordinator's d x d B.  Snapshot
@@ -236,72 +238,180 @@ static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
     return SK_OK;
 }
 
-// Orthonormal basis of Kd (rows x k, ld kmax) by `passes` CholeskyQR passes;
-// each pass writes Q1d and swaps the two buffers, so the basis ends in Kd.
-static sk_status cholqr_d(sketch_t h, int rows, int k, int passes) {
-    WindowState* w = h->win;
-    const int lk = w->kmax;
-    sk_status rc;
-    for (int p = 0; p < passes; ++p) {
-        if ((rc = gemm1(h, gd(w->Kd, lk, true, w->Kd, lk, false, w->Wk, lk, k, k, rows)))) return rc;
-        SmallDesc sd{};
-        sd.A = w->Wk;
-        sd.lda = lk;
-        sd.X = w->Xk;
-        sd.ldx = lk;
-        sd.n = k;
-        sd.work = w->w1;
-        if ((rc = small1(h, false, sd))) return rc;
-        if ((rc = gemm1(h, gd(w->Kd, lk, false, w->Xk, lk, true, w->Q1d, lk, rows, k, k)))) return rc;
-        std::swap(w->Kd, w->Q1d);
-    }
+static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
+
+// Products of a batch, one launch (descriptors with an empty output are
+// dropped; the grid covers the largest product, smaller ones exit their
+// surplus workgroups).
+static sk_status gemm_batch(sketch_t h, const std::vector<GemmDesc>& gs0) {
+    std::vector<GemmDesc> gs;
+    int mM = 0, mN = 0;
+    for (const GemmDesc& g : gs0)
+        if (g.M > 0 && g.N > 0) {
+            gs.push_back(g);
+            mM = std::max(mM, g.M);
+            mN = std::max(mN, g.N);
+        }
+    if (gs.empty()) return SK_OK;
+    const GemmDesc* dp = nullptr;
+    W_TRY(put_desc(h, gs, &dp));
+    W_TRY(launch_gemm_desc(dp, (int)gs.size(), mM, mN, h->stream));
     return SK_OK;
 }
 
-static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
+// One simul_iter call: level j, k columns, Philox counter word 3 = tag, row
+// timestamp ts, results in job slot `slot`.
+struct SiJob {
+    int j, k, slot;
+    uint64_t tag;
+    int64_t ts;
+};
 
-// Algorithm "Simultaneous Iteration" on A = C'^T with the test matrix on the
-// d side; leaves Z' = Q U in Zd (d x k) and the k estimates in h_est.
-static sk_status simul_iter(sketch_t h, int j, int k, int64_t ts, uint64_t tag) {
+// Slot views: d x kmax (K, Q1, Z), 2 ell x kmax (Y, CQ, CZ), kmax x kmax
+// (W, X, M, U, w1, w2), kmax (estimates).
+struct SlotSz {
+    size_t z, y, k;
+};
+static SlotSz slot_sz(const WindowState* w) {
+    return SlotSz{(size_t)w->d * w->kmax, (size_t)2 * w->ell * w->kmax, (size_t)w->kmax * w->kmax};
+}
+
+// Algorithm "Simultaneous Iteration" on A = C'^T (test matrix on the d side)
+// for every job at once: each stage is one batched launch over the jobs.
+// Leaves Z' = Q U in the slot's Z (d x k), Q in sQcur[slot], U in its U and
+// the k estimates of every slot in h_slam.
+static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     WindowState* w = h->win;
-    WinLevel& l = w->lv[(size_t)j];
-    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
-    const int ldc = (int)l.sub->ld;
-    const double* C = level_C(l);
-    sk_status rc;
-    MatGenDesc m{};
-    m.M = w->Kd;
-    m.rows = d;
-    m.cols = k;
-    m.ld = lk;
-    m.seed = w->seed;
-    m.stream = l.rstream;
-    m.c2 = (uint64_t)ts;
-    m.c3 = tag;
-    W_TRY(launch_philox_mat1(m, h->stream));
-    for (int it = 0; it <= w->q; ++it) {
-        if (it > 0 && (rc = cholqr_d(h, d, k, 1))) return rc;
-        if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->Y, lk, r, k, d)))) return rc;
-        if ((rc = gemm1(h, gd(C, ldc, true, w->Y, lk, false, w->Kd, lk, d, k, r)))) return rc;
+    const int n = (int)jobs.size();
+    if (n == 0) return SK_OK;
+    const int d = w->d, lk = w->kmax;
+    const SlotSz z = slot_sz(w);
+    int maxk = 0, maxslot = 0;
+    std::vector<double*> K((size_t)n), Q((size_t)n);
+    std::vector<const double*> C((size_t)n);
+    std::vector<int> ldc((size_t)n), r((size_t)n);
+    std::vector<MatGenDesc> mg((size_t)n);
+    for (int b = 0; b < n; ++b) {
+        const SiJob& J = jobs[(size_t)b];
+        const WinLevel& l = w->lv[(size_t)J.j];
+        maxk = std::max(maxk, J.k);
+        maxslot = std::max(maxslot, J.slot);
+        K[(size_t)b] = w->sK + J.slot * z.z;
+        Q[(size_t)b] = w->sQ1 + J.slot * z.z;
+        C[(size_t)b] = level_C(l);
+        ldc[(size_t)b] = (int)l.sub->ld;
+        r[(size_t)b] = (int)l.sub->fill;
+        MatGenDesc& m = mg[(size_t)b];
+        m = MatGenDesc{};
+        m.M = K[(size_t)b];
+        m.rows = d;
+        m.cols = J.k;
+        m.ld = lk;
+        m.seed = w->seed;
+        m.stream = l.rstream;
+        m.c2 = (uint64_t)J.ts;
+        m.c3 = J.tag;
     }
-    if ((rc = cholqr_d(h, d, k, 2))) return rc;  // Kd now holds Q
-    if ((rc = gemm1(h, gd(C, ldc, false, w->Kd, lk, false, w->CQ, lk, r, k, d)))) return rc;
-    if ((rc = gemm1(h, gd(w->CQ, lk, true, w->CQ, lk, false, w->Mk, lk, k, k, r)))) return rc;
-    SmallDesc sd{};
-    sd.A = w->Mk;
-    sd.lda = lk;
-    sd.X = w->Uk;
-    sd.ldx = lk;
-    sd.lam = w->lamk;
-    sd.n = k;
-    sd.work = w->w1;
-    sd.work2 = w->w2;
-    sd.info = w->info;
-    if ((rc = small1(h, true, sd))) return rc;
-    if ((rc = gemm1(h, gd(w->Kd, lk, false, w->Uk, lk, false, w->Zd, lk, d, k, k)))) return rc;
-    W_TRY(hipMemcpyAsync(w->h_est, w->lamk, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
+    {
+        const MatGenDesc* dp = nullptr;
+        W_TRY(put_desc(h, mg, &dp));
+        W_TRY(launch_philox_mat(dp, n, d, maxk, h->stream));
+    }
+    auto at = [&](double* base, int b, size_t per) { return base + (size_t)jobs[(size_t)b].slot * per; };
+    std::vector<GemmDesc> g;
+    std::vector<SmallDesc> sd((size_t)n);
+    sk_status rc;
+    // CholeskyQR passes on every K (d x k): W = K^T K, X = chol(W)^-1,
+    // Q1 = K X^T, then Q1 becomes K
+    auto cholqr = [&](int passes) -> sk_status {
+        for (int p = 0; p < passes; ++p) {
+            g.clear();
+            for (int b = 0; b < n; ++b) {
+                const int k = jobs[(size_t)b].k;
+                g.push_back(gd(K[(size_t)b], lk, true, K[(size_t)b], lk, false, at(w->sW, b, z.k), lk, k, k, d));
+            }
+            sk_status e = gemm_batch(h, g);
+            if (e) return e;
+            for (int b = 0; b < n; ++b) {
+                SmallDesc& q = sd[(size_t)b];
+                q = SmallDesc{};
+                q.A = at(w->sW, b, z.k);
+                q.lda = lk;
+                q.X = at(w->sX, b, z.k);
+                q.ldx = lk;
+                q.n = jobs[(size_t)b].k;
+                q.work = at(w->sw1, b, z.k);
+            }
+            const SmallDesc* dp = nullptr;
+            W_TRY(put_desc(h, sd, &dp));
+            W_TRY(launch_cholinv_desc(dp, n, maxk, h->stream));
+            g.clear();
+            for (int b = 0; b < n; ++b) {
+                const int k = jobs[(size_t)b].k;
+                g.push_back(gd(K[(size_t)b], lk, false, at(w->sX, b, z.k), lk, true, Q[(size_t)b], lk, d, k, k));
+            }
+            if ((e = gemm_batch(h, g))) return e;
+            std::swap(K, Q);
+        }
+        return SK_OK;
+    };
+    for (int it = 0; it <= w->q; ++it) {
+        if (it > 0 && (rc = cholqr(1))) return rc;
+        g.clear();
+        for (int b = 0; b < n; ++b)
+            g.push_back(gd(C[(size_t)b], ldc[(size_t)b], false, K[(size_t)b], lk, false, at(w->sY, b, z.y), lk,
+                           r[(size_t)b], jobs[(size_t)b].k, d));
+        if ((rc = gemm_batch(h, g))) return rc;
+        g.clear();
+        for (int b = 0; b < n; ++b)
+            g.push_back(gd(C[(size_t)b], ldc[(size_t)b], true, at(w->sY, b, z.y), lk, false, K[(size_t)b], lk, d,
+                           jobs[(size_t)b].k, r[(size_t)b]));
+        if ((rc = gemm_batch(h, g))) return rc;
+    }
+    if ((rc = cholqr(2))) return rc;  // K now holds Q
+    g.clear();
+    for (int b = 0; b < n; ++b)
+        g.push_back(gd(C[(size_t)b], ldc[(size_t)b], false, K[(size_t)b], lk, false, at(w->sCQ, b, z.y), lk,
+                       r[(size_t)b], jobs[(size_t)b].k, d));
+    if ((rc = gemm_batch(h, g))) return rc;
+    g.clear();
+    for (int b = 0; b < n; ++b) {
+        const int k = jobs[(size_t)b].k;
+        g.push_back(gd(at(w->sCQ, b, z.y), lk, true, at(w->sCQ, b, z.y), lk, false, at(w->sM, b, z.k), lk, k, k,
+                       r[(size_t)b]));
+    }
+    if ((rc = gemm_batch(h, g))) return rc;
+    for (int b = 0; b < n; ++b) {
+        SmallDesc& q = sd[(size_t)b];
+        q = SmallDesc{};
+        q.A = at(w->sM, b, z.k);
+        q.lda = lk;
+        q.X = at(w->sU, b, z.k);
+        q.ldx = lk;
+        q.lam = w->slam + (size_t)jobs[(size_t)b].slot * lk;
+        q.n = jobs[(size_t)b].k;
+        q.work = at(w->sw1, b, z.k);
+        q.work2 = at(w->sw2, b, z.k);
+        q.info = w->info;
+    }
+    {
+        const SmallDesc* dp = nullptr;
+        W_TRY(put_desc(h, sd, &dp));
+        hipError_t e = eig_solver_jacobi() ? launch_jacobi_desc(dp, n, maxk, h->stream)
+                                           : launch_tri_eig_desc(dp, n, maxk, h->stream);
+        if (e != hipSuccess) return h->device_fail(std::string("window eigen-solve: ") + hipGetErrorString(e));
+    }
+    g.clear();
+    for (int b = 0; b < n; ++b) {
+        const int k = jobs[(size_t)b].k;
+        g.push_back(gd(K[(size_t)b], lk, false, at(w->sU, b, z.k), lk, false, at(w->sZ, b, z.z), lk, d, k, k));
+        w->sQcur[(size_t)jobs[(size_t)b].slot] = K[(size_t)b];
+    }
+    if ((rc = gemm_batch(h, g))) return rc;
+    W_TRY(hipMemcpyAsync(w->h_slam, w->slam, sizeof(double) * (size_t)(maxslot + 1) * lk, hipMemcpyDeviceToHost,
+                         h->stream));
     W_TRY(sync_reset(h));
-    l.nsi += 1;
+    for (const SiJob& J : jobs) w->lv[(size_t)J.j].nsi += 1;
     return SK_OK;
 }
 
@@ -335,186 +445,271 @@ static sk_status p5_flush(sketch_t h) {
     return SK_OK;
 }
 
-// Snapshot (Z, Z^T C'^T C') of the first xi columns of Zd, then the residual
-// C <- C' - C' Z Z^T (the dump of Algorithm "AeroSketch: Update").  A P5
-// site sends the snapshot to the coordinator's message queue instead of
-// keeping it.
-static sk_status dump(sketch_t h, int j, int xi, int64_t ts) {
+// One dump: level j takes the first xi columns of the Z of job slot `slot`.
+struct DumpJob {
+    int j, slot, xi;
+    int64_t ts;
+    double *Zdst, *Wdst;  // xi rows each (ld = the sketch's ld)
+};
+
+// The products of a list of dumps (one batched launch per product): the
+// snapshot W = (C' Z)^T C' and Z^T into their rows, then the residual
+// C <- C' - (C' Z) Z^T (the dump of Algorithm "AeroSketch: Update").
+static sk_status dump_exec(sketch_t h, const std::vector<DumpJob>& ds) {
+    if (ds.empty()) return SK_OK;
     WindowState* w = h->win;
-    WinLevel& l = w->lv[(size_t)j];
-    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill;
-    const int ldc = (int)l.sub->ld;
-    double* C = (double*)level_C(l);
-    if (w->p5) {
-        sk_status rc;
-        if (w->qD + xi > w->chunk && (rc = p5_flush(h))) return rc;
-        const int64_t off = w->qD;
-        if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
-        if ((rc = gemm1(h, gd(w->CZ, lk, true, C, ldc, false, w->Ws + off * w->ld, (int)w->ld, xi, d, r))))
-            return rc;
-        W_TRY(launch_transpose(w->Zd, lk, w->Zs + off * w->ld, w->ld, d, xi, h->stream));
-        if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, C, ldc, r, d, xi, -1.0, 1.0)))) return rc;
-        for (int c = 0; c < xi; ++c) w->qent.push_back(w->qmsgs);
-        w->qD += xi;
-        w->qmsgs += 1;
-        l.ndumps += 1;
-        l.ndirs += xi;
-        w->smsgs += 1;
-        w->sdirs += xi;
-        w->words += 2 * (int64_t)d * xi;
-        return SK_OK;
-    }
-    if (w->attp && l.ptail + xi > l.pcap) {
-        // append-only store: double it (the old vectors are copied over)
-        int64_t ncap = std::max<int64_t>(2 * l.pcap, l.ptail + xi);
-        double *nZ = nullptr, *nW = nullptr;
-        W_TRY(hipStreamSynchronize(h->stream));
-        W_TRY(hipMalloc((void**)&nZ, sizeof(double) * (size_t)ncap * w->ld));
-        W_TRY(hipMalloc((void**)&nW, sizeof(double) * (size_t)ncap * w->ld));
-        W_TRY(hipMemcpyAsync(nZ, l.Zp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
-                             h->stream));
-        W_TRY(hipMemcpyAsync(nW, l.Wp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
-                             h->stream));
-        W_TRY(hipStreamSynchronize(h->stream));
-        h->replace_alloc(l.Zp, nZ, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
-        h->replace_alloc(l.Wp, nW, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
-        l.Zp = nZ;
-        l.Wp = nW;
-        l.pcap = ncap;
-    }
-    if (l.ptail + xi > l.pcap) l.ptail = 0;
-    const int64_t slot = l.ptail;
-    for (const WinEntry& e : l.q)
-        if (e.kind == 0 && e.slot < slot + xi && slot < e.slot + e.xi)
-            return h->device_fail("window: snapshot ring overflow");
-    l.ptail += xi;
+    const int d = w->d, lk = w->kmax, li = (int)w->ld;
+    const SlotSz z = slot_sz(w);
+    std::vector<GemmDesc> g;
     sk_status rc;
-    if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
-    if ((rc = gemm1(h, gd(w->CZ, lk, true, C, ldc, false, l.Wp + slot * w->ld, (int)w->ld, xi, d, r))))
-        return rc;
-    W_TRY(launch_transpose(w->Zd, lk, l.Zp + slot * w->ld, w->ld, d, xi, h->stream));
-    if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, C, ldc, r, d, xi, -1.0, 1.0)))) return rc;
-    WinEntry e{};
-    e.kind = 0;
-    e.xi = xi;
-    e.s = l.last_t + 1;
-    e.t = ts;
-    e.slot = slot;
-    l.q.push_back(e);
-    l.last_t = ts;
-    l.ndumps += 1;
-    l.ndirs += xi;
-    return SK_OK;
+    for (const DumpJob& x : ds) {
+        const WinLevel& l = w->lv[(size_t)x.j];
+        g.push_back(gd(level_C(l), (int)l.sub->ld, false, w->sZ + x.slot * z.z, lk, false, w->sCZ + x.slot * z.y, lk,
+                       (int)l.sub->fill, x.xi, d));
+    }
+    if ((rc = gemm_batch(h, g))) return rc;
+    g.clear();
+    for (const DumpJob& x : ds) {
+        const WinLevel& l = w->lv[(size_t)x.j];
+        g.push_back(gd(w->sCZ + x.slot * z.y, lk, true, level_C(l), (int)l.sub->ld, false, x.Wdst, li, x.xi, d,
+                       (int)l.sub->fill));
+    }
+    if ((rc = gemm_batch(h, g))) return rc;
+    for (const DumpJob& x : ds) W_TRY(launch_transpose(w->sZ + x.slot * z.z, lk, x.Zdst, w->ld, d, x.xi, h->stream));
+    g.clear();
+    for (const DumpJob& x : ds) {
+        const WinLevel& l = w->lv[(size_t)x.j];
+        g.push_back(gd(w->sCZ + x.slot * z.y, lk, false, w->sZ + x.slot * z.z, lk, true, (double*)level_C(l),
+                       (int)l.sub->ld, (int)l.sub->fill, d, x.xi, -1.0, 1.0));
+    }
+    return gemm_batch(h, g);
 }
 
-// Algorithm "Probability Amplification" in place of the simul_iter call of
-// doubling step s (k columns) at level j: amp_r simul_iters (candidate h
-// draws its test matrix from counter word 3 = 0x200 + 32 j + s + 0x1000 h;
-// h = 0 is the plain call), each leaving xi_h directions (the leading
-// estimates that reach theta) and the residual R_h = C' - C' Z_h Z_h^T; then
-// amp_s power iterations on every R_h (start vectors from counter word 3 =
-// 0x100000 + 0x10000 g + 0x1000 h + 32 j + s), c_h = the largest of its
-// estimates, and the candidate with the smallest c_h (the first on ties)
-// goes on in Zd / h_est as if it were the plain call's result.  The squared
-// estimates are compared; their order is that of c_h.
-static sk_status simul_iter_amplified(sketch_t h, int j, int s, int k, int64_t ts) {
+// Places the snapshots of a list of dumps (level rings, the ATTP store, or
+// the P5 coordinator's message queue) and runs their products.
+static sk_status dump_batch(sketch_t h, std::vector<DumpJob>& ds) {
     WindowState* w = h->win;
-    WinLevel& l = w->lv[(size_t)j];
-    const int d = w->d, lk = w->kmax, r = (int)l.sub->fill, R = w->amp_r, S = w->amp_s;
-    const int ldc = (int)l.sub->ld;
-    const double* C = level_C(l);
-    const size_t zsz = (size_t)d * lk, rsz = (size_t)(2 * w->ell) * w->ld;
+    const int d = w->d;
+    std::vector<DumpJob> pend;
     sk_status rc;
-    for (int hc = 0; hc < R; ++hc) {
-        if ((rc = simul_iter(h, j, k, ts,
-                             0x200u + 32u * (uint64_t)l.rlevel + (uint64_t)s + 0x1000u * (uint64_t)hc)))
-            return rc;
-        std::copy(w->h_est, w->h_est + k, w->cand_est.begin() + (size_t)hc * lk);
-        if (R > 1)
-            W_TRY(hipMemcpyAsync(w->Zc + hc * zsz, w->Zd, sizeof(double) * zsz, hipMemcpyDeviceToDevice, h->stream));
-        if (S == 0) continue;
-        int xi = 0;
-        while (xi < k && w->h_est[xi] >= l.theta) ++xi;
-        double* Rh = w->Rc + hc * rsz;
-        W_TRY(hipMemcpy2DAsync(Rh, sizeof(double) * (size_t)w->ld, C, sizeof(double) * (size_t)ldc,
-                               sizeof(double) * (size_t)d, (size_t)r, hipMemcpyDeviceToDevice, h->stream));
-        if (xi > 0) {
-            if ((rc = gemm1(h, gd(C, ldc, false, w->Zd, lk, false, w->CZ, lk, r, xi, d)))) return rc;
-            if ((rc = gemm1(h, gd(w->CZ, lk, false, w->Zd, lk, true, Rh, (int)w->ld, r, d, xi, -1.0, 1.0))))
-                return rc;
+    for (DumpJob& x : ds) {
+        WinLevel& l = w->lv[(size_t)x.j];
+        const int xi = x.xi;
+        if (w->p5) {
+            if (w->qD + xi > w->chunk) {
+                if ((rc = dump_exec(h, pend))) return rc;
+                pend.clear();
+                if ((rc = p5_flush(h))) return rc;
+            }
+            const int64_t off = w->qD;
+            x.Zdst = w->Zs + off * w->ld;
+            x.Wdst = w->Ws + off * w->ld;
+            for (int c = 0; c < xi; ++c) w->qent.push_back(w->qmsgs);
+            w->qD += xi;
+            w->qmsgs += 1;
+            w->smsgs += 1;
+            w->sdirs += xi;
+            w->words += 2 * (int64_t)d * xi;
+        } else {
+            if (w->attp && l.ptail + xi > l.pcap) {
+                // append-only store: double it (the old vectors are copied over)
+                if ((rc = dump_exec(h, pend))) return rc;
+                pend.clear();
+                int64_t ncap = std::max<int64_t>(2 * l.pcap, l.ptail + xi);
+                double *nZ = nullptr, *nW = nullptr;
+                W_TRY(hipStreamSynchronize(h->stream));
+                W_TRY(hipMalloc((void**)&nZ, sizeof(double) * (size_t)ncap * w->ld));
+                W_TRY(hipMalloc((void**)&nW, sizeof(double) * (size_t)ncap * w->ld));
+                W_TRY(hipMemcpyAsync(nZ, l.Zp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
+                                     h->stream));
+                W_TRY(hipMemcpyAsync(nW, l.Wp, sizeof(double) * (size_t)l.ptail * w->ld, hipMemcpyDeviceToDevice,
+                                     h->stream));
+                W_TRY(hipStreamSynchronize(h->stream));
+                h->replace_alloc(l.Zp, nZ, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
+                h->replace_alloc(l.Wp, nW, sizeof(double) * (size_t)(ncap - l.pcap) * w->ld);
+                l.Zp = nZ;
+                l.Wp = nW;
+                l.pcap = ncap;
+            }
+            if (l.ptail + xi > l.pcap) l.ptail = 0;
+            const int64_t slot = l.ptail;
+            for (const WinEntry& e : l.q)
+                if (e.kind == 0 && e.slot < slot + xi && slot < e.slot + e.xi)
+                    return h->device_fail("window: snapshot ring overflow");
+            l.ptail += xi;
+            x.Zdst = l.Zp + slot * w->ld;
+            x.Wdst = l.Wp + slot * w->ld;
+            WinEntry e{};
+            e.kind = 0;
+            e.xi = xi;
+            e.s = l.last_t + 1;
+            e.t = x.ts;
+            e.slot = slot;
+            l.q.push_back(e);
+            l.last_t = x.ts;
         }
+        l.ndumps += 1;
+        l.ndirs += xi;
+        pend.push_back(x);
     }
-    int best = 0;
-    if (S > 0) {
-        std::vector<PiDesc> pis;
-        const int cnt = R * S;
-        {
-            for (int u = 0; u < cnt; ++u) {
-                const int hc = u / S, g = u % S;
+    return dump_exec(h, pend);
+}
+
+// A level whose power-iteration estimate reached theta / 2 at row ts.
+struct DJob {
+    int j;
+    int64_t ts;
+};
+
+// Per-level state of the doubling loop.
+struct DState {
+    int j, s, kmax, k, best;
+    int64_t ts;
+    bool done;
+};
+
+// Algorithm "Probability Amplification" in place of the simul_iter calls of
+// one doubling step: level u of the batch ran amp_r candidates in slots
+// u amp_r + h (candidate h's test matrix from counter word 3 = 0x200 + 32 j
+// + s + 0x1000 h; h = 0 is the plain call).  Each candidate keeps xi_h
+// directions (the leading estimates that reach theta) and leaves the
+// residual R_h = C' - C' Z_h Z_h^T; amp_s power iterations on every R_h
+// (start vectors from counter word 3 = 0x100000 + 0x10000 g + 0x1000 h +
+// 32 j + s) give c_h = the largest of its estimates, and the candidate with
+// the smallest c_h (the first on ties) is kept.  The squared estimates are
+// compared; their order is that of c_h.
+static sk_status amplify_pick(sketch_t h, std::vector<DState>& st, const std::vector<int>& act) {
+    WindowState* w = h->win;
+    const int R = w->amp_r, S = w->amp_s, d = w->d, lk = w->kmax;
+    const SlotSz z = slot_sz(w);
+    const size_t rsz = (size_t)(2 * w->ell) * w->ld;
+    if (S == 0) {
+        for (int u : act) st[(size_t)u].best = u * R;
+        return SK_OK;
+    }
+    std::vector<GemmDesc> g1, g2;
+    std::vector<PiDesc> pis;
+    for (int u : act) {
+        const DState& x = st[(size_t)u];
+        const WinLevel& l = w->lv[(size_t)x.j];
+        const double* C = level_C(l);
+        const int r = (int)l.sub->fill, ldc = (int)l.sub->ld;
+        for (int hc = 0; hc < R; ++hc) {
+            const int sl = u * R + hc;
+            const double* est = w->h_slam + (size_t)sl * lk;
+            int xi = 0;
+            while (xi < x.k && est[xi] >= l.theta) ++xi;
+            double* Rh = w->sR + sl * rsz;
+            W_TRY(hipMemcpy2DAsync(Rh, sizeof(double) * (size_t)w->ld, C, sizeof(double) * (size_t)ldc,
+                                   sizeof(double) * (size_t)d, (size_t)r, hipMemcpyDeviceToDevice, h->stream));
+            if (xi > 0) {
+                g1.push_back(gd(C, ldc, false, w->sZ + sl * z.z, lk, false, w->sCZ + sl * z.y, lk, r, xi, d));
+                g2.push_back(gd(w->sCZ + sl * z.y, lk, false, w->sZ + sl * z.z, lk, true, Rh, (int)w->ld, r, d, xi,
+                                -1.0, 1.0));
+            }
+            for (int gi = 0; gi < S; ++gi) {
                 PiDesc p{};
-                p.C = w->Rc + hc * rsz;
-                p.out = w->amp_out + u;
+                p.C = Rh;
+                p.out = w->amp_out + (size_t)sl * S + gi;
                 p.ldc = w->ld;
                 p.r = r;
                 p.d = d;
                 p.steps = w->steps;
                 p.seed = w->seed;
                 p.stream = l.rstream;
-                p.c2 = (uint64_t)ts;
-                p.c3 = 0x100000u + 0x10000u * (uint64_t)g + 0x1000u * (uint64_t)hc + 32u * (uint64_t)l.rlevel +
-                       (uint64_t)s;
+                p.c2 = (uint64_t)x.ts;
+                p.c3 = 0x100000u + 0x10000u * (uint64_t)gi + 0x1000u * (uint64_t)hc + 32u * (uint64_t)l.rlevel +
+                       (uint64_t)x.s;
                 pis.push_back(p);
             }
-            sk_status prc = launch_pis(h, pis);
-            if (prc) return prc;
         }
-        W_TRY(hipMemcpyAsync(w->h_amp, w->amp_out, sizeof(double) * (size_t)cnt, hipMemcpyDeviceToHost, h->stream));
-        W_TRY(sync_reset(h));
+    }
+    sk_status rc;
+    if ((rc = gemm_batch(h, g1))) return rc;
+    if ((rc = gemm_batch(h, g2))) return rc;
+    if ((rc = launch_pis(h, pis))) return rc;
+    const int nsl = (act.back() + 1) * R;
+    W_TRY(hipMemcpyAsync(w->h_amp, w->amp_out, sizeof(double) * (size_t)nsl * S, hipMemcpyDeviceToHost, h->stream));
+    W_TRY(sync_reset(h));
+    for (int u : act) {
         double cbest = 0.0;
+        int best = u * R;
         for (int hc = 0; hc < R; ++hc) {
             double ch = 0.0;
-            for (int g = 0; g < S; ++g) {
-                const double e = w->h_amp[hc * S + g];
+            for (int gi = 0; gi < S; ++gi) {
+                const double e = w->h_amp[(size_t)(u * R + hc) * S + gi];
                 if (std::isnan(e))
                     return h->device_fail("window: amplified power iteration failed (barrier timeout or non-finite rows)");
                 if (e > ch) ch = e;
             }
             if (hc == 0 || ch < cbest) {
                 cbest = ch;
-                best = hc;
+                best = u * R + hc;
             }
         }
+        st[(size_t)u].best = best;
     }
-    if (R > 1 && best != R - 1)
-        W_TRY(hipMemcpyAsync(w->Zd, w->Zc + best * zsz, sizeof(double) * zsz, hipMemcpyDeviceToDevice, h->stream));
-    std::copy(w->cand_est.begin() + (size_t)best * lk, w->cand_est.begin() + (size_t)best * lk + k, w->h_est);
     return SK_OK;
 }
 
-// Doubling loop of Algorithm "AeroSketch: Update" (k = 2, 4, ...) for level j.
-static sk_status doubling(sketch_t h, int j, int64_t ts) {
+// Doubling loop of Algorithm "AeroSketch: Update" (k = 2, 4, ...) for many
+// levels at once: every doubling step runs the simul_iter calls of all the
+// levels still doubling as one batch (amp_r candidates per level when
+// amplified), and the dumps of the batch run together at the end.  Each
+// level's threshold is its theta.  The levels are independent, so this
+// equals running their loops one after the other.
+static sk_status doubling_batch(sketch_t h, const std::vector<DJob>& in) {
     WindowState* w = h->win;
-    WinLevel& l = w->lv[(size_t)j];
-    int kmax = std::min(w->ell, w->d);
-    if (kmax > l.sub->fill) kmax = (int)l.sub->fill;
-    if (kmax < 1) return SK_OK;
-    int nsteps = (int)std::ceil(std::log2((double)kmax));
-    if (nsteps < 1) nsteps = 1;
-    const bool amplified = w->amp_r > 1 || w->amp_s > 0;
-    for (int s = 1; s <= nsteps; ++s) {
-        int k = 1 << s;
-        if (k > kmax) k = kmax;
-        sk_status rc = amplified ? simul_iter_amplified(h, j, s, k, ts)
-                                 : simul_iter(h, j, k, ts, 0x200u + 32u * (uint64_t)l.rlevel + (uint64_t)s);
-        if (rc) return rc;
-        if (w->h_est[k - 1] < l.theta || k == kmax) {
-            int xi = 0;
-            while (xi < k && w->h_est[xi] >= l.theta) ++xi;
-            if (xi > 0) {
-                if ((rc = dump(h, j, xi, ts))) return rc;
-            }
-            break;
+    const int R = w->amp_r;
+    const bool amplified = R > 1 || w->amp_s > 0;
+    const size_t cap = (size_t)std::max(1, w->nslots / R);
+    sk_status rc;
+    for (size_t c0 = 0; c0 < in.size(); c0 += cap) {
+        std::vector<DState> st;
+        for (size_t a = c0; a < std::min(in.size(), c0 + cap); ++a) {
+            const WinLevel& l = w->lv[(size_t)in[a].j];
+            int kmax = std::min(w->ell, w->d);
+            if (kmax > l.sub->fill) kmax = (int)l.sub->fill;
+            if (kmax < 1) continue;
+            st.push_back(DState{in[a].j, 1, kmax, 0, 0, in[a].ts, false});
         }
+        std::vector<int> act;
+        for (size_t u = 0; u < st.size(); ++u) act.push_back((int)u);
+        std::vector<DumpJob> dumps;
+        std::vector<SiJob> sj;
+        while (!act.empty()) {
+            sj.clear();
+            for (int u : act) {
+                DState& x = st[(size_t)u];
+                x.k = std::min(1 << x.s, x.kmax);
+                const uint64_t base = 0x200u + 32u * (uint64_t)w->lv[(size_t)x.j].rlevel + (uint64_t)x.s;
+                for (int hc = 0; hc < R; ++hc)
+                    sj.push_back(SiJob{x.j, x.k, u * R + hc, base + 0x1000u * (uint64_t)hc, x.ts});
+            }
+            if ((rc = simul_iter_batch(h, sj))) return rc;
+            if (amplified) {
+                if ((rc = amplify_pick(h, st, act))) return rc;
+            } else {
+                for (int u : act) st[(size_t)u].best = u;
+            }
+            std::vector<int> next;
+            for (int u : act) {
+                DState& x = st[(size_t)u];
+                const double theta = w->lv[(size_t)x.j].theta;
+                const double* est = w->h_slam + (size_t)x.best * w->kmax;
+                if (est[x.k - 1] < theta || x.k == x.kmax) {
+                    int xi = 0;
+                    while (xi < x.k && est[xi] >= theta) ++xi;
+                    if (xi > 0) dumps.push_back(DumpJob{x.j, x.best, xi, x.ts, nullptr, nullptr});
+                    x.done = true;
+                } else {
+                    x.s += 1;
+                    next.push_back(u);
+                }
+            }
+            act.swap(next);
+        }
+        if ((rc = dump_batch(h, dumps))) return rc;
     }
     return SK_OK;
 }
@@ -581,20 +776,23 @@ sk_status window_create(sketch_t h) {
     }
     auto A = [&](double** p, size_t n) { return h->dalloc((void**)p, sizeof(double) * (n ? n : 1)); };
     W_TRY(A(&w->pi_out, (size_t)w->L));
-    W_TRY(A(&w->Kd, (size_t)d * lk));
-    W_TRY(A(&w->Q1d, (size_t)d * lk));
-    W_TRY(A(&w->Qd, (size_t)d * lk));
-    W_TRY(A(&w->Zd, (size_t)d * lk));
-    W_TRY(A(&w->Y, (size_t)n2 * lk));
-    W_TRY(A(&w->CQ, (size_t)n2 * lk));
-    W_TRY(A(&w->CZ, (size_t)n2 * lk));
-    W_TRY(A(&w->Wk, (size_t)lk * lk));
-    W_TRY(A(&w->Xk, (size_t)lk * lk));
-    W_TRY(A(&w->Mk, (size_t)lk * lk));
-    W_TRY(A(&w->Uk, (size_t)lk * lk));
-    W_TRY(A(&w->lamk, (size_t)lk));
-    W_TRY(A(&w->w1, (size_t)lk * lk));
-    W_TRY(A(&w->w2, (size_t)lk * lk));
+    // simul_iter slots: amp_r per doubling level, up to 64 (at least amp_r)
+    w->amp_r = cfg.amplify_r;
+    w->amp_s = cfg.amplify_s;
+    w->nslots = std::max(w->amp_r, std::min(64, w->L * w->amp_r));
+    {
+        const size_t ns = (size_t)w->nslots, zs = (size_t)d * lk, ys = (size_t)n2 * lk, ks = (size_t)lk * lk;
+        for (double** p : {&w->sK, &w->sQ1, &w->sZ}) W_TRY(A(p, ns * zs));
+        for (double** p : {&w->sY, &w->sCQ, &w->sCZ}) W_TRY(A(p, ns * ys));
+        for (double** p : {&w->sW, &w->sX, &w->sM, &w->sU, &w->sw1, &w->sw2}) W_TRY(A(p, ns * ks));
+        W_TRY(A(&w->slam, ns * lk));
+        w->sQcur.assign(ns, nullptr);
+        if (w->amp_s > 0) {
+            W_TRY(A(&w->sR, ns * (size_t)n2 * w->ld));
+            W_TRY(A(&w->amp_out, ns * (size_t)w->amp_s));
+            W_TRY(hipHostMalloc((void**)&w->h_amp, sizeof(double) * ns * (size_t)w->amp_s, hipHostMallocDefault));
+        }
+    }
     W_TRY(h->dalloc((void**)&w->info, 64));
     W_TRY(hipMemset(w->info, 0, 64));
     // query: d x d restore and eigen-solve, snapshot chunks of `chunk` directions
@@ -625,24 +823,12 @@ sk_status window_create(sketch_t h) {
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
-    W_TRY(hipHostMalloc((void**)&w->h_est, sizeof(double) * (size_t)lk, hipHostMallocDefault));
+    W_TRY(hipHostMalloc((void**)&w->h_slam, sizeof(double) * (size_t)w->nslots * lk, hipHostMallocDefault));
     if (w->p5) {
         W_TRY(A(&w->Bc, (size_t)d * d));
         W_TRY(hipMemset(w->Bc, 0, sizeof(double) * (size_t)d * d));
         w->p5rows.resize((size_t)w->m);
         w->qent.reserve((size_t)w->chunk);
-    }
-    w->amp_r = cfg.amplify_r;
-    w->amp_s = cfg.amplify_s;
-    if (w->amp_r > 1 || w->amp_s > 0) {
-        const int R = w->amp_r, S = w->amp_s;
-        w->cand_est.assign((size_t)R * lk, 0.0);
-        if (R > 1) W_TRY(A(&w->Zc, (size_t)R * d * lk));
-        if (S > 0) {
-            W_TRY(A(&w->Rc, (size_t)R * n2 * w->ld));
-            W_TRY(A(&w->amp_out, (size_t)R * S));
-            W_TRY(hipHostMalloc((void**)&w->h_amp, sizeof(double) * (size_t)R * S, hipHostMallocDefault));
-        }
     }
     return SK_OK;
 }
@@ -654,7 +840,7 @@ void window_destroy(sketch_t h) {
         if (l.sub) sketch_destroy(l.sub);
     if (w->harena) (void)hipHostFree(w->harena);
     if (w->h_pi) (void)hipHostFree(w->h_pi);
-    if (w->h_est) (void)hipHostFree(w->h_est);
+    if (w->h_slam) (void)hipHostFree(w->h_slam);
     if (w->h_amp) (void)hipHostFree(w->h_amp);
     if (w->h_norms) (void)hipHostFree(w->h_norms);
     delete w;
@@ -681,6 +867,7 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
     std::vector<Task> tasks;
     std::vector<PiDesc> pis;
     std::vector<int> pj;
+    std::vector<DJob> dj;
     for (int64_t e = 0; e < n; ++e) {
         const int64_t i = w->T + 1;
         w->T = i;
@@ -740,11 +927,12 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
         for (int j : pj)
             if (std::isnan(w->h_pi[j]))
                 return h->device_fail("window: power iteration failed (barrier timeout or non-finite rows)");
-        for (int j : pj) {
-            if (w->h_pi[j] >= w->lv[(size_t)j].theta / 2.0) {
-                sk_status rc = doubling(h, j, i);
-                if (rc) return rc;
-            }
+        dj.clear();
+        for (int j : pj)
+            if (w->h_pi[j] >= w->lv[(size_t)j].theta / 2.0) dj.push_back(DJob{j, i});
+        if (!dj.empty()) {
+            sk_status rc = doubling_batch(h, dj);
+            if (rc) return rc;
         }
     }
     return SK_OK;
@@ -974,6 +1162,7 @@ sk_status p5_update_impl(sketch_t h, const int32_t* site, const char* rows, int6
     std::vector<PiDesc> pis;
     std::vector<int> pj;
     std::vector<const P5Row*> pr;
+    std::vector<DJob> dj;
     sk_status rc;
     for (size_t t = 0; !act.empty(); ++t) {
         owners.clear();
@@ -1028,12 +1217,14 @@ sk_status p5_update_impl(sketch_t h, const int32_t* site, const char* rows, int6
         for (int j : pj)
             if (std::isnan(w->h_pi[j]))
                 return h->device_fail("P5: power iteration failed (barrier timeout or non-finite rows)");
+        dj.clear();
         for (size_t u = 0; u < pj.size(); ++u) {
             const int j = pj[u];
             WinLevel& l = w->lv[(size_t)j];
             l.theta = pr[u]->theta;
-            if (w->h_pi[j] >= l.theta / 2.0 && (rc = doubling(h, j, pr[u]->i))) return rc;
+            if (w->h_pi[j] >= l.theta / 2.0) dj.push_back(DJob{j, pr[u]->i});
         }
+        if (!dj.empty() && (rc = doubling_batch(h, dj))) return rc;
     }
     if ((rc = p5_flush(h))) return rc;
     W_TRY(sync_reset(h));
