@@ -5,12 +5,14 @@
 //   k_rownorm     |a|^2 of every arriving row (FP64), for the raw-row test
 //   k_philox_mat  Gaussian d x k matrix from Philox4x64-10 (power-iteration
 //                 start vector, simul_iter test matrix)
-//   k_win_pi      Algorithm "Power Iteration" on C'^T C' for one level:
+//   k_win_pi_reg  Algorithm "Power Iteration" on C'^T C' for many buffers:
 //                 ceil(log2 d) + 1 normalised steps x <- C'^T C' x, then the
 //                 Rayleigh quotient |C' x|^2 (the power-iteration test of
-//                 Algorithm "AeroSketch: Update")
+//                 Algorithm "AeroSketch: Update"), each buffer's column slabs
+//                 held in the registers of its workgroups
 //   k_gemm_desc   FP64 C = alpha op(A) op(B) + beta C for snapshot, residual
-//                 and restore products
+//                 and restore products and the batched simul_iter stages
+//                 (split-K partials summed by k_gemm_reduce in fixed order)
 //   k_blockmask   zeroes the off-entry blocks of W Z (the restore of Algorithm
 //                 "AeroSketch: Query" is per snapshot)
 //   k_shrink_rows rows sqrt(max(lambda_i - lambda_ell, 0)) v_i^T (the query's
@@ -64,88 +66,110 @@ __device__ double block_sum(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// Power iteration of all levels in one cooperative launch: blockIdx.y is the
-// level, its G workgroups own column slabs of C (r x d) and of x.  One level
-// barrier per step: each workgroup writes the partial y = C x of its slab
-// (x not yet normalised) and its slab's |x|^2; after the barrier every
-// workgroup sums the G partials in a fixed order, scales y by 1 / |x| and
-// forms its slab of the next x = C^T y.  The partial buffers alternate, so a
-// buffer is rewritten only two barriers after it was read.
-__global__ __launch_bounds__(256) void k_win_pi_coop(const PiDesc* ds, int G, int rmax, double* part,
-                                                    unsigned* bars) {
-    extern __shared__ double sm[];
-    __shared__ double red[4];
-    const int lv = blockIdx.y, w = blockIdx.x, tid = threadIdx.x;
+// Power iteration of many buffers in one cooperative launch: blockIdx.y is
+// the buffer, its G = ceil(d / 64) workgroups of 512 threads own 64-column
+// slabs of C (r x d) and of x.  A workgroup reads its slab once into
+// registers (lane = column, wave v = rows v, v + 8, ...; RPT rows per thread)
+// and keeps it for every step.  One barrier per step: each workgroup writes
+// the partial y = C x of its slab (x not yet normalised) and its slab's
+// |x|^2; after the barrier every workgroup sums the G partials in a fixed
+// order, scales y by 1 / |x| and forms its slab of the next x = C^T y.  The
+// partial buffers alternate, so a buffer is rewritten only two barriers
+// after it was read.
+template <int RPT>
+__global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const PiDesc* ds, int G, int rmax, double* part,
+                                                   unsigned* bars) {
+    __shared__ double ys[8 * RPT];  // y (rows beyond r stay zero)
+    __shared__ double xp[8][64];    // C^T y partials of the eight waves
+    __shared__ double red[8];
+    const int lv = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const PiDesc& q = ds[lv];
     const int r = q.r, d = q.d;
     if (r <= 0) {
-        if (w == 0 && tid == 0) *q.out = 0.0;
+        if (wg == 0 && tid == 0) *q.out = 0.0;
         return;
     }
     GridBar bar{bars + 2 * lv, (unsigned)G, 0u};
-    const int sw = (d + G - 1) / G;
-    const int c0 = min(d, w * sw), c1 = min(d, c0 + sw), nc = c1 - c0;
-    double* xs = sm;            // slab of x (sw)
-    double* y = sm + sw;        // r
-    double* colp = y + rmax;    // 4 x 64 column partials
-    // per level: py[2][G][rmax], pn[2][G]
+    const int c = wg * 64 + lane;
+    const bool cin = c < d;
     double* py = part + (int64_t)lv * 2 * G * (rmax + 1);
     double* pn = py + (int64_t)2 * G * rmax;
-    const int64_t ldc = q.ldc;
-    const double* C = q.C;
+    double cr[RPT];
+#pragma unroll
+    for (int ii = 0; ii < RPT; ++ii) {
+        const int i = wv + 8 * ii;
+        cr[ii] = (cin && i < r) ? q.C[(int64_t)i * q.ldc + c] : 0.0;
+    }
+    for (int i = tid; i < 8 * RPT; i += 512) ys[i] = 0.0;
+    double x = cin ? gauss_pick(q.seed, q.stream, (uint64_t)c, 0ull, q.c2, q.c3, 0) : 0.0;
 
     // y = C x / |x| in LDS; returns |x|^2 (the same value in every workgroup)
     auto apply_C = [&](int b) {
-        for (int i = tid; i < r; i += 256) {
-            const double* Ci = C + (int64_t)i * ldc + c0;
-            double acc = 0.0;
-            for (int c = 0; c < nc; ++c) acc = fma(Ci[c], xs[c], acc);
-            py[((int64_t)b * G + w) * rmax + i] = acc;
+        double* pyb = py + ((int64_t)b * G + wg) * rmax;
+        double mine = 0.0;
+#pragma unroll
+        for (int h = 0; h < RPT; h += 8) {
+            double yp[8];
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) yp[jj] = cr[h + jj] * x;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) yp[jj] += __shfl_xor(yp[jj], off, 64);
+            if ((lane >> 3) == (h >> 3)) {
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    if ((lane & 7) == jj) mine = yp[jj];
+            }
         }
-        double loc = 0.0;
-        for (int c = tid; c < nc; c += 256) loc = fma(xs[c], xs[c], loc);
-        const double s2 = block_sum(loc, red);
-        if (tid == 0) pn[b * G + w] = s2;
+        {
+            const int i = wv + 8 * lane;
+            if (lane < RPT && i < r) pyb[i] = mine;
+        }
+        if (wv == 0) {
+            double s2 = x * x;
+            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            if (lane == 0) pn[b * G + wg] = s2;
+        }
         bar.sync();
         double tot = 0.0;
         for (int ww = 0; ww < G; ++ww) tot += pn[b * G + ww];
         const double inv = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
-        for (int i = tid; i < r; i += 256) {
+        for (int i = tid; i < r; i += 512) {
             double acc = 0.0;
             for (int ww = 0; ww < G; ++ww) acc += py[((int64_t)b * G + ww) * rmax + i];
-            y[i] = acc * inv;
+            ys[i] = acc * inv;
         }
         __syncthreads();
         return tot;
     };
 
-    for (int c = tid; c < nc; c += 256) xs[c] = gauss_pick(q.seed, q.stream, (uint64_t)(c0 + c), 0ull, q.c2, q.c3, 0);
-    __syncthreads();
-    const int lane = tid & 63, grp = tid >> 6;
     bool zero = false;
     for (int it = 0; it < q.steps; ++it) {
-        if (apply_C(it & 1) == 0.0) {  // uniform across the level's workgroups
+        if (apply_C(it & 1) == 0.0) {  // uniform across the buffer's workgroups
             zero = true;
             break;
         }
-        for (int u = 0; u * 64 < nc; ++u) {  // x slab = C^T y, four row groups per column
-            const int c = u * 64 + lane;
-            double acc = 0.0;
-            if (c < nc)
-                for (int i = grp; i < r; i += 4) acc = fma(C[(int64_t)i * ldc + c0 + c], y[i], acc);
-            colp[grp * 64 + lane] = acc;
-            __syncthreads();
-            if (grp == 0 && c < nc) xs[c] = (colp[lane] + colp[64 + lane]) + (colp[128 + lane] + colp[192 + lane]);
-            __syncthreads();
-        }
+        double a = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < RPT; ++ii) a = fma(cr[ii], ys[wv + 8 * ii], a);
+        xp[wv][lane] = a;
+        __syncthreads();
+        x = ((xp[0][lane] + xp[1][lane]) + (xp[2][lane] + xp[3][lane])) +
+            ((xp[4][lane] + xp[5][lane]) + (xp[6][lane] + xp[7][lane]));
+        __syncthreads();
     }
     double rq = 0.0;
-    if (!zero && apply_C(q.steps & 1) > 0.0 && w == 0) {
+    if (!zero && apply_C(q.steps & 1) > 0.0 && wg == 0) {
         double loc = 0.0;
-        for (int i = tid; i < r; i += 256) loc = fma(y[i], y[i], loc);
-        rq = block_sum(loc, red);
+        for (int i = tid; i < r; i += 512) loc = fma(ys[i], ys[i], loc);
+        for (int off = 32; off > 0; off >>= 1) loc += __shfl_xor(loc, off, 64);
+        if (lane == 0) red[wv] = loc;
+        __syncthreads();
+        rq = ((red[0] + red[1]) + (red[2] + red[3])) + ((red[4] + red[5]) + (red[6] + red[7]));
     }
-    if (w == 0 && tid == 0) {
+    if (wg == 0 && tid == 0) {
         const bool timed_out = __hip_atomic_load(bars + 2 * lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         *q.out = timed_out ? __builtin_nan("") : rq;
     }
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(256) void k_gemm_part(DescArg<GemmDesc> dp) {
 
 // C = alpha * (sum of the splits in order) + beta C.
 __global__ __launch_bounds__(256) void k_gemm_reduce(DescArg<GemmDesc> dp) {
-    const GemmDesc g = dp.one;
+    const GemmDesc g = dp.get();
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)g.M * g.N) return;
     double acc = 0.0;
@@ -292,22 +316,49 @@ hipError_t launch_philox_mat1(const MatGenDesc& m, hipStream_t st) {
 }
 
 int win_pi_groups(int d) {
-    int g = (d + 63) / 64;
-    return g < 1 ? 1 : (g > 32 ? 32 : g);
+    const int g = (d + 63) / 64;
+    return g < 1 ? 1 : g;
+}
+
+template <int RPT>
+static hipError_t launch_pi_rpt(const PiDesc* dp, int count, int G, int max_r, double* part, unsigned* bars,
+                                hipStream_t st) {
+    // buffers per cooperative launch: as many as are resident at once
+    static int per_cu = -1, cus = 0;
+    if (per_cu < 0) {
+        int dev = 0, nb = 0;
+        hipDeviceProp_t prop{};
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_win_pi_reg<RPT>, 512, 0) != hipSuccess)
+            return hipErrorInvalidConfiguration;
+        per_cu = nb;
+        cus = prop.multiProcessorCount;
+    }
+    const int fit = per_cu * cus / G;
+    if (fit < 1) return hipErrorCooperativeLaunchTooLarge;
+    for (int b = 0; b < count; b += fit) {
+        const int n = count - b < fit ? count - b : fit;
+        hipError_t e = hipMemsetAsync(bars, 0, sizeof(unsigned) * 2 * (size_t)n, st);
+        if (e != hipSuccess) return e;
+        const PiDesc* d0 = dp + b;
+        int gg = G, rm = max_r;
+        void* kargs[] = {(void*)&d0, (void*)&gg, (void*)&rm, (void*)&part, (void*)&bars};
+        e = hipLaunchCooperativeKernel((const void*)k_win_pi_reg<RPT>, dim3((unsigned)G, (unsigned)n), dim3(512), kargs,
+                                       0, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double* part, unsigned* bars,
                          hipStream_t st) {
     const int G = win_pi_groups(d);
-    const int sw = (d + G - 1) / G;
-    const size_t lds = sizeof(double) * (size_t)(sw + max_r + 256);
-    hipError_t e = hipMemsetAsync(bars, 0, sizeof(unsigned) * 2 * (size_t)count, st);
-    if (e != hipSuccess) return e;
     const PiDesc* dp = (const PiDesc*)descs;
-    int gg = G, rm = max_r;
-    void* kargs[] = {(void*)&dp, (void*)&gg, (void*)&rm, (void*)&part, (void*)&bars};
-    return hipLaunchCooperativeKernel((const void*)k_win_pi_coop, dim3((unsigned)G, (unsigned)count), dim3(256),
-                                      kargs, (unsigned)lds, st);
+    if (max_r <= 64) return launch_pi_rpt<8>(dp, count, G, max_r, part, bars, st);
+    if (max_r <= 128) return launch_pi_rpt<16>(dp, count, G, max_r, part, bars, st);
+    if (max_r <= 256) return launch_pi_rpt<32>(dp, count, G, max_r, part, bars, st);
+    if (max_r <= 512) return launch_pi_rpt<64>(dp, count, G, max_r, part, bars, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st) {
@@ -318,6 +369,13 @@ hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st) {
     if (e != hipSuccess) return e;
     const int64_t tot = (int64_t)g.M * g.N;
     hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_reduce_desc(const GemmDesc* ds, int count, int64_t max_MN, hipStream_t st) {
+    DescArg<GemmDesc> a{ds, {}};
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((max_MN + 255) / 256), 1u, (unsigned)count), dim3(256), 0, st,
+                       a);
     return hipGetLastError();
 }
 

@@ -40,7 +40,9 @@ hipError_t launch_rownorm(const void* rows, int64_t ld, int dtype, int64_t n, in
 hipError_t launch_philox_mat(const void* descs, int count, int max_rows, int max_cols, hipStream_t st);
 // Workgroups per level of the cooperative power iteration for dimension d.
 int win_pi_groups(int d);
-// part: count * 2 * win_pi_groups(d) * (max_r + 1) doubles; bars: 2 * count words.
+// part: count * 2 * win_pi_groups(d) * (max_r + 1) doubles; bars: 2 * count words
+// (max_r <= 512).  Launched cooperatively, in as many launches as residency
+// requires; the buffers are reused by the launches in stream order.
 hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double* part, unsigned* bars,
                          hipStream_t st);
 // One split-K product (descriptor by value, with part, nsplit, kchunk set).
@@ -82,6 +84,9 @@ hipError_t launch_cholqr_coop_tasks(const Task* tasks, const int* idx, int count
 hipError_t launch_cholinv_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
 hipError_t launch_jacobi_desc(const SmallDesc* ds, int count, int max_n, hipStream_t st);
 hipError_t launch_gemm_desc(const GemmDesc* ds, int count, int max_M, int max_N, hipStream_t st);
+// Fixed-order sum of the split-K partials of `count` descriptors (part,
+// nsplit set): C = alpha * sum + beta C.
+hipError_t launch_gemm_reduce_desc(const GemmDesc* ds, int count, int64_t max_MN, hipStream_t st);
 hipError_t launch_transpose(const double* src, int lds, double* dst, int64_t ldd, int rows, int cols,
                             hipStream_t st);
 int jacobi_lds_max();

@@ -240,22 +240,66 @@ static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
 
 static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
 
-// Products of a batch, one launch (descriptors with an empty output are
-// dropped; the grid covers the largest product, smaller ones exit their
-// surplus workgroups).
+// Split-K factor of a batched product, from its shape alone: products with
+// few 64 x 64 output tiles and a long K are cut into chunks of >= 256 so that
+// about 32 workgroups work on each (at most 32 x 64 x 64 partials).
+static int batch_splits(const GemmDesc& g) {
+    const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+    return std::max(1, std::min(g.K / 256, 32 / tiles));
+}
+
+// Products of a batch (descriptors with an empty output are dropped; the
+// grid covers the largest product, smaller ones exit their surplus
+// workgroups): one launch of the unsplit products and of the split-K
+// partials together, then one launch of the fixed-order partial sums.
 static sk_status gemm_batch(sketch_t h, const std::vector<GemmDesc>& gs0) {
-    std::vector<GemmDesc> gs;
+    WindowState* w = h->win;
+    std::vector<GemmDesc> gs, fin;
     int mM = 0, mN = 0;
-    for (const GemmDesc& g : gs0)
-        if (g.M > 0 && g.N > 0) {
+    int64_t used = 0, mMN = 0;
+    for (const GemmDesc& g : gs0) {
+        if (g.M <= 0 || g.N <= 0) continue;
+        int ns = batch_splits(g);
+        const int64_t need = (int64_t)ns * g.M * g.N;
+        if (ns > 1 && used + need > w->gpart_cap) ns = 1;
+        if (ns == 1) {
             gs.push_back(g);
             mM = std::max(mM, g.M);
             mN = std::max(mN, g.N);
+            continue;
         }
+        const int kc = (int)round_up((g.K + ns - 1) / ns, 16);
+        ns = (g.K + kc - 1) / kc;
+        GemmDesc f = g;
+        f.part = w->gpart + used;
+        f.nsplit = ns;
+        f.kchunk = kc;
+        for (int sp = 0; sp < ns; ++sp) {
+            const int kb = sp * kc, ke = std::min(g.K, kb + kc);
+            GemmDesc p = g;
+            p.A = g.ta ? g.A + (int64_t)kb * g.lda : g.A + kb;
+            p.B = g.tb ? g.B + kb : g.B + (int64_t)kb * g.ldb;
+            p.K = ke - kb;
+            p.C = f.part + (int64_t)sp * g.M * g.N;
+            p.ldc = g.N;
+            p.alpha = 1.0;
+            p.beta = 0.0;
+            gs.push_back(p);
+        }
+        mM = std::max(mM, g.M);
+        mN = std::max(mN, g.N);
+        used += (int64_t)ns * g.M * g.N;
+        mMN = std::max(mMN, (int64_t)g.M * g.N);
+        fin.push_back(f);
+    }
     if (gs.empty()) return SK_OK;
     const GemmDesc* dp = nullptr;
     W_TRY(put_desc(h, gs, &dp));
     W_TRY(launch_gemm_desc(dp, (int)gs.size(), mM, mN, h->stream));
+    if (!fin.empty()) {
+        W_TRY(put_desc(h, fin, &dp));
+        W_TRY(launch_gemm_reduce_desc(dp, (int)fin.size(), mMN, h->stream));
+    }
     return SK_OK;
 }
 
@@ -817,7 +861,9 @@ sk_status window_create(sketch_t h) {
     W_TRY(h->dalloc((void**)&w->ctrl, 64 * sizeof(int32_t)));
     W_TRY(A(&w->pi_part, (size_t)kPiBatch * 2 * win_pi_groups(d) * (n2 + 1)));
     W_TRY(h->dalloc((void**)&w->pi_bars, sizeof(unsigned) * 2 * (size_t)kPiBatch));
-    w->gpart_cap = (int64_t)1 << 21;
+    // split-K partials: the single products, and up to 32 x 64 x 64 per
+    // product of a batch over the slots
+    w->gpart_cap = std::max<int64_t>((int64_t)1 << 21, (int64_t)w->nslots * 32 * 64 * 64);
     W_TRY(A(&w->gpart, (size_t)w->gpart_cap));
     w->acap = 1 << 20;
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
