@@ -188,26 +188,41 @@ __device__ void gemm_tile(const GemmDesc& g, int r0, int c0) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int kk = 0; kk < K; kk += 16) {
+    // the next K slice is fetched into registers while the current one is
+    // multiplied (the sum over K keeps its order)
+    double pa[4], pb[4];
+    auto fetch = [&](int kk) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = tid + 256 * u;
             if (!g.ta) {
                 const int r = e >> 4, k = e & 15;
-                As[k][r] = (r0 + r < M && kk + k < K) ? g.A[(int64_t)(r0 + r) * g.lda + kk + k] : 0.0;
+                pa[u] = (r0 + r < M && kk + k < K) ? g.A[(int64_t)(r0 + r) * g.lda + kk + k] : 0.0;
             } else {
                 const int r = e & 63, k = e >> 6;
-                As[k][r] = (r0 + r < M && kk + k < K) ? g.A[(int64_t)(kk + k) * g.lda + r0 + r] : 0.0;
+                pa[u] = (r0 + r < M && kk + k < K) ? g.A[(int64_t)(kk + k) * g.lda + r0 + r] : 0.0;
             }
             if (!g.tb) {
                 const int c = e & 63, k = e >> 6;
-                Bs[k][c] = (c0 + c < N && kk + k < K) ? g.B[(int64_t)(kk + k) * g.ldb + c0 + c] : 0.0;
+                pb[u] = (c0 + c < N && kk + k < K) ? g.B[(int64_t)(kk + k) * g.ldb + c0 + c] : 0.0;
             } else {
                 const int c = e >> 4, k = e & 15;
-                Bs[k][c] = (c0 + c < N && kk + k < K) ? g.B[(int64_t)(c0 + c) * g.ldb + kk + k] : 0.0;
+                pb[u] = (c0 + c < N && kk + k < K) ? g.B[(int64_t)(c0 + c) * g.ldb + kk + k] : 0.0;
             }
         }
+    };
+    fetch(0);
+    for (int kk = 0; kk < K; kk += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            if (!g.ta) As[e & 15][e >> 4] = pa[u];
+            else As[e >> 6][e & 63] = pa[u];
+            if (!g.tb) Bs[e >> 6][e & 63] = pb[u];
+            else Bs[e & 15][e >> 4] = pb[u];
+        }
         __syncthreads();
+        if (kk + 16 < K) fetch(kk + 16);
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             double a[4], b[4];

@@ -241,11 +241,11 @@ static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
 static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
 
 // Split-K factor of a batched product, from its shape alone: products with
-// few 64 x 64 output tiles and a long K are cut into chunks of >= 256 so that
+// few 64 x 64 output tiles and a long K are cut into chunks of >= 128 so that
 // about 32 workgroups work on each (at most 32 x 64 x 64 partials).
 static int batch_splits(const GemmDesc& g) {
     const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-    return std::max(1, std::min(g.K / 256, 32 / tiles));
+    return std::max(1, std::min(g.K / 128, 32 / tiles));
 }
 
 // Products of a batch (descriptors with an empty output are dropped; the
