@@ -102,6 +102,19 @@ def _load():
     lib.o_p5_fhat.argtypes = [ctypes.c_void_p]
     lib.o_p5_fhat.restype = ctypes.c_double
     lib.o_p5_site.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _i64p, _dp]
+    lib.o_simul_iter.argtypes = [_dp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _dp, _dp]
+    lib.o_cod_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.o_cod_create.restype = ctypes.c_void_p
+    lib.o_cod_destroy.argtypes = [ctypes.c_void_p]
+    lib.o_cod_update.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_int64, ctypes.c_int64]
+    lib.o_cod_product.argtypes = [ctypes.c_void_p, _dp]
+    lib.o_cod_query.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.o_cod_stats.argtypes = [ctypes.c_void_p, _i64p]
+    lib.o_cod_buffers.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.o_cod_snapshot.argtypes = [ctypes.c_void_p, ctypes.c_int64, _i64p, _dp, _dp, _dp, _dp]
+    lib.o_cod_reduce.argtypes = [_dp, _dp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -468,3 +481,75 @@ class P5:
         out = dict(zip(self.SITE, st.tolist()))
         out.update(F=float(f3[0]), Fhat=float(f3[1]), theta=float(f3[2]), C=C[:out["fill"]].copy())
         return out
+
+
+class COD:
+    """AeroSketchCOD over a sliding window of N pairs, one level with dump
+    threshold theta (Algorithm "AeroSketchCOD Framework")."""
+
+    STATS = ["snapshots", "dirs", "fill", "reduces", "simul_iters", "queue", "T"]
+
+    def __init__(self, dx, dy, ell, N, theta, q=1, seed=0, stream=0):
+        lib = _load()
+        self._h = lib.o_cod_create(dx, dy, ell, int(N), float(theta), q, seed, stream)
+        if not self._h:
+            raise ValueError("bad COD parameters")
+        self.dx, self.dy, self.ell = dx, dy, ell
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.o_cod_destroy(self._h)
+            self._h = None
+
+    def update(self, X, Y):
+        X = _f64(np.atleast_2d(X))
+        Y = _f64(np.atleast_2d(Y))
+        if X.shape[0] != Y.shape[0]:
+            raise ValueError("X and Y need the same number of rows")
+        if X.shape[0] == 0:
+            return
+        _check(_lib.o_cod_update(self._h, _p(X), X.shape[1], _p(Y), Y.shape[1], X.shape[0]), "cod_update")
+
+    def product(self):
+        M = np.zeros((self.dx, self.dy))
+        _check(_lib.o_cod_product(self._h, _p(M)), "cod_product")
+        return M
+
+    def query(self):
+        A = np.zeros((self.dx, self.ell))
+        B = np.zeros((self.dy, self.ell))
+        _check(_lib.o_cod_query(self._h, _p(A), _p(B)), "cod_query")
+        return A, B
+
+    def stats(self):
+        st = np.zeros(7, dtype=np.int64)
+        _check(_lib.o_cod_stats(self._h, st.ctypes.data_as(_i64p)), "cod_stats")
+        return dict(zip(self.STATS, st.tolist()))
+
+    def buffers(self):
+        A = np.zeros((2 * self.ell, self.dx))
+        B = np.zeros((2 * self.ell, self.dy))
+        r = _lib.o_cod_buffers(self._h, _p(A), _p(B))
+        return A[:r].copy(), B[:r].copy()
+
+    def snapshots(self):
+        out = []
+        meta = np.zeros(3, dtype=np.int64)
+        for e in range(self.stats()["queue"]):
+            _check(_lib.o_cod_snapshot(self._h, e, meta.ctypes.data_as(_i64p), None, None, None, None), "cod_snap")
+            xi = int(meta[0])
+            Z, ZM = np.zeros((self.dx, xi)), np.zeros((xi, self.dy))
+            MH, H = np.zeros((self.dx, xi)), np.zeros((self.dy, xi))
+            _check(_lib.o_cod_snapshot(self._h, e, meta.ctypes.data_as(_i64p), _p(Z), _p(ZM), _p(MH), _p(H)),
+                   "cod_snap")
+            out.append({"xi": xi, "s": int(meta[1]), "t": int(meta[2]), "Z": Z, "ZM": ZM, "MH": MH, "H": H})
+        return out
+
+
+def cod_reduce(A, B, ell):
+    """The co-occurring-directions reduce of row buffers A (r x dx), B (r x dy)."""
+    _load()
+    A = np.ascontiguousarray(A, dtype=np.float64).copy()
+    B = np.ascontiguousarray(B, dtype=np.float64).copy()
+    _check(_lib.o_cod_reduce(_p(A), _p(B), A.shape[0], A.shape[1], B.shape[1], ell), "cod_reduce")
+    return A, B

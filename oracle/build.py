@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["philox.c", "linalg.c", "fd.c", "window.c", "attp.c", "p5.c"]
+SOURCES = ["philox.c", "linalg.c", "fd.c", "window.c", "attp.c", "p5.c", "cod.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -134,6 +134,12 @@ int o_aero_dump_amp(int d, int ell, int q, uint64_t seed, uint64_t stream, int l
                     int64_t r, int64_t i, double* Z, double* W, int* xi, int* nsi, double* pi, int amp_r, int amp_s,
                     double* amp_c, int* amp_h);
 int o_win_set_amplify(o_win* w, int r, int s);
+/* Algorithm "Simultaneous Iteration" on A = C^T (C: r x d, row stride d),
+ * test matrix on the d side from counter (row, column/4, ts, tag), q power
+ * steps re-orthonormalised: Z (d x k) = Q U, est (k, descending) the
+ * eigenvalues of Q^T C^T C Q (squared singular-value estimates of C). */
+int o_simul_iter(const double* C, int64_t r, int d, int k, int q, uint64_t seed, uint64_t stream, uint64_t ts,
+                 uint64_t tag, double* Z, double* est);
 
 /* ---- ATTP persistent sketch (Algorithm "ATTP Sketch using AeroSketch") --
  * One AeroSketch whose dump threshold is theta_i = eps ||A_i||_F^2 (eps =
@@ -178,6 +184,27 @@ int o_p5_query(const o_p5* p, double* out);
  * [7] rows seen. */
 int o_p5_stats(const o_p5* p, int64_t* st /* [8] */);
 double o_p5_fhat(const o_p5* p);
+/* ---- AeroSketchCOD: approximate matrix multiplication over a sliding
+ * window (Algorithm "AeroSketchCOD Framework"), one level with threshold
+ * theta; the co-occurring-directions reduce is the SVD of A~^T B~ shrunk by
+ * its ell-th singular value and split evenly between the factors. */
+typedef struct o_cod o_cod;
+o_cod* o_cod_create(int dx, int dy, int ell, int64_t N, double theta, int q, uint64_t seed, uint64_t stream);
+void o_cod_destroy(o_cod* c);
+/* n pairs: X (n x dx, ldx), Y (n x dy, ldy). */
+int o_cod_update(o_cod* c, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n);
+/* The restored window product M_W (dx x dy) before the query's shrink. */
+int o_cod_product(const o_cod* c, double* MW);
+/* A* (dx x ell), B* (dy x ell). */
+int o_cod_query(const o_cod* c, double* Aout, double* Bout);
+/* [0] snapshots [1] directions [2] buffer rows [3] reduces [4] simul_iter
+ * calls [5] snapshots in the queue [6] T. */
+int o_cod_stats(const o_cod* c, int64_t* st /* [7] */);
+int o_cod_buffers(const o_cod* c, double* A, double* B);
+int o_cod_snapshot(const o_cod* c, int64_t e, int64_t* meta, double* Z, double* ZM, double* MH, double* H);
+/* The reduce alone, in place on r rows (r <= 2 ell). */
+int o_cod_reduce(double* A, double* B, int64_t r, int dx, int dy, int ell);
+
 /* Site j: f3 = {F_j, Fhat_j, theta_j}; st = {rows, buffer rows, FD reduces,
  * snapshots, directions, rows sent as they are, simul_iter calls}; C: the
  * buffer rows.  Any output may be NULL. */

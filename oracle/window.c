@@ -219,6 +219,13 @@ out:
     return rc;
 }
 
+int o_simul_iter(const double* C, int64_t r, int d, int k, int q, uint64_t seed, uint64_t stream, uint64_t ts,
+                 uint64_t tag, double* Z, double* est) {
+    if (!C || !Z || !est || r < 1 || d < 1 || k < 1 || k > d || q < 0) return -1;
+    dump_par par = {d, k, q, seed, stream, 1, 0, NULL, NULL};
+    return simul_iter_window(&par, C, r, k, ts, tag, Z, est);
+}
+
 /* Algorithm "Probability Amplification" in place of the simul_iter call of
  * doubling step s (k columns): r independent simul_iters, candidate h with
  * Omega counter (row, column/4, i, 0x200 + 32 j + s + 0x1000 h) (h = 0 is the

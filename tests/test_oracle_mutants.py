@@ -15,7 +15,9 @@ kept, the smallest of the power iterations taken, the residual not formed,
 and a wrong start-vector counter; in P5 the listing's unscaled site
 threshold, a counter not reset after its message, a broadcast at every
 message or to all sites but one, a wrong restore sign and a wrong key of a
-site's FD reduce.
+site's FD reduce; in AeroSketchCOD a wrong reduce index, firing at theta,
+dumping by squared values, a strict expiry, a B side not downdated and a wrong
+restore sign.
 """
 import os
 import shutil
@@ -33,6 +35,7 @@ FD_PINS = ["tests/test_oracle_pins.py"]
 ATTP_PINS = ["tests/test_oracle_attp.py"]
 AMP_PINS = ["tests/test_oracle_amplify.py"]
 P5_PINS = ["tests/test_oracle_p5.py"]
+COD_PINS = ["tests/test_oracle_cod.py"]
 MUTANTS = {
     "pi_threshold_theta": ("window.c", "if (!(s1 >= theta / 2.0)) return 0;",
                            "if (!(s1 >= theta)) return 0;", WINDOW_PINS),
@@ -85,6 +88,17 @@ MUTANTS = {
     "p5_restore_sign": ("p5.c", "p->B[(int64_t)x * d + y] += acc - sub;", "p->B[(int64_t)x * d + y] += acc + sub;",
                         P5_PINS),
     "p5_site_reduce_key": ("p5.c", "sid * 64u + 1u", "sid * 64u", P5_PINS),
+    "cod_reduce_index": ("cod.c", "const double delta = (p >= ell) ? s[ell - 1] : 0.0;\n        memset(A",
+                         "const double delta = (p > ell) ? s[ell] : 0.0;\n        memset(A", COD_PINS),
+    "cod_fire_at_theta": ("cod.c", "if (s1 >= c->theta / 2.0) {", "if (s1 >= c->theta) {", COD_PINS),
+    "cod_dump_squared": ("cod.c", "while (xi < k && sqrt(fmax(eh[xi], 0.0)) >= c->theta) ++xi;",
+                         "while (xi < k && fmax(eh[xi], 0.0) >= c->theta) ++xi;", COD_PINS),
+    "cod_expiry_strict": ("cod.c", "c->sn[c->head].t + c->N <= i", "c->sn[c->head].t + c->N < i", COD_PINS),
+    "cod_b_not_downdated": ("cod.c", "for (int b = 0; b < dy; ++b) br[b] -= bh[e] * sn.H[(int64_t)b * xi + e];",
+                            "for (int b = 0; b < dy; ++b) br[b] -= 0.0 * bh[e] * sn.H[(int64_t)b * xi + e];",
+                            COD_PINS),
+    "cod_restore_sign": ("cod.c", "MW[(int64_t)a * dy + b] += acc - sub;", "MW[(int64_t)a * dy + b] += acc + sub;",
+                         COD_PINS),
     "power_iteration_step": ("fd.c", "for (int it = 0; it < steps; ++it) {", "for (int it = 1; it < steps; ++it) {",
                              FD_PINS + WINDOW_PINS),
 }
