@@ -21,7 +21,10 @@
  *   - distributed streams: per-site sketches combined by sketch_merge
  *     (Lemma "Decomposability"), or tracked continuously by the protocol
  *     of Algorithm "P5" (SK_P5, Sec. 4.3): m simulated sites and their
- *     coordinator on one GPU (p5_update).
+ *     coordinator on one GPU (p5_update);
+ *   - approximate matrix multiplication over a sliding window (SK_COD,
+ *     Sec. 4.2): Algorithm "AeroSketchCOD Framework" on pairs (x_i, y_i)
+ *     (cod_update, cod_query).
  *
  * Conventions (all entry points):
  *   - Matrices are row-major.  A row block is n_rows x d with leading
@@ -71,7 +74,7 @@ typedef enum {
 } sk_status;
 
 typedef enum { SK_F64 = 0, SK_F32 = 1, SK_BF16 = 2 } sk_dtype;
-typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1, SK_ATTP = 2, SK_P5 = 3 } sk_kind;
+typedef enum { SK_PERSISTENT = 0, SK_WINDOW = 1, SK_ATTP = 2, SK_P5 = 3, SK_COD = 4 } sk_kind;
 typedef enum { SK_SHRINK_EXACT = 0, SK_SHRINK_RAND = 1 } sk_shrink;
 
 typedef struct {
@@ -109,6 +112,8 @@ typedef struct {
     int32_t amplify_r;
     int32_t amplify_s;
     int32_t sites;        /* SK_P5: number of sites m, 1..4096                  */
+    int32_t d_y;          /* SK_COD: dimension of the second stream (d is d_x)   */
+    double theta;         /* SK_COD: dump threshold (> 0)                        */
 } sketch_config;
 
 /* Fills *cfg with defaults: exact FP64 persistent sketch, q = 1, no
@@ -197,7 +202,8 @@ SK_EXPORT sk_status sketch_info(sketch_t h, sketch_info_t* info);
 /* SK_WINDOW and SK_ATTP: counters of one level: [0] snapshots dumped,
  * [1] raw rows stored, [2] directions dumped, [3] rows in the level's FD
  * buffer, [4] queue length, [5] FD reduces.  SK_P5: level j is site j, and
- * [1] counts the rows it sent as they are, [4] is 0. */
+ * [1] counts the rows it sent as they are, [4] is 0.  SK_COD: level 0, [1]
+ * is 0, [3] the buffer rows, [4] the live snapshots, [5] the COD reduces. */
 SK_EXPORT sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6);
 
 /* SK_P5 only (Sec. 4.3, Algorithm "P5"; Theorem "dist"): n_rows rows (rows,
@@ -220,6 +226,38 @@ SK_EXPORT sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6);
  * eigen-decomposition shrunk by its ell-th eigenvalue. */
 SK_EXPORT sk_status p5_update(sketch_t h, const int32_t* sites, const void* rows, int64_t n_rows, int64_t ld,
                               int32_t dtype, int32_t on_device);
+
+/* SK_COD only (Sec. 4.2, Algorithm "AeroSketchCOD Framework"; Theorem
+ * "sw-amm"): n pairs arrive in order, x_i = row i of X (n x d, leading
+ * dimension ldx) and y_i = row i of Y (n x d_y, ldy), both of dtype SK_F64 /
+ * SK_F32 / SK_BF16 in host or device memory as on_device.  The sketch keeps
+ * FD-style buffers A (2 ell x d) and B (2 ell x d_y) whose product A^T B
+ * tracks the window's X_W^T Y_W: a pair is appended, the
+ * co-occurring-directions reduce (the product's SVD shrunk by its ell-th
+ * singular value, split evenly between A and B) runs when the buffers hold
+ * 2 ell rows (ell - 1 remain), a power iteration estimates the top singular
+ * value s1 of A^T B, and when s1 >= theta / 2 the doubling loop (k = 2, 4,
+ * ...; left directions Z by simul_iter on A^T B with Philox counter word 3 =
+ * 0x200 + step, right directions H and the estimates by simul_iter on its
+ * transpose with 0x400 + step) dumps the directions whose singular-value
+ * estimate reaches theta as a snapshot (Z, Z^T M, M H, H) and removes them
+ * from A and B.  Snapshots leave after window_N pairs.  Blocks until done.
+ * Requires d, d_y <= 4096, min(d, d_y) <= 512, ell <= 256, window_N >= 1,
+ * theta > 0; SK_EUNSUPPORTED for other kinds. */
+SK_EXPORT sk_status cod_update(sketch_t h, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t n,
+                               int32_t dtype, int32_t on_device);
+
+/* SK_COD only: the query of Algorithm "AeroSketchCOD Framework": M_W = A^T B
+ * plus every live snapshot's Z (Z^T M) + (M H) H^T - Z (Z^T M H) H^T; with its
+ * SVD U S V^T, A_out = U sqrt(max(S - s_ell, 0)) (d x ell, row-major) and
+ * B_out = V sqrt(max(S - s_ell, 0)) (d_y x ell), dtype SK_F64 or SK_F32, host
+ * or device as on_device.  A_out B_out^T approximates X_W^T Y_W; compare
+ * products, never the factors.  Blocks until written. */
+SK_EXPORT sk_status cod_query(sketch_t h, void* A_out, void* B_out, int32_t dtype, int32_t on_device);
+
+/* SK_COD only: the restored product M_W (d x d_y, FP64, row-major) before
+ * the query's shrink, host or device as on_device. */
+SK_EXPORT sk_status cod_product(sketch_t h, void* M_out, int32_t on_device);
 
 /* SK_P5 only: [0] counter messages, [1] broadcasts, [2] snapshot messages,
  * [3] dumped directions, [4] rows sent as they are, [5] words sent (1 per

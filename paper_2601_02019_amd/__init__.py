@@ -16,7 +16,7 @@ import torch
 from . import _lib
 from ._lib import (  # noqa: F401
     SK_BF16, SK_EDEVICE, SK_EINVAL, SK_ENOMEM, SK_ESHAPE, SK_ESTATE, SK_EUNSUPPORTED, SK_F32,
-    SK_ATTP, SK_P5, SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
+    SK_ATTP, SK_COD, SK_P5, SK_F64, SK_OK, SK_PERSISTENT, SK_SHRINK_EXACT, SK_SHRINK_RAND, SK_WINDOW, SketchError,
     sk_completion, sk_server_config, sk_server_stats, sketch_config, sketch_info_t,
 )
 
@@ -170,6 +170,31 @@ def p5_coordinator(h, gram=None):
     return f.value, gram
 
 
+def cod_update(h, X, Y):
+    """Pairs (row e of X, row e of Y) arrive in order (Algorithm "AeroSketchCOD Framework")."""
+    px, n, ldx, dt, dev, kx = _rows_arg(X)
+    py, ny, ldy, dty, devy, ky = _rows_arg(Y)
+    if n != ny or dt != dty or dev != devy:
+        raise ValueError("cod_update: X and Y need the same rows, dtype and memory")
+    _lib.check(_lib.load().cod_update(h, ctypes.c_void_p(px), ldx, ctypes.c_void_p(py), ldy, n, dt, dev),
+               "cod_update")
+    return kx, ky
+
+
+def cod_query(h, A_out, B_out):
+    for t in (A_out, B_out):
+        assert t.is_cuda and t.is_contiguous() and t.dtype in (torch.float64, torch.float32)
+    _lib.check(_lib.load().cod_query(h, ctypes.c_void_p(A_out.data_ptr()), ctypes.c_void_p(B_out.data_ptr()),
+                                     _TORCH_DT[A_out.dtype], 1), "cod_query")
+    return A_out, B_out
+
+
+def cod_product(h, M_out):
+    assert M_out.is_cuda and M_out.is_contiguous() and M_out.dtype == torch.float64
+    _lib.check(_lib.load().cod_product(h, ctypes.c_void_p(M_out.data_ptr()), 1), "cod_product")
+    return M_out
+
+
 def window_stats(h, level):
     st = (ctypes.c_int64 * 6)()
     _lib.check(_lib.load().window_stats(h, level, st), "window_stats")
@@ -286,10 +311,11 @@ def sketch_profile_read(h):
 
 
 def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", proj_dtype="f64", q=1,
-                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0, amplify=(1, 0), sites=0):
+                oversample=0, window_N=0, R=1.0, seed=0, stream_id=0, device=0, amplify=(1, 0), sites=0,
+                d_y=0, theta=0.0):
     cfg = sketch_config_init()
     cfg.d, cfg.ell = d, ell
-    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP, "p5": SK_P5}[kind]
+    cfg.kind = {"persistent": SK_PERSISTENT, "window": SK_WINDOW, "attp": SK_ATTP, "p5": SK_P5, "cod": SK_COD}[kind]
     cfg.shrink = {"exact": SK_SHRINK_EXACT, "rand": SK_SHRINK_RAND}[shrink]
     cfg.state_dtype = _dt(state_dtype)
     cfg.proj_dtype = _dt(proj_dtype)
@@ -298,6 +324,7 @@ def make_config(d, ell, kind="persistent", shrink="exact", state_dtype="f64", pr
     cfg.seed, cfg.stream_id, cfg.device = seed, stream_id, device
     cfg.amplify_r, cfg.amplify_s = int(amplify[0]), int(amplify[1])
     cfg.sites = int(sites)
+    cfg.d_y, cfg.theta = int(d_y), float(theta)
     return cfg
 
 
@@ -476,9 +503,9 @@ class Sketch:
 
     def __init__(self, d, ell, kind="persistent", shrink="exact", state_dtype="f64",
                  proj_dtype="f64", q=1, oversample=0, window_N=0, R=1.0, seed=0, stream_id=0,
-                 device=0, stream=None, amplify=(1, 0), sites=0):
+                 device=0, stream=None, amplify=(1, 0), sites=0, d_y=0, theta=0.0):
         cfg = make_config(d, ell, kind, shrink, state_dtype, proj_dtype, q, oversample, window_N, R,
-                          seed, stream_id, device, amplify, sites)
+                          seed, stream_id, device, amplify, sites, d_y, theta)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         if stream is not False:
@@ -486,7 +513,7 @@ class Sketch:
             # default stream, which the C ABI takes only with this flag)
             cfg.hip_stream = ctypes.c_void_p(stream.cuda_stream)
             cfg.use_given_stream = 1
-        self.d, self.ell = d, ell
+        self.d, self.ell, self.d_y = d, ell, d_y
         self.device = device
         self.handle = sketch_create(cfg)
         _LIVE.add(self)
@@ -532,6 +559,19 @@ class Sketch:
 
     def p5_stats(self):
         return p5_stats(self.handle)
+
+    def cod_update(self, X, Y):
+        cod_update(self.handle, X, Y)  # returns once the pairs are processed
+        return self
+
+    def cod_query(self, dtype=torch.float64):
+        A = torch.empty((self.d, self.ell), dtype=dtype, device=f"cuda:{self.device}")
+        B = torch.empty((self.d_y, self.ell), dtype=dtype, device=f"cuda:{self.device}")
+        return cod_query(self.handle, A, B)
+
+    def cod_product(self):
+        M = torch.empty((self.d, self.d_y), dtype=torch.float64, device=f"cuda:{self.device}")
+        return cod_product(self.handle, M)
 
     def p5_coordinator(self):
         g = torch.empty((self.d, self.d), dtype=torch.float64, device=f"cuda:{self.device}")

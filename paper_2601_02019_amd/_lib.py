@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libsketch.so")
 
 SK_OK, SK_EINVAL, SK_ENOMEM, SK_EDEVICE, SK_ESHAPE, SK_EUNSUPPORTED, SK_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SK_F64, SK_F32, SK_BF16 = 0, 1, 2
-SK_PERSISTENT, SK_WINDOW, SK_ATTP, SK_P5 = 0, 1, 2, 3
+SK_PERSISTENT, SK_WINDOW, SK_ATTP, SK_P5, SK_COD = 0, 1, 2, 3, 4
 SK_SHRINK_EXACT, SK_SHRINK_RAND = 0, 1
 
 STATUS_NAMES = {0: "SK_OK", -1: "SK_EINVAL", -2: "SK_ENOMEM", -3: "SK_EDEVICE", -4: "SK_ESHAPE",
@@ -31,6 +31,7 @@ class sketch_config(ctypes.Structure):
         ("R", ctypes.c_double), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint64),
         ("device", ctypes.c_int32), ("use_given_stream", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
         ("amplify_r", ctypes.c_int32), ("amplify_s", ctypes.c_int32), ("sites", ctypes.c_int32),
+        ("d_y", ctypes.c_int32), ("theta", ctypes.c_double),
     ]
 
 
@@ -124,6 +125,9 @@ def load():
     lib.p5_update.argtypes = [vp, ctypes.POINTER(i32), vp, i64, i64, i32, i32]
     lib.p5_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.p5_coordinator.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, i32]
+    lib.cod_update.argtypes = [vp, vp, i64, vp, i64, i64, i32, i32]
+    lib.cod_query.argtypes = [vp, vp, vp, i32, i32]
+    lib.cod_product.argtypes = [vp, vp, i32]
     lib.sketch_profile_enable.argtypes = [vp, ctypes.c_uint32]
     lib.sketch_profile_read.argtypes = [vp, ctypes.POINTER(sketch_stage_time), i32, ctypes.POINTER(i32)]
     lib.server_config_init.argtypes = [ctypes.POINTER(sk_server_config)]

@@ -7,8 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsketch.so")
-SOURCES = ["k_stream.hip", "k_core.hip", "k_mfma.hip", "k_coop.hip", "k_window.hip", "k_tri.hip", "k_trix.hip", "k_cholx.hip", "sk_api.cpp",
-           "sk_window.cpp", "sk_server.cpp"]
+SOURCES = ["k_stream.hip", "k_core.hip", "k_mfma.hip", "k_coop.hip", "k_window.hip", "k_tri.hip", "k_trix.hip", "k_cholx.hip", "k_cod.hip", "sk_api.cpp",
+           "sk_window.cpp", "sk_cod.cpp", "sk_server.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-fvisibility=hidden"]

@@ -449,8 +449,17 @@ static sk_status validate_config(const sketch_config* cfg) {
         return fail(SK_EINVAL, "sketch_create: bad proj_dtype");
     if (cfg->shrink != SK_SHRINK_EXACT && cfg->shrink != SK_SHRINK_RAND)
         return fail(SK_EINVAL, "sketch_create: bad shrink");
-    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW && cfg->kind != SK_ATTP && cfg->kind != SK_P5)
+    if (cfg->kind != SK_PERSISTENT && cfg->kind != SK_WINDOW && cfg->kind != SK_ATTP && cfg->kind != SK_P5 &&
+        cfg->kind != SK_COD)
         return fail(SK_EINVAL, "sketch_create: bad kind");
+    if (cfg->kind == SK_COD) {
+        if (cfg->d_y < 1 || cfg->d > 4096 || cfg->d_y > 4096 || std::min(cfg->d, cfg->d_y) > 512)
+            return fail(SK_EINVAL, "sketch_create: COD needs 1 <= d, d_y <= 4096 and min(d, d_y) <= 512");
+        if (cfg->window_N < 1 || !(cfg->theta > 0.0))
+            return fail(SK_EINVAL, "sketch_create: COD needs window_N >= 1 and theta > 0");
+        if (cfg->amplify_r != 1 || cfg->amplify_s != 0)
+            return fail(SK_EINVAL, "sketch_create: amplification is not available for COD sketches");
+    }
     if (cfg->kind == SK_P5 && (cfg->sites < 1 || cfg->sites > 4096))
         return fail(SK_EINVAL, "sketch_create: P5 needs 1 <= sites <= 4096");
     if (cfg->q < 0 || cfg->q > 64 || cfg->oversample < 0)
@@ -488,7 +497,7 @@ int64_t sketch_state_bytes(const sketch_config* cfg) {
 }
 
 sk_status sketch_reset(sketch_t h, uint64_t seed, uint64_t stream_id) {
-    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_reset: window sketch");
+    if (h->win || h->cod) return fail(SK_EUNSUPPORTED, "sketch_reset: window sketch");
     h->cfg.seed = seed;
     h->cfg.stream_id = stream_id;
     h->host.seed = seed;
@@ -559,6 +568,7 @@ sk_status sketch_create(const sketch_config* cfg, sketch_t* out) {
     }
     sk_status rc;
     if (cfg->kind == SK_WINDOW || cfg->kind == SK_ATTP || cfg->kind == SK_P5) rc = window_create(h);
+    else if (cfg->kind == SK_COD) rc = cod_create(h);
     else rc = build_device_state(h);
     const int64_t budget = g_budget.load();
     if (rc == SK_OK && budget > 0 && g_in_use.load() + h->bytes > budget) {
@@ -595,7 +605,9 @@ sk_status sketch_update(sketch_t h, const void* rows, int64_t n_rows, int64_t ld
         HIP_TRY(h, hipMemcpyAsync(h->stage, rows, nb, hipMemcpyHostToDevice, h->stream));
         src = (const char*)h->stage;
     }
-    if (h->win) {
+    if (h->cod) {
+        rc = fail(SK_EUNSUPPORTED, "sketch_update: COD sketches take pairs by cod_update");
+    } else if (h->win) {
         rc = h->cfg.kind == SK_P5 ? fail(SK_EUNSUPPORTED, "sketch_update: P5 sketches take rows by p5_update")
                                   : window_update(h, src, n_rows, ld, dtype);
     } else {
@@ -616,7 +628,7 @@ sk_status sketch_update_csr(sketch_t h, const int64_t* indptr, const int32_t* in
     if (n_rows < 0) return fail(SK_EINVAL, "sketch_update_csr: n_rows < 0");
     if (n_rows == 0) return SK_OK;
     if (!indptr || !indices || !values) return fail(SK_EINVAL, "sketch_update_csr: NULL array");
-    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_update_csr: window sketches take dense rows");
+    if (h->win || h->cod) return fail(SK_EUNSUPPORTED, "sketch_update_csr: window sketches take dense rows");
     if (h->d > 16384) return fail(SK_EUNSUPPORTED, "sketch_update_csr: d > 16384");
     HIP_TRY(h, hipSetDevice(h->cfg.device));
     const int64_t* ip = indptr;
@@ -671,7 +683,7 @@ static sk_status query_to_qout(sketch_t h) {
 
 static sk_status check_info(sketch_t h) {
     int32_t info[4] = {0, 0, 0, 0};
-    const int32_t* dinfo = h->win ? window_info_ptr(h) : h->host.info;
+    const int32_t* dinfo = h->win ? window_info_ptr(h) : h->cod ? cod_info_ptr(h) : h->host.info;
     HIP_TRY(h, hipMemcpy(info, dinfo, sizeof(info), hipMemcpyDeviceToHost));
     if (info[0] != 0) return h->device_fail("eigen-solver did not converge");
     if (info[3] != 0) return h->device_fail("multi-workgroup reduction: exchange wait timed out");
@@ -693,6 +705,7 @@ sk_status sketch_query(sketch_t h, void* B_out, int32_t dtype, int32_t on_device
     if (!B_out) return fail(SK_EINVAL, "sketch_query: B_out is NULL");
     if (dtype != SK_F64 && dtype != SK_F32) return fail(SK_EINVAL, "sketch_query: dtype must be F64 or F32");
     HIP_TRY(h, hipSetDevice(h->cfg.device));
+    if (h->cod) return fail(SK_EUNSUPPORTED, "sketch_query: COD sketches answer cod_query");
     const double* src = nullptr;
     if (h->win) {
         rc = window_query(h, &src);
@@ -741,11 +754,11 @@ sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src) {
     sk_status rc = check_handle(dst, "sketch_merge");
     if (rc) return rc;
     if (n_src < 0 || (n_src > 0 && !srcs)) return fail(SK_EINVAL, "sketch_merge: bad source list");
-    if (dst->win) return fail(SK_EUNSUPPORTED, "sketch_merge: window sketches cannot be merged");
+    if (dst->win || dst->cod) return fail(SK_EUNSUPPORTED, "sketch_merge: window sketches cannot be merged");
     for (int i = 0; i < n_src; ++i) {
         if ((rc = check_handle(srcs[i], "sketch_merge"))) return rc;
         if (srcs[i]->d != dst->d) return fail(SK_ESHAPE, "sketch_merge: d differs");
-        if (srcs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_merge: window source");
+        if (srcs[i]->win || srcs[i]->cod) return fail(SK_EUNSUPPORTED, "sketch_merge: window source");
         if (srcs[i] == dst) return fail(SK_EINVAL, "sketch_merge: dst listed as a source");
     }
     HIP_TRY(dst, hipSetDevice(dst->cfg.device));
@@ -772,7 +785,7 @@ sk_status sketch_merge(sketch_t dst, const sketch_t* srcs, int32_t n_src) {
 sk_status sketch_debug_fail_solver(sketch_t h) {
     sk_status rc = check_handle(h, "sketch_debug_fail_solver");
     if (rc) return rc;
-    if (h->win) return fail(SK_EUNSUPPORTED, "sketch_debug_fail_solver: window sketch");
+    if (h->win || h->cod) return fail(SK_EUNSUPPORTED, "sketch_debug_fail_solver: window sketch");
     HIP_TRY(h, hipSetDevice(h->cfg.device));
     // one failed solve, stream-ordered after the work queued so far (a
     // host-to-device copy: the library's kernels are not involved)
@@ -794,6 +807,7 @@ static void destroy_impl(sketch_t h, bool sync) {
     (void)hipSetDevice(h->cfg.device);
     if (sync && h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->win) window_destroy(h);
+    if (h->cod) cod_destroy(h);
     for (void* p : h->allocs) (void)hipFree(p);
     if (h->stage) (void)hipFree(h->stage);
     h->arena.release();
@@ -812,7 +826,7 @@ const char* sketch_last_error(void) { return g_err.c_str(); }
 
 sk_status sketch_info(sketch_t h, sketch_info_t* info) {
     if (!h || !info) return fail(SK_EINVAL, "sketch_info: NULL argument");
-    info->rows_seen = h->win ? window_time(h) : h->rows_seen;
+    info->rows_seen = h->win ? window_time(h) : h->cod ? cod_time(h) : h->rows_seen;
     info->fill = h->fill;
     info->shrinks = h->shrinks;
     info->device_bytes = h->bytes;
@@ -861,11 +875,87 @@ sk_status p5_coordinator(sketch_t h, double* fhat, void* gram, int32_t on_device
     return p5_coordinator_impl(h, fhat, gram, on_device);
 }
 
+sk_status cod_update(sketch_t h, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t n, int32_t dtype,
+                     int32_t on_device) {
+    sk_status rc = check_handle(h, "cod_update");
+    if (rc) return rc;
+    if (!h->cod) return fail(SK_EUNSUPPORTED, "cod_update: not a COD sketch");
+    if (n < 0) return fail(SK_EINVAL, "cod_update: n < 0");
+    if (n == 0) return SK_OK;
+    if (!X || !Y) return fail(SK_EINVAL, "cod_update: NULL X or Y");
+    if (ldx < h->cfg.d || ldy < h->cfg.d_y) return fail(SK_EINVAL, "cod_update: ldx < d or ldy < d_y");
+    if (dtype < SK_F64 || dtype > SK_BF16) return fail(SK_EINVAL, "cod_update: bad dtype");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const char* xs = (const char*)X;
+    const char* ys = (const char*)Y;
+    if (!on_device) {
+        const size_t es = (size_t)dtype_size(dtype);
+        const size_t nx = es * (size_t)((n - 1) * ldx + h->cfg.d), ny = es * (size_t)((n - 1) * ldy + h->cfg.d_y);
+        const size_t ox = (nx + 255) / 256 * 256;
+        HIP_TRY(h, h->ensure_stage(ox + ny));
+        HIP_TRY(h, hipMemcpyAsync(h->stage, X, nx, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync((char*)h->stage + ox, Y, ny, hipMemcpyHostToDevice, h->stream));
+        xs = (const char*)h->stage;
+        ys = (const char*)h->stage + ox;
+    }
+    return cod_update_impl(h, xs, ldx, ys, ldy, n, dtype);
+}
+
+sk_status cod_query(sketch_t h, void* A_out, void* B_out, int32_t dtype, int32_t on_device) {
+    sk_status rc = check_handle(h, "cod_query");
+    if (rc) return rc;
+    if (!h->cod) return fail(SK_EUNSUPPORTED, "cod_query: not a COD sketch");
+    if (!A_out || !B_out) return fail(SK_EINVAL, "cod_query: NULL output");
+    if (dtype != SK_F64 && dtype != SK_F32) return fail(SK_EINVAL, "cod_query: dtype must be F64 or F32");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const double *A = nullptr, *B = nullptr;
+    if ((rc = cod_query_impl(h, &A, &B))) return rc;
+    const int ell = h->cfg.ell, dx = h->cfg.d, dy = h->cfg.d_y;
+    const size_t es = (size_t)dtype_size(dtype);
+    const size_t na = es * (size_t)dx * ell, nb = es * (size_t)dy * ell;
+    if (on_device) {
+        HIP_TRY(h, launch_convert_rows(A, ell, A_out, ell, dx, ell, dtype, h->stream));
+        HIP_TRY(h, launch_convert_rows(B, ell, B_out, ell, dy, ell, dtype, h->stream));
+    } else {
+        const size_t oa = (na + 255) / 256 * 256;
+        HIP_TRY(h, h->ensure_stage(oa + nb));
+        HIP_TRY(h, launch_convert_rows(A, ell, h->stage, ell, dx, ell, dtype, h->stream));
+        HIP_TRY(h, launch_convert_rows(B, ell, (char*)h->stage + oa, ell, dy, ell, dtype, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(A_out, h->stage, na, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(B_out, (char*)h->stage + oa, nb, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_info(h);
+}
+
+sk_status cod_product(sketch_t h, void* M_out, int32_t on_device) {
+    sk_status rc = check_handle(h, "cod_product");
+    if (rc) return rc;
+    if (!h->cod) return fail(SK_EUNSUPPORTED, "cod_product: not a COD sketch");
+    if (!M_out) return fail(SK_EINVAL, "cod_product: NULL output");
+    HIP_TRY(h, hipSetDevice(h->cfg.device));
+    const size_t nb = sizeof(double) * (size_t)h->cfg.d * h->cfg.d_y;
+    double* dst = (double*)M_out;
+    if (!on_device) {
+        HIP_TRY(h, h->ensure_stage(nb));
+        dst = (double*)h->stage;
+    }
+    if ((rc = cod_product_impl(h, dst))) return rc;
+    if (!on_device) HIP_TRY(h, hipMemcpyAsync(M_out, h->stage, nb, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_info(h);
+}
+
 sk_status window_stats(sketch_t h, int32_t level, int64_t* stats6) {
     sk_status rc = check_handle(h, "window_stats");
     if (rc) return rc;
-    if (!h->win) return fail(SK_EUNSUPPORTED, "window_stats: not a window sketch");
+    if (!h->win && !h->cod) return fail(SK_EUNSUPPORTED, "window_stats: not a window sketch");
     if (!stats6) return fail(SK_EINVAL, "window_stats: NULL output");
+    if (h->cod) {
+        if (level != 0) return fail(SK_EINVAL, "window_stats: COD sketches have one level");
+        cod_stats(h, stats6);
+        return SK_OK;
+    }
     return window_level_stats(h, level, stats6);
 }
 
@@ -894,7 +984,7 @@ static sk_status update_batch_impl(const char* what, sketch_t* hs, const void* c
     sk_status rc;
     for (int i = 0; i < count; ++i) {
         if ((rc = check_handle(hs[i], what))) return rc;
-        if (hs[i]->win) return fail(SK_EUNSUPPORTED, std::string(what) + ": window sketch");
+        if (hs[i]->win || hs[i]->cod) return fail(SK_EUNSUPPORTED, std::string(what) + ": window sketch");
         if (hs[i]->stream != hs[0]->stream || hs[i]->cfg.device != hs[0]->cfg.device)
             return fail(SK_EINVAL, std::string(what) + ": sketches must share stream and device");
         if (n[i] < 0) return fail(SK_EINVAL, std::string(what) + ": negative row count");
@@ -1097,13 +1187,13 @@ extern "C" sk_status sketch_merge_tree(sketch_t dst, const sketch_t* srcs, int32
     sk_status rc = check_handle(dst, "sketch_merge_tree");
     if (rc) return rc;
     if (n_src < 1 || !srcs) return fail(SK_EINVAL, "sketch_merge_tree: need at least one source");
-    if (dst->win) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window sketch");
+    if (dst->win || dst->cod) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window sketch");
     if (dst->fill != 0 || dst->rows_seen != 0) return fail(SK_ESTATE, "sketch_merge_tree: dst must be empty");
     for (int i = 0; i < n_src; ++i) {
         if ((rc = check_handle(srcs[i], "sketch_merge_tree"))) return rc;
         if (srcs[i]->d != dst->d || srcs[i]->ell != dst->ell)
             return fail(SK_ESHAPE, "sketch_merge_tree: d and ell must match");
-        if (srcs[i]->win) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window source");
+        if (srcs[i]->win || srcs[i]->cod) return fail(SK_EUNSUPPORTED, "sketch_merge_tree: window source");
     }
     HIP_TRY(dst, hipSetDevice(dst->cfg.device));
     // leaves: each source's queried sketch

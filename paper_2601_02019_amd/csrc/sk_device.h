@@ -133,6 +133,9 @@ struct MatGenDesc {
 // Power iteration of one window level on C (r x d).  out receives the
 // Rayleigh quotient, or NaN when a grid barrier of the cooperative kernel
 // timed out.
+// Column factors of the approximate-matrix-multiplication kernels (k_cod.hip).
+enum CodScale { COD_SQRT = 0, COD_INVSQRT = 1, COD_KEPT = 2, COD_SHRINK_GAIN = 3, COD_SHRINK_SQRT = 4 };
+
 struct PiDesc {
     const double* C;
     double* out;

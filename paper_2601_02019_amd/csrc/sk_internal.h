@@ -13,6 +13,7 @@
 #include "sk_kernels.h"
 
 struct WindowState;
+struct CodState;
 
 using namespace sk;
 
@@ -192,6 +193,7 @@ struct sketch_s {
     int64_t* csr_stage_ptr = nullptr;
     TaskArena arena;
     WindowState* win = nullptr;
+    CodState* cod = nullptr;  // SK_COD sketches (sk_cod.cpp)
     bool counted = false;
     bool dry = false;         // size computation only: dalloc counts, allocates nothing
     double* coop = nullptr;   // cooperative-kernel scratch (see coop_* offsets)

@@ -89,6 +89,15 @@ hipError_t launch_gemm_desc(const GemmDesc* ds, int count, int max_M, int max_N,
 hipError_t launch_gemm_reduce_desc(const GemmDesc* ds, int count, int64_t max_MN, hipStream_t st);
 hipError_t launch_transpose(const double* src, int lds, double* dst, int64_t ldd, int rows, int cols,
                             hipStream_t st);
+// dst = src with column c scaled by f(c) from the n eigenvalues lam (descending):
+// COD_SQRT sqrt(lam_c), COD_INVSQRT 1/sqrt(lam_c), COD_KEPT 1 (0 for columns with
+// lam_c <= tol lam_0), COD_SHRINK_GAIN sqrt(max(s_c - s_ell, 0)) / s_c and
+// COD_SHRINK_SQRT sqrt(max(s_c - s_ell, 0)) with s = sqrt(lam).
+hipError_t launch_cod_scale(const double* src, int lds, double* dst, int ldd, int rows, int cols, const double* lam,
+                            int n, int mode, double tol, int ell, hipStream_t st);
+// Power iteration on A^T B in the row space (Gx = A A^T, Gy = B B^T, ld; r <= 512).
+hipError_t launch_cod_pi(const double* Gx, const double* Gy, int ld, const double* u0, const double* n0, int r,
+                         int steps, double* out, hipStream_t st);
 int jacobi_lds_max();
 int chol_lds_max();
 

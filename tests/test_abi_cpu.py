@@ -85,3 +85,22 @@ def test_p5_configuration_is_validated_without_gpu():
     st = (ctypes.c_int64 * 8)()
     assert lib.p5_stats(None, st) == _lib.SK_EINVAL
     assert lib.p5_update(None, None, None, 1, 8, 0, 1) == _lib.SK_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsketch.so not built")
+def test_cod_configuration_is_validated_without_gpu():
+    from paper_2601_02019_amd import _lib
+    lib = _lib.load()
+    cfg = _lib.sketch_config()
+    assert lib.sketch_config_init(ctypes.byref(cfg)) == 0
+    cfg.d, cfg.ell, cfg.kind, cfg.window_N, cfg.theta = 8, 4, _lib.SK_COD, 10, 1.0
+    h = ctypes.c_void_p()
+    cfg.d_y = 0
+    assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+    assert b"d_y" in lib.sketch_last_error()
+    cfg.d_y, cfg.theta = 6, 0.0
+    assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+    assert b"theta" in lib.sketch_last_error()
+    cfg.theta, cfg.d, cfg.d_y = 1.0, 600, 700
+    assert lib.sketch_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.SK_EINVAL
+    assert lib.cod_update(None, None, 1, None, 1, 1, 0, 1) == _lib.SK_EINVAL
