@@ -45,18 +45,21 @@ def parse():
     ap.add_argument("--cpu-shrinks", type=int, default=1,
                     help="shrinks of the CPU oracle sample")
     ap.add_argument("--workload", choices=["persistent", "small", "window", "sites", "serving", "copy", "attp",
-                                           "p5"],
+                                           "p5", "cod"],
                     default="persistent",
                     help="persistent: the tight-error single stream (default); small: the FP64 exact "
                          "small stream; window: the sliding-window stream; sites: 64 CSR sites with "
                          "tree merges; serving: many concurrent streams with Poisson bursts; copy: a "
                          "plain device copy of known size (HBM reference and counter calibration); attp: "
-                         "the ATTP stream; p5: continuous distributed tracking over the sites' rows")
+                         "the ATTP stream; p5: continuous distributed tracking over the sites' rows; cod: "
+                         "approximate matrix multiplication over a sliding window (Uniform Random pairs)")
     ap.add_argument("--window-rows", type=int, default=200_000, help="rows of the window stream")
     ap.add_argument("--site-rows", type=int, default=100_000, help="rows per site")
     ap.add_argument("--attp-rows", type=int, default=10_000, help="rows of the ATTP stream")
     ap.add_argument("--sites", type=int, default=64)
     ap.add_argument("--p5-rows", type=int, default=2000, help="rows per site (on average) of the p5 workload")
+    ap.add_argument("--cod-pairs", type=int, default=10_000, help="pairs of the cod stream")
+    ap.add_argument("--cod-ell", type=int, default=32, help="ell of the cod workload")
     ap.add_argument("--streams", type=int, default=512)
     ap.add_argument("--bursts", type=int, default=2000, help="bursts per load point")
     ap.add_argument("--loads", default="0.25,0.5,0.75,0.9",
@@ -670,6 +673,66 @@ def p5_main(args):
                "words_over_raw_rows": st["words"] / float(n * d), "cpu_baseline": cpu})
 
 
+def cod_main(args):
+    """Approximate matrix multiplication over a sliding window (Algorithm
+    "AeroSketchCOD Framework") on the paper's AMM setting: Uniform Random
+    pairs (entries in (0, 1]), d_x = 300, d_y = 500, N = 5,000, T = --cod-pairs
+    (10,000); ell = --cod-ell (eps = 2 / ell) and theta = eps N min ||x|| ||y||
+    (at most eps ||X_W||_F ||Y_W||_F for every window).  Queried every 1,000
+    pairs; the error is taken against the exact window product."""
+    import numpy as np
+    import torch
+    from paper_2601_02019_amd import Sketch
+    dx, dy, N, n, ell = 300, 500, 5000, args.cod_pairs, args.cod_ell
+    rng = np.random.default_rng(6)
+    X = 1.0 - rng.random((n, dx))
+    Y = 1.0 - rng.random((n, dy))
+    nx = np.sqrt(np.sum(X ** 2, axis=1))
+    ny = np.sqrt(np.sum(Y ** 2, axis=1))
+    theta = (2.0 / ell) * N * float(np.min(nx * ny))
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    warm = Sketch(dx, ell, kind="cod", window_N=N, q=1, seed=6, stream_id=1, d_y=dy, theta=theta)
+    warm.cod_update(Xt[:300], Yt[:300])
+    warm.cod_query()
+    warm.close()
+    s = Sketch(dx, ell, kind="cod", window_N=N, q=1, seed=6, stream_id=0, d_y=dy, theta=theta)
+    upd, qms, errs = 0.0, [], []
+    for r0 in range(0, n, 1000):
+        m = min(1000, n - r0)
+        _, t = timed(lambda: s.cod_update(Xt[r0:r0 + m], Yt[r0:r0 + m]))
+        upd += t
+        (A, B), tq = timed(lambda: s.cod_query())
+        qms.append(1e3 * tq)
+        lo = max(0, r0 + m - N)
+        W = Xt[lo:r0 + m].T @ Yt[lo:r0 + m]
+        fro = float(torch.linalg.norm(Xt[lo:r0 + m]) * torch.linalg.norm(Yt[lo:r0 + m]))
+        errs.append(float(torch.linalg.matrix_norm(W - A @ B.T, ord=2)) / fro)
+        print(f"[bench] cod pairs {r0 + m}: update {t:.2f}s query {1e3 * tq:.0f} ms err {errs[-1]:.2e}",
+              file=sys.stderr, flush=True)
+    st = s.window_stats(0)
+    s.close()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        o = oracle.COD(dx, dy, ell, N=N, theta=theta, q=1, seed=6, stream=0)
+        done, tc = 0, 0.0
+        while done < n and tc < 20.0:
+            m = min(50, n - done)
+            t = time.perf_counter()
+            o.update(X[done:done + m], Y[done:done + m])
+            tc += time.perf_counter() - t
+            done += m
+        cpu = {"value": done / tc, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} pairs of the stream (about 20 s), FP64 plain C, one thread, {tc:.1f}s",
+               "cpu": cpu_model(), "nproc": os.cpu_count()}
+    base_line(args, n / upd, "pairs/s", None,
+              "AMM over a sliding window (AeroSketchCOD): Uniform Random pairs, d_x=300, d_y=500, N=5000, "
+              "T=%d, ell=%d, theta = eps N min|x||y|, FP64; query every 1000 pairs" % (n, ell),
+              {"dtype": "f64", "pairs": n, "update_s": upd, "query_ms_median": float(np.median(qms)),
+               "err_rel_max": max(errs), "bound_rel_eps": 2.0 / ell, "theta": theta, "snapshots": st["dumps"],
+               "reduces": st["shrinks"], "cpu_baseline": cpu})
+
+
 def copy_main(args):
     """A plain device-to-device copy of 1 GiB, args.steps times: the measured
     HBM rate, and a kernel of known traffic for calibrating the FETCH_SIZE /
@@ -701,7 +764,8 @@ def main():
         sys.exit(2)
     if args.workload != "persistent":
         return {"serving": serving_main, "small": small_main, "window": window_main,
-                "sites": sites_main, "copy": copy_main, "attp": attp_main, "p5": p5_main}[args.workload](args)
+                "sites": sites_main, "copy": copy_main, "attp": attp_main, "p5": p5_main,
+                "cod": cod_main}[args.workload](args)
     import torch
     from paper_2601_02019_amd import Sketch
 

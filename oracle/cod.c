@@ -17,9 +17,9 @@
  *      (coordinate, 0, i, 0x100)) estimates sigma_1(M')^2;
  *   4. if sigma_1 >= theta / 2: for k = 2, 4, ... (capped at
  *      min(ell, d_x, d_y, rows)): Z' = simul_iter(M', k) (left directions,
- *      test matrix on the d_y side, counter word 3 = 0x200 + step) and
- *      [H', S] = simul_iter(M'^T, k) (right directions, test matrix on the
- *      d_x side, counter word 3 = 0x400 + step); when S_k < theta (or k is
+ *      test matrix in R^{d_x}, counter word 3 = 0x200 + step) and
+ *      [H', S] = simul_iter(M'^T, k) (right directions, test matrix in
+ *      R^{d_y}, counter word 3 = 0x400 + step); when S_k < theta (or k is
  *      the cap) the k' leading directions with S >= theta are dumped:
  *      snapshot (Z, Z^T M', M' H, H) with Z = Z'[:, :k'], H = H'[:, :k'],
  *      then A <- A' - A' Z Z^T, B <- B' - B' H H^T.

@@ -165,9 +165,9 @@ static sk_status cholqr(sketch_t h, double** K, double** Q, int rows, int k, int
     return SK_OK;
 }
 
-// Algorithm "Simultaneous Iteration" on M = A^T B (left = true: directions in
-// R^{d_x}, test matrix in R^{d_y}) or on M^T (left = false), through products
-// with A and B.  The oracle's form: simul_iter on the matrix C^T with
+// Algorithm "Simultaneous Iteration" for the left directions of M = A^T B
+// (left = true: directions and test matrix in R^{d_x}) or its right ones
+// (left = false: in R^{d_y}), through products with A and B.  The oracle's form: simul_iter on the matrix C^T with
 // C = M^T (left) or C = M (right), test matrix Omega (d x k) on C's column
 // side, q re-orthonormalised power steps, Rayleigh-Ritz.  Leaves the
 // directions (d x k, ld kmax) in out and the k eigenvalue estimates (squared
