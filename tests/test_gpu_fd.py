@@ -544,3 +544,39 @@ def test_csr_duplicate_indices_summed_in_row_order():
     assert rel_fro(gram(a.query()), gram(o.query())) <= 1e-9
     for h in (a, b, other):
         h.close()
+
+
+# ------------------------ the tight-error workload at full size (bench shape)
+def test_tight_error_full_stream_properties():
+    # the whole tight-error stream in the launch configuration the benchmark
+    # times (200,000 FP32 rows, d = 4096, ell = k = 256, q = 1, FP32 state,
+    # bf16 projection, seed 7 / stream 1): at this size the oracle cannot run
+    # (25 s per shrink, 778 shrinks), so the properties that hold at any size
+    # are checked: B^T B below A^T A (the randomized shrink keeps the order;
+    # FP32 state rounding allows 1e-5 ||A||_F^2), the FD bound, and an error
+    # no larger than the exact-SVD FD path's on the same rows
+    import bench
+    d, ell, n = 4096, 256, 200_000
+    note(f"tight-error stream at full size: n={n} d={d} ell={ell}")
+    A = bench.make_stream(n, d, 1024, 1, torch.device("cuda:0"))
+    G = bench.gram_f64(A)
+    fro2 = float(torch.trace(G))
+    s = make(d, ell, shrink="rand", q=1, state_dtype="f32", proj_dtype="bf16", seed=7, stream_id=1)
+    s.update(A)
+    B = s.query().double()
+    assert s.info()["shrinks"] == (n - 2 * ell) // (ell + 1) + 1
+    s.close()
+    D = G - B.T @ B
+    w = torch.linalg.eigvalsh((D + D.T) / 2)
+    note(f"  min/max eig of A^T A - B^T B: {float(w[0]) / fro2:.3e} {float(w[-1]) / fro2:.3e} of |A|_F^2")
+    assert float(w[0]) >= -1e-5 * fro2
+    err_rand = float(w.abs().max())
+    assert err_rand <= fro2 / ell
+    e = make(d, ell, shrink="exact", state_dtype="f32", seed=7, stream_id=1)
+    e.update(A)
+    Be = e.query().double()
+    e.close()
+    De = G - Be.T @ Be
+    err_exact = float(torch.linalg.eigvalsh((De + De.T) / 2).abs().max())
+    note(f"  cov-err rand {err_rand / fro2:.4e} exact {err_exact / fro2:.4e} bound {1 / ell:.4e}")
+    assert err_rand <= err_exact
