@@ -231,9 +231,9 @@ static sk_status gemm1(sketch_t h, const GemmDesc& g0) {
     return SK_OK;
 }
 
-static sk_status small1(sketch_t h, bool eig, const SmallDesc& q) {
-    hipError_t e = !eig ? launch_cholinv1(q, h->stream)
-                        : (eig_solver_jacobi() ? launch_jacobi1(q, h->stream) : launch_tri_eig1(q, h->stream));
+// One symmetric eigen-solve (the query's d x d restore when d is small).
+static sk_status small_eig(sketch_t h, const SmallDesc& q) {
+    hipError_t e = eig_solver_jacobi() ? launch_jacobi1(q, h->stream) : launch_tri_eig1(q, h->stream);
     if (e != hipSuccess) return h->device_fail(std::string("window small solve: ") + hipGetErrorString(e));
     return SK_OK;
 }
@@ -1008,7 +1008,7 @@ static sk_status eig_d(sketch_t h) {
         sd.work = w->Eq;
         sd.work2 = w->Vq;
         sd.info = w->info;
-        return small1(h, true, sd);
+        return small_eig(h, sd);
     }
     CoopEig a{};
     a.Ain = w->Bq;
