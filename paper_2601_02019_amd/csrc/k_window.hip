@@ -82,6 +82,7 @@ __global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const Pi
     __shared__ double ys[8 * RPT];  // y (rows beyond r stay zero)
     __shared__ double xp[8][64];    // C^T y partials of the eight waves
     __shared__ double red[8];
+    __shared__ double tb[8][8][65]; // per wave: 8 rows x 64 column products
     const int lv = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const PiDesc& q = ds[lv];
@@ -105,27 +106,28 @@ __global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const Pi
     double x = cin ? gauss_pick(q.seed, q.stream, (uint64_t)c, 0ull, q.c2, q.c3, 0) : 0.0;
 
     // y = C x / |x| in LDS; returns |x|^2 (the same value in every workgroup)
+    // rows of y summed per step: `per` threads share a row's G partials
+    const int per = r <= 64 ? 8 : r <= 128 ? 4 : r <= 256 ? 2 : 1;
     auto apply_C = [&](int b) {
         double* pyb = py + ((int64_t)b * G + wg) * rmax;
-        double mine = 0.0;
+        // the slab's y partial, 8 rows of each wave at a time: the 64 column
+        // products go through LDS, lane l sums row l & 7 over columns
+        // 8 (l >> 3) .. 8 (l >> 3) + 7, and three exchanges add the segments
+        const int jj = lane & 7, seg = lane >> 3;
 #pragma unroll
         for (int h = 0; h < RPT; h += 8) {
-            double yp[8];
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) yp[jj] = cr[h + jj] * x;
+            for (int q8 = 0; q8 < 8; ++q8) tb[wv][q8][lane] = cr[h + q8] * x;
+            __syncthreads();
+            double sacc = 0.0;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) yp[jj] += __shfl_xor(yp[jj], off, 64);
-            if ((lane >> 3) == (h >> 3)) {
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj)
-                    if ((lane & 7) == jj) mine = yp[jj];
-            }
-        }
-        {
-            const int i = wv + 8 * lane;
-            if (lane < RPT && i < r) pyb[i] = mine;
+            for (int cc = 0; cc < 8; ++cc) sacc += tb[wv][jj][seg * 8 + cc];
+            sacc += __shfl_xor(sacc, 8, 64);
+            sacc += __shfl_xor(sacc, 16, 64);
+            sacc += __shfl_xor(sacc, 32, 64);
+            const int i = wv + 8 * (h + jj);
+            if (seg == 0 && i < r) pyb[i] = sacc;
+            __syncthreads();
         }
         if (wv == 0) {
             double s2 = x * x;
@@ -136,10 +138,15 @@ __global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const Pi
         double tot = 0.0;
         for (int ww = 0; ww < G; ++ww) tot += pn[b * G + ww];
         const double inv = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
-        for (int i = tid; i < r; i += 512) {
+        {
+            const int i = tid / per, p = tid % per;
             double acc = 0.0;
-            for (int ww = 0; ww < G; ++ww) acc += py[((int64_t)b * G + ww) * rmax + i];
-            ys[i] = acc * inv;
+            if (i < r) {
+#pragma unroll 4
+                for (int ww = p; ww < G; ww += per) acc += py[((int64_t)b * G + ww) * rmax + i];
+            }
+            for (int off = 1; off < per; off <<= 1) acc += __shfl_xor(acc, off, 64);
+            if (p == 0 && i < r) ys[i] = acc * inv;
         }
         __syncthreads();
         return tot;
