@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
+#include <functional>
 
 #include "sk_internal.h"
 #include "sk_window.h"
@@ -97,10 +98,15 @@ struct WindowState {
     double* h_slam = nullptr;    // pinned mirror
     double* sR = nullptr;        // nslots x (2 ell x ld): residuals of amplification candidates
     std::vector<double*> sQcur;  // per slot: the buffer holding Q after its simul_iter
-    // descriptor arena (device + pinned mirror), reset after every sync
+    // descriptor arena (device + pinned mirror), reset after every sync.
+    // While `defer` is set descriptors are only staged (from dlo on) and the
+    // launches that read them wait in `queued` for one upload of the range.
     char* darena = nullptr;
     char* harena = nullptr;
     size_t acap = 0, aoff = 0;
+    bool defer = false;
+    size_t dlo = 0;
+    std::vector<std::function<hipError_t()>> queued;
     // query scratch
     double *Bq = nullptr, *Eq = nullptr, *Vq = nullptr, *Uq = nullptr, *lamq = nullptr;
     double *Zs = nullptr, *Ws = nullptr, *S = nullptr, *T2 = nullptr, *Rs = nullptr;
@@ -151,7 +157,7 @@ static const int kWinDmax = 4096;  // largest d of a window sketch
     } while (0)
 
 // Copies descriptors to the device arena (ordered on the stream); returns
-// the device address.
+// the device address.  While deferring, the copy waits for DeferDesc::flush.
 template <typename D>
 static hipError_t put_desc(sketch_t h, const std::vector<D>& ds, const D** out) {
     WindowState* w = h->win;
@@ -159,11 +165,54 @@ static hipError_t put_desc(sketch_t h, const std::vector<D>& ds, const D** out) 
     const size_t off = (w->aoff + 255) / 256 * 256;
     if (off + nb > w->acap) return hipErrorOutOfMemory;
     std::memcpy(w->harena + off, ds.data(), nb);
-    hipError_t e = hipMemcpyAsync(w->darena + off, w->harena + off, nb, hipMemcpyHostToDevice, h->stream);
+    hipError_t e = hipSuccess;
+    if (!w->defer) e = hipMemcpyAsync(w->darena + off, w->harena + off, nb, hipMemcpyHostToDevice, h->stream);
     w->aoff = off + nb;
     *out = (const D*)(w->darena + off);
     return e;
 }
+
+// A stream operation: issued now, or queued behind the staged descriptors.
+static hipError_t w_issue(sketch_t h, std::function<hipError_t()> f) {
+    WindowState* w = h->win;
+    if (!w->defer) return f();
+    w->queued.push_back(std::move(f));
+    return hipSuccess;
+}
+
+// Scope in which every descriptor is staged in the host arena and every
+// stream operation of the window engine's batches goes through w_issue;
+// flush() uploads the staged range with one copy and then issues the queued
+// operations in their order.  Leaving the scope without flush() drops them.
+struct DeferDesc {
+    sketch_t h;
+    explicit DeferDesc(sketch_t hh) : h(hh) {
+        WindowState* w = h->win;
+        w->defer = true;
+        w->dlo = (w->aoff + 255) / 256 * 256;
+        w->queued.clear();
+    }
+    hipError_t flush() {
+        WindowState* w = h->win;
+        w->defer = false;
+        std::vector<std::function<hipError_t()>> q;
+        q.swap(w->queued);
+        if (w->aoff > w->dlo) {
+            hipError_t e = hipMemcpyAsync(w->darena + w->dlo, w->harena + w->dlo, w->aoff - w->dlo,
+                                          hipMemcpyHostToDevice, h->stream);
+            if (e != hipSuccess) return e;
+        }
+        for (auto& f : q) {
+            hipError_t e = f();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    ~DeferDesc() {
+        h->win->defer = false;
+        h->win->queued.clear();
+    }
+};
 
 static hipError_t sync_reset(sketch_t h) {
     hipError_t e = hipStreamSynchronize(h->stream);
@@ -180,7 +229,11 @@ static sk_status launch_pis(sketch_t h, const std::vector<PiDesc>& pis) {
         std::vector<PiDesc> part(pis.begin() + (ptrdiff_t)b, pis.begin() + (ptrdiff_t)(b + cnt));
         const PiDesc* dp = nullptr;
         W_TRY(put_desc(h, part, &dp));
-        W_TRY(launch_win_pi(dp, (int)cnt, w->d, 2 * w->ell, w->pi_part, w->pi_bars, h->stream));
+        const int d = w->d, mr = 2 * w->ell;
+        double* pp = w->pi_part;
+        unsigned* bars = w->pi_bars;
+        hipStream_t st = h->stream;
+        W_TRY(w_issue(h, [=] { return launch_win_pi(dp, (int)cnt, d, mr, pp, bars, st); }));
     }
     return SK_OK;
 }
@@ -294,11 +347,14 @@ static sk_status gemm_batch(sketch_t h, const std::vector<GemmDesc>& gs0) {
     }
     if (gs.empty()) return SK_OK;
     const GemmDesc* dp = nullptr;
+    hipStream_t st = h->stream;
     W_TRY(put_desc(h, gs, &dp));
-    W_TRY(launch_gemm_desc(dp, (int)gs.size(), mM, mN, h->stream));
+    const int ng = (int)gs.size();
+    W_TRY(w_issue(h, [=] { return launch_gemm_desc(dp, ng, mM, mN, st); }));
     if (!fin.empty()) {
         W_TRY(put_desc(h, fin, &dp));
-        W_TRY(launch_gemm_reduce_desc(dp, (int)fin.size(), mMN, h->stream));
+        const int nf = (int)fin.size();
+        W_TRY(w_issue(h, [=] { return launch_gemm_reduce_desc(dp, nf, mMN, st); }));
     }
     return SK_OK;
 }
@@ -330,6 +386,8 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     if (n == 0) return SK_OK;
     const int d = w->d, lk = w->kmax;
     const SlotSz z = slot_sz(w);
+    hipStream_t st = h->stream;
+    DeferDesc defer(h);  // every stage's descriptors go up in one copy
     int maxk = 0, maxslot = 0;
     std::vector<double*> K((size_t)n), Q((size_t)n);
     std::vector<const double*> C((size_t)n);
@@ -359,7 +417,7 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     {
         const MatGenDesc* dp = nullptr;
         W_TRY(put_desc(h, mg, &dp));
-        W_TRY(launch_philox_mat(dp, n, d, maxk, h->stream));
+        W_TRY(w_issue(h, [=] { return launch_philox_mat(dp, n, d, maxk, st); }));
     }
     auto at = [&](double* base, int b, size_t per) { return base + (size_t)jobs[(size_t)b].slot * per; };
     std::vector<GemmDesc> g;
@@ -388,7 +446,7 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
             }
             const SmallDesc* dp = nullptr;
             W_TRY(put_desc(h, sd, &dp));
-            W_TRY(launch_cholinv_desc(dp, n, maxk, h->stream));
+            W_TRY(w_issue(h, [=] { return launch_cholinv_desc(dp, n, maxk, st); }));
             g.clear();
             for (int b = 0; b < n; ++b) {
                 const int k = jobs[(size_t)b].k;
@@ -441,9 +499,10 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     {
         const SmallDesc* dp = nullptr;
         W_TRY(put_desc(h, sd, &dp));
-        hipError_t e = eig_solver_jacobi() ? launch_jacobi_desc(dp, n, maxk, h->stream)
-                                           : launch_tri_eig_desc(dp, n, maxk, h->stream);
-        if (e != hipSuccess) return h->device_fail(std::string("window eigen-solve: ") + hipGetErrorString(e));
+        const bool jac = eig_solver_jacobi();
+        W_TRY(w_issue(h, [=] {
+            return jac ? launch_jacobi_desc(dp, n, maxk, st) : launch_tri_eig_desc(dp, n, maxk, st);
+        }));
     }
     g.clear();
     for (int b = 0; b < n; ++b) {
@@ -452,6 +511,7 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
         w->sQcur[(size_t)jobs[(size_t)b].slot] = K[(size_t)b];
     }
     if ((rc = gemm_batch(h, g))) return rc;
+    W_TRY(defer.flush());
     W_TRY(hipMemcpyAsync(w->h_slam, w->slam, sizeof(double) * (size_t)(maxslot + 1) * lk, hipMemcpyDeviceToHost,
                          h->stream));
     W_TRY(sync_reset(h));
@@ -506,6 +566,8 @@ static sk_status dump_exec(sketch_t h, const std::vector<DumpJob>& ds) {
     const SlotSz z = slot_sz(w);
     std::vector<GemmDesc> g;
     sk_status rc;
+    hipStream_t st = h->stream;
+    DeferDesc defer(h);
     for (const DumpJob& x : ds) {
         const WinLevel& l = w->lv[(size_t)x.j];
         g.push_back(gd(level_C(l), (int)l.sub->ld, false, w->sZ + x.slot * z.z, lk, false, w->sCZ + x.slot * z.y, lk,
@@ -519,14 +581,20 @@ static sk_status dump_exec(sketch_t h, const std::vector<DumpJob>& ds) {
                        (int)l.sub->fill));
     }
     if ((rc = gemm_batch(h, g))) return rc;
-    for (const DumpJob& x : ds) W_TRY(launch_transpose(w->sZ + x.slot * z.z, lk, x.Zdst, w->ld, d, x.xi, h->stream));
+    for (const DumpJob& x : ds) {
+        const double* src = w->sZ + x.slot * z.z;
+        const int64_t ld = w->ld;
+        W_TRY(w_issue(h, [=] { return launch_transpose(src, lk, x.Zdst, ld, d, x.xi, st); }));
+    }
     g.clear();
     for (const DumpJob& x : ds) {
         const WinLevel& l = w->lv[(size_t)x.j];
         g.push_back(gd(w->sCZ + x.slot * z.y, lk, false, w->sZ + x.slot * z.z, lk, true, (double*)level_C(l),
                        (int)l.sub->ld, (int)l.sub->fill, d, x.xi, -1.0, 1.0));
     }
-    return gemm_batch(h, g);
+    if ((rc = gemm_batch(h, g))) return rc;
+    W_TRY(defer.flush());
+    return SK_OK;
 }
 
 // Places the snapshots of a list of dumps (level rings, the ATTP store, or
@@ -633,6 +701,8 @@ static sk_status amplify_pick(sketch_t h, std::vector<DState>& st, const std::ve
     }
     std::vector<GemmDesc> g1, g2;
     std::vector<PiDesc> pis;
+    hipStream_t stm = h->stream;
+    DeferDesc defer(h);
     for (int u : act) {
         const DState& x = st[(size_t)u];
         const WinLevel& l = w->lv[(size_t)x.j];
@@ -644,8 +714,11 @@ static sk_status amplify_pick(sketch_t h, std::vector<DState>& st, const std::ve
             int xi = 0;
             while (xi < x.k && est[xi] >= l.theta) ++xi;
             double* Rh = w->sR + sl * rsz;
-            W_TRY(hipMemcpy2DAsync(Rh, sizeof(double) * (size_t)w->ld, C, sizeof(double) * (size_t)ldc,
-                                   sizeof(double) * (size_t)d, (size_t)r, hipMemcpyDeviceToDevice, h->stream));
+            const size_t pitch = sizeof(double) * (size_t)w->ld;
+            W_TRY(w_issue(h, [=] {
+                return hipMemcpy2DAsync(Rh, pitch, C, sizeof(double) * (size_t)ldc, sizeof(double) * (size_t)d,
+                                        (size_t)r, hipMemcpyDeviceToDevice, stm);
+            }));
             if (xi > 0) {
                 g1.push_back(gd(C, ldc, false, w->sZ + sl * z.z, lk, false, w->sCZ + sl * z.y, lk, r, xi, d));
                 g2.push_back(gd(w->sCZ + sl * z.y, lk, false, w->sZ + sl * z.z, lk, true, Rh, (int)w->ld, r, d, xi,
@@ -672,6 +745,7 @@ static sk_status amplify_pick(sketch_t h, std::vector<DState>& st, const std::ve
     if ((rc = gemm_batch(h, g1))) return rc;
     if ((rc = gemm_batch(h, g2))) return rc;
     if ((rc = launch_pis(h, pis))) return rc;
+    W_TRY(defer.flush());
     const int nsl = (act.back() + 1) * R;
     W_TRY(hipMemcpyAsync(w->h_amp, w->amp_out, sizeof(double) * (size_t)nsl * S, hipMemcpyDeviceToHost, h->stream));
     W_TRY(sync_reset(h));
@@ -865,7 +939,7 @@ sk_status window_create(sketch_t h) {
     // product of a batch over the slots
     w->gpart_cap = std::max<int64_t>((int64_t)1 << 21, (int64_t)w->nslots * 32 * 64 * 64);
     W_TRY(A(&w->gpart, (size_t)w->gpart_cap));
-    w->acap = 1 << 20;
+    w->acap = (size_t)8 << 20;
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
