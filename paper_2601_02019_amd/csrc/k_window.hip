@@ -10,6 +10,10 @@
 //                 Rayleigh quotient |C' x|^2 (the power-iteration test of
 //                 Algorithm "AeroSketch: Update"), each buffer's column slabs
 //                 held in the registers of its workgroups
+//   k_win_gemv,   the same power iteration in the row space of C' through
+//   k_win_pig     the level's Gram C' C'^T, kept between rows: one pass over
+//                 C' (start vector, new Gram row), then r x r steps on one
+//                 workgroup per level
 //   k_gemm_desc   FP64 C = alpha op(A) op(B) + beta C for snapshot, residual
 //                 and restore products and the batched simul_iter stages
 //                 (split-K partials summed by k_gemm_reduce in fixed order)
@@ -180,6 +184,135 @@ __global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const Pi
         const bool timed_out = __hip_atomic_load(bars + 2 * lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         *q.out = timed_out ? __builtin_nan("") : rq;
     }
+}
+
+// ------------------------------------------------- row-space power iteration
+// Pass over C: blockIdx.y = level, 16 rows of C per workgroup (four per
+// wave).  x0 (the draws of the column-slab kernel: normal 0 of the Philox
+// block at counter (c, 0, c2, c3) for column c) is generated into LDS; a
+// wave forms u_i = C_i . x0 and, for i <= grow, G_{grow,i} = C_i . C_grow,
+// each with a fixed-order lane reduction.  Workgroup 0 also writes |x0|^2.
+__global__ __launch_bounds__(256) void k_win_gemv(const GramPiDesc* ds) {
+    extern __shared__ double x0[];  // d doubles
+    __shared__ double red[4];
+    const GramPiDesc& q = ds[blockIdx.y];
+    const int r = q.r, d = q.d;
+    const int i0 = blockIdx.x * 16;
+    if (r <= 0 || i0 >= r) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c = tid; c < d; c += 256) x0[c] = gauss_pick(q.seed, q.stream, (uint64_t)c, 0ull, q.c2, q.c3, 0);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        double s = 0.0;
+        for (int c = tid; c < d; c += 256) s = fma(x0[c], x0[c], s);
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) red[wv] = s;
+        __syncthreads();
+        if (tid == 0) q.u[q.ldg] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+    const double* a = q.grow >= 0 ? q.C + (int64_t)q.grow * q.ldc : nullptr;
+    for (int t = 0; t < 4; ++t) {
+        const int i = i0 + wv * 4 + t;
+        if (i >= r) break;
+        const double* ci = q.C + (int64_t)i * q.ldc;
+        const bool g = a != nullptr && i <= q.grow;
+        double sx = 0.0, sa = 0.0;
+        if (g) {
+            for (int c = lane; c < d; c += 64) {
+                const double v = ci[c];
+                sx = fma(v, x0[c], sx);
+                sa = fma(v, a[c], sa);
+            }
+        } else {
+            for (int c = lane; c < d; c += 64) sx = fma(ci[c], x0[c], sx);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off, 64);
+            sa += __shfl_xor(sa, off, 64);
+        }
+        if (lane == 0) {
+            q.u[i] = sx;
+            if (g) {
+                q.G[(int64_t)q.grow * q.ldg + i] = sa;
+                q.G[(int64_t)i * q.ldg + q.grow] = sa;
+            }
+        }
+    }
+}
+
+// Steps, one workgroup of 1024 threads per level.  With y = u / |x0|:
+// `steps` times { v = G y; n = y . v; y = v / sqrt(n) }, then out = |y|^2.
+// In exact arithmetic this is the column-slab kernel's sequence (its
+// y = C x / |x|, x <- C^T y, and |x|^2 = y^T G y for the next x).  Column j
+// of G goes to the threads j mod R (R = r rounded up to a power of two
+// >= 64); the rows are cut into 1024 / R chunks, one per thread group, and
+// the chunk partials are added in chunk order.
+__global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds) {
+    __shared__ double y[1024];
+    __shared__ double part[1024];
+    __shared__ double red[16];
+    const GramPiDesc& q = ds[blockIdx.x];
+    const int r = q.r, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (r <= 0) {
+        if (tid == 0) *q.out = 0.0;
+        return;
+    }
+    int R = 64;
+    while (R < r) R <<= 1;
+    const int P = 1024 / R, j = tid % R, p = tid / R;
+    const int per = (r + P - 1) / P;
+    const int ib = p * per, ie = min(r, ib + per);
+    const double* G = q.G;
+    const int64_t ldg = q.ldg;
+    // block sum in a fixed order (the same value in every thread)
+    auto block_total = [&](double v) -> double {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        __syncthreads();
+        if (lane == 0) red[wv] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) s += red[w];
+        return s;
+    };
+    const double n0 = q.u[q.ldg];
+    const double inv0 = n0 > 0.0 ? 1.0 / sqrt(n0) : 0.0;
+    if (tid < r) y[tid] = q.u[tid] * inv0;
+    __syncthreads();
+    bool zero = !(n0 > 0.0);
+    for (int it = 0; it < q.steps && !zero; ++it) {
+        double acc = 0.0;
+        if (j < r) {
+#pragma unroll 8
+            for (int i = ib; i < ie; ++i) acc = fma(G[(int64_t)i * ldg + j], y[i], acc);
+        }
+        part[tid] = acc;
+        __syncthreads();
+        double v = 0.0;
+        if (tid < r)
+            for (int pp = 0; pp < P; ++pp) v += part[pp * R + tid];
+        const double n = block_total(tid < r ? v * y[tid] : 0.0);
+        if (!(n > 0.0)) {
+            zero = true;
+            break;
+        }
+        if (tid < r) y[tid] = v * (1.0 / sqrt(n));
+        __syncthreads();
+    }
+    const double rq = zero ? 0.0 : block_total(tid < r ? y[tid] * y[tid] : 0.0);
+    if (tid == 0) *q.out = rq;
+}
+
+hipError_t launch_win_pi_gram(const void* descs, int count, int max_r, int max_d, hipStream_t st) {
+    if (count <= 0 || max_r <= 0) return hipSuccess;
+    if (max_r > 1024 || max_d < 1 || max_d > 4096) return hipErrorInvalidValue;
+    const GramPiDesc* ds = (const GramPiDesc*)descs;
+    hipLaunchKernelGGL(k_win_gemv, dim3((unsigned)((max_r + 15) / 16), (unsigned)count), dim3(256),
+                       sizeof(double) * (size_t)max_d, st, ds);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_win_pig, dim3((unsigned)count), dim3(1024), 0, st, ds);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- GEMM

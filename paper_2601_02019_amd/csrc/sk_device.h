@@ -130,17 +130,33 @@ struct MatGenDesc {
     uint64_t seed, stream, c2, c3;
 };
 
-// Power iteration of one window level on C (r x d).  out receives the
-// Rayleigh quotient, or NaN when a grid barrier of the cooperative kernel
-// timed out.
 // Column factors of the approximate-matrix-multiplication kernels (k_cod.hip).
 enum CodScale { COD_SQRT = 0, COD_INVSQRT = 1, COD_KEPT = 2, COD_SHRINK_GAIN = 3, COD_SHRINK_SQRT = 4 };
 
+// Power iteration of one window level on C (r x d).  out receives the
+// Rayleigh quotient, or NaN when a grid barrier of the cooperative kernel
+// timed out.
 struct PiDesc {
     const double* C;
     double* out;
     int64_t ldc;
     int32_t r, d, steps, pad;
+    uint64_t seed, stream, c2, c3;
+};
+
+// The same power iteration carried out in the row space of C through the
+// level's Gram G = C C^T (r x r, ld ldg, kept between rows): u = C x0 and
+// |x0|^2 come from one pass over C, which also fills row and column grow of
+// G (the row appended since G was last complete; grow < 0: G is complete),
+// and the steps are r x r products.  u holds ldg + 1 doubles (u, then
+// |x0|^2).
+struct GramPiDesc {
+    const double* C;
+    double* out;
+    double* G;
+    double* u;
+    int64_t ldc;
+    int32_t r, d, steps, grow, ldg, pad;
     uint64_t seed, stream, c2, c3;
 };
 

@@ -45,6 +45,10 @@ int win_pi_groups(int d);
 // requires; the buffers are reused by the launches in stream order.
 hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double* part, unsigned* bars,
                          hipStream_t st);
+// Row-space power iteration (GramPiDesc list on the device, r <= 1024): one
+// pass over every C (u = C x0, |x0|^2, the new row and column of G), then
+// one workgroup per level for the steps.
+hipError_t launch_win_pi_gram(const void* descs, int count, int max_r, int max_d, hipStream_t st);
 // One split-K product (descriptor by value, with part, nsplit, kchunk set).
 hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st);
 // Single-descriptor launches with the descriptor passed by value.

@@ -59,6 +59,11 @@ struct WinLevel {
     // P5 site: row clock and unsent counter F_j
     int64_t clock = 0;
     double F = 0.0;
+    // the level's Gram C' C'^T (row-space power iteration): complete for the
+    // first g_rows rows of buffer g_C after g_shr shrinks; g_rows < 0 after
+    // any other change of the buffer
+    int64_t g_rows = -1, g_shr = -1;
+    const double* g_C = nullptr;
 };
 
 // one row of a P5 update call: its index in the block, the site's timestamp,
@@ -87,6 +92,8 @@ struct WindowState {
     double* h_norms = nullptr;   // pinned
     double* pi_out = nullptr;
     double* h_pi = nullptr;      // pinned
+    double* pg = nullptr;        // L x (2 ell)^2 level Grams
+    double* pu = nullptr;        // L x (2 ell + 1): C' x0 and |x0|^2
     int32_t* info = nullptr;     // eigen-solver counters (all simul_iter slots, the query)
     // simul_iter job slots: every stage of a batch of simul_iter calls is one
     // launch over the slots it uses
@@ -220,24 +227,6 @@ static hipError_t sync_reset(sketch_t h) {
     return e;
 }
 
-// Algorithm "Power Iteration" for every descriptor, kPiBatch per cooperative
-// launch (the launches share one partial buffer, in stream order).
-static sk_status launch_pis(sketch_t h, const std::vector<PiDesc>& pis) {
-    WindowState* w = h->win;
-    for (size_t b = 0; b < pis.size(); b += kPiBatch) {
-        const size_t cnt = std::min(pis.size() - b, (size_t)kPiBatch);
-        std::vector<PiDesc> part(pis.begin() + (ptrdiff_t)b, pis.begin() + (ptrdiff_t)(b + cnt));
-        const PiDesc* dp = nullptr;
-        W_TRY(put_desc(h, part, &dp));
-        const int d = w->d, mr = 2 * w->ell;
-        double* pp = w->pi_part;
-        unsigned* bars = w->pi_bars;
-        hipStream_t st = h->stream;
-        W_TRY(w_issue(h, [=] { return launch_win_pi(dp, (int)cnt, d, mr, pp, bars, st); }));
-    }
-    return SK_OK;
-}
-
 static GemmDesc gd(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
                    int ldc, int M, int N, int K, double alpha = 1.0, double beta = 0.0) {
     GemmDesc g{};
@@ -255,6 +244,24 @@ static GemmDesc gd(const double* A, int lda, bool ta, const double* B, int ldb, 
     g.alpha = alpha;
     g.beta = beta;
     return g;
+}
+
+// Algorithm "Power Iteration" for every descriptor, kPiBatch per cooperative
+// launch (the launches share one partial buffer, in stream order).
+static sk_status launch_pis(sketch_t h, const std::vector<PiDesc>& pis) {
+    WindowState* w = h->win;
+    for (size_t b = 0; b < pis.size(); b += kPiBatch) {
+        const size_t cnt = std::min(pis.size() - b, (size_t)kPiBatch);
+        std::vector<PiDesc> part(pis.begin() + (ptrdiff_t)b, pis.begin() + (ptrdiff_t)(b + cnt));
+        const PiDesc* dp = nullptr;
+        W_TRY(put_desc(h, part, &dp));
+        const int d = w->d, mr = 2 * w->ell;
+        double* pp = w->pi_part;
+        unsigned* bars = w->pi_bars;
+        hipStream_t st = h->stream;
+        W_TRY(w_issue(h, [=] { return launch_win_pi(dp, (int)cnt, d, mr, pp, bars, st); }));
+    }
+    return SK_OK;
 }
 
 static sk_status gemm1(sketch_t h, const GemmDesc& g0) {
@@ -294,11 +301,12 @@ static sk_status small_eig(sketch_t h, const SmallDesc& q) {
 static const double* level_C(const WinLevel& l) { return (const double*)l.sub->host.buf[l.sub->par]; }
 
 // Split-K factor of a batched product, from its shape alone: products with
-// few 64 x 64 output tiles and a long K are cut into chunks of >= 128 so that
-// about 32 workgroups work on each (at most 32 x 64 x 64 partials).
+// few 64 x 64 output tiles and a long K are cut into chunks of >= 64 so that
+// about 128 workgroups work on each (at most 128 x 64 x 64 partials): a batch
+// of one or two levels then spreads over half the chip instead of an eighth.
 static int batch_splits(const GemmDesc& g) {
     const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-    return std::max(1, std::min(g.K / 128, 32 / tiles));
+    return std::max(1, std::min(g.K / 64, 128 / tiles));
 }
 
 // Products of a batch (descriptors with an empty output are dropped; the
@@ -356,6 +364,61 @@ static sk_status gemm_batch(sketch_t h, const std::vector<GemmDesc>& gs0) {
         const int nf = (int)fin.size();
         W_TRY(w_issue(h, [=] { return launch_gemm_reduce_desc(dp, nf, mMN, st); }));
     }
+    return SK_OK;
+}
+
+// Algorithm "Power Iteration" of the levels js (descriptors pis, in the
+// same order) in the row space of their buffers (GramPiDesc): a level whose
+// buffer only gained its last row since its Gram was complete has that row
+// and column filled by the pass over C'; after any other change (a reduce,
+// a dump, the other buffer of the pair) G = C' C'^T is recomputed first.
+// The estimates land in each descriptor's out, as with launch_pis.
+static sk_status launch_pis_gram(sketch_t h, const std::vector<int>& js, const std::vector<PiDesc>& pis) {
+    WindowState* w = h->win;
+    if (js.empty()) return SK_OK;
+    const int n2 = 2 * w->ell;
+    hipStream_t st = h->stream;
+    DeferDesc defer(h);
+    std::vector<GemmDesc> full;
+    std::vector<GramPiDesc> gs;
+    int max_r = 0;
+    for (size_t u = 0; u < js.size(); ++u) {
+        WinLevel& l = w->lv[(size_t)js[u]];
+        const PiDesc& p = pis[u];
+        GramPiDesc g{};
+        g.C = p.C;
+        g.out = p.out;
+        g.G = w->pg + (size_t)js[u] * n2 * n2;
+        g.u = w->pu + (size_t)js[u] * (n2 + 1);
+        g.ldc = p.ldc;
+        g.r = p.r;
+        g.d = p.d;
+        g.steps = p.steps;
+        g.ldg = n2;
+        g.grow = -1;
+        g.seed = p.seed;
+        g.stream = p.stream;
+        g.c2 = p.c2;
+        g.c3 = p.c3;
+        const bool same = l.g_rows >= 0 && l.g_C == p.C && l.g_shr == l.sub->shrinks;
+        if (p.r > 0 && same && l.g_rows == p.r - 1) {
+            g.grow = p.r - 1;
+        } else if (p.r > 0 && !(same && l.g_rows == p.r)) {
+            full.push_back(gd(p.C, (int)p.ldc, false, p.C, (int)p.ldc, true, g.G, n2, p.r, p.r, p.d));
+        }
+        l.g_rows = p.r;
+        l.g_C = p.C;
+        l.g_shr = l.sub->shrinks;
+        max_r = std::max(max_r, p.r);
+        gs.push_back(g);
+    }
+    sk_status rc = gemm_batch(h, full);
+    if (rc) return rc;
+    const GramPiDesc* dp = nullptr;
+    W_TRY(put_desc(h, gs, &dp));
+    const int cnt = (int)gs.size(), dd = w->d;
+    W_TRY(w_issue(h, [=] { return launch_win_pi_gram(dp, cnt, max_r, dd, st); }));
+    W_TRY(defer.flush());
     return SK_OK;
 }
 
@@ -588,7 +651,8 @@ static sk_status dump_exec(sketch_t h, const std::vector<DumpJob>& ds) {
     }
     g.clear();
     for (const DumpJob& x : ds) {
-        const WinLevel& l = w->lv[(size_t)x.j];
+        WinLevel& l = w->lv[(size_t)x.j];
+        l.g_rows = -1;  // the residual rewrites the buffer
         g.push_back(gd(w->sCZ + x.slot * z.y, lk, false, w->sZ + x.slot * z.z, lk, true, (double*)level_C(l),
                        (int)l.sub->ld, (int)l.sub->fill, d, x.xi, -1.0, 1.0));
     }
@@ -934,10 +998,12 @@ sk_status window_create(sketch_t h) {
     W_TRY(A(&w->stats, 16));
     W_TRY(h->dalloc((void**)&w->ctrl, 64 * sizeof(int32_t)));
     W_TRY(A(&w->pi_part, (size_t)kPiBatch * 2 * win_pi_groups(d) * (n2 + 1)));
+    W_TRY(A(&w->pg, (size_t)w->L * n2 * n2));
+    W_TRY(A(&w->pu, (size_t)w->L * (n2 + 1)));
     W_TRY(h->dalloc((void**)&w->pi_bars, sizeof(unsigned) * 2 * (size_t)kPiBatch));
-    // split-K partials: the single products, and up to 32 x 64 x 64 per
+    // split-K partials: the single products, and up to 128 x 64 x 64 per
     // product of a batch over the slots
-    w->gpart_cap = std::max<int64_t>((int64_t)1 << 21, (int64_t)w->nslots * 32 * 64 * 64);
+    w->gpart_cap = std::max<int64_t>((int64_t)1 << 21, (int64_t)w->nslots * 128 * 64 * 64);
     W_TRY(A(&w->gpart, (size_t)w->gpart_cap));
     w->acap = (size_t)8 << 20;
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
@@ -1041,7 +1107,7 @@ sk_status window_update(sketch_t h, const char* rows, int64_t n, int64_t ld, int
             p.c3 = 0x100u + (uint64_t)l.rlevel;
             pis.push_back(p);
         }
-        if (sk_status prc = launch_pis(h, pis)) return prc;
+        if (sk_status prc = launch_pis_gram(h, pj, pis)) return prc;
         W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
         W_TRY(sync_reset(h));
         for (int j : pj)
@@ -1331,7 +1397,7 @@ sk_status p5_update_impl(sketch_t h, const int32_t* site, const char* rows, int6
             p.c3 = 0x100u + (uint64_t)l.rlevel;
             pis.push_back(p);
         }
-        if ((rc = launch_pis(h, pis))) return rc;
+        if ((rc = launch_pis_gram(h, pj, pis))) return rc;
         W_TRY(hipMemcpyAsync(w->h_pi, w->pi_out, sizeof(double) * (size_t)w->L, hipMemcpyDeviceToHost, h->stream));
         W_TRY(sync_reset(h));
         for (int j : pj)
