@@ -187,17 +187,17 @@ __global__ __launch_bounds__(512, (RPT > 32 ? 2 : 4)) void k_win_pi_reg(const Pi
 }
 
 // ------------------------------------------------- row-space power iteration
-// Pass over C: blockIdx.y = level, 16 rows of C per workgroup (four per
+// Pass over C: blockIdx.y = level, 4 rpw rows of C per workgroup (rpw per
 // wave).  x0 (the draws of the column-slab kernel: normal 0 of the Philox
 // block at counter (c, 0, c2, c3) for column c) is generated into LDS; a
 // wave forms u_i = C_i . x0 and, for i <= grow, G_{grow,i} = C_i . C_grow,
 // each with a fixed-order lane reduction.  Workgroup 0 also writes |x0|^2.
-__global__ __launch_bounds__(256) void k_win_gemv(const GramPiDesc* ds) {
+__global__ __launch_bounds__(256) void k_win_gemv(const GramPiDesc* ds, int rpw) {
     extern __shared__ double x0[];  // d doubles
     __shared__ double red[4];
     const GramPiDesc& q = ds[blockIdx.y];
     const int r = q.r, d = q.d;
-    const int i0 = blockIdx.x * 16;
+    const int i0 = blockIdx.x * 4 * rpw;
     if (r <= 0 || i0 >= r) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int c = tid; c < d; c += 256) x0[c] = gauss_pick(q.seed, q.stream, (uint64_t)c, 0ull, q.c2, q.c3, 0);
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(256) void k_win_gemv(const GramPiDesc* ds) {
         if (tid == 0) q.u[q.ldg] = (red[0] + red[1]) + (red[2] + red[3]);
     }
     const double* a = q.grow >= 0 ? q.C + (int64_t)q.grow * q.ldc : nullptr;
-    for (int t = 0; t < 4; ++t) {
-        const int i = i0 + wv * 4 + t;
+    for (int t = 0; t < rpw; ++t) {
+        const int i = i0 + wv * rpw + t;
         if (i >= r) break;
         const double* ci = q.C + (int64_t)i * q.ldc;
         const bool g = a != nullptr && i <= q.grow;
@@ -245,9 +245,14 @@ __global__ __launch_bounds__(256) void k_win_gemv(const GramPiDesc* ds) {
 // In exact arithmetic this is the column-slab kernel's sequence (its
 // y = C x / |x|, x <- C^T y, and |x|^2 = y^T G y for the next x).  Column j
 // of G goes to the threads j mod R (R = r rounded up to a power of two
-// >= 64); the rows are cut into 1024 / R chunks, one per thread group, and
-// the chunk partials are added in chunk order.
-__global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds) {
+// >= 64); the rows are cut into P = 1024 / R chunks, one per thread group,
+// and the chunk partials are added in chunk order.  G is read once from
+// memory: the first cpc rows of every chunk are kept in LDS (lds_doubles of
+// dynamic LDS) and the next kPigRegs in each thread's registers; only the
+// rest of a chunk is re-read at every step.
+static constexpr int kPigRegs = 16;
+__global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds, int lds_doubles) {
+    extern __shared__ double gl[];
     __shared__ double y[1024];
     __shared__ double part[1024];
     __shared__ double red[16];
@@ -262,8 +267,22 @@ __global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds) {
     const int P = 1024 / R, j = tid % R, p = tid / R;
     const int per = (r + P - 1) / P;
     const int ib = p * per, ie = min(r, ib + per);
+    const int cpc = min(per, lds_doubles / (P * r));
     const double* G = q.G;
     const int64_t ldg = q.ldg;
+    for (int e = tid; e < P * cpc * r; e += 1024) {
+        const int row = e / r, c = e - row * r;
+        const int i = (row / cpc) * per + row % cpc;
+        gl[e] = i < r ? G[(int64_t)i * ldg + c] : 0.0;
+    }
+    double rg[kPigRegs];
+#pragma unroll
+    for (int t = 0; t < kPigRegs; ++t) {
+        const int i = ib + cpc + t;
+        rg[t] = (j < r && i < ie) ? G[(int64_t)i * ldg + j] : 0.0;
+    }
+    const int i_mem = min(ie, ib + cpc + kPigRegs);
+    const double* gll = gl + (int64_t)p * cpc * r;
     // block sum in a fixed order (the same value in every thread)
     auto block_total = [&](double v) -> double {
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -283,8 +302,15 @@ __global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds) {
     for (int it = 0; it < q.steps && !zero; ++it) {
         double acc = 0.0;
         if (j < r) {
+            const int il = min(ie, ib + cpc);
+            for (int i = ib; i < il; ++i) acc = fma(gll[(i - ib) * r + j], y[i], acc);
+#pragma unroll
+            for (int t = 0; t < kPigRegs; ++t) {
+                const int i = ib + cpc + t;
+                if (i < ie) acc = fma(rg[t], y[i], acc);
+            }
 #pragma unroll 8
-            for (int i = ib; i < ie; ++i) acc = fma(G[(int64_t)i * ldg + j], y[i], acc);
+            for (int i = i_mem; i < ie; ++i) acc = fma(G[(int64_t)i * ldg + j], y[i], acc);
         }
         part[tid] = acc;
         __syncthreads();
@@ -306,12 +332,33 @@ __global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds) {
 hipError_t launch_win_pi_gram(const void* descs, int count, int max_r, int max_d, hipStream_t st) {
     if (count <= 0 || max_r <= 0) return hipSuccess;
     if (max_r > 1024 || max_d < 1 || max_d > 4096) return hipErrorInvalidValue;
+    // dynamic LDS of the step kernel: what the device grants beyond the
+    // static arrays, at most 160 KiB in all (none if the request fails)
+    static int pig_lds = -1;
+    if (pig_lds < 0) {
+        int dev = 0, cap = 0;
+        pig_lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cap, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess) {
+            const int stat = (int)(sizeof(double) * (1024 + 1024 + 16));
+            int want = (cap < 160 * 1024 ? cap : 160 * 1024) - stat;
+            want = want / 8 * 8;
+            if (want > 0 && hipFuncSetAttribute((const void*)k_win_pig, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                want) == hipSuccess)
+                pig_lds = want;
+        }
+        (void)hipGetLastError();
+    }
     const GramPiDesc* ds = (const GramPiDesc*)descs;
-    hipLaunchKernelGGL(k_win_gemv, dim3((unsigned)((max_r + 15) / 16), (unsigned)count), dim3(256),
-                       sizeof(double) * (size_t)max_d, st, ds);
+    // rows of C per wave: enough workgroups to cover the chip (about 1024)
+    const int wg4 = count * ((max_r + 15) / 16);
+    const int rpw = wg4 >= 1024 ? 4 : wg4 >= 512 ? 2 : 1;
+    const int rows_wg = 4 * rpw;
+    hipLaunchKernelGGL(k_win_gemv, dim3((unsigned)((max_r + rows_wg - 1) / rows_wg), (unsigned)count), dim3(256),
+                       sizeof(double) * (size_t)max_d, st, ds, rpw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_win_pig, dim3((unsigned)count), dim3(1024), 0, st, ds);
+    hipLaunchKernelGGL(k_win_pig, dim3((unsigned)count), dim3(1024), (size_t)pig_lds, st, ds, pig_lds / 8);
     return hipGetLastError();
 }
 
