@@ -98,13 +98,12 @@ struct WindowState {
     // simul_iter job slots: every stage of a batch of simul_iter calls is one
     // launch over the slots it uses
     int nslots = 0;
-    double *sK = nullptr, *sQ1 = nullptr, *sZ = nullptr;   // nslots x (d x kmax)
+    double *sK = nullptr, *sQ = nullptr, *sZ = nullptr;   // nslots x (d x kmax)
     double *sY = nullptr, *sCQ = nullptr, *sCZ = nullptr;  // nslots x (2 ell x kmax)
     double *sW = nullptr, *sX = nullptr, *sM = nullptr, *sU = nullptr, *sw1 = nullptr, *sw2 = nullptr;  // kmax^2
     double* slam = nullptr;      // nslots x kmax estimates
     double* h_slam = nullptr;    // pinned mirror
     double* sR = nullptr;        // nslots x (2 ell x ld): residuals of amplification candidates
-    std::vector<double*> sQcur;  // per slot: the buffer holding Q after its simul_iter
     // descriptor arena (device + pinned mirror), reset after every sync.
     // While `defer` is set descriptors are only staged (from dlo on) and the
     // launches that read them wait in `queued` for one upload of the range.
@@ -430,7 +429,7 @@ struct SiJob {
     int64_t ts;
 };
 
-// Slot views: d x kmax (K, Q1, Z), 2 ell x kmax (Y, CQ, CZ), kmax x kmax
+// Slot views: d x kmax (K, Q, Z), 2 ell x kmax (Y, CQ, CZ; the row-space iterates), kmax x kmax
 // (W, X, M, U, w1, w2), kmax (estimates).
 struct SlotSz {
     size_t z, y, k;
@@ -440,10 +439,11 @@ static SlotSz slot_sz(const WindowState* w) {
 }
 
 // Algorithm "Simultaneous Iteration" on A = C'^T (test matrix on the d side)
-// for every job at once: each stage is one batched launch over the jobs.
-// Leaves Z' = Q U in the slot's Z (d x k), Q in sQcur[slot], U in its U and
-// the k estimates of every slot in h_slam.
-static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
+// for every job at once, every product on the d side: each stage is one
+// batched launch over the jobs.  Leaves Z' = Q U in the slot's Z (d x k), U
+// in its U and the k estimates of every slot in h_slam.  The buffer sQ
+// (d x kmax per slot) is the second iterate of the CholeskyQR passes.
+static sk_status simul_iter_cols(sketch_t h, const std::vector<SiJob>& jobs) {
     WindowState* w = h->win;
     const int n = (int)jobs.size();
     if (n == 0) return SK_OK;
@@ -462,7 +462,7 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
         maxk = std::max(maxk, J.k);
         maxslot = std::max(maxslot, J.slot);
         K[(size_t)b] = w->sK + J.slot * z.z;
-        Q[(size_t)b] = w->sQ1 + J.slot * z.z;
+        Q[(size_t)b] = w->sQ + J.slot * z.z;
         C[(size_t)b] = level_C(l);
         ldc[(size_t)b] = (int)l.sub->ld;
         r[(size_t)b] = (int)l.sub->fill;
@@ -571,7 +571,6 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     for (int b = 0; b < n; ++b) {
         const int k = jobs[(size_t)b].k;
         g.push_back(gd(K[(size_t)b], lk, false, at(w->sU, b, z.k), lk, false, at(w->sZ, b, z.z), lk, d, k, k));
-        w->sQcur[(size_t)jobs[(size_t)b].slot] = K[(size_t)b];
     }
     if ((rc = gemm_batch(h, g))) return rc;
     W_TRY(defer.flush());
@@ -580,6 +579,182 @@ static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
     W_TRY(sync_reset(h));
     for (const SiJob& J : jobs) w->lv[(size_t)J.j].nsi += 1;
     return SK_OK;
+}
+
+// The same batch of simul_iter calls with the iterate carried in the row
+// space of each buffer.  After the first product Y = C' K0 the iterate K (d x k) is carried as
+// K = C'^T T with T (r x k) in the row space of the buffer, and every later
+// step goes through the level's Gram G = C' C'^T (kept by the power
+// iteration of the same row): C' K = G T, K^T K = T^T G T, K X^T = C'^T (T
+// X^T).  In exact arithmetic these are the d-side steps; only the first
+// product and the final Z = K U = C'^T (T U) read C'.  Leaves Z in the slot's
+// Z (d x k), U in its U and the k estimates of every slot in h_slam.
+static sk_status simul_iter_rows(sketch_t h, const std::vector<SiJob>& jobs) {
+    WindowState* w = h->win;
+    const int n = (int)jobs.size();
+    if (n == 0) return SK_OK;
+    const int d = w->d, lk = w->kmax, n2 = 2 * w->ell;
+    const SlotSz z = slot_sz(w);
+    hipStream_t st = h->stream;
+    DeferDesc defer(h);  // every stage's descriptors go up in one copy
+    int maxk = 0, maxslot = 0;
+    std::vector<const double*> C((size_t)n);
+    std::vector<const double*> G((size_t)n);
+    std::vector<double*> T((size_t)n), T2((size_t)n), GT((size_t)n);
+    std::vector<int> ldc((size_t)n), r((size_t)n);
+    std::vector<MatGenDesc> mg((size_t)n);
+    std::vector<GemmDesc> g;
+    auto at = [&](double* base, int b, size_t per) { return base + (size_t)jobs[(size_t)b].slot * per; };
+    for (int b = 0; b < n; ++b) {
+        const SiJob& J = jobs[(size_t)b];
+        WinLevel& l = w->lv[(size_t)J.j];
+        maxk = std::max(maxk, J.k);
+        maxslot = std::max(maxslot, J.slot);
+        C[(size_t)b] = level_C(l);
+        ldc[(size_t)b] = (int)l.sub->ld;
+        r[(size_t)b] = (int)l.sub->fill;
+        double* Gl = w->pg + (size_t)J.j * n2 * n2;
+        G[(size_t)b] = Gl;
+        T[(size_t)b] = at(w->sY, b, z.y);
+        T2[(size_t)b] = at(w->sCQ, b, z.y);
+        GT[(size_t)b] = at(w->sCZ, b, z.y);
+        // the Gram is complete after the power iteration of this row; any
+        // level whose buffer changed since (none in the engine's order) gets
+        // it recomputed here, once per level
+        if (!(l.g_rows == l.sub->fill && l.g_C == level_C(l) && l.g_shr == l.sub->shrinks)) {
+            g.push_back(gd(C[(size_t)b], ldc[(size_t)b], false, C[(size_t)b], ldc[(size_t)b], true, Gl, n2,
+                           r[(size_t)b], r[(size_t)b], d));
+            l.g_rows = l.sub->fill;
+            l.g_C = level_C(l);
+            l.g_shr = l.sub->shrinks;
+        }
+        MatGenDesc& m = mg[(size_t)b];
+        m = MatGenDesc{};
+        m.M = w->sK + J.slot * z.z;
+        m.rows = d;
+        m.cols = J.k;
+        m.ld = lk;
+        m.seed = w->seed;
+        m.stream = l.rstream;
+        m.c2 = (uint64_t)J.ts;
+        m.c3 = J.tag;
+    }
+    sk_status rc;
+    if ((rc = gemm_batch(h, g))) return rc;
+    {
+        const MatGenDesc* dp = nullptr;
+        W_TRY(put_desc(h, mg, &dp));
+        W_TRY(w_issue(h, [=] { return launch_philox_mat(dp, n, d, maxk, st); }));
+    }
+    std::vector<SmallDesc> sd((size_t)n);
+    auto kk = [&](int b) { return jobs[(size_t)b].k; };
+    // T = C' K0 (r x k): K = C'^T T is the first power step
+    g.clear();
+    for (int b = 0; b < n; ++b)
+        g.push_back(gd(C[(size_t)b], ldc[(size_t)b], false, w->sK + jobs[(size_t)b].slot * z.z, lk, false,
+                       T[(size_t)b], lk, r[(size_t)b], kk(b), d));
+    if ((rc = gemm_batch(h, g))) return rc;
+    // GT = G T for every job
+    auto gram_times_T = [&]() -> sk_status {
+        g.clear();
+        for (int b = 0; b < n; ++b)
+            g.push_back(gd(G[(size_t)b], n2, false, T[(size_t)b], lk, false, GT[(size_t)b], lk, r[(size_t)b], kk(b),
+                           r[(size_t)b]));
+        return gemm_batch(h, g);
+    };
+    // CholeskyQR passes on K = C'^T T: W = T^T G T, X = chol(W)^-1, T <- T X^T
+    auto cholqr = [&](int passes) -> sk_status {
+        for (int p = 0; p < passes; ++p) {
+            sk_status e = gram_times_T();
+            if (e) return e;
+            g.clear();
+            for (int b = 0; b < n; ++b)
+                g.push_back(gd(T[(size_t)b], lk, true, GT[(size_t)b], lk, false, at(w->sW, b, z.k), lk, kk(b), kk(b),
+                               r[(size_t)b]));
+            if ((e = gemm_batch(h, g))) return e;
+            for (int b = 0; b < n; ++b) {
+                SmallDesc& q = sd[(size_t)b];
+                q = SmallDesc{};
+                q.A = at(w->sW, b, z.k);
+                q.lda = lk;
+                q.X = at(w->sX, b, z.k);
+                q.ldx = lk;
+                q.n = kk(b);
+                q.work = at(w->sw1, b, z.k);
+            }
+            const SmallDesc* dp = nullptr;
+            W_TRY(put_desc(h, sd, &dp));
+            W_TRY(w_issue(h, [=] { return launch_cholinv_desc(dp, n, maxk, st); }));
+            g.clear();
+            for (int b = 0; b < n; ++b)
+                g.push_back(gd(T[(size_t)b], lk, false, at(w->sX, b, z.k), lk, true, T2[(size_t)b], lk, r[(size_t)b],
+                               kk(b), kk(b)));
+            if ((e = gemm_batch(h, g))) return e;
+            std::swap(T, T2);
+        }
+        return SK_OK;
+    };
+    for (int it = 1; it <= w->q; ++it) {
+        if ((rc = cholqr(1))) return rc;
+        // C' K = G T, and K <- C'^T (G T)
+        if ((rc = gram_times_T())) return rc;
+        std::swap(T, GT);
+    }
+    if ((rc = cholqr(2))) return rc;  // K = C'^T T now has orthonormal columns
+    // C' Q = G T; M = (C' Q)^T (C' Q)
+    if ((rc = gram_times_T())) return rc;
+    g.clear();
+    for (int b = 0; b < n; ++b)
+        g.push_back(gd(GT[(size_t)b], lk, true, GT[(size_t)b], lk, false, at(w->sM, b, z.k), lk, kk(b), kk(b),
+                       r[(size_t)b]));
+    if ((rc = gemm_batch(h, g))) return rc;
+    for (int b = 0; b < n; ++b) {
+        SmallDesc& q = sd[(size_t)b];
+        q = SmallDesc{};
+        q.A = at(w->sM, b, z.k);
+        q.lda = lk;
+        q.X = at(w->sU, b, z.k);
+        q.ldx = lk;
+        q.lam = w->slam + (size_t)jobs[(size_t)b].slot * lk;
+        q.n = kk(b);
+        q.work = at(w->sw1, b, z.k);
+        q.work2 = at(w->sw2, b, z.k);
+        q.info = w->info;
+    }
+    {
+        const SmallDesc* dp = nullptr;
+        W_TRY(put_desc(h, sd, &dp));
+        const bool jac = eig_solver_jacobi();
+        W_TRY(w_issue(h, [=] {
+            return jac ? launch_jacobi_desc(dp, n, maxk, st) : launch_tri_eig_desc(dp, n, maxk, st);
+        }));
+    }
+    // Z = K U = C'^T (T U)
+    g.clear();
+    for (int b = 0; b < n; ++b)
+        g.push_back(gd(T[(size_t)b], lk, false, at(w->sU, b, z.k), lk, false, T2[(size_t)b], lk, r[(size_t)b], kk(b),
+                       kk(b)));
+    if ((rc = gemm_batch(h, g))) return rc;
+    g.clear();
+    for (int b = 0; b < n; ++b)
+        g.push_back(gd(C[(size_t)b], ldc[(size_t)b], true, T2[(size_t)b], lk, false, at(w->sZ, b, z.z), lk, d, kk(b),
+                       r[(size_t)b]));
+    if ((rc = gemm_batch(h, g))) return rc;
+    W_TRY(defer.flush());
+    W_TRY(hipMemcpyAsync(w->h_slam, w->slam, sizeof(double) * (size_t)(maxslot + 1) * lk, hipMemcpyDeviceToHost,
+                         h->stream));
+    W_TRY(sync_reset(h));
+    for (const SiJob& J : jobs) w->lv[(size_t)J.j].nsi += 1;
+    return SK_OK;
+}
+
+// One batch of simul_iter calls.  The row-space form trades the d-side
+// products for r x r ones and one more product per CholeskyQR pass; it is
+// taken when d exceeds 8 ell (four times the largest buffer), where it was
+// the faster of the two on the P5 shape (d = 2048, ell = 128) and the slower
+// on the window shape (d = 1024, ell = 128).
+static sk_status simul_iter_batch(sketch_t h, const std::vector<SiJob>& jobs) {
+    return h->win->d > 8 * h->win->ell ? simul_iter_rows(h, jobs) : simul_iter_cols(h, jobs);
 }
 
 // P5 coordinator (Receive_Update of Algorithm "P5"): adds the waiting
@@ -964,11 +1139,11 @@ sk_status window_create(sketch_t h) {
     w->nslots = std::max(w->amp_r, std::min(64, w->L * w->amp_r));
     {
         const size_t ns = (size_t)w->nslots, zs = (size_t)d * lk, ys = (size_t)n2 * lk, ks = (size_t)lk * lk;
-        for (double** p : {&w->sK, &w->sQ1, &w->sZ}) W_TRY(A(p, ns * zs));
+        for (double** p : {&w->sK, &w->sZ}) W_TRY(A(p, ns * zs));
+        if (d <= 8 * w->ell) W_TRY(A(&w->sQ, ns * zs));  // the d-side form's second iterate
         for (double** p : {&w->sY, &w->sCQ, &w->sCZ}) W_TRY(A(p, ns * ys));
         for (double** p : {&w->sW, &w->sX, &w->sM, &w->sU, &w->sw1, &w->sw2}) W_TRY(A(p, ns * ks));
         W_TRY(A(&w->slam, ns * lk));
-        w->sQcur.assign(ns, nullptr);
         if (w->amp_s > 0) {
             W_TRY(A(&w->sR, ns * (size_t)n2 * w->ld));
             W_TRY(A(&w->amp_out, ns * (size_t)w->amp_s));
