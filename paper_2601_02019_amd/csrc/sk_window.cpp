@@ -110,6 +110,7 @@ struct WindowState {
     char* darena = nullptr;
     char* harena = nullptr;
     size_t acap = 0, aoff = 0;
+    hipEvent_t done = nullptr;  // recorded at every wait of the engine
     bool defer = false;
     size_t dlo = 0;
     std::vector<std::function<hipError_t()>> queued;
@@ -220,9 +221,18 @@ struct DeferDesc {
     }
 };
 
+// Waits for the stream by polling an event recorded on it (the engine's
+// per-row decisions wait on short GPU stages, where a polled wait returns
+// sooner than a blocking one), then resets the descriptor arena.
 static hipError_t sync_reset(sketch_t h) {
-    hipError_t e = hipStreamSynchronize(h->stream);
-    h->win->aoff = 0;
+    WindowState* w = h->win;
+    hipError_t e = hipEventRecord(w->done, h->stream);
+    while (e == hipSuccess) {
+        e = hipEventQuery(w->done);
+        if (e == hipErrorNotReady) e = hipSuccess;
+        else break;
+    }
+    w->aoff = 0;
     return e;
 }
 
@@ -1183,6 +1193,7 @@ sk_status window_create(sketch_t h) {
     w->acap = (size_t)8 << 20;
     W_TRY(h->dalloc((void**)&w->darena, w->acap));
     W_TRY(hipHostMalloc((void**)&w->harena, w->acap, hipHostMallocDefault));
+    W_TRY(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
     W_TRY(hipHostMalloc((void**)&w->h_pi, sizeof(double) * (size_t)w->L, hipHostMallocDefault));
     W_TRY(hipHostMalloc((void**)&w->h_slam, sizeof(double) * (size_t)w->nslots * lk, hipHostMallocDefault));
     if (w->p5) {
@@ -1200,6 +1211,7 @@ void window_destroy(sketch_t h) {
     for (WinLevel& l : w->lv)
         if (l.sub) sketch_destroy(l.sub);
     if (w->harena) (void)hipHostFree(w->harena);
+    if (w->done) (void)hipEventDestroy(w->done);
     if (w->h_pi) (void)hipHostFree(w->h_pi);
     if (w->h_slam) (void)hipHostFree(w->h_slam);
     if (w->h_amp) (void)hipHostFree(w->h_amp);
