@@ -349,16 +349,22 @@ hipError_t launch_win_pi_gram(const void* descs, int count, int max_r, int max_d
         }
         (void)hipGetLastError();
     }
-    const GramPiDesc* ds = (const GramPiDesc*)descs;
+    hipError_t e = launch_win_gemv(descs, count, max_r, max_d, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_win_pig, dim3((unsigned)count), dim3(1024), (size_t)pig_lds, st, (const GramPiDesc*)descs,
+                       pig_lds / 8);
+    return hipGetLastError();
+}
+
+hipError_t launch_win_gemv(const void* descs, int count, int max_r, int max_d, hipStream_t st) {
+    if (count <= 0 || max_r <= 0) return hipSuccess;
+    if (max_d < 1 || max_d > 4096) return hipErrorInvalidValue;
     // rows of C per wave: enough workgroups to cover the chip (about 1024)
     const int wg4 = count * ((max_r + 15) / 16);
     const int rpw = wg4 >= 1024 ? 4 : wg4 >= 512 ? 2 : 1;
     const int rows_wg = 4 * rpw;
     hipLaunchKernelGGL(k_win_gemv, dim3((unsigned)((max_r + rows_wg - 1) / rows_wg), (unsigned)count), dim3(256),
-                       sizeof(double) * (size_t)max_d, st, ds, rpw);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_win_pig, dim3((unsigned)count), dim3(1024), (size_t)pig_lds, st, ds, pig_lds / 8);
+                       sizeof(double) * (size_t)max_d, st, (const GramPiDesc*)descs, rpw);
     return hipGetLastError();
 }
 

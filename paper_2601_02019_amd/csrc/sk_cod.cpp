@@ -58,7 +58,14 @@ struct CodState {
     // simul_iter scratch
     double *Om = nullptr, *Q1 = nullptr, *Yd = nullptr, *Tr = nullptr, *Z = nullptr, *H = nullptr;
     double *Wk = nullptr, *Xk = nullptr, *Mk = nullptr, *Uk = nullptr, *lam = nullptr, *w1 = nullptr, *w2 = nullptr;
-    double *pi_x0 = nullptr, *pi_u0 = nullptr, *pi_n0 = nullptr, *pi_out = nullptr;
+    // power iteration: the kept Grams A A^T and B B^T (n2 x n2, complete for
+    // the first g_rows rows of buffer pair g_par; g_rows < 0 after a dump),
+    // u = B x0 with |x0|^2 in ub[n2], the pass descriptors (device, pinned)
+    double *Gkx = nullptr, *Gky = nullptr, *ua = nullptr, *ub = nullptr, *pi_out = nullptr;
+    GramPiDesc* gdd = nullptr;
+    GramPiDesc* gdh = nullptr;
+    int64_t g_rows = -1;
+    int g_par = -1;
     double* h_small = nullptr;  // pinned: estimates / power-iteration result
     int32_t* info = nullptr;
     // snapshot ring: directions as rows
@@ -320,6 +327,7 @@ static sk_status dump(sketch_t h, int xi, int64_t ts) {
     e.slot = slot;
     c->q_.push_back(e);
     c->last_t = ts;
+    c->g_rows = -1;  // the residual rewrote both buffers
     c->dumps += 1;
     c->dirs += xi;
     return SK_OK;
@@ -333,23 +341,40 @@ static sk_status dump_step(sketch_t h, int64_t i) {
     const double* B = c->B[c->par];
     const int lx = (int)c->ldx, ly = (int)c->ldy;
     sk_status rc;
-    // power iteration in the row space
-    if ((rc = gemm(h, cg(A, lx, false, A, lx, true, c->Gx, ld, r, r, c->dx)))) return rc;
-    if ((rc = gemm(h, cg(B, ly, false, B, ly, true, c->Gy, ld, r, r, c->dy)))) return rc;
-    MatGenDesc m{};
-    m.M = c->pi_x0;
-    m.rows = c->dy;
-    m.cols = 1;
-    m.ld = 1;
-    m.seed = c->seed;
-    m.stream = c->stream;
-    m.c2 = (uint64_t)i;
-    m.c3 = 0x100u;
-    C_TRY(launch_philox_mat1(m, h->stream));
-    if ((rc = gemm(h, cg(B, ly, false, c->pi_x0, 1, false, c->pi_u0, 1, r, 1, c->dy)))) return rc;
-    if ((rc = gemm(h, cg(c->pi_x0, 1, true, c->pi_x0, 1, false, c->pi_n0, 1, 1, 1, c->dy)))) return rc;
+    // power iteration in the row space.  The kept Grams gain the new pair's
+    // row and column in one pass over the buffers, which also forms
+    // u0 = B x0 and |x0|^2 (x0: normal 0 of the Philox block at counter
+    // (t, 0, i, 0x100) for coordinate t); after a reduce (the other buffer
+    // pair) or a dump they are recomputed first.
+    const bool same = c->g_rows >= 0 && c->g_par == c->par;
+    const bool inc = same && c->g_rows == r - 1;
+    if (!inc && !(same && c->g_rows == r)) {
+        if ((rc = gemm(h, cg(A, lx, false, A, lx, true, c->Gkx, ld, r, r, c->dx)))) return rc;
+        if ((rc = gemm(h, cg(B, ly, false, B, ly, true, c->Gky, ld, r, r, c->dy)))) return rc;
+    }
+    GramPiDesc* gd = c->gdh;
+    for (int s = 0; s < 2; ++s) {
+        GramPiDesc& g = gd[s];
+        g = GramPiDesc{};
+        g.C = s == 0 ? B : A;
+        g.G = s == 0 ? c->Gky : c->Gkx;
+        g.u = s == 0 ? c->ub : c->ua;
+        g.ldc = s == 0 ? ly : lx;
+        g.d = s == 0 ? c->dy : c->dx;
+        g.r = (s == 0 || inc) ? r : 0;  // A's pass only extends its Gram
+        g.grow = inc ? r - 1 : -1;
+        g.ldg = ld;
+        g.seed = c->seed;
+        g.stream = c->stream;
+        g.c2 = (uint64_t)i;
+        g.c3 = 0x100u;
+    }
+    C_TRY(hipMemcpyAsync(c->gdd, c->gdh, 2 * sizeof(GramPiDesc), hipMemcpyHostToDevice, h->stream));
+    C_TRY(launch_win_gemv(c->gdd, 2, r, std::max(c->dx, c->dy), h->stream));
+    c->g_rows = r;
+    c->g_par = c->par;
     const int steps = (int)std::ceil(std::log2((double)c->dy)) + 1;
-    C_TRY(launch_cod_pi(c->Gx, c->Gy, ld, c->pi_u0, c->pi_n0, r, steps, c->pi_out, h->stream));
+    C_TRY(launch_cod_pi(c->Gkx, c->Gky, ld, c->ub, c->ub + ld, r, steps, c->pi_out, h->stream));
     C_TRY(hipMemcpyAsync(c->h_small, c->pi_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     C_TRY(hipStreamSynchronize(h->stream));
     const double s1 = std::sqrt(std::max(c->h_small[0], 0.0));
@@ -410,10 +435,10 @@ sk_status cod_create(sketch_t h) {
     for (double** p : {&c->Wk, &c->Xk, &c->Mk, &c->Uk}) C_TRY(A(p, (size_t)kl * kl));
     for (double** p : {&c->w1, &c->w2}) C_TRY(A(p, wk));
     C_TRY(A(&c->lam, (size_t)kl));
-    C_TRY(A(&c->pi_x0, (size_t)c->dy));
-    C_TRY(A(&c->pi_u0, (size_t)n));
-    C_TRY(A(&c->pi_n0, 1));
+    for (double** p : {&c->Gkx, &c->Gky}) C_TRY(A(p, (size_t)n * n));
+    for (double** p : {&c->ua, &c->ub}) C_TRY(A(p, (size_t)n + 1));
     C_TRY(A(&c->pi_out, 1));
+    C_TRY(h->dalloc((void**)&c->gdd, 2 * sizeof(GramPiDesc)));
     C_TRY(h->dalloc((void**)&c->info, 64));
     C_TRY(hipMemset(c->info, 0, 64));
     c->cap = 8 * (int64_t)c->ell;
@@ -434,6 +459,7 @@ sk_status cod_create(sketch_t h) {
     c->gpart_cap = (int64_t)1 << 21;
     C_TRY(A(&c->gpart, (size_t)c->gpart_cap));
     C_TRY(hipHostMalloc((void**)&c->h_small, sizeof(double) * (size_t)std::max(kl, 1), hipHostMallocDefault));
+    C_TRY(hipHostMalloc((void**)&c->gdh, 2 * sizeof(GramPiDesc), hipHostMallocDefault));
     return SK_OK;
 }
 
@@ -441,6 +467,7 @@ void cod_destroy(sketch_t h) {
     CodState* c = h->cod;
     if (!c) return;
     if (c->h_small) (void)hipHostFree(c->h_small);
+    if (c->gdh) (void)hipHostFree(c->gdh);
     delete c;
     h->cod = nullptr;
 }

@@ -49,6 +49,9 @@ hipError_t launch_win_pi(const void* descs, int count, int d, int max_r, double*
 // pass over every C (u = C x0, |x0|^2, the new row and column of G), then
 // one workgroup per level for the steps.
 hipError_t launch_win_pi_gram(const void* descs, int count, int max_r, int max_d, hipStream_t st);
+// The pass over C alone (u = C x0, |x0|^2 in u[ldg], the new Gram row and
+// column); descriptors with r = 0 are skipped.  max_d <= 4096.
+hipError_t launch_win_gemv(const void* descs, int count, int max_r, int max_d, hipStream_t st);
 // One split-K product (descriptor by value, with part, nsplit, kchunk set).
 hipError_t launch_gemm_split(const GemmDesc& g, hipStream_t st);
 // Single-descriptor launches with the descriptor passed by value.
