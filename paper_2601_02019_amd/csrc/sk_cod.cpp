@@ -67,6 +67,7 @@ struct CodState {
     int64_t g_rows = -1;
     int g_par = -1;
     double* h_small = nullptr;  // pinned: estimates / power-iteration result
+    hipEvent_t done = nullptr;  // polled by the per-pair waits
     int32_t* info = nullptr;
     // snapshot ring: directions as rows
     double *Zs = nullptr, *ZMs = nullptr, *MHs = nullptr, *Hs = nullptr;
@@ -87,6 +88,18 @@ struct CodState {
         if (_e != hipSuccess) return h->device_fail(std::string("cod: ") + #expr + ": " + \
                                                     hipGetErrorString(_e));              \
     } while (0)
+
+// Waits for the stream by polling an event recorded on it (the per-pair
+// decisions wait on short GPU stages, where a polled wait returns sooner).
+static hipError_t wait_stream(sketch_t h) {
+    hipError_t e = hipEventRecord(h->cod->done, h->stream);
+    while (e == hipSuccess) {
+        e = hipEventQuery(h->cod->done);
+        if (e == hipErrorNotReady) e = hipSuccess;
+        else break;
+    }
+    return e;
+}
 
 static GemmDesc cg(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C, int ldc, int M,
                    int N, int K, double alpha = 1.0, double beta = 0.0) {
@@ -219,7 +232,7 @@ static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t t
     if ((rc = eig(h, c->Mk, kl, c->Uk, kl, c->lam, k, c->w1, c->w2))) return rc;
     if ((rc = gemm(h, cg(Kb, kl, false, c->Uk, kl, false, out, kl, d, k, k)))) return rc;
     C_TRY(hipMemcpyAsync(c->h_small, c->lam, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
-    C_TRY(hipStreamSynchronize(h->stream));
+    C_TRY(wait_stream(h));
     c->nsi += 1;
     return SK_OK;
 }
@@ -376,7 +389,7 @@ static sk_status dump_step(sketch_t h, int64_t i) {
     const int steps = (int)std::ceil(std::log2((double)c->dy)) + 1;
     C_TRY(launch_cod_pi(c->Gkx, c->Gky, ld, c->ub, c->ub + ld, r, steps, c->pi_out, h->stream));
     C_TRY(hipMemcpyAsync(c->h_small, c->pi_out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    C_TRY(hipStreamSynchronize(h->stream));
+    C_TRY(wait_stream(h));
     const double s1 = std::sqrt(std::max(c->h_small[0], 0.0));
     if (!(s1 >= c->theta / 2.0)) return SK_OK;
     int kmax = std::min(std::min(c->ell, c->dx), std::min(c->dy, r));
@@ -460,6 +473,7 @@ sk_status cod_create(sketch_t h) {
     C_TRY(A(&c->gpart, (size_t)c->gpart_cap));
     C_TRY(hipHostMalloc((void**)&c->h_small, sizeof(double) * (size_t)std::max(kl, 1), hipHostMallocDefault));
     C_TRY(hipHostMalloc((void**)&c->gdh, 2 * sizeof(GramPiDesc), hipHostMallocDefault));
+    C_TRY(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
     return SK_OK;
 }
 
@@ -468,6 +482,7 @@ void cod_destroy(sketch_t h) {
     if (!c) return;
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->gdh) (void)hipHostFree(c->gdh);
+    if (c->done) (void)hipEventDestroy(c->done);
     delete c;
     h->cod = nullptr;
 }
