@@ -121,7 +121,8 @@ static GemmDesc cg(const double* A, int lda, bool ta, const double* B, int ldb, 
 }
 
 // One FP64 product; products with few output tiles and a long K are cut
-// along K (the cut depends on the shape alone, partials summed in order).
+// along K into chunks of >= 64, about 128 workgroups per product (the cut
+// depends on the shape alone, partials summed in order).
 static sk_status gemm(sketch_t h, const GemmDesc& g0) {
     if (g0.M <= 0 || g0.N <= 0) return SK_OK;
     CodState* c = h->cod;
@@ -129,7 +130,7 @@ static sk_status gemm(sketch_t h, const GemmDesc& g0) {
     const int64_t tiles = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
     if (g.K <= 0) return h->device_fail("cod: product with an empty inner dimension");
     if (tiles < 64 && g.K >= 256) {
-        int ns = (int)std::min<int64_t>(g.K / 128, std::max<int64_t>(2, 256 / tiles));
+        int ns = (int)std::min<int64_t>(g.K / 64, std::max<int64_t>(2, 128 / tiles));
         const int kc = (int)round_up((g.K + ns - 1) / ns, 16);
         ns = (g.K + kc - 1) / kc;
         if (ns > 1 && (int64_t)ns * g.M * g.N <= c->gpart_cap) {
