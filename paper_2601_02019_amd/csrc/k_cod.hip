@@ -70,7 +70,10 @@ __device__ double cod_block_sum(double v, double* red) {
 
 // One workgroup; r <= 512.  u0 = B x0, n0 = |x0|^2; out = |M x|^2 after
 // `steps` normalised steps (0 when an iterate vanishes).  With in_lds the two
-// Grams are first copied to LDS (dynamic, 2 r^2 doubles).
+// Grams are first copied to LDS (dynamic, 2 r^2 doubles).  The Grams are
+// exactly symmetric (both triangles come from the same products), so row i
+// of a product is read as column i: consecutive threads then read
+// consecutive words (no LDS bank conflicts, coalesced from memory).
 __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double* Gy0, int ld0, const double* u0,
                                                const double* n0, int r, int steps, double* out, int in_lds) {
     __shared__ double u[512], v[512], w[512];
@@ -97,14 +100,14 @@ __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double*
     for (int it = 0; it < steps && !zero; ++it) {
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
-            for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)i * ld + j], u[j], a);
+            for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)j * ld + i], u[j], a);
             v[i] = a;
         }
         __syncthreads();
         double loc = 0.0;
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
-            for (int j = 0; j < r; ++j) a = fma(Gy[(int64_t)i * ld + j], v[j], a);
+            for (int j = 0; j < r; ++j) a = fma(Gy[(int64_t)j * ld + i], v[j], a);
             w[i] = a;
             loc = fma(v[i], a, loc);
         }
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double*
     if (!zero)
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
-            for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)i * ld + j], u[j], a);
+            for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)j * ld + i], u[j], a);
             loc = fma(u[i], a, loc);
         }
     const double rq = cod_block_sum(loc, red);

@@ -191,9 +191,10 @@ static sk_status cholqr(sketch_t h, double** K, double** Q, int rows, int k, int
 // (left = false: in R^{d_y}), through products with A and B.  The oracle's form: simul_iter on the matrix C^T with
 // C = M^T (left) or C = M (right), test matrix Omega (d x k) on C's column
 // side, q re-orthonormalised power steps, Rayleigh-Ritz.  Leaves the
-// directions (d x k, ld kmax) in out and the k eigenvalue estimates (squared
-// singular values) in h_small.
-static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t tag, double* out) {
+// directions (d x k, ld kmax) in out and, with wait, the k eigenvalue
+// estimates (squared singular values) in h_small once the stream is done
+// (without wait nothing is read back and the call returns after queueing).
+static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t tag, double* out, bool wait) {
     CodState* c = h->cod;
     const int kl = c->kmax, r = (int)c->r;
     const double* A = c->A[c->par];
@@ -232,8 +233,10 @@ static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t t
     if ((rc = gemm(h, cg(c->Yd, kl, true, c->Yd, kl, false, c->Mk, kl, k, k, e)))) return rc;
     if ((rc = eig(h, c->Mk, kl, c->Uk, kl, c->lam, k, c->w1, c->w2))) return rc;
     if ((rc = gemm(h, cg(Kb, kl, false, c->Uk, kl, false, out, kl, d, k, k)))) return rc;
-    C_TRY(hipMemcpyAsync(c->h_small, c->lam, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
-    C_TRY(wait_stream(h));
+    if (wait) {
+        C_TRY(hipMemcpyAsync(c->h_small, c->lam, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
+        C_TRY(wait_stream(h));
+    }
     c->nsi += 1;
     return SK_OK;
 }
@@ -399,8 +402,10 @@ static sk_status dump_step(sketch_t h, int64_t i) {
     for (int s = 1; s <= nsteps && kmax >= 1; ++s) {
         int k = 1 << s;
         if (k > kmax) k = kmax;
-        if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z))) return rc;
-        if ((rc = simul_iter(h, false, k, i, 0x400u + (uint64_t)s, c->H))) return rc;
+        // the two calls run back to back; only the second call's estimates
+        // are read, so only it waits
+        if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z, false))) return rc;
+        if ((rc = simul_iter(h, false, k, i, 0x400u + (uint64_t)s, c->H, true))) return rc;
         const double* est = c->h_small;  // the second call's estimates
         if (!(std::sqrt(std::max(est[k - 1], 0.0)) >= c->theta) || k == kmax) {
             int xi = 0;
