@@ -56,12 +56,13 @@ struct CodState {
     double *Px = nullptr, *Py = nullptr, *K = nullptr, *KK = nullptr, *V = nullptr, *T1 = nullptr, *T2 = nullptr;
     double *lx = nullptr, *ly = nullptr, *lk = nullptr, *e1 = nullptr, *e2 = nullptr;
     // simul_iter scratch
-    double *Om = nullptr, *Q1 = nullptr, *Yd = nullptr, *Tr = nullptr, *Z = nullptr, *H = nullptr;
+    double *Om = nullptr, *Yd = nullptr, *Tr = nullptr, *Z = nullptr, *H = nullptr;
     double *Wk = nullptr, *Xk = nullptr, *Mk = nullptr, *Uk = nullptr, *lam = nullptr, *w1 = nullptr, *w2 = nullptr;
     // power iteration: the kept Grams A A^T and B B^T (n2 x n2, complete for
     // the first g_rows rows of buffer pair g_par; g_rows < 0 after a dump),
     // u = B x0 with |x0|^2 in ub[n2], the pass descriptors (device, pinned)
     double *Gkx = nullptr, *Gky = nullptr, *ua = nullptr, *ub = nullptr, *pi_out = nullptr;
+    double* rs[4] = {nullptr, nullptr, nullptr, nullptr};  // row-space simul_iter iterates (n2 x kmax)
     GramPiDesc* gdd = nullptr;
     GramPiDesc* gdh = nullptr;
     int64_t g_rows = -1;
@@ -164,46 +165,28 @@ static sk_status eig(sketch_t h, const double* A, int lda, double* X, int ldx, d
     return SK_OK;
 }
 
-// Orthonormal basis of K (rows x k, ld kl) by `passes` CholeskyQR passes
-// (rank dropping as in the shrink); the basis ends in *K (swapped with *Q).
-static sk_status cholqr(sketch_t h, double** K, double** Q, int rows, int k, int passes) {
-    CodState* c = h->cod;
-    const int kl = c->kmax;
-    sk_status rc;
-    for (int p = 0; p < passes; ++p) {
-        if ((rc = gemm(h, cg(*K, kl, true, *K, kl, false, c->Wk, kl, k, k, rows)))) return rc;
-        SmallDesc sd{};
-        sd.A = c->Wk;
-        sd.lda = kl;
-        sd.X = c->Xk;
-        sd.ldx = kl;
-        sd.n = k;
-        sd.work = c->w1;
-        C_TRY(launch_cholinv1(sd, h->stream));
-        if ((rc = gemm(h, cg(*K, kl, false, c->Xk, kl, true, *Q, kl, rows, k, k)))) return rc;
-        std::swap(*K, *Q);
-    }
-    return SK_OK;
-}
-
 // Algorithm "Simultaneous Iteration" for the left directions of M = A^T B
 // (left = true: directions and test matrix in R^{d_x}) or its right ones
-// (left = false: in R^{d_y}), through products with A and B.  The oracle's form: simul_iter on the matrix C^T with
-// C = M^T (left) or C = M (right), test matrix Omega (d x k) on C's column
-// side, q re-orthonormalised power steps, Rayleigh-Ritz.  Leaves the
-// directions (d x k, ld kmax) in out and, with wait, the k eigenvalue
-// estimates (squared singular values) in h_small once the stream is done
-// (without wait nothing is read back and the call returns after queueing).
+// (left = false: in R^{d_y}).  The oracle's form: simul_iter on the matrix
+// C^T with C = M^T (left) or C = M (right), test matrix Omega (d x k) on C's
+// column side, q re-orthonormalised power steps, Rayleigh-Ritz.  With P the
+// buffer applied first (A left, B right), R the other, C v = R^T (P v), and
+// the kept Grams G_P = P P^T, G_R = R R^T, the iterate K is carried as
+// K = P^T S with S (r x k) in the row space: C^T C K = P^T (G_R G_P S),
+// K^T K = S^T G_P S, K X^T = P^T (S X^T), (C K)^T (C K) = S^T G_P G_R G_P S.
+// In exact arithmetic these are the d-side steps; only P Omega and the final
+// K U = P^T (S U) read a buffer.  Leaves the directions (d x k, ld kmax) in
+// out and, with wait, the k eigenvalue estimates (squared singular values) in
+// h_small once the stream is done (without wait nothing is read back and the
+// call returns after queueing).  The kept Grams must be complete.
 static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t tag, double* out, bool wait) {
     CodState* c = h->cod;
-    const int kl = c->kmax, r = (int)c->r;
-    const double* A = c->A[c->par];
-    const double* B = c->B[c->par];
-    // C = M^T: C v = B^T (A v), C^T w = A^T (B w), d = d_x; right: swap A, B
-    const double* P = left ? A : B;  // applied first in C v
-    const double* R = left ? B : A;
-    const int ldp = (int)(left ? c->ldx : c->ldy), ldr = (int)(left ? c->ldy : c->ldx);
-    const int d = left ? c->dx : c->dy, e = left ? c->dy : c->dx;
+    const int kl = c->kmax, r = (int)c->r, ld = c->n2;
+    const double* P = left ? c->A[c->par] : c->B[c->par];
+    const int ldp = (int)(left ? c->ldx : c->ldy);
+    const int d = left ? c->dx : c->dy;
+    const double* GP = left ? c->Gkx : c->Gky;
+    const double* GR = left ? c->Gky : c->Gkx;
     sk_status rc;
     MatGenDesc m{};
     m.M = c->Om;
@@ -215,24 +198,48 @@ static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t t
     m.c2 = (uint64_t)ts;
     m.c3 = tag;
     C_TRY(launch_philox_mat1(m, h->stream));
-    double* Kb = c->Om;
-    double* Qb = c->Q1;
-    for (int it = 0; it <= c->q; ++it) {
-        if (it > 0 && (rc = cholqr(h, &Kb, &Qb, d, k, 1))) return rc;
-        // Y = C K = R^T (P K)
-        if ((rc = gemm(h, cg(P, ldp, false, Kb, kl, false, c->Tr, kl, r, k, d)))) return rc;
-        if ((rc = gemm(h, cg(R, ldr, true, c->Tr, kl, false, c->Yd, kl, e, k, r)))) return rc;
-        // K = C^T Y = P^T (R Y)
-        if ((rc = gemm(h, cg(R, ldr, false, c->Yd, kl, false, c->Tr, kl, r, k, e)))) return rc;
-        if ((rc = gemm(h, cg(P, ldp, true, c->Tr, kl, false, Kb, kl, d, k, r)))) return rc;
+    double* S = c->rs[0];
+    double* S2 = c->rs[1];
+    double* GS = c->rs[2];
+    double* V = c->rs[3];
+    // the first power step: K = C^T C Omega = P^T (G_R (P Omega))
+    if ((rc = gemm(h, cg(P, ldp, false, c->Om, kl, false, V, kl, r, k, d)))) return rc;
+    if ((rc = gemm(h, cg(GR, ld, false, V, kl, false, S, kl, r, k, r)))) return rc;
+    // CholeskyQR passes on K = P^T S: W = S^T G_P S, X = chol(W)^-1, S <- S X^T
+    auto cholqr_rows = [&](int passes) -> sk_status {
+        for (int p = 0; p < passes; ++p) {
+            sk_status e;
+            if ((e = gemm(h, cg(GP, ld, false, S, kl, false, GS, kl, r, k, r)))) return e;
+            if ((e = gemm(h, cg(S, kl, true, GS, kl, false, c->Wk, kl, k, k, r)))) return e;
+            SmallDesc sd{};
+            sd.A = c->Wk;
+            sd.lda = kl;
+            sd.X = c->Xk;
+            sd.ldx = kl;
+            sd.n = k;
+            sd.work = c->w1;
+            C_TRY(launch_cholinv1(sd, h->stream));
+            if ((e = gemm(h, cg(S, kl, false, c->Xk, kl, true, S2, kl, r, k, k)))) return e;
+            std::swap(S, S2);
+        }
+        return SK_OK;
+    };
+    for (int it = 1; it <= c->q; ++it) {
+        if ((rc = cholqr_rows(1))) return rc;
+        // K <- C^T C K: S <- G_R G_P S
+        if ((rc = gemm(h, cg(GP, ld, false, S, kl, false, GS, kl, r, k, r)))) return rc;
+        if ((rc = gemm(h, cg(GR, ld, false, GS, kl, false, S2, kl, r, k, r)))) return rc;
+        std::swap(S, S2);
     }
-    if ((rc = cholqr(h, &Kb, &Qb, d, k, 2))) return rc;  // Kb holds Q
-    // CQ = C Q (e x k) into Yd; M_k = CQ^T CQ
-    if ((rc = gemm(h, cg(P, ldp, false, Kb, kl, false, c->Tr, kl, r, k, d)))) return rc;
-    if ((rc = gemm(h, cg(R, ldr, true, c->Tr, kl, false, c->Yd, kl, e, k, r)))) return rc;
-    if ((rc = gemm(h, cg(c->Yd, kl, true, c->Yd, kl, false, c->Mk, kl, k, k, e)))) return rc;
+    if ((rc = cholqr_rows(2))) return rc;  // K = P^T S has orthonormal columns
+    // M_k = (C K)^T (C K) = (G_P S)^T G_R (G_P S)
+    if ((rc = gemm(h, cg(GP, ld, false, S, kl, false, GS, kl, r, k, r)))) return rc;
+    if ((rc = gemm(h, cg(GR, ld, false, GS, kl, false, V, kl, r, k, r)))) return rc;
+    if ((rc = gemm(h, cg(GS, kl, true, V, kl, false, c->Mk, kl, k, k, r)))) return rc;
     if ((rc = eig(h, c->Mk, kl, c->Uk, kl, c->lam, k, c->w1, c->w2))) return rc;
-    if ((rc = gemm(h, cg(Kb, kl, false, c->Uk, kl, false, out, kl, d, k, k)))) return rc;
+    // directions K U = P^T (S U)
+    if ((rc = gemm(h, cg(S, kl, false, c->Uk, kl, false, S2, kl, r, k, k)))) return rc;
+    if ((rc = gemm(h, cg(P, ldp, true, S2, kl, false, out, kl, d, k, r)))) return rc;
     if (wait) {
         C_TRY(hipMemcpyAsync(c->h_small, c->lam, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
         C_TRY(wait_stream(h));
@@ -449,13 +456,14 @@ sk_status cod_create(sketch_t h) {
         C_TRY(A(p, (size_t)n * n));
     for (double** p : {&c->e1, &c->e2}) C_TRY(A(p, wn));
     for (double** p : {&c->lx, &c->ly, &c->lk}) C_TRY(A(p, (size_t)n));
-    for (double** p : {&c->Om, &c->Q1, &c->Yd, &c->Z, &c->H}) C_TRY(A(p, (size_t)dmax * kl));
+    for (double** p : {&c->Om, &c->Yd, &c->Z, &c->H}) C_TRY(A(p, (size_t)dmax * kl));
     C_TRY(A(&c->Tr, (size_t)n * kl));
     for (double** p : {&c->Wk, &c->Xk, &c->Mk, &c->Uk}) C_TRY(A(p, (size_t)kl * kl));
     for (double** p : {&c->w1, &c->w2}) C_TRY(A(p, wk));
     C_TRY(A(&c->lam, (size_t)kl));
     for (double** p : {&c->Gkx, &c->Gky}) C_TRY(A(p, (size_t)n * n));
     for (double** p : {&c->ua, &c->ub}) C_TRY(A(p, (size_t)n + 1));
+    for (double*& p : c->rs) C_TRY(A(&p, (size_t)n * kl));
     C_TRY(A(&c->pi_out, 1));
     C_TRY(h->dalloc((void**)&c->gdd, 2 * sizeof(GramPiDesc)));
     C_TRY(h->dalloc((void**)&c->info, 64));
