@@ -100,6 +100,7 @@ __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double*
     for (int it = 0; it < steps && !zero; ++it) {
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
+#pragma unroll 8
             for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)j * ld + i], u[j], a);
             v[i] = a;
         }
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double*
         double loc = 0.0;
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
+#pragma unroll 8
             for (int j = 0; j < r; ++j) a = fma(Gy[(int64_t)j * ld + i], v[j], a);
             w[i] = a;
             loc = fma(v[i], a, loc);
@@ -124,6 +126,7 @@ __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double*
     if (!zero)
         for (int i = tid; i < r; i += 256) {
             double a = 0.0;
+#pragma unroll 8
             for (int j = 0; j < r; ++j) a = fma(Gx[(int64_t)j * ld + i], u[j], a);
             loc = fma(u[i], a, loc);
         }

@@ -303,6 +303,7 @@ __global__ __launch_bounds__(1024) void k_win_pig(const GramPiDesc* ds, int lds_
         double acc = 0.0;
         if (j < r) {
             const int il = min(ie, ib + cpc);
+#pragma unroll 8
             for (int i = ib; i < il; ++i) acc = fma(gll[(i - ib) * r + j], y[i], acc);
 #pragma unroll
             for (int t = 0; t < kPigRegs; ++t) {
