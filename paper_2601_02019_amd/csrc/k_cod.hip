@@ -69,29 +69,27 @@ __device__ double cod_block_sum(double v, double* red) {
 }
 
 // One workgroup; r <= 512.  u0 = B x0, n0 = |x0|^2; out = |M x|^2 after
-// `steps` normalised steps (0 when an iterate vanishes).  With in_lds the two
+// `steps` normalised steps (0 when an iterate vanishes).  With IN_LDS the two
 // Grams are first copied to LDS (dynamic, 2 r^2 doubles).  The Grams are
 // exactly symmetric (both triangles come from the same products), so row i
 // of a product is read as column i: consecutive threads then read
 // consecutive words (no LDS bank conflicts, coalesced from memory).
+template <bool IN_LDS>
 __global__ __launch_bounds__(256) void k_cod_pi(const double* Gx0, const double* Gy0, int ld0, const double* u0,
-                                               const double* n0, int r, int steps, double* out, int in_lds) {
+                                               const double* n0, int r, int steps, double* out) {
     __shared__ double u[512], v[512], w[512];
     __shared__ double red[4];
     extern __shared__ double gl[];
     const int tid = threadIdx.x;
-    const double* Gx = Gx0;
-    const double* Gy = Gy0;
-    int ld = ld0;
-    if (in_lds) {
+    // (a compile-time choice, so that LDS reads compile to LDS instructions)
+    if (IN_LDS)
         for (int e = tid; e < r * r; e += 256) {
             gl[e] = Gx0[(int64_t)(e / r) * ld0 + e % r];
             gl[r * r + e] = Gy0[(int64_t)(e / r) * ld0 + e % r];
         }
-        Gx = gl;
-        Gy = gl + r * r;
-        ld = r;
-    }
+    const double* Gx = IN_LDS ? gl : Gx0;
+    const double* Gy = IN_LDS ? gl + r * r : Gy0;
+    const int ld = IN_LDS ? r : ld0;
     const double nn = *n0;
     const double inv0 = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     for (int i = tid; i < r; i += 256) u[i] = u0[i] * inv0;
@@ -141,7 +139,7 @@ hipError_t launch_cod_pi(const double* Gx, const double* Gy, int ld, const doubl
     static int lds_cap = -1;
     if (lds_cap < 0) {
         const int want = (int)(sizeof(double) * 2 * 64 * 64);
-        lds_cap = hipFuncSetAttribute((const void*)k_cod_pi, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
+        lds_cap = hipFuncSetAttribute((const void*)k_cod_pi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
                           hipSuccess
                       ? want
                       : 0;
@@ -149,7 +147,10 @@ hipError_t launch_cod_pi(const double* Gx, const double* Gy, int ld, const doubl
     }
     const size_t need = sizeof(double) * 2 * (size_t)r * r;
     const int in_lds = need <= (size_t)lds_cap ? 1 : 0;
-    hipLaunchKernelGGL(k_cod_pi, dim3(1), dim3(256), in_lds ? need : 0, st, Gx, Gy, ld, u0, n0, r, steps, out, in_lds);
+    if (in_lds)
+        hipLaunchKernelGGL(k_cod_pi<true>, dim3(1), dim3(256), need, st, Gx, Gy, ld, u0, n0, r, steps, out);
+    else
+        hipLaunchKernelGGL(k_cod_pi<false>, dim3(1), dim3(256), 0, st, Gx, Gy, ld, u0, n0, r, steps, out);
     return hipGetLastError();
 }
 
