@@ -759,7 +759,7 @@ def copy_main(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus {args.gpus} "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (--gpus {args.gpus} "
               f"requested). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.workload != "persistent":
