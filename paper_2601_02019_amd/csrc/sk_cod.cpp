@@ -409,17 +409,25 @@ static sk_status dump_step(sketch_t h, int64_t i) {
     for (int s = 1; s <= nsteps && kmax >= 1; ++s) {
         int k = 1 << s;
         if (k > kmax) k = kmax;
-        // the two calls run back to back; only the second call's estimates
-        // are read, so only it waits
-        if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z, false))) return rc;
+        // Each step makes a left and a right simul_iter call with their own
+        // Philox counters; only the right call's estimates decide, and the
+        // left call's directions are used only by a dump at this step.  So
+        // the left call runs only before a dump (its values do not depend on
+        // the order of the two calls); a step that does not dump elides it
+        // and still counts it, so the call count is the algorithm's.
         if ((rc = simul_iter(h, false, k, i, 0x400u + (uint64_t)s, c->H, true))) return rc;
-        const double* est = c->h_small;  // the second call's estimates
-        if (!(std::sqrt(std::max(est[k - 1], 0.0)) >= c->theta) || k == kmax) {
-            int xi = 0;
+        const double* est = c->h_small;  // the right call's estimates
+        const bool stop = !(std::sqrt(std::max(est[k - 1], 0.0)) >= c->theta) || k == kmax;
+        int xi = 0;
+        if (stop)
             while (xi < k && std::sqrt(std::max(est[xi], 0.0)) >= c->theta) ++xi;
-            if (xi > 0 && (rc = dump(h, xi, i))) return rc;
-            break;
+        if (xi > 0) {
+            if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z, false))) return rc;
+            if ((rc = dump(h, xi, i))) return rc;
+        } else {
+            c->nsi += 1;
         }
+        if (stop) break;
     }
     return SK_OK;
 }
