@@ -63,6 +63,7 @@ struct CodState {
     // u = B x0 with |x0|^2 in ub[n2], the pass descriptors (device, pinned)
     double *Gkx = nullptr, *Gky = nullptr, *ua = nullptr, *ub = nullptr, *pi_out = nullptr;
     double* rs[4] = {nullptr, nullptr, nullptr, nullptr};  // row-space simul_iter iterates (n2 x kmax)
+    double* s_last = nullptr;                             // the rs buffer holding the last call's S
     GramPiDesc* gdd = nullptr;
     GramPiDesc* gdh = nullptr;
     int64_t g_rows = -1;
@@ -179,7 +180,8 @@ static sk_status eig(sketch_t h, const double* A, int lda, double* X, int ldx, d
 // out and, with wait, the k eigenvalue estimates (squared singular values) in
 // h_small once the stream is done (without wait nothing is read back and the
 // call returns after queueing).  The kept Grams must be complete.
-static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t tag, double* out, bool wait) {
+static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t tag, double* out, bool wait,
+                            bool dirs) {
     CodState* c = h->cod;
     const int kl = c->kmax, r = (int)c->r, ld = c->n2;
     const double* P = left ? c->A[c->par] : c->B[c->par];
@@ -237,15 +239,32 @@ static sk_status simul_iter(sketch_t h, bool left, int k, int64_t ts, uint64_t t
     if ((rc = gemm(h, cg(GR, ld, false, GS, kl, false, V, kl, r, k, r)))) return rc;
     if ((rc = gemm(h, cg(GS, kl, true, V, kl, false, c->Mk, kl, k, k, r)))) return rc;
     if ((rc = eig(h, c->Mk, kl, c->Uk, kl, c->lam, k, c->w1, c->w2))) return rc;
-    // directions K U = P^T (S U)
-    if ((rc = gemm(h, cg(S, kl, false, c->Uk, kl, false, S2, kl, r, k, k)))) return rc;
-    if ((rc = gemm(h, cg(P, ldp, true, S2, kl, false, out, kl, d, k, r)))) return rc;
+    // directions K U = P^T (S U), now or (dirs false) by directions_of_last
+    c->s_last = S;
+    if (dirs) {
+        if ((rc = gemm(h, cg(S, kl, false, c->Uk, kl, false, S2, kl, r, k, k)))) return rc;
+        if ((rc = gemm(h, cg(P, ldp, true, S2, kl, false, out, kl, d, k, r)))) return rc;
+    }
     if (wait) {
         C_TRY(hipMemcpyAsync(c->h_small, c->lam, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, h->stream));
         C_TRY(wait_stream(h));
     }
     c->nsi += 1;
     return SK_OK;
+}
+
+// The directions K U = P^T (S U) of the last simul_iter call (made with
+// dirs = false), from its S and U, before another call reuses them.
+static sk_status directions_of_last(sketch_t h, bool left, int k, double* out) {
+    CodState* c = h->cod;
+    const int kl = c->kmax, r = (int)c->r;
+    const double* P = left ? c->A[c->par] : c->B[c->par];
+    const int ldp = (int)(left ? c->ldx : c->ldy);
+    const int d = left ? c->dx : c->dy;
+    double* T = c->s_last == c->rs[0] ? c->rs[1] : c->rs[0];
+    sk_status rc;
+    if ((rc = gemm(h, cg(c->s_last, kl, false, c->Uk, kl, false, T, kl, r, k, k)))) return rc;
+    return gemm(h, cg(P, ldp, true, T, kl, false, out, kl, d, k, r));
 }
 
 // The co-occurring-directions reduce of the full buffers (2 ell rows) into
@@ -415,14 +434,15 @@ static sk_status dump_step(sketch_t h, int64_t i) {
         // the left call runs only before a dump (its values do not depend on
         // the order of the two calls); a step that does not dump elides it
         // and still counts it, so the call count is the algorithm's.
-        if ((rc = simul_iter(h, false, k, i, 0x400u + (uint64_t)s, c->H, true))) return rc;
+        if ((rc = simul_iter(h, false, k, i, 0x400u + (uint64_t)s, c->H, true, false))) return rc;
         const double* est = c->h_small;  // the right call's estimates
         const bool stop = !(std::sqrt(std::max(est[k - 1], 0.0)) >= c->theta) || k == kmax;
         int xi = 0;
         if (stop)
             while (xi < k && std::sqrt(std::max(est[xi], 0.0)) >= c->theta) ++xi;
         if (xi > 0) {
-            if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z, false))) return rc;
+            if ((rc = directions_of_last(h, false, k, c->H))) return rc;
+            if ((rc = simul_iter(h, true, k, i, 0x200u + (uint64_t)s, c->Z, false, true))) return rc;
             if ((rc = dump(h, xi, i))) return rc;
         } else {
             c->nsi += 1;
